@@ -1,0 +1,93 @@
+"""Wilson fermion operator, even-odd preconditioning and K = M^dag M (FP64 oracle).
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+Sec. 2 names the fermion matrix M and K = M^dag M; Sec. 3.1 fixes Wilson
+fermions with hopping parameter kappa and even-odd preconditioning, but prints
+no formula.  The reading (standard hopping-parameter form):
+
+    M = 1 - kappa D,
+    (D psi)(x) = sum_mu (1 - g_mu) U_mu(x) psi(x + mu)
+                      + (1 + g_mu) U_mu(x - mu)^dag psi(x - mu),
+
+with the time-boundary phase of ``lattice.shift``.  D^dag is written out from
+the definition of the adjoint (the projectors swap), not through gamma_5; the
+gamma_5-hermiticity D^dag = g5 D g5 is a test, not an assumption.
+
+Even-odd: with M_ee = M_oo = 1 the Schur complement on the even sites is
+M-hat = 1 - kappa^2 D_eo D_oe, and K-hat = M-hat^dag M-hat.  The Hasenbusch
+shift is J = K-hat + mu^2 (mass-preconditioner in the mu^2 form).
+Half-lattice fields are [V/2, 4, 3] arrays of one parity's sites in
+lexicographic order.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import lattice as lat
+
+
+def hop(U, psi, L, t_bc=-1, dagger=False):
+    """Full-lattice D psi (or D^dag psi).  U: [4,V,3,3], psi: [V,4,3]."""
+    g = lat.gammas()
+    one = np.eye(4)
+    s = -1.0 if dagger else 1.0
+    out = np.zeros_like(psi)
+    for mu in range(4):
+        fwd = lat.shift(psi, L, mu, +1, t_bc)                      # psi(x + mu)
+        u_fwd = np.einsum("xab,xsb->xsa", U[mu], fwd)               # U_mu(x) psi(x + mu)
+        out += lat.apply_spin(one - s * g[mu], u_fwd)
+        udag_psi = np.einsum("xba,xsb->xsa", np.conj(U[mu]), psi)   # U_mu(x)^dag psi(x)
+        bwd = lat.shift(udag_psi, L, mu, -1, t_bc)                  # ... at x - mu
+        out += lat.apply_spin(one + s * g[mu], bwd)
+    return out
+
+
+def M(U, psi, L, kappa, t_bc=-1, dagger=False):
+    return psi - kappa * hop(U, psi, L, t_bc, dagger)
+
+
+def K(U, psi, L, kappa, t_bc=-1):
+    """K = M^dag M on the full lattice (Sec. 2)."""
+    return M(U, M(U, psi, L, kappa, t_bc), L, kappa, t_bc, dagger=True)
+
+
+# ---------------------------------------------------------------- even-odd
+def hop_eo(U, psi_h, L, out_parity, t_bc=-1, dagger=False):
+    """The parity block of D (or D^dag) that maps parity 1-p to parity p."""
+    full = lat.embed(psi_h, L, 1 - out_parity)
+    return lat.restrict(hop(U, full, L, t_bc, dagger), L, out_parity)
+
+
+def Mhat(U, psi_e, L, kappa, t_bc=-1, dagger=False):
+    """M-hat = 1 - kappa^2 D_eo D_oe on even sites (or its adjoint)."""
+    odd = hop_eo(U, psi_e, L, 1, t_bc, dagger)
+    return psi_e - kappa ** 2 * hop_eo(U, odd, L, 0, t_bc, dagger)
+
+
+def Khat(U, psi_e, L, kappa, t_bc=-1):
+    return Mhat(U, Mhat(U, psi_e, L, kappa, t_bc), L, kappa, t_bc, dagger=True)
+
+
+def J(U, psi_e, L, kappa, mu2, t_bc=-1):
+    """Hasenbusch-shifted operator J = K-hat + mu^2."""
+    return Khat(U, psi_e, L, kappa, t_bc) + mu2 * psi_e
+
+
+def W(U, psi_e, L, kappa, mu, t_bc=-1, dagger=False):
+    """W = M-hat + i mu g5 (W^dag W = J, derived from g5-hermiticity)."""
+    g5 = lat.gamma5()
+    s = -1.0 if dagger else 1.0
+    return Mhat(U, psi_e, L, kappa, t_bc, dagger) + s * 1j * mu * lat.apply_spin(g5, psi_e)
+
+
+def dense(op, n_sites, dtype=np.complex128):
+    """Dense matrix of a linear map on [n_sites, 4, 3] fields (brute force, tiny lattices)."""
+    n = n_sites * 12
+    A = np.zeros((n, n), dtype=dtype)
+    e = np.zeros(n, dtype=dtype)
+    for j in range(n):
+        e[:] = 0
+        e[j] = 1
+        A[:, j] = op(e.reshape(n_sites, 4, 3)).reshape(n)
+    return A
