@@ -1,0 +1,235 @@
+/* wilson_hmc.h -- C ABI of the MI355X (gfx950) two-flavour Wilson-fermion HMC hot path.
+ *
+ * Method: Haar, Kamleh, Zanotti, Nakamura, "Improving Polynomial-filtered
+ * Hybrid Monte Carlo With Hasenbusch" (arXiv:1702.00124).  Sec. 2 defines the
+ * HMC (heatbath, momenta, H = sum tr P^2 + S, the time step T[eps] and space
+ * step S[eps], Metropolis), the two-flavour action phi^dag (M^dag M)^-1 phi
+ * and its force, mass preconditioning and polynomial filtering; Sec. 3.1 fixes
+ * Wilson fermions, hopping parameter kappa and even-odd preconditioning;
+ * Sec. 3.2 the generalised multi-time-scale integrator; Sec. 4.1 the PF-MP
+ * action.  Readings where the paper prints no formula:
+ *
+ *   M = 1 - kappa D,  (D psi)(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu)
+ *                                       + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)
+ *   (time-boundary phase t_bc on hops that wrap in t), chiral Hermitian gammas
+ *   with g5 = diag(1,1,-1,-1); M-hat = 1 - kappa^2 D_eo D_oe on even sites;
+ *   K-hat = M-hat^dag M-hat; J = K-hat + mu^2 (Hasenbusch shift, mu^2 form);
+ *   Chebyshev filter 1 - x P_n(x) = T_{n+1}(y(x)) / T_{n+1}(y(0)),
+ *   y(x) = (b + a - 2x)/(b - a);  su(3) coefficients p^a of P = sum p^a T^a,
+ *   T^a = lambda^a / 2.
+ *
+ * Conventions of every buffer:
+ *   * all field pointers are DEVICE pointers on the context's device;
+ *   * canonical spinor: complex128 [nrhs][n][4 spin][3 colour], n = V (full
+ *     lattice, site s = x + Lx*(y + Ly*(z + Lz*t))) or n = V/2 (the sites of
+ *     one parity in lexicographic order);
+ *   * canonical links: complex128 [4 mu][V][3][3];
+ *   * canonical su(3) field (momenta, forces): float64 [4 mu][V][8];
+ *   * internal half-lattice spinor: precision-dependent structure-of-arrays,
+ *     wl_field_bytes() bytes; an internal FULL field is the even half
+ *     followed by the odd half (two half fields back to back);
+ *   * internal su(3) field: float64 [2 parity][4 mu][8][V/2], 256*V bytes.
+ * The caller owns every field buffer; the library owns the context (packed
+ * links, workspace).  Calls are ordered on the context's HIP stream; calls
+ * that return host values synchronise it.
+ *
+ * Errors: every function returns WL_OK (0) or a negative code; nothing throws
+ * or aborts across the ABI.  wl_last_error() gives the calling thread's
+ * message for the last failure.  All lattice extents must be even.
+ */
+#ifndef WILSON_HMC_H
+#define WILSON_HMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { WL_OK = 0, WL_EINVAL = -1, WL_EUNSUPPORTED = -2, WL_ENOMEM = -3, WL_EHIP = -4, WL_ENOCONV = -5 };
+
+typedef enum { WL_F64 = 0, WL_F32 = 1, WL_BF16 = 2 } wl_prec;
+
+typedef struct wl_lattice wl_lattice;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* wl_last_error(void);
+
+/* Create a context for an Lx x Ly x Lz x Lt lattice (all even, Lx >= 2) with
+ * fermion time boundary phase t_bc (+1 periodic, -1 antiperiodic, Sec. 3.1
+ * workload).  hip_stream: a hipStream_t (NULL = default stream). */
+int wl_create(wl_lattice** out, const int32_t L[4], int32_t t_bc, void* hip_stream);
+int wl_destroy(wl_lattice* lat);
+int wl_set_stream(wl_lattice* lat, void* hip_stream);
+
+/* Gauge links U (Sec. 2): copy canonical complex128 [4][V][3][3] in / out. */
+int wl_set_links(wl_lattice* lat, const void* U_canon);
+int wl_get_links(wl_lattice* lat, void* U_canon);
+
+/* Bytes of one internal half-lattice spinor field of nrhs right-hand sides. */
+int wl_field_bytes(const wl_lattice* lat, wl_prec prec, int nrhs, size_t* bytes);
+
+/* Canonical half-lattice spinors (complex128 [nrhs][V/2][4][3]) <-> internal. */
+int wl_import_spinor(wl_lattice* lat, void* dst_internal, const void* src_canon, wl_prec prec, int nrhs);
+int wl_export_spinor(wl_lattice* lat, void* dst_canon, const void* src_internal, wl_prec prec, int nrhs);
+/* Canonical full spinor (complex128 [V][4][3]) <-> internal F64 full field. */
+int wl_import_full(wl_lattice* lat, void* dst_internal_full, const void* src_canon);
+int wl_export_full(wl_lattice* lat, void* dst_canon, const void* src_internal_full);
+/* Canonical su(3) field float64 [4][V][8] <-> internal float64 [2][4][8][V/2]. */
+int wl_import_su3(wl_lattice* lat, double* dst_internal, const double* src_canon);
+int wl_export_su3(wl_lattice* lat, double* dst_canon, const double* src_internal);
+
+/* Wilson hopping operator, one even-odd block (Sec. 3.1; formula above):
+ * out (parity out_parity) = D_{p,1-p} in, or the same block of D^dag when
+ * dagger != 0.  in/out: internal half fields, nrhs right-hand sides, in the
+ * storage precision prec (F64 computes in FP64, F32/BF16 in FP32). */
+int wilson_dslash(wl_lattice* lat, void* out, const void* in, int out_parity, int dagger,
+                  wl_prec prec, int nrhs);
+
+/* Operators built from the hop (Sec. 2 and 3.1). */
+typedef enum {
+  WL_OP_M = 0,        /* full lattice M = 1 - kappa D; FULL internal fields, nrhs = 1 */
+  WL_OP_MDAG = 1,     /* full lattice M^dag */
+  WL_OP_K = 2,        /* full lattice K = M^dag M */
+  WL_OP_MHAT = 3,     /* even sites: M-hat = 1 - kappa^2 D_eo D_oe */
+  WL_OP_MHAT_DAG = 4, /* even sites: M-hat^dag */
+  WL_OP_J = 5         /* even sites: J = K-hat + mu2[r] (K-hat when mu2 = 0) */
+} wl_op;
+
+/* out = op(in).  kappa: hopping parameter.  mu2: host array of nrhs shifts
+ * (only WL_OP_J reads it; may be NULL = all zero).  Precision as wilson_dslash. */
+int apply_K(wl_lattice* lat, void* out, const void* in, double kappa, const double* mu2, int nrhs,
+            wl_op op, wl_prec prec);
+
+/* Conjugate gradient (Sec. 2: inversion of K by CG) on op = WL_OP_J (even
+ * sites, nrhs right-hand sides, shifts mu2[r]) or WL_OP_K (full lattice,
+ * nrhs = 1).  x0 = 0; stops when the FP64 true residual |b - A x| <= tol |b|
+ * for every rhs.  inner = WL_F64 runs plain FP64 CG; WL_F32 / WL_BF16 run the
+ * inner iteration with that storage (FP32 arithmetic, FP64 dot products) and
+ * FP64 reliable updates r = b - A x whenever the iterated residual fell by
+ * delta since the last update.  x and b: internal F64 fields.  stats: host
+ * array of nrhs entries (may be NULL).  Returns WL_ENOCONV, with x the last
+ * iterate and stats filled, if some rhs misses tol within maxiter. */
+typedef struct {
+  double tol;      /* relative true-residual target, e.g. 1e-10 */
+  int maxiter;     /* per rhs */
+  wl_prec inner;   /* precision of the inner iteration */
+  double delta;    /* reliable-update threshold (0 -> 0.1) */
+  int chunk;       /* iterations between host convergence checks (0 -> 8) */
+  int use_graph;   /* capture each chunk as a hipGraph and replay it */
+} wl_cg_params;
+
+typedef struct {
+  int iters;
+  int reliable_updates;
+  int converged;
+  double true_rel_res;
+} wl_cg_stats;
+
+int cg_solve(wl_lattice* lat, void* x, const void* b, double kappa, const double* mu2, int nrhs,
+             wl_op op, const wl_cg_params* params, wl_cg_stats* stats);
+
+/* Chebyshev filter polynomial (Sec. 2, polynomial filtering): order degree on
+ * [a, b] approximating 1/x; applied to J = K-hat + mu2 on even sites.
+ * P = Q^dag Q with Q built from the degree/2 roots of negative imaginary part
+ * (degree even for the Q modes).  F64 internal fields, nrhs = 1. */
+typedef struct {
+  int degree;
+  double a, b;
+} wl_poly;
+
+typedef enum { WL_POLY_P = 0, WL_POLY_PJ = 1, WL_POLY_Q = 2, WL_POLY_QDAG = 3 } wl_poly_mode;
+
+int poly_filter_apply(wl_lattice* lat, void* out, const void* in, double kappa, double mu2,
+                      const wl_poly* poly, wl_poly_mode mode);
+
+/* Pseudofermion action terms (Sec. 2 and 4.1), mu2 form of the Hasenbusch shift:
+ *   WL_TERM_KINV_FULL  phi^dag K^-1 phi, full lattice (two-flavour action, Sec. 2)
+ *   WL_TERM_KINV       phi^dag J^-1 phi
+ *   WL_TERM_RATIO      phi^dag W K-hat^-1 W^dag phi, W = M-hat + i mu g5
+ *                      (Hermitian form of the J K^-1 correction term)
+ *   WL_TERM_POLY       phi^dag P(J) phi
+ *   WL_TERM_POLYK_INV  phi^dag [P(J) J]^-1 phi
+ * phi / chi: internal F64 fields (FULL for KINV_FULL, even half otherwise). */
+typedef enum {
+  WL_TERM_KINV_FULL = 0,
+  WL_TERM_KINV = 1,
+  WL_TERM_RATIO = 2,
+  WL_TERM_POLY = 3,
+  WL_TERM_POLYK_INV = 4
+} wl_term_kind;
+
+typedef struct {
+  wl_term_kind kind;
+  double kappa;
+  double mu2;
+  wl_poly poly;
+  wl_cg_params cg;
+} wl_term;
+
+/* phi drawn from Gaussian chi so that S(phi) = chi^dag chi (Sec. 2 heatbath). */
+int wl_heatbath(wl_lattice* lat, void* phi, const wl_term* term, const void* chi);
+/* S_term(phi) to host *S. */
+int wl_action(wl_lattice* lat, const wl_term* term, const void* phi, double* S);
+
+/* Fermion force (Sec. 2: dS_F/dU): F += coeff * grad^a S_term, the Lie
+ * derivatives d/de S(exp(i e T^a) U_mu(x)) at e = 0.  F: internal su(3)
+ * field, accumulated.  S_out: optional host action value (NULL to skip). */
+int fermion_force(wl_lattice* lat, double* F, const wl_term* term, const void* phi, double coeff,
+                  double* S_out);
+/* The link-derivative primitive: F += coeff * grad^a Re(A^dag D C) for full
+ * internal F64 fields A and C. */
+int wl_force_bilinear(wl_lattice* lat, double* F, const void* A_full, const void* C_full, double coeff);
+
+/* Wilson plaquette gauge action S_G = beta sum (1 - Re tr U_p / 3) (the
+ * gauge action of the HMC workload): F += coeff * grad^a S_G. */
+int wl_gauge_force(wl_lattice* lat, double* F, double beta, double coeff);
+/* Mean plaquette (1/6V) sum_{x,mu<nu} Re tr U_munu / 3 to host. */
+int wl_plaquette(wl_lattice* lat, double* plaq);
+/* T[eps] (Sec. 2): U -> exp(i eps P) U, FP64, then SU(3) reunitarisation. */
+int wl_link_update(wl_lattice* lat, const double* P, double eps);
+
+/* One HMC trajectory (Sec. 2) with the generalised multi-scale integrator
+ * (Sec. 3.2): every term i has its own leapfrog or Omelyan scheme with
+ * nsteps[i] steps on [0, tau]; the gauge action is scale nterms
+ * (nsteps[nterms]); updates are overlaid by time.  P: internal su(3) momenta,
+ * read at the start and left at the end point.  chi: nterms internal F64
+ * fields back to back (each a FULL field for KINV_FULL, else a half field).
+ * u_metropolis: caller's uniform in [0,1); accept iff u < exp(-dH).  On
+ * rejection the links are restored.  flags: WL_HMC_NO_METROPOLIS always keeps
+ * the end point (reversibility tests). */
+enum { WL_HMC_NO_METROPOLIS = 1 };
+enum { WL_INT_LEAPFROG = 0, WL_INT_OMELYAN = 1 };
+
+typedef struct {
+  double beta;
+  double tau;
+  double omelyan_lambda; /* 0 -> 0.1931833275037836 */
+  int integrator;        /* WL_INT_LEAPFROG or WL_INT_OMELYAN */
+  int nterms;            /* <= 8 */
+  wl_term terms[8];
+  int nsteps[9];         /* per term, then the gauge action */
+  int flags;
+} wl_hmc_params;
+
+typedef struct {
+  double dH, H0, H1;
+  double S0[9], S1[9];   /* per term, then gauge */
+  double plaquette;      /* of the links the call leaves */
+  int accepted;
+  long long n_kmat;      /* K-hat (or K) applications, the cost numerator of Sec. 3.1 */
+  long long cg_iters;
+} wl_hmc_result;
+
+int hmc_trajectory(wl_lattice* lat, const wl_hmc_params* params, double* P, const void* chi,
+                   double u_metropolis, wl_hmc_result* result);
+
+/* Counters: hop applications and K applications since create (single rhs units). */
+int wl_counters(const wl_lattice* lat, long long* n_hop, long long* n_kmat);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WILSON_HMC_H */

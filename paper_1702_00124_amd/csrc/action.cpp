@@ -1,0 +1,251 @@
+// Pseudofermion action terms: heatbath, action value and force (Sec. 2: the
+// two-flavour action phi^dag (M^dag M)^-1 phi and its force; mass
+// preconditioning phi1^dag J^-1 phi1 + phi2^dag J K^-1 phi2; polynomial
+// filtering phi1^dag P phi1 + phi2^dag [P K]^-1 phi2; Sec. 4.1: PF-MP).
+//
+// J = K-hat + mu2 and W = M-hat + i mu g5 (W^dag W = J by gamma5-hermiticity).
+//
+//   term        S(phi)                        heatbath from chi
+//   KINV_FULL   phi^dag K^-1 phi (full)       phi = M^dag chi
+//   KINV        phi^dag J^-1 phi              phi = W^dag chi
+//   RATIO       phi^dag W K-hat^-1 W^dag phi  phi = W J^-1 M-hat^dag chi
+//   POLY        phi^dag P(J) phi              phi = Q^dag P(J)^-1 chi
+//   POLYK_INV   phi^dag [P(J) J]^-1 phi       phi = Q^dag W^dag chi
+//
+// Forces are the Lie derivatives grad^a S along exp(i e T^a) U_mu(x), by the
+// product rule down to the single link-derivative primitive
+//   grad Re(A^dag D C)   (bilinear kernel, full-lattice fields),
+// with Re(A^dag dM-hat B) = -kappa^2 grad Re(A'^dag D B'),
+//   A' = (A, (D^dag)_oe A),  B' = (B, D_oe B),
+// and Re(L^dag dJ R) = Re((M-hat R)^dag dM-hat L) + Re((M-hat L)^dag dM-hat R).
+#include <cmath>
+
+#include "wl_ops.h"
+
+namespace wl {
+
+namespace {
+
+size_t hbytes(const wl_lattice* L) { return spinor_bytes(F64, L->Vh); }
+
+PolyDesc pdesc(const wl_term& t) { return PolyDesc{t.poly.degree, t.poly.a, t.poly.b}; }
+
+void check_term(const wl_term& t) {
+  WL_REQUIRE(t.kind >= WL_TERM_KINV_FULL && t.kind <= WL_TERM_POLYK_INV, WL_EINVAL, "unknown term kind");
+  WL_REQUIRE(t.mu2 >= 0.0, WL_EINVAL, "mu2 must be non-negative");
+  WL_REQUIRE(t.kind != WL_TERM_KINV_FULL || t.mu2 == 0.0, WL_EUNSUPPORTED, "full-lattice term takes mu2 = 0");
+}
+
+// out = W in (dagger: W^dag in), W = M-hat + i mu g5
+void op_w(wl_lattice* L, void* out, const void* in, double kappa, double mu2, int dagger) {
+  void* t = ws_get(L, "act_wtmp", hbytes(L));
+  op_mhat(L, F64, t, in, kappa, dagger, 1);
+  const double one[2] = {1.0, 0.0};
+  const double imu[2] = {0.0, (dagger ? -1.0 : 1.0) * std::sqrt(mu2)};
+  launch_caxpby(L, out, one, t, imu, in, 1, 1);
+}
+
+int solve_j(wl_lattice* L, void* x, const void* b, double kappa, double mu2, const wl_cg_params& cg,
+            long long* iters) {
+  wl_cg_stats st{};
+  const int rc = cg_run(L, x, b, kappa, &mu2, 1, WL_OP_J, cg, &st);
+  if (iters) *iters += st.iters;
+  WL_REQUIRE(rc == WL_OK, rc, "inner CG did not converge");
+  return rc;
+}
+
+void solve_poly(wl_lattice* L, void* x, const void* b, const wl_term& t, int mode, long long* iters) {
+  wl_cg_stats st{};
+  const PolyDesc pd = pdesc(t);
+  auto apply = [&](void* out, const void* in) { poly_apply(L, mode, out, in, t.kappa, t.mu2, pd); };
+  const int rc = cg_run_generic(L, x, b, apply, t.cg, &st);
+  if (iters) *iters += st.iters;
+  WL_REQUIRE(rc == WL_OK, rc, "polynomial CG did not converge");
+}
+
+double re_dot(wl_lattice* L, const void* x, const void* y, int nhalves = 1) {
+  double d[2];
+  cdot_host(L, x, y, 1, d, nhalves);
+  return d[0];
+}
+
+// F += coeff * grad Re(A^dag dM-hat B)
+void grad_re_dmhat(wl_lattice* L, double* F, const void* A, const void* B, double kappa, double coeff) {
+  void* Ao = ws_get(L, "gm_Ao", hbytes(L));
+  void* Bo = ws_get(L, "gm_Bo", hbytes(L));
+  HopEpi e;
+  launch_hop(L, F64, Ao, A, 1, 1, 1, e);  // (D^dag)_oe A
+  launch_hop(L, F64, Bo, B, 1, 0, 1, e);  // D_oe B
+  launch_bilinear(L, F, A, Ao, B, Bo, -kappa * kappa * coeff);
+}
+
+// F += coeff * grad Re(Lv^dag dJ Rv)
+void grad_re_dj(wl_lattice* L, double* F, const void* Lv, const void* Rv, double kappa, double coeff) {
+  void* MR = ws_get(L, "gj_M", hbytes(L));
+  op_mhat(L, F64, MR, Rv, kappa, 0, 1);
+  grad_re_dmhat(L, F, MR, Lv, kappa, coeff);
+  op_mhat(L, F64, MR, Lv, kappa, 0, 1);
+  grad_re_dmhat(L, F, MR, Rv, kappa, coeff);
+}
+
+// F += coeff * sum_k grad Re(L_k^dag dJ R_k) over the factors (J - z_k) of Q:
+// R_k = prod_{j<k} (J - z_j) right,  L_k = prod_{j>k} (J - conj z_j) left_top
+void chain_grad(wl_lattice* L, double* F, const wl_term& t, const void* right, const void* left_top, double coeff) {
+  const PolyDesc pd = pdesc(t);
+  std::vector<double> zr, zi;
+  poly_q_roots(pd, zr, zi);
+  const int m = int(zr.size());
+  const size_t fb = hbytes(L);
+  std::vector<void*> R(m);
+  for (int j = 0; j < m; ++j) R[j] = ws_get(L, "ch_R" + std::to_string(j), fb);
+  void* w = ws_get(L, "ch_w", fb);
+  void* Lv = ws_get(L, "ch_L", fb);
+  const double one[2] = {1.0, 0.0};
+  copy_dev(L, R[0], right, fb);
+  for (int j = 0; j + 1 < m; ++j) {
+    op_j(L, F64, w, R[j], t.kappa, &t.mu2, 1);
+    const double mz[2] = {-zr[j], -zi[j]};
+    launch_caxpby(L, R[j + 1], one, w, mz, R[j], 0, 1);
+  }
+  copy_dev(L, Lv, left_top, fb);
+  for (int k = m - 1; k >= 0; --k) {
+    grad_re_dj(L, F, Lv, R[k], t.kappa, coeff);
+    if (k > 0) {
+      op_j(L, F64, w, Lv, t.kappa, &t.mu2, 1);
+      const double mzc[2] = {-zr[k], zi[k]};
+      launch_caxpby(L, Lv, one, w, mzc, Lv, 0, 1);
+    }
+  }
+}
+
+}  // namespace
+
+void term_heatbath(wl_lattice* L, const wl_term& t, void* phi, const void* chi) {
+  check_term(t);
+  const size_t fb = hbytes(L);
+  switch (t.kind) {
+    case WL_TERM_KINV_FULL: op_m_full(L, F64, phi, chi, t.kappa, 1); break;
+    case WL_TERM_KINV: op_w(L, phi, chi, t.kappa, t.mu2, 1); break;
+    case WL_TERM_RATIO: {
+      void* a = ws_get(L, "hb_a", fb);
+      void* x = ws_get(L, "hb_x", fb);
+      op_mhat(L, F64, a, chi, t.kappa, 1, 1);
+      solve_j(L, x, a, t.kappa, t.mu2, t.cg, nullptr);
+      op_w(L, phi, x, t.kappa, t.mu2, 0);
+      break;
+    }
+    case WL_TERM_POLY: {
+      void* x = ws_get(L, "hb_x", fb);
+      solve_poly(L, x, chi, t, WL_POLY_P, nullptr);
+      poly_apply(L, WL_POLY_QDAG, phi, x, t.kappa, t.mu2, pdesc(t));
+      break;
+    }
+    case WL_TERM_POLYK_INV: {
+      void* a = ws_get(L, "hb_a", fb);
+      op_w(L, a, chi, t.kappa, t.mu2, 1);
+      poly_apply(L, WL_POLY_QDAG, phi, a, t.kappa, t.mu2, pdesc(t));
+      break;
+    }
+  }
+}
+
+double term_action(wl_lattice* L, const wl_term& t, const void* phi, long long* iters) {
+  check_term(t);
+  const size_t fb = hbytes(L);
+  switch (t.kind) {
+    case WL_TERM_KINV_FULL: {
+      void* x = ws_get(L, "ac_xf", 2 * fb);
+      wl_cg_stats st{};
+      const int rc = cg_run(L, x, phi, t.kappa, nullptr, 1, WL_OP_K, t.cg, &st);
+      if (iters) *iters += st.iters;
+      WL_REQUIRE(rc == WL_OK, rc, "inner CG did not converge");
+      return re_dot(L, phi, x, 2);
+    }
+    case WL_TERM_KINV: {
+      void* x = ws_get(L, "ac_x", fb);
+      solve_j(L, x, phi, t.kappa, t.mu2, t.cg, iters);
+      return re_dot(L, phi, x);
+    }
+    case WL_TERM_RATIO: {
+      void* v = ws_get(L, "ac_v", fb);
+      void* x = ws_get(L, "ac_x", fb);
+      op_w(L, v, phi, t.kappa, t.mu2, 1);
+      solve_j(L, x, v, t.kappa, 0.0, t.cg, iters);
+      return re_dot(L, v, x);
+    }
+    case WL_TERM_POLY: {
+      void* x = ws_get(L, "ac_x", fb);
+      poly_apply(L, WL_POLY_P, x, phi, t.kappa, t.mu2, pdesc(t));
+      return re_dot(L, phi, x);
+    }
+    case WL_TERM_POLYK_INV: {
+      void* x = ws_get(L, "ac_x", fb);
+      solve_poly(L, x, phi, t, WL_POLY_PJ, iters);
+      return re_dot(L, phi, x);
+    }
+  }
+  return 0.0;
+}
+
+void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, double coeff, long long* iters) {
+  check_term(t);
+  const size_t fb = hbytes(L);
+  switch (t.kind) {
+    case WL_TERM_KINV_FULL: {
+      // dS = -X^dag dK X = 2 kappa grad Re(Y^dag D X), X = K^-1 phi, Y = M X
+      char* x = static_cast<char*>(ws_get(L, "fo_xf", 2 * fb));
+      char* y = static_cast<char*>(ws_get(L, "fo_yf", 2 * fb));
+      wl_cg_stats st{};
+      const int rc = cg_run(L, x, phi, t.kappa, nullptr, 1, WL_OP_K, t.cg, &st);
+      if (iters) *iters += st.iters;
+      WL_REQUIRE(rc == WL_OK, rc, "inner CG did not converge");
+      op_m_full(L, F64, y, x, t.kappa, 0);
+      launch_bilinear(L, F, y, y + fb, x, x + fb, 2.0 * t.kappa * coeff);
+      break;
+    }
+    case WL_TERM_KINV: {
+      // dS = -2 Re(Y^dag dM-hat X), X = J^-1 phi, Y = M-hat X
+      void* x = ws_get(L, "fo_x", fb);
+      void* y = ws_get(L, "fo_y", fb);
+      solve_j(L, x, phi, t.kappa, t.mu2, t.cg, iters);
+      op_mhat(L, F64, y, x, t.kappa, 0, 1);
+      grad_re_dmhat(L, F, y, x, t.kappa, -2.0 * coeff);
+      break;
+    }
+    case WL_TERM_RATIO: {
+      // dS = 2 Re((phi - Y)^dag dM-hat X), v = W^dag phi, X = K-hat^-1 v, Y = M-hat X
+      void* v = ws_get(L, "fo_v", fb);
+      void* x = ws_get(L, "fo_x", fb);
+      void* y = ws_get(L, "fo_y", fb);
+      op_w(L, v, phi, t.kappa, t.mu2, 1);
+      solve_j(L, x, v, t.kappa, 0.0, t.cg, iters);
+      op_mhat(L, F64, y, x, t.kappa, 0, 1);
+      const double one[2] = {1.0, 0.0}, mone[2] = {-1.0, 0.0};
+      launch_caxpby(L, y, one, phi, mone, y, 0, 1);
+      grad_re_dmhat(L, F, y, x, t.kappa, 2.0 * coeff);
+      break;
+    }
+    case WL_TERM_POLY: {
+      // S = |Q phi|^2: dS = 2 sqrt(c) sum_k Re(L_k^dag dJ R_k), R from phi, L from Q phi
+      void* psi = ws_get(L, "fo_psi", fb);
+      poly_apply(L, WL_POLY_Q, psi, phi, t.kappa, t.mu2, pdesc(t));
+      chain_grad(L, F, t, phi, psi, 2.0 * std::sqrt(poly_lead(pdesc(t))) * coeff);
+      break;
+    }
+    case WL_TERM_POLYK_INV: {
+      // S = phi^dag (Q^dag J Q)^-1 phi, X = S's solution:
+      // dS = -[2 sqrt(c) sum_k Re(L_k^dag dJ R_k) + Re((QX)^dag dJ (QX))], R from X, L from J Q X
+      void* x = ws_get(L, "fo_x", fb);
+      void* qx = ws_get(L, "fo_qx", fb);
+      void* jqx = ws_get(L, "fo_jqx", fb);
+      solve_poly(L, x, phi, t, WL_POLY_PJ, iters);
+      poly_apply(L, WL_POLY_Q, qx, x, t.kappa, t.mu2, pdesc(t));
+      op_j(L, F64, jqx, qx, t.kappa, &t.mu2, 1);
+      chain_grad(L, F, t, x, jqx, -2.0 * std::sqrt(poly_lead(pdesc(t))) * coeff);
+      grad_re_dj(L, F, qx, qx, t.kappa, -coeff);
+      break;
+    }
+  }
+}
+
+}  // namespace wl

@@ -1,0 +1,307 @@
+// Level-1 vector kernels of the solvers and of the polynomial filter, with
+// dot products accumulated in FP64 at every storage precision, and the
+// device-side scalar steps of conjugate gradient (alpha, beta, convergence
+// flag), so that a CG iteration needs no host round trip.
+//
+// Reductions are deterministic: each workgroup writes one partial per rhs
+// (wavefront shuffles, then LDS), and a single workgroup per rhs sums the
+// partials in a fixed order.
+#include "wl_internal.h"
+#include "wl_solver_state.h"
+
+namespace wl {
+
+int blas_blocks(const wl_lattice* L) { return site_blocks(L->Vh); }
+
+// ------------------------------------------------------------------ CG update
+// fields are indexed f = rhs * nh + half (nh = 2 for full-lattice fields)
+template <typename P>
+__global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, double* x64, char* r, const char* p,
+                                                          const char* Ap, const double* st, size_t stride,
+                                                          double* partials, int pstride, int nh) {
+  using R = typename P::real;
+  __shared__ double lds[kBlock / 64];
+  const int f = blockIdx.y;
+  const int rhs = f / nh;
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int Vh = g.Vh;
+  const double alpha = st[CG_ALPHA * kMaxRhs + rhs];
+  const bool done = st[CG_DONE * kMaxRhs + rhs] != 0.0;
+  double part = 0.0;
+  if (h < Vh && !done) {
+    const size_t off = f * stride;
+    Spinor<R> pv = SpinorIO<P>::load(p + off, h, Vh);
+    Spinor<R> av = SpinorIO<P>::load(Ap + off, h, Vh);
+    Spinor<R> rv = SpinorIO<P>::load(r + off, h, Vh);
+    char* xb = reinterpret_cast<char*>(x64) + f * size_t(192) * Vh;
+    Spinor<double> xv = SpinorIO<PrecF64>::load(xb, h, Vh);
+    const R ar = R(alpha);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      xv.c[k].r += alpha * double(pv.c[k].r);
+      xv.c[k].i += alpha * double(pv.c[k].i);
+      rv.c[k] = rv.c[k] - ar * av.c[k];
+    }
+    SpinorIO<PrecF64>::store(xb, h, Vh, xv);
+    SpinorIO<P>::store(r + off, h, Vh, rv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part += double(rv.c[k].r) * double(rv.c[k].r) + double(rv.c[k].i) * double(rv.c[k].i);
+  }
+  const double s = block_sum(part, lds);
+  if (threadIdx.x == 0) partials[rhs * pstride + (f % nh) * gridDim.x + blockIdx.x] = s;
+}
+
+template <typename P>
+__global__ __launch_bounds__(kBlock) void cg_xpay_kernel(Geo g, char* p, const char* r, const double* st,
+                                                        size_t stride, int nh) {
+  using R = typename P::real;
+  const int f = blockIdx.y;
+  const int rhs = f / nh;
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int Vh = g.Vh;
+  if (h >= Vh || st[CG_DONE * kMaxRhs + rhs] != 0.0) return;
+  const R beta = R(st[CG_BETA * kMaxRhs + rhs]);
+  const size_t off = f * stride;
+  Spinor<R> pv = SpinorIO<P>::load(p + off, h, Vh);
+  const Spinor<R> rv = SpinorIO<P>::load(r + off, h, Vh);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) pv.c[k] = rv.c[k] + beta * pv.c[k];
+  SpinorIO<P>::store(p + off, h, Vh, pv);
+}
+
+template <typename PD, typename PS>
+__global__ __launch_bounds__(kBlock) void convert_kernel(Geo g, char* dst, size_t dstride, const char* src,
+                                                        size_t sstride) {
+  const int rhs = blockIdx.y;
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  if (h >= g.Vh) return;
+  const auto s = SpinorIO<PS>::load(src + rhs * sstride, h, g.Vh);
+  Spinor<typename PD::real> d;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) d.c[k] = {typename PD::real(s.c[k].r), typename PD::real(s.c[k].i)};
+  SpinorIO<PD>::store(dst + rhs * dstride, h, g.Vh, d);
+}
+
+struct CaxpbyArgs {
+  double a[2 * kMaxRhs];
+  double b[2 * kMaxRhs];
+};
+
+__global__ __launch_bounds__(kBlock) void caxpby_kernel(Geo g, char* out, const char* x, const char* y, int g5y,
+                                                       CaxpbyArgs c) {
+  const int rhs = blockIdx.y;
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  if (h >= g.Vh) return;
+  const size_t off = rhs * size_t(192) * g.Vh;
+  const cplx<double> ca = {c.a[2 * rhs], c.a[2 * rhs + 1]};
+  const cplx<double> cb = {c.b[2 * rhs], c.b[2 * rhs + 1]};
+  Spinor<double> o;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) o.c[k] = zero<double>();
+  if (x) {
+    const Spinor<double> xv = SpinorIO<PrecF64>::load(x + off, h, g.Vh);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o.c[k] = ca * xv.c[k];
+  }
+  if (y) {
+    const Spinor<double> yv = SpinorIO<PrecF64>::load(y + off, h, g.Vh);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const cplx<double> t = cb * yv.c[k];
+      o.c[k] = (g5y && k >= 6) ? o.c[k] - t : o.c[k] + t;
+    }
+  }
+  SpinorIO<PrecF64>::store(out + off, h, g.Vh, o);
+}
+
+// complex <x, y> = sum conj(x) y (two rows per rhs) or |x|^2 (one row per rhs)
+__global__ __launch_bounds__(kBlock) void dot_kernel(Geo g, const char* x, const char* y, double* partials,
+                                                    int pstride, int cdot) {
+  __shared__ double lds[kBlock / 64];
+  const int rhs = blockIdx.y;
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const size_t off = rhs * size_t(192) * g.Vh;
+  double re = 0.0, im = 0.0;
+  if (h < g.Vh) {
+    const Spinor<double> xv = SpinorIO<PrecF64>::load(x + off, h, g.Vh);
+    if (cdot) {
+      const Spinor<double> yv = SpinorIO<PrecF64>::load(y + off, h, g.Vh);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const cplx<double> t = cmul(xv.c[k], yv.c[k]);
+        re += t.r;
+        im += t.i;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) re += xv.c[k].r * xv.c[k].r + xv.c[k].i * xv.c[k].i;
+    }
+  }
+  const double sr = block_sum(re, lds);
+  if (cdot) {
+    const double si = block_sum(im, lds);
+    if (threadIdx.x == 0) {
+      partials[(2 * rhs) * pstride + blockIdx.x] = sr;
+      partials[(2 * rhs + 1) * pstride + blockIdx.x] = si;
+    }
+  } else if (threadIdx.x == 0) {
+    partials[rhs * pstride + blockIdx.x] = sr;
+  }
+}
+
+// one workgroup per row
+__device__ __forceinline__ double row_sum(const double* partials, int stride, int nb, int row, double* lds) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partials[row * stride + b];
+  return block_sum(s, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void finish_sum_kernel(const double* partials, int stride, int nb,
+                                                           double* out) {
+  __shared__ double lds[kBlock / 64];
+  const double s = row_sum(partials, stride, nb, blockIdx.x, lds);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void cg_alpha_kernel(const double* partials, int stride, int nb, double* st) {
+  __shared__ double lds[kBlock / 64];
+  const int r = blockIdx.x;
+  const double pAp = row_sum(partials, stride, nb, r, lds);
+  if (threadIdx.x == 0) {
+    st[CG_PAP * kMaxRhs + r] = pAp;
+    const bool done = st[CG_DONE * kMaxRhs + r] != 0.0;
+    st[CG_ALPHA * kMaxRhs + r] = done ? 0.0 : st[CG_RR * kMaxRhs + r] / pAp;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void cg_beta_kernel(const double* partials, int stride, int nb, double* st) {
+  __shared__ double lds[kBlock / 64];
+  const int r = blockIdx.x;
+  const double rr_new = row_sum(partials, stride, nb, r, lds);
+  if (threadIdx.x == 0) {
+    if (st[CG_DONE * kMaxRhs + r] == 0.0) {
+      const double rr = st[CG_RR * kMaxRhs + r];
+      st[CG_BETA * kMaxRhs + r] = rr_new / rr;
+      st[CG_RR * kMaxRhs + r] = rr_new;
+      st[CG_ITERS * kMaxRhs + r] += 1.0;
+      if (rr_new > st[CG_MAXRR * kMaxRhs + r]) st[CG_MAXRR * kMaxRhs + r] = rr_new;
+      if (rr_new <= st[CG_TOL2 * kMaxRhs + r] * st[CG_BB * kMaxRhs + r]) st[CG_DONE * kMaxRhs + r] = 1.0;
+    } else {
+      st[CG_BETA * kMaxRhs + r] = 0.0;
+    }
+  }
+}
+
+
+// One step of the Chebyshev filter recurrence (F64):
+//   tprev <- ct * t + cw * w - tprev        (t_{m+1} = 2 y(J) t_m - t_{m-1}, w = J t_m)
+//   eprev <- ce * e + 2 t - eprev           (e_{m+1} = 2 y0 e_m + 2 t_m - e_{m-1})
+__global__ __launch_bounds__(kBlock) void cheb_step_kernel(Geo g, const char* t, const char* w, char* tprev,
+                                                          const char* e, char* eprev, double ct, double cw,
+                                                          double ce) {
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  if (h >= g.Vh) return;
+  const size_t off = blockIdx.y * size_t(192) * g.Vh;
+  const Spinor<double> tv = SpinorIO<PrecF64>::load(t + off, h, g.Vh);
+  const Spinor<double> wv = SpinorIO<PrecF64>::load(w + off, h, g.Vh);
+  const Spinor<double> ev = SpinorIO<PrecF64>::load(e + off, h, g.Vh);
+  Spinor<double> tp = SpinorIO<PrecF64>::load(tprev + off, h, g.Vh);
+  Spinor<double> ep = SpinorIO<PrecF64>::load(eprev + off, h, g.Vh);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    tp.c[k] = ct * tv.c[k] + cw * wv.c[k] - tp.c[k];
+    ep.c[k] = ce * ev.c[k] + 2.0 * tv.c[k] - ep.c[k];
+  }
+  SpinorIO<PrecF64>::store(tprev + off, h, g.Vh, tp);
+  SpinorIO<PrecF64>::store(eprev + off, h, g.Vh, ep);
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename F>
+static void by_prec(Prec p, F&& f) {
+  switch (p) {
+    case F64: f(PrecF64{}); break;
+    case F32: f(PrecF32{}); break;
+    case BF16: f(PrecBF16{}); break;
+  }
+}
+
+void launch_cg_update(wl_lattice* L, Prec prec, void* x64, void* r, const void* p, const void* Ap,
+                      const double* st, int nrhs, int nh, double* partials, int stride) {
+  dim3 grid(blas_blocks(L), nrhs * nh);
+  by_prec(prec, [&](auto P) {
+    using PT = decltype(P);
+    hipLaunchKernelGGL((cg_update_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (double*)x64, (char*)r,
+                       (const char*)p, (const char*)Ap, st, spinor_bytes(prec, L->Vh), partials, stride, nh);
+  });
+  WL_HIP(hipGetLastError());
+}
+
+void launch_cg_xpay(wl_lattice* L, Prec prec, void* p, const void* r, const double* st, int nrhs, int nh) {
+  dim3 grid(blas_blocks(L), nrhs * nh);
+  by_prec(prec, [&](auto P) {
+    using PT = decltype(P);
+    hipLaunchKernelGGL((cg_xpay_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (char*)p, (const char*)r,
+                       st, spinor_bytes(prec, L->Vh), nh);
+  });
+  WL_HIP(hipGetLastError());
+}
+
+void launch_convert(wl_lattice* L, Prec dprec, void* dst, Prec sprec, const void* src, int nrhs) {
+  dim3 grid(blas_blocks(L), nrhs);
+  by_prec(dprec, [&](auto PD) {
+    by_prec(sprec, [&](auto PS) {
+      using D = decltype(PD);
+      using S = decltype(PS);
+      hipLaunchKernelGGL((convert_kernel<D, S>), grid, dim3(kBlock), 0, L->stream, L->geo, (char*)dst,
+                         spinor_bytes(dprec, L->Vh), (const char*)src, spinor_bytes(sprec, L->Vh));
+    });
+  });
+  WL_HIP(hipGetLastError());
+}
+
+void launch_caxpby(wl_lattice* L, void* out, const double* a, const void* x, const double* b, const void* y,
+                   int g5y, int nrhs) {
+  CaxpbyArgs c{};
+  for (int r = 0; r < 2 * nrhs; ++r) {
+    c.a[r] = a ? a[r] : 0.0;
+    c.b[r] = b ? b[r] : 0.0;
+  }
+  dim3 grid(blas_blocks(L), nrhs);
+  hipLaunchKernelGGL(caxpby_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (char*)out, (const char*)x,
+                     (const char*)y, g5y, c);
+  WL_HIP(hipGetLastError());
+}
+
+void launch_dot_partials(wl_lattice* L, const void* x, const void* y, int nrhs, double* partials, int stride,
+                         int complex_dot) {
+  dim3 grid(blas_blocks(L), nrhs);
+  hipLaunchKernelGGL(dot_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (const char*)x, (const char*)y,
+                     partials, stride, complex_dot);
+  WL_HIP(hipGetLastError());
+}
+
+void launch_finish_sum(wl_lattice* L, const double* partials, int stride, int nb, int nrows, double* out) {
+  hipLaunchKernelGGL(finish_sum_kernel, dim3(nrows), dim3(kBlock), 0, L->stream, partials, stride, nb, out);
+  WL_HIP(hipGetLastError());
+}
+
+void launch_cg_alpha(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs) {
+  hipLaunchKernelGGL(cg_alpha_kernel, dim3(nrhs), dim3(kBlock), 0, L->stream, partials, stride, nb, st);
+  WL_HIP(hipGetLastError());
+}
+
+void launch_cg_beta(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs) {
+  hipLaunchKernelGGL(cg_beta_kernel, dim3(nrhs), dim3(kBlock), 0, L->stream, partials, stride, nb, st);
+  WL_HIP(hipGetLastError());
+}
+
+void launch_cheb_step(wl_lattice* L, const void* t, const void* w, void* tprev, const void* e, void* eprev, double ct,
+                      double cw, double ce, int nrhs) {
+  dim3 grid(blas_blocks(L), nrhs);
+  hipLaunchKernelGGL(cheb_step_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (const char*)t, (const char*)w,
+                     (char*)tprev, (const char*)e, (char*)eprev, ct, cw, ce);
+  WL_HIP(hipGetLastError());
+}
+
+}  // namespace wl

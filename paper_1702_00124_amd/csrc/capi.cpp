@@ -1,0 +1,391 @@
+// extern "C" entry points of libwilson_hmc (declared in include/wilson_hmc.h).
+// Every call validates its arguments, runs inside a guard that turns internal
+// errors into return codes, and records the message for wl_last_error().
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "wl_ops.h"
+
+namespace wl {
+int hmc_run(wl_lattice* L, const wl_hmc_params& prm, double* P, const void* chi, double u, wl_hmc_result* res);
+double plaquette_host(wl_lattice* L);
+}  // namespace wl
+
+using namespace wl;
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F>
+int guard(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return WL_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return WL_EINVAL;
+  } catch (...) {
+    g_err = "unknown error";
+    return WL_EINVAL;
+  }
+}
+
+void check_lat(const wl_lattice* L) { WL_REQUIRE(L != nullptr, WL_EINVAL, "null lattice"); }
+
+void set_device(const wl_lattice* L) { WL_HIP(hipSetDevice(L->device)); }
+
+void device_alloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory) throw Error(WL_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  WL_HIP(e);
+}
+
+}  // namespace
+
+namespace wl {
+
+void* ws_get(wl_lattice* L, const std::string& name, size_t bytes) {
+  auto it = L->ws.find(name);
+  if (it != L->ws.end() && it->second.second >= bytes) return it->second.first;
+  if (it != L->ws.end()) {
+    WL_HIP(hipStreamSynchronize(L->stream));
+    WL_HIP(hipFree(it->second.first));
+    L->ws.erase(it);
+  }
+  void* p = nullptr;
+  device_alloc(&p, bytes);
+  L->ws[name] = {p, bytes};
+  return p;
+}
+
+void ensure_partials(wl_lattice* L, size_t n) {
+  if (L->partials_len >= n) return;
+  if (L->partials) {
+    WL_HIP(hipStreamSynchronize(L->stream));
+    WL_HIP(hipFree(L->partials));
+    L->partials = nullptr;
+  }
+  device_alloc(reinterpret_cast<void**>(&L->partials), n * sizeof(double));
+  L->partials_len = n;
+}
+
+void ensure_lowp_links(wl_lattice* L) {
+  if (!L->lowp_valid) launch_lowp_links(L);
+}
+
+}  // namespace wl
+
+extern "C" {
+
+const char* wl_last_error(void) { return g_err.c_str(); }
+
+int wl_create(wl_lattice** out, const int32_t Ls[4], int32_t t_bc, void* hip_stream) {
+  return guard([&]() {
+    WL_REQUIRE(out && Ls, WL_EINVAL, "null argument");
+    *out = nullptr;
+    for (int m = 0; m < 4; ++m) WL_REQUIRE(Ls[m] >= 2 && Ls[m] % 2 == 0, WL_EINVAL, "lattice extents must be even and >= 2");
+    WL_REQUIRE(t_bc == 1 || t_bc == -1, WL_EINVAL, "t_bc must be +1 or -1");
+    const long long V = (long long)Ls[0] * Ls[1] * Ls[2] * Ls[3];
+    WL_REQUIRE(V <= (1LL << 30), WL_EUNSUPPORTED, "volume too large");
+    wl_lattice* L = new wl_lattice();
+    try {
+      WL_HIP(hipGetDevice(&L->device));
+      for (int m = 0; m < 4; ++m) {
+        L->L[m] = Ls[m];
+        L->geo.L[m] = Ls[m];
+      }
+      L->V = int(V);
+      L->Vh = int(V / 2);
+      L->geo.Lxh = Ls[0] / 2;
+      L->geo.Vh = L->Vh;
+      L->geo.tbc = t_bc;
+      L->stream = static_cast<hipStream_t>(hip_stream);
+      device_alloc(&L->U[F64], size_t(576) * L->V);
+      device_alloc(&L->U[F32], size_t(192) * L->V);
+      device_alloc(&L->U[BF16], size_t(96) * L->V);
+      device_alloc(reinterpret_cast<void**>(&L->dscal), kScal * sizeof(double));
+      WL_HIP(hipHostMalloc(reinterpret_cast<void**>(&L->hscal), kScal * sizeof(double), hipHostMallocDefault));
+      WL_HIP(hipMemsetAsync(L->U[F64], 0, size_t(576) * L->V, L->stream));
+      WL_HIP(hipMemsetAsync(L->dscal, 0, kScal * sizeof(double), L->stream));
+      ensure_partials(L, size_t(4) * kMaxRhs * site_blocks(L->Vh) + 64);
+      WL_HIP(hipStreamSynchronize(L->stream));
+    } catch (...) {
+      wl_destroy(L);
+      throw;
+    }
+    *out = L;
+    return WL_OK;
+  });
+}
+
+int wl_destroy(wl_lattice* L) {
+  if (!L) return WL_OK;
+  (void)hipSetDevice(L->device);
+  (void)hipStreamSynchronize(L->stream);
+  for (auto& kv : L->ws) (void)hipFree(kv.second.first);
+  for (int p = 0; p < 3; ++p)
+    if (L->U[p]) (void)hipFree(L->U[p]);
+  if (L->partials) (void)hipFree(L->partials);
+  if (L->dscal) (void)hipFree(L->dscal);
+  if (L->hscal) (void)hipHostFree(L->hscal);
+  if (L->capture_stream) (void)hipStreamDestroy(L->capture_stream);
+  delete L;
+  return WL_OK;
+}
+
+int wl_set_stream(wl_lattice* L, void* s) {
+  return guard([&]() {
+    check_lat(L);
+    WL_HIP(hipStreamSynchronize(L->stream));
+    L->stream = static_cast<hipStream_t>(s);
+    return WL_OK;
+  });
+}
+
+int wl_set_links(wl_lattice* L, const void* U) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(U, WL_EINVAL, "null links");
+    set_device(L);
+    launch_pack_links(L, U);
+    return WL_OK;
+  });
+}
+
+int wl_get_links(wl_lattice* L, void* U) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(U, WL_EINVAL, "null links");
+    set_device(L);
+    launch_unpack_links(L, U);
+    return WL_OK;
+  });
+}
+
+int wl_field_bytes(const wl_lattice* L, wl_prec prec, int nrhs, size_t* bytes) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(bytes && nrhs >= 1 && nrhs <= kMaxRhs, WL_EINVAL, "bad arguments");
+    WL_REQUIRE(prec == WL_F64 || prec == WL_F32 || prec == WL_BF16, WL_EINVAL, "unknown precision");
+    *bytes = spinor_bytes(Prec(prec), L->Vh) * nrhs;
+    return WL_OK;
+  });
+}
+
+static void check_prec_rhs(wl_prec prec, int nrhs) {
+  WL_REQUIRE(prec == WL_F64 || prec == WL_F32 || prec == WL_BF16, WL_EINVAL, "unknown precision");
+  WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs, WL_EINVAL, "nrhs must be 1..16");
+}
+
+int wl_import_spinor(wl_lattice* L, void* dst, const void* src, wl_prec prec, int nrhs) {
+  return guard([&]() {
+    check_lat(L);
+    check_prec_rhs(prec, nrhs);
+    WL_REQUIRE(dst && src, WL_EINVAL, "null field");
+    set_device(L);
+    launch_import_spinor(L, Prec(prec), dst, src, nrhs);
+    return WL_OK;
+  });
+}
+
+int wl_export_spinor(wl_lattice* L, void* dst, const void* src, wl_prec prec, int nrhs) {
+  return guard([&]() {
+    check_lat(L);
+    check_prec_rhs(prec, nrhs);
+    WL_REQUIRE(dst && src, WL_EINVAL, "null field");
+    set_device(L);
+    launch_export_spinor(L, Prec(prec), dst, src, nrhs);
+    return WL_OK;
+  });
+}
+
+int wl_import_full(wl_lattice* L, void* dst, const void* src) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(dst && src, WL_EINVAL, "null field");
+    set_device(L);
+    char* d = static_cast<char*>(dst);
+    launch_split_full(L, d, d + spinor_bytes(F64, L->Vh), src, 0);
+    return WL_OK;
+  });
+}
+
+int wl_export_full(wl_lattice* L, void* dst, const void* src) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(dst && src, WL_EINVAL, "null field");
+    set_device(L);
+    char* s = const_cast<char*>(static_cast<const char*>(src));
+    launch_split_full(L, s, s + spinor_bytes(F64, L->Vh), dst, 1);
+    return WL_OK;
+  });
+}
+
+int wl_import_su3(wl_lattice* L, double* dst, const double* src) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(dst && src, WL_EINVAL, "null field");
+    set_device(L);
+    launch_su3_io(L, dst, src, 0);
+    return WL_OK;
+  });
+}
+
+int wl_export_su3(wl_lattice* L, double* dst, const double* src) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(dst && src, WL_EINVAL, "null field");
+    set_device(L);
+    launch_su3_io(L, const_cast<double*>(src), dst, 1);
+    return WL_OK;
+  });
+}
+
+int wilson_dslash(wl_lattice* L, void* out, const void* in, int out_parity, int dagger, wl_prec prec, int nrhs) {
+  return guard([&]() {
+    check_lat(L);
+    check_prec_rhs(prec, nrhs);
+    WL_REQUIRE(out && in, WL_EINVAL, "null field");
+    WL_REQUIRE(out_parity == 0 || out_parity == 1, WL_EINVAL, "parity must be 0 or 1");
+    set_device(L);
+    HopEpi e;
+    launch_hop(L, Prec(prec), out, in, out_parity, dagger ? 1 : 0, nrhs, e);
+    return WL_OK;
+  });
+}
+
+int apply_K(wl_lattice* L, void* out, const void* in, double kappa, const double* mu2, int nrhs, wl_op op,
+            wl_prec prec) {
+  return guard([&]() {
+    check_lat(L);
+    check_prec_rhs(prec, nrhs);
+    WL_REQUIRE(out && in && out != in, WL_EINVAL, "null or aliased field");
+    set_device(L);
+    op_apply(L, op, Prec(prec), out, in, kappa, mu2, nrhs);
+    return WL_OK;
+  });
+}
+
+int cg_solve(wl_lattice* L, void* x, const void* b, double kappa, const double* mu2, int nrhs, wl_op op,
+             const wl_cg_params* params, wl_cg_stats* stats) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(x && b && params && x != b, WL_EINVAL, "null or aliased argument");
+    set_device(L);
+    return cg_run(L, x, b, kappa, mu2, nrhs, op, *params, stats);
+  });
+}
+
+int poly_filter_apply(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const wl_poly* poly,
+                      wl_poly_mode mode) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(out && in && poly, WL_EINVAL, "null argument");
+    set_device(L);
+    poly_apply(L, mode, out, in, kappa, mu2, PolyDesc{poly->degree, poly->a, poly->b});
+    return WL_OK;
+  });
+}
+
+int wl_heatbath(wl_lattice* L, void* phi, const wl_term* term, const void* chi) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(phi && term && chi && phi != chi, WL_EINVAL, "null or aliased argument");
+    set_device(L);
+    term_heatbath(L, *term, phi, chi);
+    return WL_OK;
+  });
+}
+
+int wl_action(wl_lattice* L, const wl_term* term, const void* phi, double* S) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(term && phi && S, WL_EINVAL, "null argument");
+    set_device(L);
+    *S = term_action(L, *term, phi, nullptr);
+    return WL_OK;
+  });
+}
+
+int fermion_force(wl_lattice* L, double* F, const wl_term* term, const void* phi, double coeff, double* S_out) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(F && term && phi, WL_EINVAL, "null argument");
+    set_device(L);
+    term_force(L, *term, F, phi, coeff, nullptr);
+    if (S_out) *S_out = term_action(L, *term, phi, nullptr);
+    return WL_OK;
+  });
+}
+
+int wl_force_bilinear(wl_lattice* L, double* F, const void* A, const void* C, double coeff) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(F && A && C, WL_EINVAL, "null argument");
+    set_device(L);
+    const size_t hb = spinor_bytes(F64, L->Vh);
+    const char* a = static_cast<const char*>(A);
+    const char* c = static_cast<const char*>(C);
+    launch_bilinear(L, F, a, a + hb, c, c + hb, coeff);
+    return WL_OK;
+  });
+}
+
+int wl_gauge_force(wl_lattice* L, double* F, double beta, double coeff) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(F, WL_EINVAL, "null argument");
+    set_device(L);
+    launch_gauge_force(L, F, -coeff * beta / 3.0);
+    return WL_OK;
+  });
+}
+
+int wl_plaquette(wl_lattice* L, double* plaq) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(plaq, WL_EINVAL, "null argument");
+    set_device(L);
+    *plaq = plaquette_host(L);
+    return WL_OK;
+  });
+}
+
+int wl_link_update(wl_lattice* L, const double* P, double eps) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(P, WL_EINVAL, "null argument");
+    set_device(L);
+    launch_link_update(L, P, eps);
+    return WL_OK;
+  });
+}
+
+int hmc_trajectory(wl_lattice* L, const wl_hmc_params* params, double* P, const void* chi, double u,
+                   wl_hmc_result* result) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(params && P && (chi || params->nterms == 0), WL_EINVAL, "null argument");
+    set_device(L);
+    return hmc_run(L, *params, P, chi, u, result);
+  });
+}
+
+int wl_counters(const wl_lattice* L, long long* n_hop, long long* n_kmat) {
+  return guard([&]() {
+    check_lat(L);
+    if (n_hop) *n_hop = L->n_hop;
+    if (n_kmat) *n_kmat = L->n_kmat;
+    return WL_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Chebyshev filter polynomial applied to J = K-hat + mu2 (Sec. 2, polynomial
+// filtering: P(K) a low-order polynomial approximating K^-1, Chebyshev, order
+// the only parameter).  Reading of the family (see include/wilson_hmc.h):
+//
+//   1 - x P_n(x) = T_{n+1}(y(x)) / T_{n+1}(y0),  y(x) = (b + a - 2x)/(b - a),  y0 = y(0).
+//
+// P_n(J) psi runs the real three-term recurrence
+//   t_{m+1} = 2 y(J) t_m - t_{m-1}        (t_m = T_m(y(J)) psi)
+//   e_{m+1} = 2 y0 e_m + 2 t_m - e_{m-1}  (e_m = (T_m(y0) - T_m(y(J)))/(y0 - y(J)) psi)
+// so that P_n(J) psi = (2/(b-a)) e_{n+1} / T_{n+1}(y0): n J applications and
+// one fused vector kernel per order.  Q(J), with P = Q^dag Q, is the product
+// over the n/2 roots z_k = ((b+a)/2)(1 - cos t_k) - i sqrt(ab) sin t_k,
+// t_k = 2 pi k/(n+1), times sqrt(c), c the leading coefficient of P_n.
+#include <cmath>
+
+#include "wl_ops.h"
+
+namespace wl {
+
+static double cheb_T_above_one(int m, double y) { return std::cosh(m * std::acosh(y)); }
+
+double poly_lead(const PolyDesc& pd) {
+  const double y0 = (pd.b + pd.a) / (pd.b - pd.a);
+  const double sgn = (pd.n % 2) ? -1.0 : 1.0;
+  return sgn * std::pow(2.0, pd.n) * std::pow(2.0 / (pd.b - pd.a), pd.n + 1) / cheb_T_above_one(pd.n + 1, y0);
+}
+
+void poly_q_roots(const PolyDesc& pd, std::vector<double>& re, std::vector<double>& im) {
+  re.clear();
+  im.clear();
+  for (int k = 1; k <= pd.n / 2; ++k) {
+    const double th = 2.0 * M_PI * k / (pd.n + 1);
+    re.push_back(0.5 * (pd.b + pd.a) * (1.0 - std::cos(th)));
+    im.push_back(-std::sqrt(pd.a * pd.b) * std::sin(th));
+  }
+}
+
+static void check_poly(const PolyDesc& pd) {
+  WL_REQUIRE(pd.n >= 1 && pd.n <= 512, WL_EINVAL, "polynomial degree out of range");
+  WL_REQUIRE(pd.a > 0.0 && pd.b > pd.a, WL_EINVAL, "polynomial interval needs 0 < a < b");
+}
+
+// out = P_n(J) in by the recurrence
+static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd) {
+  const size_t fb = spinor_bytes(F64, L->Vh);
+  void* tA = ws_get(L, "pl_tA", fb);
+  void* tB = ws_get(L, "pl_tB", fb);
+  void* eA = ws_get(L, "pl_eA", fb);
+  void* eB = ws_get(L, "pl_eB", fb);
+  void* w = ws_get(L, "pl_w", fb);
+  const double a = pd.a, b = pd.b;
+  const double y0 = (b + a) / (b - a);
+  const double ct = 2.0 * (b + a) / (b - a), cw = -4.0 / (b - a);
+  // t0 = in, t1 = y(J) in, e0 = 0, e1 = in
+  copy_dev(L, tA, in, fb);
+  op_j(L, F64, w, in, kappa, &mu2, 1);
+  const double c1[2] = {(b + a) / (b - a), 0.0}, c2[2] = {-2.0 / (b - a), 0.0};
+  launch_caxpby(L, tB, c1, in, c2, w, 0, 1);
+  zero_dev(L, eA, fb);
+  copy_dev(L, eB, in, fb);
+  for (int m = 1; m <= pd.n; ++m) {
+    const bool need_t = m < pd.n;
+    if (need_t) op_j(L, F64, w, tB, kappa, &mu2, 1);
+    launch_cheb_step(L, tB, need_t ? w : tB, tA, eB, eA, ct, need_t ? cw : 0.0, 2.0 * y0, 1);
+    std::swap(tA, tB);
+    std::swap(eA, eB);
+  }
+  const double s[2] = {(2.0 / (b - a)) / cheb_T_above_one(pd.n + 1, y0), 0.0};
+  launch_caxpby(L, out, s, eB, nullptr, nullptr, 0, 1);
+}
+
+// out = sqrt(c) prod_k (J - z_k) in   (conjugate roots for Q^dag)
+static void poly_Q(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
+                   int dagger) {
+  WL_REQUIRE(pd.n % 2 == 0, WL_EINVAL, "P = Q^dag Q needs an even degree");
+  const size_t fb = spinor_bytes(F64, L->Vh);
+  void* v = ws_get(L, "pl_qv", fb);
+  void* w = ws_get(L, "pl_w", fb);
+  std::vector<double> zr, zi;
+  poly_q_roots(pd, zr, zi);
+  copy_dev(L, v, in, fb);
+  for (size_t k = 0; k < zr.size(); ++k) {
+    op_j(L, F64, w, v, kappa, &mu2, 1);
+    const double one[2] = {1.0, 0.0};
+    const double mz[2] = {-zr[k], dagger ? zi[k] : -zi[k]};
+    launch_caxpby(L, v, one, w, mz, v, 0, 1);
+  }
+  const double sc[2] = {std::sqrt(poly_lead(pd)), 0.0};
+  launch_caxpby(L, out, sc, v, nullptr, nullptr, 0, 1);
+}
+
+void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd) {
+  check_poly(pd);
+  switch (mode) {
+    case WL_POLY_P: poly_P(L, out, in, kappa, mu2, pd); break;
+    case WL_POLY_PJ: {
+      void* jin = ws_get(L, "pl_jin", spinor_bytes(F64, L->Vh));
+      op_j(L, F64, jin, in, kappa, &mu2, 1);
+      poly_P(L, out, jin, kappa, mu2, pd);
+      break;
+    }
+    case WL_POLY_Q: poly_Q(L, out, in, kappa, mu2, pd, 0); break;
+    case WL_POLY_QDAG: poly_Q(L, out, in, kappa, mu2, pd, 1); break;
+    default: throw Error(WL_EINVAL, "unknown polynomial mode");
+  }
+}
+
+}  // namespace wl

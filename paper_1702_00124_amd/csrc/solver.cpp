@@ -1,0 +1,250 @@
+// Conjugate gradient on J = K-hat + mu2 (even sites, batched rhs) or on the
+// full-lattice K = M^dag M (Sec. 2: K is inverted by an iterative solver such
+// as CG; Sec. 3.1: even-odd preconditioning).
+//
+// Textbook CG with x0 = 0; every scalar (alpha, beta, |r|^2, the per-rhs
+// convergence flag) lives on the device, so an iteration is five kernels and
+// no host round trip.  The host looks at the state once per chunk of
+// iterations; a converged rhs is frozen on the device (alpha = 0) while the
+// others continue.  The stop rule is the FP64 true residual
+// |b - A x| <= tol |b|, checked whenever the iterated residual says so.
+//
+// Mixed precision: the inner iteration keeps r, p and A p in FP32 (or BF16)
+// storage with FP32 arithmetic; x accumulates in FP64 and every dot product
+// is accumulated in FP64.  A reliable update r = b - A x in FP64 replaces the
+// iterated residual whenever it fell below delta times its largest value since
+// the previous update (checked at chunk boundaries), and before exit.
+//
+// Optionally each chunk is captured once as a hipGraph on a side stream and
+// replayed on the context stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+#include "wl_ops.h"
+#include "wl_solver_state.h"
+
+namespace wl {
+
+namespace {
+
+struct CgGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~CgGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+}  // namespace
+
+using ApplyLowp = std::function<void(Prec, void*, const void*, const DotOut&)>;
+using Apply64 = std::function<void(void*, const void*)>;
+
+// CG core.  apply_lp: inner-precision operator with fused Re<in, out>
+// partials (rows of nbrow); apply64: FP64 operator for true residuals.
+// Fields hold nrhs right-hand sides of nh halves each.
+static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int nbrow, size_t hb64, size_t hbi,
+                   const ApplyLowp& apply_lp, const Apply64& apply64, const wl_cg_params& prm,
+                   wl_cg_stats* stats, bool count_kmat) {
+  WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs && nrhs * nh <= kMaxRhs, WL_EINVAL, "nrhs out of range");
+  WL_REQUIRE(prm.tol > 0.0 && prm.maxiter > 0, WL_EINVAL, "cg: tol and maxiter must be positive");
+  const Prec ip = Prec(prm.inner);
+  WL_REQUIRE(ip == F64 || ip == F32 || ip == BF16, WL_EINVAL, "cg: unknown inner precision");
+  const bool mixed = ip != F64;
+  const double delta = prm.delta > 0.0 ? prm.delta : 0.1;
+  const int chunk = prm.chunk > 0 ? prm.chunk : 8;
+  const size_t fb64 = hb64 * nh * nrhs;
+  const size_t fbi = hbi * nh * nrhs;
+
+  void* r = ws_get(L, "cg_r", fbi);
+  void* p = ws_get(L, "cg_p", fbi);
+  void* Ap = ws_get(L, "cg_Ap", fbi);
+  void* r64 = ws_get(L, "cg_r64", fb64);
+  void* Ax64 = ws_get(L, "cg_Ax64", fb64);
+  ensure_partials(L, size_t(nrhs) * nbrow * 2 + 64);
+  double* st = L->dscal + kCgState;
+  const long long kmat0 = L->n_kmat;
+  long long kmat_extra = 0;
+
+  // true residual r64 = b - A x (FP64); rr_true[r] = |r64|^2
+  std::vector<double> rr_true(nrhs), bb(nrhs);
+  auto true_residual = [&]() {
+    apply64(Ax64, x);
+    ++kmat_extra;
+    double ca[2 * kMaxRhs] = {0}, cb[2 * kMaxRhs] = {0};
+    for (int f = 0; f < nrhs * nh; ++f) {
+      ca[2 * f] = 1.0;
+      cb[2 * f] = -1.0;
+    }
+    launch_caxpby(L, r64, ca, b, cb, Ax64, 0, nrhs * nh);
+    norm2_host(L, r64, nrhs, rr_true.data(), nh);
+  };
+
+  // ---- initial state: x = 0, r = b, p = r
+  zero_dev(L, x, fb64);
+  norm2_host(L, b, nrhs, bb.data(), nh);
+  if (mixed) launch_convert(L, ip, r, F64, b, nrhs * nh);
+  else copy_dev(L, r, b, fb64);
+  copy_dev(L, p, r, fbi);
+  std::vector<double> hs(CG_NROWS * kMaxRhs, 0.0);
+  auto S = [&](int row, int rr) -> double& { return hs[row * kMaxRhs + rr]; };
+  std::vector<char> verified(nrhs, 0);
+  for (int i = 0; i < nrhs; ++i) {
+    S(CG_RR, i) = bb[i];
+    S(CG_BB, i) = bb[i];
+    S(CG_TOL2, i) = prm.tol * prm.tol;
+    S(CG_MAXRR, i) = bb[i];
+    if (bb[i] == 0.0) {
+      S(CG_DONE, i) = 1.0;
+      verified[i] = 1;
+      rr_true[i] = 0.0;
+    }
+  }
+  auto push_state = [&]() {
+    std::memcpy(L->hscal + kCgState, hs.data(), sizeof(double) * hs.size());
+    WL_HIP(hipMemcpyAsync(st, L->hscal + kCgState, sizeof(double) * hs.size(), hipMemcpyHostToDevice, L->stream));
+  };
+  auto pull_state = [&]() {
+    WL_HIP(hipMemcpyAsync(L->hscal + kCgState, st, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, L->stream));
+    WL_HIP(hipStreamSynchronize(L->stream));
+    std::memcpy(hs.data(), L->hscal + kCgState, sizeof(double) * hs.size());
+  };
+  push_state();
+
+  auto issue_chunk = [&]() {
+    for (int it = 0; it < chunk; ++it) {
+      apply_lp(ip, Ap, p, DotOut{L->partials, nbrow});
+      launch_cg_alpha(L, L->partials, nbrow, nbrow, st, nrhs);
+      launch_cg_update(L, ip, x, r, p, Ap, st, nrhs, nh, L->partials, nbrow);
+      launch_cg_beta(L, L->partials, nbrow, nbrow, st, nrhs);
+      launch_cg_xpay(L, ip, p, r, st, nrhs, nh);
+    }
+  };
+
+  CgGraph cg_graph;
+  int chunks = 0;
+  int reliable = 0;
+  bool all_verified = false;
+  bool out_of_iters = false;
+  while (true) {
+    if (prm.use_graph && chunks > 0) {
+      if (!cg_graph.exec) {
+        if (!L->capture_stream) WL_HIP(hipStreamCreateWithFlags(&L->capture_stream, hipStreamNonBlocking));
+        hipStream_t keep = L->stream;
+        L->stream = L->capture_stream;
+        WL_HIP(hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
+        try {
+          issue_chunk();
+        } catch (...) {
+          hipGraph_t g;
+          (void)hipStreamEndCapture(L->stream, &g);
+          L->stream = keep;
+          throw;
+        }
+        WL_HIP(hipStreamEndCapture(L->stream, &cg_graph.graph));
+        L->stream = keep;
+        WL_HIP(hipGraphInstantiate(&cg_graph.exec, cg_graph.graph, nullptr, nullptr, 0));
+      }
+      WL_HIP(hipGraphLaunch(cg_graph.exec, L->stream));
+    } else {
+      issue_chunk();
+    }
+    ++chunks;
+    pull_state();
+
+    bool all_done = true, need_ru = false;
+    for (int i = 0; i < nrhs; ++i) {
+      if (verified[i]) continue;
+      if (S(CG_DONE, i) == 0.0) all_done = false;
+      if (S(CG_DONE, i) != 0.0 || S(CG_RR, i) < delta * delta * S(CG_MAXRR, i)) need_ru = true;
+    }
+    int max_it = 0;
+    for (int i = 0; i < nrhs; ++i) max_it = std::max(max_it, int(S(CG_ITERS, i)));
+
+    if ((mixed && need_ru) || (!mixed && all_done)) {
+      true_residual();
+      if (mixed) launch_convert(L, ip, r, F64, r64, nrhs * nh);
+      ++reliable;
+      bool restart = false;
+      for (int i = 0; i < nrhs; ++i) {
+        if (verified[i]) continue;
+        const double t2 = prm.tol * prm.tol * bb[i];
+        if (rr_true[i] <= t2) {
+          S(CG_DONE, i) = 1.0;
+          verified[i] = 1;
+        } else if (mixed) {
+          S(CG_DONE, i) = 0.0;
+        } else if (S(CG_DONE, i) != 0.0) {
+          S(CG_DONE, i) = 0.0;  // FP64: the iterated residual drifted; restart from x
+          restart = true;
+        }
+        if (mixed || S(CG_DONE, i) == 0.0) {
+          S(CG_RR, i) = rr_true[i];
+          S(CG_MAXRR, i) = rr_true[i];
+        }
+      }
+      if (!mixed && restart) {
+        copy_dev(L, r, r64, fb64);
+        copy_dev(L, p, r, fbi);
+      }
+      push_state();
+    }
+    all_verified = true;
+    for (int i = 0; i < nrhs; ++i) all_verified = all_verified && verified[i];
+    if (all_verified) break;
+    if (max_it >= prm.maxiter) {
+      out_of_iters = true;
+      break;
+    }
+  }
+  if (out_of_iters) true_residual();
+
+  long long iters_total = 0;
+  for (int i = 0; i < nrhs; ++i) iters_total += (long long)S(CG_ITERS, i);
+  // K applications actually made (graph replays are not seen by the launch counters)
+  if (count_kmat) L->n_kmat = kmat0 + iters_total + kmat_extra * nrhs;
+  if (stats) {
+    for (int i = 0; i < nrhs; ++i) {
+      stats[i].iters = int(S(CG_ITERS, i));
+      stats[i].reliable_updates = reliable;
+      stats[i].converged = verified[i] ? 1 : 0;
+      stats[i].true_rel_res = bb[i] > 0 ? std::sqrt(rr_true[i] / bb[i]) : 0.0;
+    }
+  }
+  return all_verified ? WL_OK : WL_ENOCONV;
+}
+
+int cg_run(wl_lattice* L, void* x, const void* b, double kappa, const double* mu2, int nrhs, int op,
+           const wl_cg_params& prm, wl_cg_stats* stats) {
+  WL_REQUIRE(op == WL_OP_J || op == WL_OP_K, WL_EINVAL, "cg_solve needs WL_OP_J or WL_OP_K");
+  WL_REQUIRE(op != WL_OP_K || nrhs == 1, WL_EUNSUPPORTED, "full-lattice CG takes one rhs");
+  const Prec ip = Prec(prm.inner);
+  const int nh = op == WL_OP_K ? 2 : 1;
+  ApplyLowp lp = [&](Prec pr, void* out, const void* in, const DotOut& d) {
+    op_apply(L, op, pr, out, in, kappa, mu2, nrhs, d);
+  };
+  Apply64 a64 = [&](void* out, const void* in) { op_apply(L, op, F64, out, in, kappa, mu2, nrhs); };
+  return cg_core(L, x, b, nrhs, nh, op_dot_blocks(L, op), spinor_bytes(F64, L->Vh),
+                 spinor_bytes((ip == F32 || ip == BF16) ? ip : F64, L->Vh), lp, a64, prm, stats, true);
+}
+
+int cg_run_generic(wl_lattice* L, void* x, const void* b, const std::function<void(void*, const void*)>& apply,
+                   const wl_cg_params& prm_in, wl_cg_stats* stats) {
+  wl_cg_params prm = prm_in;
+  prm.inner = WL_F64;   // the polynomial operators run in FP64
+  prm.use_graph = 0;    // they synchronise the host inside (nothing to capture)
+  const int nb = blas_blocks(L);
+  ApplyLowp lp = [&](Prec, void* out, const void* in, const DotOut& d) {
+    apply(out, in);
+    // complex <in, out>: row 0 holds the real part, which CG needs
+    launch_dot_partials(L, in, out, 1, d.partials, d.stride, 1);
+  };
+  Apply64 a64 = [&](void* out, const void* in) { apply(out, in); };
+  return cg_core(L, x, b, 1, 1, nb, spinor_bytes(F64, L->Vh), spinor_bytes(F64, L->Vh), lp, a64, prm, stats,
+                 false);
+}
+
+}  // namespace wl

@@ -1,0 +1,372 @@
+// Device-side building blocks for the Wilson-fermion kernels on gfx950.
+//
+// Conventions (the paper fixes none; see include/wilson_hmc.h):
+//   * half-lattice site h of parity p: xh = h % (Lx/2), then y, z, t from
+//     h / (Lx/2); x = 2*xh + ((y + z + t + p) & 1).  The i-th site of a parity
+//     in lexicographic order s = x + Lx*(y + Ly*(z + Lz*t)) has h = i.
+//   * spinor component c = 3*spin + colour; chiral gamma basis with
+//     gamma_5 = diag(1, 1, -1, -1).
+//   * storage is structure-of-arrays over h so that a wavefront reads 64
+//     consecutive sites per load instruction, 16 bytes per lane:
+//       F64  spinor: double2 [12][Vh]   link: double2 [9][Vh]
+//       F32  spinor: float4  [6][Vh]    link: float4  [3][Vh]  (two rows)
+//       BF16 spinor: uint4   [3][Vh]    link: uint2   [3][Vh]  (two rows)
+//     with the third link row rebuilt as conj(row0 x row1) (SU(3)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wl {
+
+// ------------------------------------------------------------------ complex
+template <typename T>
+struct cplx {
+  T r, i;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> mk(T r, T i) { return cplx<T>{r, i}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> operator*(T s, cplx<T> a) { return {s * a.r, s * a.i}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> conj(cplx<T> a) { return {a.r, -a.i}; }
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
+}
+// i * a
+template <typename T>
+__device__ __forceinline__ cplx<T> times_i(cplx<T> a) { return {-a.i, a.r}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> zero() { return {T(0), T(0)}; }
+
+// ------------------------------------------------------------------ bf16
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+// round to nearest even (inputs here are finite)
+__device__ __forceinline__ uint32_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  return f32_to_bf16(lo) | (f32_to_bf16(hi) << 16);
+}
+
+// ------------------------------------------------------------------ storage precisions
+struct PrecF64 {
+  using real = double;
+  static constexpr int spinor_bytes = 192;  // per site per rhs
+};
+struct PrecF32 {
+  using real = float;
+  static constexpr int spinor_bytes = 96;
+};
+struct PrecBF16 {
+  using real = float;  // compute type
+  static constexpr int spinor_bytes = 48;
+};
+
+template <typename T>
+struct Spinor {
+  cplx<T> c[12];  // 3*spin + colour
+};
+template <typename T>
+struct Half {
+  cplx<T> c[6];  // 3*k + colour, k = 0, 1
+};
+template <typename T>
+struct SU3 {
+  cplx<T> m[9];  // row-major
+};
+
+// spinor load/store: base points at one rhs of one parity
+template <typename P>
+struct SpinorIO;
+
+template <>
+struct SpinorIO<PrecF64> {
+  static __device__ __forceinline__ Spinor<double> load(const void* base, int h, int Vh) {
+    const double2* b = reinterpret_cast<const double2*>(base);
+    Spinor<double> s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      double2 v = b[c * Vh + h];
+      s.c[c] = {v.x, v.y};
+    }
+    return s;
+  }
+  static __device__ __forceinline__ void store(void* base, int h, int Vh, const Spinor<double>& s) {
+    double2* b = reinterpret_cast<double2*>(base);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) b[c * Vh + h] = make_double2(s.c[c].r, s.c[c].i);
+  }
+};
+
+template <>
+struct SpinorIO<PrecF32> {
+  static __device__ __forceinline__ Spinor<float> load(const void* base, int h, int Vh) {
+    const float4* b = reinterpret_cast<const float4*>(base);
+    Spinor<float> s;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      float4 v = b[j * Vh + h];
+      s.c[2 * j] = {v.x, v.y};
+      s.c[2 * j + 1] = {v.z, v.w};
+    }
+    return s;
+  }
+  static __device__ __forceinline__ void store(void* base, int h, int Vh, const Spinor<float>& s) {
+    float4* b = reinterpret_cast<float4*>(base);
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      b[j * Vh + h] = make_float4(s.c[2 * j].r, s.c[2 * j].i, s.c[2 * j + 1].r, s.c[2 * j + 1].i);
+  }
+};
+
+template <>
+struct SpinorIO<PrecBF16> {
+  static __device__ __forceinline__ Spinor<float> load(const void* base, int h, int Vh) {
+    const uint4* b = reinterpret_cast<const uint4*>(base);
+    Spinor<float> s;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      uint4 v = b[j * Vh + h];
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s.c[4 * j + q] = {bf16_to_f32(w[q] & 0xFFFFu), bf16_to_f32(w[q] >> 16)};
+    }
+    return s;
+  }
+  static __device__ __forceinline__ void store(void* base, int h, int Vh, const Spinor<float>& s) {
+    uint4* b = reinterpret_cast<uint4*>(base);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      uint4 v;
+      v.x = pack_bf16x2(s.c[4 * j + 0].r, s.c[4 * j + 0].i);
+      v.y = pack_bf16x2(s.c[4 * j + 1].r, s.c[4 * j + 1].i);
+      v.z = pack_bf16x2(s.c[4 * j + 2].r, s.c[4 * j + 2].i);
+      v.w = pack_bf16x2(s.c[4 * j + 3].r, s.c[4 * j + 3].i);
+      b[j * Vh + h] = v;
+    }
+  }
+};
+
+// link load: base points at [mu] block of one parity
+template <typename T>
+__device__ __forceinline__ void third_row(SU3<T>& u) {
+  u.m[6] = conj(u.m[1] * u.m[5] - u.m[2] * u.m[4]);
+  u.m[7] = conj(u.m[2] * u.m[3] - u.m[0] * u.m[5]);
+  u.m[8] = conj(u.m[0] * u.m[4] - u.m[1] * u.m[3]);
+}
+
+template <typename P>
+struct LinkIO;
+
+template <>
+struct LinkIO<PrecF64> {
+  static constexpr int bytes = 144;  // per link
+  static __device__ __forceinline__ SU3<double> load(const void* base, int h, int Vh) {
+    const double2* b = reinterpret_cast<const double2*>(base);
+    SU3<double> u;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      double2 v = b[k * Vh + h];
+      u.m[k] = {v.x, v.y};
+    }
+    return u;
+  }
+};
+
+template <>
+struct LinkIO<PrecF32> {
+  static constexpr int bytes = 48;
+  static __device__ __forceinline__ SU3<float> load(const void* base, int h, int Vh) {
+    const float4* b = reinterpret_cast<const float4*>(base);
+    SU3<float> u;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float4 v = b[j * Vh + h];
+      u.m[2 * j] = {v.x, v.y};
+      u.m[2 * j + 1] = {v.z, v.w};
+    }
+    third_row(u);
+    return u;
+  }
+};
+
+template <>
+struct LinkIO<PrecBF16> {
+  static constexpr int bytes = 24;
+  static __device__ __forceinline__ SU3<float> load(const void* base, int h, int Vh) {
+    const uint2* b = reinterpret_cast<const uint2*>(base);
+    SU3<float> u;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      uint2 v = b[j * Vh + h];
+      u.m[2 * j] = {bf16_to_f32(v.x & 0xFFFFu), bf16_to_f32(v.x >> 16)};
+      u.m[2 * j + 1] = {bf16_to_f32(v.y & 0xFFFFu), bf16_to_f32(v.y >> 16)};
+    }
+    third_row(u);
+    return u;
+  }
+};
+
+// ------------------------------------------------------------------ SU(3) x colour vector
+template <typename T>
+__device__ __forceinline__ void su3_mul(const SU3<T>& u, const cplx<T>* v, cplx<T>* w) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) w[a] = u.m[3 * a] * v[0] + u.m[3 * a + 1] * v[1] + u.m[3 * a + 2] * v[2];
+}
+template <typename T>
+__device__ __forceinline__ void su3_dag_mul(const SU3<T>& u, const cplx<T>* v, cplx<T>* w) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) w[a] = cmul(u.m[a], v[0]) + cmul(u.m[3 + a], v[1]) + cmul(u.m[6 + a], v[2]);
+}
+
+// ------------------------------------------------------------------ spin projection
+// (1 + S gamma_MU) psi has two independent spin rows h0, h1 (chiral basis);
+// the lower rows are phases times h0 / h1.  MU = 0..3 is x, y, z, t.
+template <int MU, int S, typename T>
+__device__ __forceinline__ Half<T> project(const Spinor<T>& p) {
+  Half<T> h;
+  const T s = T(S);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<T> p0 = p.c[a], p1 = p.c[3 + a], p2 = p.c[6 + a], p3 = p.c[9 + a];
+    if (MU == 0) {         // h0 = p0 - s i p3, h1 = p1 - s i p2
+      h.c[a] = p0 - s * times_i(p3);
+      h.c[3 + a] = p1 - s * times_i(p2);
+    } else if (MU == 1) {  // h0 = p0 - s p3, h1 = p1 + s p2
+      h.c[a] = p0 - s * p3;
+      h.c[3 + a] = p1 + s * p2;
+    } else if (MU == 2) {  // h0 = p0 - s i p2, h1 = p1 + s i p3
+      h.c[a] = p0 - s * times_i(p2);
+      h.c[3 + a] = p1 + s * times_i(p3);
+    } else {               // h0 = p0 + s p2, h1 = p1 + s p3
+      h.c[a] = p0 + s * p2;
+      h.c[3 + a] = p1 + s * p3;
+    }
+  }
+  return h;
+}
+
+// acc += (1 + S gamma_MU)-reconstruction of the half spinor w
+template <int MU, int S, typename T>
+__device__ __forceinline__ void reconstruct_add(Spinor<T>& acc, const Half<T>& w) {
+  const T s = T(S);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<T> h0 = w.c[a], h1 = w.c[3 + a];
+    acc.c[a] = acc.c[a] + h0;
+    acc.c[3 + a] = acc.c[3 + a] + h1;
+    if (MU == 0) {         // r2 = s i h1, r3 = s i h0
+      acc.c[6 + a] = acc.c[6 + a] + s * times_i(h1);
+      acc.c[9 + a] = acc.c[9 + a] + s * times_i(h0);
+    } else if (MU == 1) {  // r2 = s h1, r3 = -s h0
+      acc.c[6 + a] = acc.c[6 + a] + s * h1;
+      acc.c[9 + a] = acc.c[9 + a] - s * h0;
+    } else if (MU == 2) {  // r2 = s i h0, r3 = -s i h1
+      acc.c[6 + a] = acc.c[6 + a] + s * times_i(h0);
+      acc.c[9 + a] = acc.c[9 + a] - s * times_i(h1);
+    } else {               // r2 = s h0, r3 = s h1
+      acc.c[6 + a] = acc.c[6 + a] + s * h0;
+      acc.c[9 + a] = acc.c[9 + a] + s * h1;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ geometry
+struct Geo {
+  int L[4];
+  int Lxh;   // Lx / 2
+  int Vh;    // V / 2
+  int tbc;   // +1 periodic, -1 antiperiodic in time (fermions only)
+};
+
+struct Coord {
+  int x, y, z, t;
+};
+
+__device__ __forceinline__ Coord site_coords(const Geo& g, int h, int parity) {
+  Coord c;
+  int xh = h % g.Lxh;
+  int r = h / g.Lxh;
+  c.y = r % g.L[1];
+  r /= g.L[1];
+  c.z = r % g.L[2];
+  c.t = r / g.L[2];
+  c.x = 2 * xh + ((c.y + c.z + c.t + parity) & 1);
+  return c;
+}
+
+__device__ __forceinline__ int half_index(const Geo& g, int x, int y, int z, int t) {
+  return (x >> 1) + g.Lxh * (y + g.L[1] * (z + g.L[2] * t));
+}
+
+// half index of x + dir * mu_hat (periodic wrap); *wrapped = crossed the time edge
+template <int MU>
+__device__ __forceinline__ int neighbour(const Geo& g, Coord c, int dir, bool* wrapped) {
+  int x = c.x, y = c.y, z = c.z, t = c.t;
+  *wrapped = false;
+  if (MU == 0) {
+    x += dir;
+    x = (x < 0) ? x + g.L[0] : (x >= g.L[0] ? x - g.L[0] : x);
+  } else if (MU == 1) {
+    y += dir;
+    y = (y < 0) ? y + g.L[1] : (y >= g.L[1] ? y - g.L[1] : y);
+  } else if (MU == 2) {
+    z += dir;
+    z = (z < 0) ? z + g.L[2] : (z >= g.L[2] ? z - g.L[2] : z);
+  } else {
+    t += dir;
+    if (t < 0) {
+      t += g.L[3];
+      *wrapped = true;
+    } else if (t >= g.L[3]) {
+      t -= g.L[3];
+      *wrapped = true;
+    }
+  }
+  return half_index(g, x, y, z, t);
+}
+
+// XCD-aware tile order: the hardware deals consecutive workgroups round-robin
+// over the 8 XCDs (each with its own L2); renumber so that each XCD walks a
+// contiguous range of sites and finds its neighbours' data in its own L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  if ((nb & 7) != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// ------------------------------------------------------------------ wavefront reduction
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block-wide sum (blockDim.x a multiple of 64, at most 1024); result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    int nw = blockDim.x >> 6;
+    for (int k = 0; k < nw; ++k) s += lds[k];
+  }
+  __syncthreads();
+  return s;
+}
+
+}  // namespace wl

@@ -1,0 +1,145 @@
+// Host-side internals of libwilson_hmc: the lattice context, workspace,
+// error reporting and the kernel launchers shared between translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/wilson_hmc.h"
+#include "wl_device.h"
+
+namespace wl {
+
+constexpr int kMaxRhs = 16;
+constexpr int kBlock = 256;  // threads per workgroup of the site kernels
+constexpr int kScal = 2048;  // device scalar slots; the CG state starts at kCgState
+constexpr int kCgState = 1024;
+
+enum Prec { F64 = WL_F64, F32 = WL_F32, BF16 = WL_BF16 };
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define WL_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::wl::Error(WL_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+#define WL_REQUIRE(cond, code, msg)         \
+  do {                                      \
+    if (!(cond)) throw ::wl::Error(code, msg); \
+  } while (0)
+
+inline size_t spinor_bytes(Prec p, int Vh) {
+  return size_t(p == F64 ? 192 : (p == F32 ? 96 : 48)) * size_t(Vh);
+}
+inline size_t link_bytes(Prec p) { return p == F64 ? 144 : (p == F32 ? 48 : 24); }
+
+}  // namespace wl
+
+// Opaque context of the C-ABI.  Owns packed links (FP64 and derived low
+// precision copies), momentum backup, reduction partials and a workspace of
+// named device buffers.
+struct wl_lattice {
+  wl::Geo geo;
+  int L[4];
+  int V, Vh;
+  hipStream_t stream;
+  int device;
+  void* U[3] = {nullptr, nullptr, nullptr};  // F64, F32, BF16 packed links
+  bool lowp_valid = false;                   // U[F32], U[BF16] match U[F64]
+  double* partials = nullptr;                // reduction partials
+  size_t partials_len = 0;
+  double* dscal = nullptr;                   // device scalars [kScal]: results, then CG state
+  double* hscal = nullptr;                   // pinned host mirror
+  hipStream_t capture_stream = nullptr;      // side stream for hipGraph capture
+  std::map<std::string, std::pair<void*, size_t>> ws;
+  long long n_hop = 0;                       // hop applications (single rhs units)
+  long long n_kmat = 0;                      // K-hat / K applications (single rhs units)
+  int use_xcd = 1;
+  int hop_block = wl::kBlock;
+};
+
+namespace wl {
+
+// workspace: named device buffer of at least `bytes`, kept for the lifetime of
+// the context (grown on demand)
+void* ws_get(wl_lattice* L, const std::string& name, size_t bytes);
+void ensure_partials(wl_lattice* L, size_t n);
+void ensure_lowp_links(wl_lattice* L);
+inline int site_blocks(int n) { return (n + kBlock - 1) / kBlock; }
+
+// ------------------------------------------------------------------ hop
+struct HopEpi {
+  const void* x = nullptr;  // same-parity field (precision of the hop)
+  double cx = 1.0;
+  double a = 1.0;           // coefficient of the hop
+  int g5 = 0;               // gamma_5 applied to (cx x + a hop)
+  const void* y = nullptr;  // + by[r] y
+  double by[kMaxRhs] = {0};
+  int dot = 0;              // 0 none, 1 Re<dotv, out>, 2 |out|^2 into partials
+  const void* dotv = nullptr;
+  double* partials = nullptr;
+  int part_stride = 0;      // per-rhs stride of partials
+  int part_off = 0;         // block offset inside a rhs row
+};
+int hop_grid_blocks(const wl_lattice* L);
+// out (parity p, nrhs fields) = epilogue(D_{p,1-p} in) or its dagger
+void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_parity, int dagger,
+                int nrhs, const HopEpi& e);
+
+// ------------------------------------------------------------------ BLAS-1 (blas.hip)
+int blas_blocks(const wl_lattice* L);
+// x (F64) += alpha[r] p ; r -= alpha[r] Ap ; partial |r|^2   (p, r, Ap in prec);
+// alpha and the done flags are read from the device CG state st
+// (nh = 2 when every rhs is a full-lattice field of two halves)
+void launch_cg_update(wl_lattice* L, Prec prec, void* x64, void* r, const void* p, const void* Ap,
+                      const double* st, int nrhs, int nh, double* partials, int stride);
+// p = r + beta[r] p
+void launch_cg_xpay(wl_lattice* L, Prec prec, void* p, const void* r, const double* st, int nrhs, int nh);
+// dst = convert(src), both nrhs half fields
+void launch_convert(wl_lattice* L, Prec dprec, void* dst, Prec sprec, const void* src, int nrhs);
+// out = a[r] x + b[r] (g5 ? gamma5 y : y), complex coefficients, F64 fields; x or y may be null
+void launch_caxpby(wl_lattice* L, void* out, const double* a /*2*nrhs host*/, const void* x,
+                   const double* b /*2*nrhs host*/, const void* y, int g5y, int nrhs);
+// partials of <x, y> (complex, 2 values per block) or |x|^2 over nrhs F64 fields
+void launch_dot_partials(wl_lattice* L, const void* x, const void* y, int nrhs, double* partials,
+                         int stride, int complex_dot);
+// sum partials: out[r * ncomp + c] = sum_b partials[(r * ncomp + c) * stride + b], b < nb
+void launch_finish_sum(wl_lattice* L, const double* partials, int stride, int nb, int nrows,
+                       double* out_dev);
+// Chebyshev recurrence step: tprev <- ct t + cw w - tprev ; eprev <- ce e + 2 t - eprev (F64)
+void launch_cheb_step(wl_lattice* L, const void* t, const void* w, void* tprev, const void* e, void* eprev,
+                      double ct, double cw, double ce, int nrhs);
+// CG scalar steps on the device state (see solver.cpp for the layout)
+void launch_cg_alpha(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);
+void launch_cg_beta(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);
+
+// ------------------------------------------------------------------ pack (pack.hip)
+void launch_pack_links(wl_lattice* L, const void* canon);
+void launch_unpack_links(wl_lattice* L, void* canon);
+void launch_lowp_links(wl_lattice* L);
+void launch_import_spinor(wl_lattice* L, Prec prec, void* dst, const void* canon, int nrhs);
+void launch_export_spinor(wl_lattice* L, Prec prec, void* canon, const void* src, int nrhs);
+void launch_split_full(wl_lattice* L, void* even, void* odd, const void* canon_full, int to_canon);
+void launch_su3_io(wl_lattice* L, double* internal, const double* canon, int to_canon);
+
+// ------------------------------------------------------------------ force / gauge (force.hip)
+// F (or P) [parity][mu][8][Vh] += coeff * grad Re(A^dag D C), A and C full fields given as halves
+void launch_bilinear(wl_lattice* L, double* F, const void* Ae, const void* Ao, const void* Ce,
+                     const void* Co, double coeff);
+void launch_gauge_force(wl_lattice* L, double* F, double coeff);  // F += coeff * grad S_G / beta
+void launch_link_update(wl_lattice* L, const double* P, double eps);
+void launch_plaquette_partials(wl_lattice* L, double* partials);  // per block, nb = 2 * site_blocks(Vh)
+void launch_su3_sumsq_partials(wl_lattice* L, const double* P, double* partials);
+void launch_unitarity_partials(wl_lattice* L, double* partials);  // max |U U^dag - 1|
+
+}  // namespace wl

@@ -1,0 +1,64 @@
+// Operators built from the hop kernel, and the host orchestration layers
+// (solver, polynomial filter, action terms, HMC) that call them.
+#pragma once
+#include <functional>
+
+#include "wl_internal.h"
+
+namespace wl {
+
+struct DotOut {
+  double* partials = nullptr;  // Re<in, out> partials; nullptr = no reduction
+  int stride = 0;
+};
+
+// even sites: out = M-hat in (dagger: M-hat^dag), nrhs fields of precision prec
+void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger, int nrhs);
+// even sites: out = K-hat in + mu2[r] in; optional partials of Re<in, out>
+// (one row per rhs, hop_grid_blocks(L) blocks)
+void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const double* mu2, int nrhs,
+          const DotOut& dot = DotOut());
+// full lattice (F64 halves back to back, nrhs = 1): M, M^dag, K = M^dag M
+void op_m_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger);
+void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const DotOut& dot = DotOut());
+// generic dispatch used by the solver; dot rows hold 2 * blocks for the full lattice
+void op_apply(wl_lattice* L, int op, Prec prec, void* out, const void* in, double kappa, const double* mu2,
+              int nrhs, const DotOut& dot = DotOut());
+inline int op_dot_blocks(const wl_lattice* L, int op) {
+  return (op == WL_OP_K ? 2 : 1) * hop_grid_blocks(L);
+}
+inline size_t op_field_bytes(const wl_lattice* L, int op, Prec prec, int nrhs) {
+  return (op == WL_OP_K ? 2 : 1) * spinor_bytes(prec, L->Vh) * size_t(nrhs);
+}
+
+// host-visible reductions over F64 fields (synchronise the stream)
+void norm2_host(wl_lattice* L, const void* x, int nrhs, double* out, int nhalves = 1);
+void cdot_host(wl_lattice* L, const void* x, const void* y, int nrhs, double* out /*2*nrhs*/, int nhalves = 1);
+
+// CG (solver.cpp) on J (even sites) or the full-lattice K
+int cg_run(wl_lattice* L, void* x, const void* b, double kappa, const double* mu2, int nrhs, int op,
+           const wl_cg_params& prm, wl_cg_stats* stats);
+// CG on a general HPD operator on even-site F64 fields (one rhs):
+// apply(out, in) must leave out = A in.  Used for P(J) and P(J) J.
+int cg_run_generic(wl_lattice* L, void* x, const void* b, const std::function<void(void*, const void*)>& apply,
+                   const wl_cg_params& prm, wl_cg_stats* stats);
+
+// polynomial filter (poly.cpp), F64, one rhs
+struct PolyDesc {
+  int n;
+  double a, b;
+};
+void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd);
+double poly_lead(const PolyDesc& pd);
+void poly_q_roots(const PolyDesc& pd, std::vector<double>& re, std::vector<double>& im);
+
+// action terms (action.cpp)
+void term_heatbath(wl_lattice* L, const wl_term& t, void* phi, const void* chi);
+double term_action(wl_lattice* L, const wl_term& t, const void* phi, long long* cg_iters);
+void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, double coeff, long long* cg_iters);
+
+// field copies on the context stream
+void copy_dev(wl_lattice* L, void* dst, const void* src, size_t bytes);
+void zero_dev(wl_lattice* L, void* dst, size_t bytes);
+
+}  // namespace wl

@@ -1,0 +1,306 @@
+"""Python binding of libwilson_hmc: torch tensors for device memory and streams.
+
+Argument marshalling only.  Every computation (layout packing, hops,
+operators, solves, polynomial filter, forces, HMC) runs in the HIP library;
+torch allocates the buffers and supplies the stream.
+
+Field conventions (see include/wilson_hmc.h): canonical spinors are complex128
+``[nrhs, V/2, 4, 3]`` (one parity, lexicographic) or ``[V, 4, 3]`` (full);
+links complex128 ``[4, V, 3, 3]``; su(3) fields float64 ``[4, V, 8]``.  Internal
+fields are opaque uint8 device tensors of ``field_bytes`` bytes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as W
+
+PREC = {"f64": W.WL_F64, "f32": W.WL_F32, "bf16": W.WL_BF16}
+TERM_KIND = {"KINV_FULL": W.WL_TERM_KINV_FULL, "KINV": W.WL_TERM_KINV, "RATIO": W.WL_TERM_RATIO,
+             "POLY": W.WL_TERM_POLY, "POLYK_INV": W.WL_TERM_POLYK_INV}
+POLY_MODE = {"P": W.WL_POLY_P, "PJ": W.WL_POLY_PJ, "Q": W.WL_POLY_Q, "QDAG": W.WL_POLY_QDAG}
+OPS = {"M": W.WL_OP_M, "MDAG": W.WL_OP_MDAG, "K": W.WL_OP_K, "MHAT": W.WL_OP_MHAT,
+       "MHAT_DAG": W.WL_OP_MHAT_DAG, "J": W.WL_OP_J}
+
+
+def _ptr(t: torch.Tensor) -> C.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("libwilson_hmc takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _prec(p) -> int:
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def _need(t: torch.Tensor, nbytes: int, what: str = "buffer"):
+    """Reject device buffers smaller than the library will touch (it sees plain pointers)."""
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{what} has {have} bytes, needs {nbytes}")
+
+
+@dataclass
+class CG:
+    tol: float = 1e-10
+    maxiter: int = 10000
+    inner: str = "f64"
+    delta: float = 0.1
+    chunk: int = 8
+    use_graph: bool = False
+
+    def c(self) -> W.CgParams:
+        return W.CgParams(self.tol, self.maxiter, _prec(self.inner), self.delta, self.chunk, int(self.use_graph))
+
+
+@dataclass
+class Term:
+    """A pseudofermion action term (kinds: KINV_FULL, KINV, RATIO, POLY, POLYK_INV)."""
+    kind: str
+    kappa: float
+    mu2: float = 0.0
+    degree: int = 0
+    a: float = 0.001
+    b: float = 8.0
+    cg: CG = field(default_factory=CG)
+
+    def c(self) -> W.Term:
+        return W.Term(TERM_KIND[self.kind], self.kappa, self.mu2, W.Poly(self.degree, self.a, self.b), self.cg.c())
+
+    @property
+    def full(self) -> bool:
+        return self.kind == "KINV_FULL"
+
+
+@dataclass
+class CgResult:
+    iters: int
+    reliable_updates: int
+    converged: bool
+    true_rel_res: float
+
+
+class WilsonLattice:
+    """One lattice context: geometry, packed links, workspace (owned by the library)."""
+
+    def __init__(self, L: Sequence[int], t_bc: int = -1, device: Optional[torch.device] = None):
+        self.lib = W.load()
+        dev = torch.device(device or "cuda")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        torch.cuda.set_device(self.device)
+        self.L = tuple(int(x) for x in L)
+        self.V = self.L[0] * self.L[1] * self.L[2] * self.L[3]
+        self.Vh = self.V // 2
+        self.t_bc = t_bc
+        h = C.c_void_p()
+        arr = (C.c_int32 * 4)(*self.L)
+        W.check(self.lib.wl_create(C.byref(h), arr, t_bc, self._stream()))
+        self.h = h
+
+    def _stream(self) -> C.c_void_p:
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _sync_stream(self):
+        W.check(self.lib.wl_set_stream(self.h, self._stream()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.wl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- memory
+    def field_bytes(self, prec="f64", nrhs: int = 1) -> int:
+        n = C.c_size_t()
+        W.check(self.lib.wl_field_bytes(self.h, _prec(prec), nrhs, C.byref(n)))
+        return n.value
+
+    def new_field(self, prec="f64", nrhs: int = 1, full: bool = False) -> torch.Tensor:
+        n = self.field_bytes(prec, nrhs) * (2 if full else 1)
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def new_su3(self) -> torch.Tensor:
+        # [2 parity][4 mu][8][V/2] float64
+        return torch.zeros(32 * self.V, dtype=torch.float64, device=self.device)
+
+    # ---------------------------------------------------------------- links / fields
+    def set_links(self, U: torch.Tensor):
+        U = U.to(device=self.device, dtype=torch.complex128).contiguous()
+        assert U.shape == (4, self.V, 3, 3)
+        W.check(self.lib.wl_set_links(self.h, _ptr(U)))
+
+    def get_links(self) -> torch.Tensor:
+        U = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device=self.device)
+        W.check(self.lib.wl_get_links(self.h, _ptr(U)))
+        return U
+
+    def import_spinor(self, psi: torch.Tensor, prec="f64") -> torch.Tensor:
+        psi = psi.to(device=self.device, dtype=torch.complex128).contiguous()
+        nrhs = 1 if psi.dim() == 3 else psi.shape[0]
+        assert psi.shape[-3:] == (self.Vh, 4, 3)
+        out = self.new_field(prec, nrhs)
+        W.check(self.lib.wl_import_spinor(self.h, _ptr(out), _ptr(psi), _prec(prec), nrhs))
+        return out
+
+    def export_spinor(self, buf: torch.Tensor, prec="f64", nrhs: int = 1) -> torch.Tensor:
+        _need(buf, self.field_bytes(prec, nrhs), "internal field")
+        out = torch.empty((nrhs, self.Vh, 4, 3), dtype=torch.complex128, device=self.device)
+        W.check(self.lib.wl_export_spinor(self.h, _ptr(out), _ptr(buf), _prec(prec), nrhs))
+        return out[0] if nrhs == 1 else out
+
+    def import_full(self, psi: torch.Tensor) -> torch.Tensor:
+        psi = psi.to(device=self.device, dtype=torch.complex128).contiguous()
+        assert psi.shape == (self.V, 4, 3)
+        out = self.new_field("f64", 1, full=True)
+        W.check(self.lib.wl_import_full(self.h, _ptr(out), _ptr(psi)))
+        return out
+
+    def export_full(self, buf: torch.Tensor) -> torch.Tensor:
+        _need(buf, 2 * self.field_bytes("f64"), "internal field")
+        out = torch.empty((self.V, 4, 3), dtype=torch.complex128, device=self.device)
+        W.check(self.lib.wl_export_full(self.h, _ptr(out), _ptr(buf)))
+        return out
+
+    def import_su3(self, p: torch.Tensor) -> torch.Tensor:
+        p = p.to(device=self.device, dtype=torch.float64).contiguous()
+        assert p.shape == (4, self.V, 8)
+        out = self.new_su3()
+        W.check(self.lib.wl_import_su3(self.h, _ptr(out), _ptr(p)))
+        return out
+
+    def export_su3(self, buf: torch.Tensor) -> torch.Tensor:
+        _need(buf, 256 * self.V, "internal su(3) field")
+        out = torch.empty((4, self.V, 8), dtype=torch.float64, device=self.device)
+        W.check(self.lib.wl_export_su3(self.h, _ptr(out), _ptr(buf)))
+        return out
+
+    # ---------------------------------------------------------------- operators
+    def dslash(self, buf: torch.Tensor, out_parity: int, dagger: bool = False, prec="f64", nrhs: int = 1,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.new_field(prec, nrhs) if out is None else out
+        if 1 <= nrhs <= 16:
+            _need(buf, self.field_bytes(prec, nrhs), "input")
+            _need(out, self.field_bytes(prec, nrhs), "output")
+        W.check(self.lib.wilson_dslash(self.h, _ptr(out), _ptr(buf), out_parity, int(dagger), _prec(prec), nrhs))
+        return out
+
+    def apply_K(self, buf: torch.Tensor, kappa: float, op: str = "J", mu2: Sequence[float] = (0.0,),
+                prec="f64", nrhs: int = 1, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        full = op in ("M", "MDAG", "K")
+        out = self.new_field(prec, nrhs, full=full) if out is None else out
+        if 1 <= nrhs <= 16:
+            need = self.field_bytes(prec, nrhs) * (2 if full else 1)
+            _need(buf, need, "input")
+            _need(out, need, "output")
+        m = (C.c_double * max(nrhs, 1))(*list(mu2)[:nrhs]) if mu2 is not None else None
+        W.check(self.lib.apply_K(self.h, _ptr(out), _ptr(buf), kappa, m, nrhs, OPS[op], _prec(prec)))
+        return out
+
+    def cg_solve(self, b: torch.Tensor, kappa: float, op: str = "J", mu2: Sequence[float] = (0.0,), nrhs: int = 1,
+                 params: Optional[CG] = None, x: Optional[torch.Tensor] = None):
+        params = params or CG()
+        full = op == "K"
+        x = self.new_field("f64", nrhs, full=full) if x is None else x
+        if 1 <= nrhs <= 16:
+            need = self.field_bytes("f64", nrhs) * (2 if full else 1)
+            _need(b, need, "rhs")
+            _need(x, need, "solution")
+        m = (C.c_double * nrhs)(*[float(v) for v in list(mu2)[:nrhs]]) if mu2 is not None else None
+        st = (W.CgStats * nrhs)()
+        prm = params.c()
+        rc = W.check(self.lib.cg_solve(self.h, _ptr(x), _ptr(b), kappa, m, nrhs, OPS[op], C.byref(prm), st))
+        res = [CgResult(s.iters, s.reliable_updates, bool(s.converged), s.true_rel_res) for s in st]
+        return x, res, rc
+
+    def poly_filter_apply(self, buf: torch.Tensor, kappa: float, mu2: float, degree: int, a: float, b: float,
+                          mode: str = "P", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.new_field("f64") if out is None else out
+        _need(buf, self.field_bytes("f64"), "input")
+        _need(out, self.field_bytes("f64"), "output")
+        p = W.Poly(degree, a, b)
+        W.check(self.lib.poly_filter_apply(self.h, _ptr(out), _ptr(buf), kappa, mu2, C.byref(p), POLY_MODE[mode]))
+        return out
+
+    # ---------------------------------------------------------------- action terms / forces
+    def heatbath(self, term: Term, chi: torch.Tensor) -> torch.Tensor:
+        phi = self.new_field("f64", 1, full=term.full)
+        _need(chi, phi.numel(), "noise")
+        t = term.c()
+        W.check(self.lib.wl_heatbath(self.h, _ptr(phi), C.byref(t), _ptr(chi)))
+        return phi
+
+    def action(self, term: Term, phi: torch.Tensor) -> float:
+        s = C.c_double()
+        _need(phi, self.field_bytes("f64") * (2 if term.full else 1), "pseudofermion")
+        t = term.c()
+        W.check(self.lib.wl_action(self.h, C.byref(t), _ptr(phi), C.byref(s)))
+        return s.value
+
+    def fermion_force(self, term: Term, phi: torch.Tensor, F: Optional[torch.Tensor] = None,
+                      coeff: float = 1.0) -> torch.Tensor:
+        F = self.new_su3() if F is None else F
+        _need(F, 256 * self.V, "force")
+        _need(phi, self.field_bytes("f64") * (2 if term.full else 1), "pseudofermion")
+        t = term.c()
+        W.check(self.lib.fermion_force(self.h, _ptr(F), C.byref(t), _ptr(phi), coeff, None))
+        return F
+
+    def force_bilinear(self, A_full: torch.Tensor, C_full: torch.Tensor, F: Optional[torch.Tensor] = None,
+                       coeff: float = 1.0) -> torch.Tensor:
+        F = self.new_su3() if F is None else F
+        _need(F, 256 * self.V, "force")
+        _need(A_full, 2 * self.field_bytes("f64"), "A")
+        _need(C_full, 2 * self.field_bytes("f64"), "C")
+        W.check(self.lib.wl_force_bilinear(self.h, _ptr(F), _ptr(A_full), _ptr(C_full), coeff))
+        return F
+
+    def gauge_force(self, beta: float, F: Optional[torch.Tensor] = None, coeff: float = 1.0) -> torch.Tensor:
+        F = self.new_su3() if F is None else F
+        _need(F, 256 * self.V, "force")
+        W.check(self.lib.wl_gauge_force(self.h, _ptr(F), beta, coeff))
+        return F
+
+    def plaquette(self) -> float:
+        p = C.c_double()
+        W.check(self.lib.wl_plaquette(self.h, C.byref(p)))
+        return p.value
+
+    def link_update(self, P: torch.Tensor, eps: float):
+        _need(P, 256 * self.V, "momenta")
+        W.check(self.lib.wl_link_update(self.h, _ptr(P), eps))
+
+    def hmc_trajectory(self, terms: List[Term], nsteps: Sequence[int], P: torch.Tensor, chi: torch.Tensor,
+                       u: float, beta: float = 5.6, tau: float = 1.0, integrator: str = "omelyan",
+                       no_metropolis: bool = False, omelyan_lambda: float = 0.0) -> W.HmcResult:
+        prm = W.HmcParams()
+        prm.beta, prm.tau, prm.omelyan_lambda = beta, tau, omelyan_lambda
+        prm.integrator = W.WL_INT_OMELYAN if integrator == "omelyan" else W.WL_INT_LEAPFROG
+        prm.nterms = len(terms)
+        for i, t in enumerate(terms):
+            prm.terms[i] = t.c()
+        for i, n in enumerate(nsteps):
+            prm.nsteps[i] = int(n)
+        prm.flags = W.WL_HMC_NO_METROPOLIS if no_metropolis else 0
+        _need(P, 256 * self.V, "momenta")
+        _need(chi, sum(self.field_bytes("f64") * (2 if t.full else 1) for t in terms), "noise")
+        res = W.HmcResult()
+        W.check(self.lib.hmc_trajectory(self.h, C.byref(prm), _ptr(P), _ptr(chi), u, C.byref(res)))
+        return res
+
+    def counters(self):
+        a, b = C.c_longlong(), C.c_longlong()
+        W.check(self.lib.wl_counters(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value

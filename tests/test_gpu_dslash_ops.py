@@ -1,0 +1,144 @@
+"""GPU parity: layout round trips, the hop kernel and the operators, against the FP64 oracle.
+
+FP64 bar: relative l2 error <= 1e-12 (the operator is a fixed sum of a few
+hundred products per site; observed errors are ~1e-16).  FP32 / BF16 storage
+is compared to the FP64 oracle with the error stated in each test: unit
+roundoff times the O(10) growth of one stencil application (FP32: 2^-24 ->
+bound 1e-6; BF16 storage of links and spinors: 2^-9 -> bound 2e-2).
+"""
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+from oracle import wilson as ow
+from tests.gpu_common import full_noise, half_noise, make_lattice, need_gpu, rel, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+# 4^4: one partial workgroup; 6x4x4x10: two workgroups, ragged tail;
+# 8^4: eight workgroups (XCD-aware tile order active)
+SHAPES = [(4, 4, 4, 4), (6, 4, 4, 10), (8, 8, 8, 8)]
+
+
+@pytest.mark.parametrize("L", SHAPES)
+def test_layout_roundtrips(L):
+    say("layout roundtrip", L)
+    lat, U = make_lattice(L)
+    assert np.array_equal(to_np(lat.get_links()), U)
+    psi = half_noise(L, 1, nrhs=3)
+    for prec in ("f64", "f32", "bf16"):
+        back = to_np(lat.export_spinor(lat.import_spinor(torch.from_numpy(psi), prec), prec, 3))
+        tol = {"f64": 0.0, "f32": 1e-7, "bf16": 8e-3}[prec]
+        assert rel(back, psi) <= tol, prec
+    f = full_noise(L, 2)
+    assert np.array_equal(to_np(lat.export_full(lat.import_full(torch.from_numpy(f)))), f)
+    p = li.gaussian_momenta(L, 3)
+    assert np.array_equal(to_np(lat.export_su3(lat.import_su3(torch.from_numpy(p)))), p)
+
+
+@pytest.mark.parametrize("L", SHAPES)
+@pytest.mark.parametrize("parity", [0, 1])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_dslash_f64_matches_oracle(L, parity, dagger):
+    say("dslash f64", L, parity, dagger)
+    lat, U = make_lattice(L)
+    psi = half_noise(L, 10 + parity)
+    got = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi)), parity, dagger)))
+    ref = ow.hop_eo(U, psi, L, parity, t_bc=-1, dagger=dagger)
+    assert rel(got, ref) <= 1e-12
+
+
+def test_dslash_free_field_plane_wave_at_full_size():
+    """U = 1 at 16^3 x 32: D maps each plane wave to its closed-form momentum-space image."""
+    L = (16, 16, 16, 32)
+    say("free-field plane wave", L)
+    lat, U = make_lattice(L, unit=True)
+    from oracle import lattice as olat
+    g = olat.gammas()
+    x, y, z, t = olat.coords(L)
+    n = (3, 5, 7, 2)
+    p = np.array([2 * np.pi * n[0] / L[0], 2 * np.pi * n[1] / L[1], 2 * np.pi * n[2] / L[2], (2 * n[3] + 1) * np.pi / L[3]])
+    u = li.gaussian_spinor((4, 3), 4)
+    psi = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))[:, None, None] * u[None]
+    Dk = sum(2 * np.cos(p[m]) * np.eye(4) - 2j * np.sin(p[m]) * g[m] for m in range(4))
+    expect = np.einsum("st,xtc->xsc", Dk, psi)
+    ev, od = olat.parity_sites(L, 0), olat.parity_sites(L, 1)
+    got_e = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi[od])), 0)))
+    got_o = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi[ev])), 1)))
+    assert rel(got_e, expect[ev]) <= 1e-13
+    assert rel(got_o, expect[od]) <= 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-6), ("bf16", 2e-2)])
+def test_dslash_low_precision_error(prec, tol):
+    L = (8, 8, 8, 8)
+    say("dslash", prec, L)
+    lat, U = make_lattice(L)
+    psi = half_noise(L, 21, nrhs=4)
+    got = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi), prec), 0, prec=prec, nrhs=4),
+                                  prec, 4))
+    for r in range(4):
+        ref = ow.hop_eo(U, psi[r], L, 0)
+        e = rel(got[r], ref)
+        say(f"  rhs {r}: relative error vs FP64 oracle {e:.3e}")
+        assert e <= tol
+
+
+@pytest.mark.parametrize("nrhs", [2, 3])
+def test_dslash_multi_rhs_equals_single(nrhs):
+    L = (6, 4, 4, 10)
+    say("dslash multi-rhs", nrhs)
+    lat, U = make_lattice(L)
+    psi = half_noise(L, 31, nrhs=nrhs)
+    multi = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi)), 1, nrhs=nrhs), "f64", nrhs))
+    for r in range(nrhs):
+        single = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi[r])), 1)))
+        assert np.array_equal(multi[r], single)
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 4, 10)])
+def test_operators_match_oracle(L):
+    say("operators", L)
+    kappa = 0.155
+    lat, U = make_lattice(L)
+    e = half_noise(L, 41)
+    eb = lat.import_spinor(torch.from_numpy(e))
+    got = to_np(lat.export_spinor(lat.apply_K(eb, kappa, "MHAT")))
+    assert rel(got, ow.Mhat(U, e, L, kappa)) <= 1e-12
+    got = to_np(lat.export_spinor(lat.apply_K(eb, kappa, "MHAT_DAG")))
+    assert rel(got, ow.Mhat(U, e, L, kappa, dagger=True)) <= 1e-12
+    for mu2 in (0.0, 0.05):
+        got = to_np(lat.export_spinor(lat.apply_K(eb, kappa, "J", mu2=[mu2])))
+        assert rel(got, ow.J(U, e, L, kappa, mu2)) <= 1e-12
+    f = full_noise(L, 42)
+    fb = lat.import_full(torch.from_numpy(f))
+    assert rel(to_np(lat.export_full(lat.apply_K(fb, 0.12, "M"))), ow.M(U, f, L, 0.12)) <= 1e-12
+    assert rel(to_np(lat.export_full(lat.apply_K(fb, 0.12, "MDAG"))), ow.M(U, f, L, 0.12, dagger=True)) <= 1e-12
+    assert rel(to_np(lat.export_full(lat.apply_K(fb, 0.12, "K"))), ow.K(U, f, L, 0.12)) <= 1e-12
+
+
+def test_shifted_operator_batch_per_rhs_shift():
+    L = (6, 4, 4, 10)
+    say("J batch with per-rhs shifts")
+    lat, U = make_lattice(L)
+    mu2 = [0.0, 0.005, 0.05, 0.5]
+    e = half_noise(L, 51, nrhs=4)
+    got = to_np(lat.export_spinor(lat.apply_K(lat.import_spinor(torch.from_numpy(e)), 0.155, "J", mu2=mu2, nrhs=4),
+                                  "f64", 4))
+    for r in range(4):
+        assert rel(got[r], ow.J(U, e[r], L, 0.155, mu2[r])) <= 1e-12
+
+
+def test_errors_are_reported():
+    need_gpu()
+    from paper_1702_00124_amd import WilsonError
+    from paper_1702_00124_amd.lattice import WilsonLattice
+    with pytest.raises(WilsonError):
+        WilsonLattice((5, 4, 4, 4))
+    lat, _ = make_lattice((4, 4, 4, 4))
+    b = lat.new_field()
+    with pytest.raises(WilsonError):
+        lat.dslash(b, 0, nrhs=17)
+    with pytest.raises(WilsonError):
+        lat.apply_K(b, 0.1, "J", out=b)

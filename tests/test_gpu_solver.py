@@ -1,0 +1,80 @@
+"""GPU parity: CG (FP64, mixed precision, batched, graph-captured) against the FP64 oracle.
+
+Protocol (solutions are only tolerance-accurate): both sides solve to a
+relative true residual tol; the difference of solutions is bounded by
+cond(A) * (r_gpu + r_cpu) <= cond * 2 tol.  With cond(K) < 100 on these
+lattices, tol = 1e-12 gives <= 2e-10, asserted as 1e-9.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import solver as osol, wilson as ow
+from paper_1702_00124_amd.lattice import CG
+from tests.gpu_common import full_noise, half_noise, make_lattice, need_gpu, rel, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def test_cg_full_lattice_small_workload():
+    """4^4, kappa = 0.12, full K = M^dag M, FP64 (the small two-flavour workload)."""
+    L, kappa = (4, 4, 4, 4), 0.12
+    say("cg full K", L)
+    lat, U = make_lattice(L, a=0.3, seed=1001)
+    b = full_noise(L, 2001)
+    x, st, rc = lat.cg_solve(lat.import_full(torch.from_numpy(b)), kappa, "K", params=CG(tol=1e-12))
+    assert rc == 0 and st[0].converged and st[0].true_rel_res <= 1e-12
+    xg = to_np(lat.export_full(x))
+    xr, _, _ = osol.cg(lambda v: ow.K(U, v, L, kappa), b, tol=1e-12)
+    assert rel(xg, xr) <= 1e-9
+    assert rel(ow.K(U, xg, L, kappa), b) <= 1e-11
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_cg_even_odd_precisions(inner, graph):
+    L, kappa, mu2 = (8, 8, 8, 8), 0.155, 0.0
+    say("cg J", inner, "graph" if graph else "eager")
+    lat, U = make_lattice(L)
+    b = half_noise(L, 2002)
+    x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), kappa, "J", mu2=[mu2],
+                             params=CG(tol=1e-10, inner=inner, use_graph=graph))
+    say(f"  iters {st[0].iters} reliable {st[0].reliable_updates} true res {st[0].true_rel_res:.2e}")
+    assert rc == 0 and st[0].converged and st[0].true_rel_res <= 1e-10
+    xg = to_np(lat.export_spinor(x))
+    assert rel(ow.J(U, xg, L, kappa, mu2), b) <= 1e-10 * 1.01
+    xr, _, _ = osol.cg(lambda v: ow.J(U, v, L, kappa, mu2), b, tol=1e-10)
+    assert rel(xg, xr) <= 200 * 2e-10
+
+
+def test_cg_batched_shifts_match_single():
+    """8 rhs, rhs j with shift mu2[j mod 4] (the batched multi-rhs workload's pairing)."""
+    L, kappa = (6, 4, 4, 10), 0.155
+    mu2 = [0.0, 0.005, 0.05, 0.5] * 2
+    say("cg batched 8 rhs")
+    lat, U = make_lattice(L)
+    b = half_noise(L, 2010, nrhs=8)
+    for inner in ("f64", "f32"):
+        x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), kappa, "J", mu2=mu2, nrhs=8,
+                                 params=CG(tol=1e-10, inner=inner, use_graph=True))
+        assert rc == 0
+        xg = to_np(lat.export_spinor(x, "f64", 8))
+        for j in range(8):
+            assert st[j].converged and st[j].true_rel_res <= 1e-10
+            assert rel(ow.J(U, xg[j], L, kappa, mu2[j]), b[j]) <= 1.01e-10
+        its = [s.iters for s in st]
+        say(f"  {inner}: iterations per rhs {its}")
+        # heavier shifts converge faster
+        assert its[3] < its[0]
+
+
+def test_cg_nonconvergence_and_zero_rhs():
+    L = (4, 4, 4, 4)
+    say("cg edge cases")
+    lat, U = make_lattice(L)
+    b = half_noise(L, 3)
+    x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), 0.155, "J", params=CG(tol=1e-10, maxiter=1, chunk=1))
+    assert rc == -5 and not st[0].converged and st[0].iters == 1
+    z = np.zeros_like(b)
+    x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(z)), 0.155, "J")
+    assert rc == 0 and st[0].iters == 0 and np.abs(to_np(lat.export_spinor(x))).max() == 0.0
