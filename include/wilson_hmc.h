@@ -198,8 +198,9 @@ int wl_link_update(wl_lattice* lat, const double* P, double eps);
  * fields back to back (each a FULL field for KINV_FULL, else a half field).
  * u_metropolis: caller's uniform in [0,1); accept iff u < exp(-dH).  On
  * rejection the links are restored.  flags: WL_HMC_NO_METROPOLIS always keeps
- * the end point (reversibility tests). */
-enum { WL_HMC_NO_METROPOLIS = 1 };
+ * the end point; WL_HMC_PHI_GIVEN takes chi as the pseudofermions themselves
+ * and skips the heatbath (both for reversibility tests). */
+enum { WL_HMC_NO_METROPOLIS = 1, WL_HMC_PHI_GIVEN = 2 };
 enum { WL_INT_LEAPFROG = 0, WL_INT_OMELYAN = 1 };
 
 typedef struct {
@@ -227,6 +228,16 @@ int hmc_trajectory(wl_lattice* lat, const wl_hmc_params* params, double* P, cons
 
 /* Counters: hop applications and K applications since create (single rhs units). */
 int wl_counters(const wl_lattice* lat, long long* n_hop, long long* n_kmat);
+/* Hop applications since create per storage precision (counts[wl_prec], single rhs units). */
+int wl_hop_counts(const wl_lattice* lat, long long* counts);
+
+/* Tracing: wl_profile(lat, 1) clears and starts HIP-event timing of sampled
+ * single-rhs hop launches (at most 4096 per storage precision, none inside a
+ * graph capture); wl_profile_read() synchronises and returns the average
+ * launch duration in microseconds and the sample count per precision
+ * (index = wl_prec).  wl_profile(lat, 0) stops and clears. */
+int wl_profile(wl_lattice* lat, int enable);
+int wl_profile_read(wl_lattice* lat, double* avg_us, long long* samples);
 
 #ifdef __cplusplus
 }

@@ -83,14 +83,49 @@ def _project_su3(u: np.ndarray) -> np.ndarray:
     return np.stack([r1, r2, r3], axis=1)
 
 
+def _expi_hermitian(h: np.ndarray, a: float) -> np.ndarray:
+    """exp(i a H) for a stack of traceless Hermitian 3x3 matrices [N, 3, 3].
+
+    Eigenvalues from the trigonometric solution of l^3 - p l - q = 0
+    (p = tr H^2 / 2, q = det H), then Lagrange interpolation on them:
+    exp(i a H) = sum_k e^{i a l_k} prod_{j != k} (H - l_j) / (l_k - l_j)
+               = f2 H^2 + f1 H + f0 1.
+    Vectorised over N with one batched product (H^2); eigenvalue gaps of
+    Gaussian Hermitian matrices are repelled, so the divisions are benign.
+    """
+    H = np.moveaxis(h, 0, -1)                      # [3, 3, N]
+    H2 = np.empty_like(H)
+    for i in range(3):
+        for k in range(3):
+            H2[i, k] = H[i, 0] * H[0, k] + H[i, 1] * H[1, k] + H[i, 2] * H[2, k]
+    p = 0.5 * (H2[0, 0] + H2[1, 1] + H2[2, 2]).real
+    q = (H[0, 0] * (H[1, 1] * H[2, 2] - H[1, 2] * H[2, 1])
+         - H[0, 1] * (H[1, 0] * H[2, 2] - H[1, 2] * H[2, 0])
+         + H[0, 2] * (H[1, 0] * H[2, 1] - H[1, 1] * H[2, 0])).real
+    r = np.sqrt(np.maximum(p, 1e-300) / 3.0)
+    th = np.arccos(np.clip(q / (2.0 * r ** 3), -1.0, 1.0))
+    lam = [2.0 * r * np.cos((th - 2.0 * np.pi * k) / 3.0) for k in range(3)]
+    f0 = np.zeros(H.shape[-1], dtype=np.complex128)
+    f1 = np.zeros_like(f0)
+    f2 = np.zeros_like(f0)
+    for k in range(3):
+        j, l = (k + 1) % 3, (k + 2) % 3
+        w = np.exp(1j * a * lam[k]) / ((lam[k] - lam[j]) * (lam[k] - lam[l]))
+        f2 += w
+        f1 -= w * (lam[j] + lam[l])
+        f0 += w * (lam[j] * lam[l])
+    U = f2 * H2 + f1 * H
+    for i in range(3):
+        U[i, i] += f0
+    return np.moveaxis(U, -1, 0)
+
+
 def random_links(L, a: float, seed: int) -> np.ndarray:
     """U_mu(x) = SU(3)-projected exp(i a H), H Gaussian traceless Hermitian."""
     V = volume(L)
     rng = np.random.default_rng(seed)
     h = _gaussian_traceless_hermitian(rng, 4 * V)
-    w, vec = np.linalg.eigh(h)
-    u = np.einsum("nij,nj,nkj->nik", vec, np.exp(1j * a * w), np.conj(vec))
-    u = _project_su3(u)
+    u = _project_su3(np.ascontiguousarray(_expi_hermitian(h, a)))
     return np.ascontiguousarray(u.reshape(4, V, 3, 3))
 
 

@@ -15,7 +15,7 @@ WL_F64, WL_F32, WL_BF16 = 0, 1, 2
 WL_OP_M, WL_OP_MDAG, WL_OP_K, WL_OP_MHAT, WL_OP_MHAT_DAG, WL_OP_J = range(6)
 WL_POLY_P, WL_POLY_PJ, WL_POLY_Q, WL_POLY_QDAG = range(4)
 WL_TERM_KINV_FULL, WL_TERM_KINV, WL_TERM_RATIO, WL_TERM_POLY, WL_TERM_POLYK_INV = range(5)
-WL_HMC_NO_METROPOLIS = 1
+WL_HMC_NO_METROPOLIS, WL_HMC_PHI_GIVEN = 1, 2
 WL_INT_LEAPFROG, WL_INT_OMELYAN = 0, 1
 
 
@@ -78,6 +78,9 @@ SIGNATURES = {
     "wl_link_update": (I, [P, P, D]),
     "hmc_trajectory": (I, [P, C.POINTER(HmcParams), P, P, D, C.POINTER(HmcResult)]),
     "wl_counters": (I, [P, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+    "wl_profile": (I, [P, I]),
+    "wl_hop_counts": (I, [P, C.POINTER(C.c_longlong)]),
+    "wl_profile_read": (I, [P, C.POINTER(D), C.POINTER(C.c_longlong)]),
 }
 
 _lib = None

@@ -170,7 +170,10 @@ __global__ __launch_bounds__(kBlock) void cg_alpha_kernel(const double* partials
   if (threadIdx.x == 0) {
     st[CG_PAP * kMaxRhs + r] = pAp;
     const bool done = st[CG_DONE * kMaxRhs + r] != 0.0;
-    st[CG_ALPHA * kMaxRhs + r] = done ? 0.0 : st[CG_RR * kMaxRhs + r] / pAp;
+    // breakdown guard: A is HPD, so <p, A p> must be positive and finite
+    const bool ok = pAp > 0.0 && pAp < 1e300;
+    if (!done && !ok) st[CG_BREAK * kMaxRhs + r] = 1.0;
+    st[CG_ALPHA * kMaxRhs + r] = (done || !ok || st[CG_BREAK * kMaxRhs + r] != 0.0) ? 0.0 : st[CG_RR * kMaxRhs + r] / pAp;
   }
 }
 
@@ -179,7 +182,10 @@ __global__ __launch_bounds__(kBlock) void cg_beta_kernel(const double* partials,
   const int r = blockIdx.x;
   const double rr_new = row_sum(partials, stride, nb, r, lds);
   if (threadIdx.x == 0) {
-    if (st[CG_DONE * kMaxRhs + r] == 0.0) {
+    if (!(rr_new < 1e300)) st[CG_BREAK * kMaxRhs + r] = 1.0;  // also catches NaN
+    if (st[CG_BREAK * kMaxRhs + r] != 0.0) {
+      st[CG_BETA * kMaxRhs + r] = 0.0;  // frozen until the host restarts it
+    } else if (st[CG_DONE * kMaxRhs + r] == 0.0) {
       const double rr = st[CG_RR * kMaxRhs + r];
       st[CG_BETA * kMaxRhs + r] = rr_new / rr;
       st[CG_RR * kMaxRhs + r] = rr_new;

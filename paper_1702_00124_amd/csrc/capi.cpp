@@ -137,6 +137,8 @@ int wl_destroy(wl_lattice* L) {
   if (L->dscal) (void)hipFree(L->dscal);
   if (L->hscal) (void)hipHostFree(L->hscal);
   if (L->capture_stream) (void)hipStreamDestroy(L->capture_stream);
+  for (int p = 0; p < 3; ++p)
+    for (hipEvent_t e : L->prof_ev[p]) (void)hipEventDestroy(e);
   delete L;
   return WL_OK;
 }
@@ -376,6 +378,53 @@ int hmc_trajectory(wl_lattice* L, const wl_hmc_params* params, double* P, const 
     WL_REQUIRE(params && P && (chi || params->nterms == 0), WL_EINVAL, "null argument");
     set_device(L);
     return hmc_run(L, *params, P, chi, u, result);
+  });
+}
+
+int wl_profile(wl_lattice* L, int enable) {
+  return guard([&]() {
+    check_lat(L);
+    WL_HIP(hipStreamSynchronize(L->stream));
+    for (int p = 0; p < 3; ++p) {
+      for (hipEvent_t e : L->prof_ev[p]) WL_HIP(hipEventDestroy(e));
+      L->prof_ev[p].clear();
+      L->prof_ms[p] = 0.0;
+      L->prof_n[p] = 0;
+    }
+    L->prof_on = enable ? 1 : 0;
+    return WL_OK;
+  });
+}
+
+int wl_profile_read(wl_lattice* L, double* avg_us /*[3]*/, long long* samples /*[3]*/) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(avg_us && samples, WL_EINVAL, "null argument");
+    WL_HIP(hipStreamSynchronize(L->stream));
+    for (int p = 0; p < 3; ++p) {
+      auto& ev = L->prof_ev[p];
+      for (size_t k = 0; k + 1 < ev.size(); k += 2) {
+        float ms = 0.f;
+        WL_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+        L->prof_ms[p] += ms;
+        L->prof_n[p] += 1;
+        WL_HIP(hipEventDestroy(ev[k]));
+        WL_HIP(hipEventDestroy(ev[k + 1]));
+      }
+      ev.clear();
+      samples[p] = L->prof_n[p];
+      avg_us[p] = L->prof_n[p] ? 1e3 * L->prof_ms[p] / L->prof_n[p] : 0.0;
+    }
+    return WL_OK;
+  });
+}
+
+int wl_hop_counts(const wl_lattice* L, long long* counts) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(counts, WL_EINVAL, "null argument");
+    for (int p = 0; p < 3; ++p) counts[p] = L->n_hop_p[p];
+    return WL_OK;
   });
 }
 

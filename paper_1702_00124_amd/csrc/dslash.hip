@@ -198,13 +198,27 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
   a.part_off = e.part_off;
   a.use_xcd = L->use_xcd;
   const int nb = hop_grid_blocks(L);
+  // sampled event timing (never inside a graph capture)
+  const bool timed = L->prof_on && !L->prof_capturing && nrhs == 1 && L->prof_ev[prec].size() < 2 * kProfPairs;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    WL_HIP(hipEventCreate(&e0));
+    WL_HIP(hipEventCreate(&e1));
+    WL_HIP(hipEventRecord(e0, L->stream));
+  }
   switch (prec) {
     case F64: dispatch<PrecF64>(a, dagger, nrhs, L->stream, nb); break;
     case F32: dispatch<PrecF32>(a, dagger, nrhs, L->stream, nb); break;
     case BF16: dispatch<PrecBF16>(a, dagger, nrhs, L->stream, nb); break;
   }
   WL_HIP(hipGetLastError());
+  if (timed) {
+    WL_HIP(hipEventRecord(e1, L->stream));
+    L->prof_ev[prec].push_back(e0);
+    L->prof_ev[prec].push_back(e1);
+  }
   L->n_hop += nrhs;
+  L->n_hop_p[prec] += nrhs;
 }
 
 }  // namespace wl

@@ -115,7 +115,8 @@ int hmc_run(wl_lattice* L, const wl_hmc_params& prm, double* P, const void* chi,
   for (int i = 0; i < nt; ++i) {
     const size_t fb = (prm.terms[i].kind == WL_TERM_KINV_FULL ? 2 : 1) * hb;
     phi[i] = ws_get(L, "hmc_phi" + std::to_string(i), fb);
-    term_heatbath(L, prm.terms[i], phi[i], c);
+    if (prm.flags & WL_HMC_PHI_GIVEN) copy_dev(L, phi[i], c, fb);
+    else term_heatbath(L, prm.terms[i], phi[i], c);
     c += fb;
   }
 

@@ -125,6 +125,7 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   };
 
   CgGraph cg_graph;
+  long long hops_per_chunk = 0, hops_p_chunk[3] = {0, 0, 0};
   int chunks = 0;
   int reliable = 0;
   bool all_verified = false;
@@ -134,7 +135,10 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
       if (!cg_graph.exec) {
         if (!L->capture_stream) WL_HIP(hipStreamCreateWithFlags(&L->capture_stream, hipStreamNonBlocking));
         hipStream_t keep = L->stream;
+        const long long hop0 = L->n_hop;
+        const long long hp0[3] = {L->n_hop_p[0], L->n_hop_p[1], L->n_hop_p[2]};
         L->stream = L->capture_stream;
+        L->prof_capturing = 1;
         WL_HIP(hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
         try {
           issue_chunk();
@@ -142,36 +146,50 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
           hipGraph_t g;
           (void)hipStreamEndCapture(L->stream, &g);
           L->stream = keep;
+          L->prof_capturing = 0;
           throw;
         }
         WL_HIP(hipStreamEndCapture(L->stream, &cg_graph.graph));
         L->stream = keep;
+        L->prof_capturing = 0;
+        hops_per_chunk = L->n_hop - hop0;
+        L->n_hop = hop0;  // capture executes nothing; replays are counted below
+        for (int q = 0; q < 3; ++q) {
+          hops_p_chunk[q] = L->n_hop_p[q] - hp0[q];
+          L->n_hop_p[q] = hp0[q];
+        }
         WL_HIP(hipGraphInstantiate(&cg_graph.exec, cg_graph.graph, nullptr, nullptr, 0));
       }
       WL_HIP(hipGraphLaunch(cg_graph.exec, L->stream));
+      L->n_hop += hops_per_chunk;
+      for (int q = 0; q < 3; ++q) L->n_hop_p[q] += hops_p_chunk[q];
     } else {
       issue_chunk();
     }
     ++chunks;
     pull_state();
 
-    bool all_done = true, need_ru = false;
+    bool all_done = true, need_ru = false, broke = false;
     for (int i = 0; i < nrhs; ++i) {
       if (verified[i]) continue;
       if (S(CG_DONE, i) == 0.0) all_done = false;
       if (S(CG_DONE, i) != 0.0 || S(CG_RR, i) < delta * delta * S(CG_MAXRR, i)) need_ru = true;
+      if (S(CG_BREAK, i) != 0.0) broke = true;
     }
     int max_it = 0;
     for (int i = 0; i < nrhs; ++i) max_it = std::max(max_it, int(S(CG_ITERS, i)));
 
-    if ((mixed && need_ru) || (!mixed && all_done)) {
+    if ((mixed && need_ru) || (!mixed && all_done) || broke) {
       true_residual();
       if (mixed) launch_convert(L, ip, r, F64, r64, nrhs * nh);
       ++reliable;
-      bool restart = false;
+      // BF16 storage (and any breakdown) restarts the Krylov space from the
+      // fresh residual (restarted defect correction); FP32 keeps p
+      bool restart = broke || ip == BF16;
       for (int i = 0; i < nrhs; ++i) {
         if (verified[i]) continue;
         const double t2 = prm.tol * prm.tol * bb[i];
+        S(CG_BREAK, i) = 0.0;
         if (rr_true[i] <= t2) {
           S(CG_DONE, i) = 1.0;
           verified[i] = 1;
@@ -186,9 +204,11 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
           S(CG_MAXRR, i) = rr_true[i];
         }
       }
-      if (!mixed && restart) {
-        copy_dev(L, r, r64, fb64);
+      if (restart) {
+        if (!mixed) copy_dev(L, r, r64, fb64);
         copy_dev(L, p, r, fbi);
+        for (int i = 0; i < nrhs; ++i)
+          if (!verified[i]) S(CG_RR, i) = rr_true[i];
       }
       push_state();
     }

@@ -18,6 +18,7 @@ constexpr int kMaxRhs = 16;
 constexpr int kBlock = 256;  // threads per workgroup of the site kernels
 constexpr int kScal = 2048;  // device scalar slots; the CG state starts at kCgState
 constexpr int kCgState = 1024;
+constexpr int kProfPairs = 4096;  // sampled hop launches timed per precision
 
 enum Prec { F64 = WL_F64, F32 = WL_F32, BF16 = WL_BF16 };
 
@@ -63,9 +64,16 @@ struct wl_lattice {
   hipStream_t capture_stream = nullptr;      // side stream for hipGraph capture
   std::map<std::string, std::pair<void*, size_t>> ws;
   long long n_hop = 0;                       // hop applications (single rhs units)
+  long long n_hop_p[3] = {0, 0, 0};          // ... per storage precision
   long long n_kmat = 0;                      // K-hat / K applications (single rhs units)
   int use_xcd = 1;
   int hop_block = wl::kBlock;
+  // optional event timing of sampled hop launches, per storage precision
+  int prof_on = 0;
+  int prof_capturing = 0;
+  std::vector<hipEvent_t> prof_ev[3];   // start/stop pairs
+  double prof_ms[3] = {0, 0, 0};
+  long long prof_n[3] = {0, 0, 0};
 };
 
 namespace wl {

@@ -13,7 +13,8 @@ enum CgStateRow {
   CG_ITERS = 6,
   CG_TOL2 = 7,
   CG_MAXRR = 8,  // largest |r|^2 since the last reliable update
-  CG_NROWS = 9
+  CG_BREAK = 9,  // set when <p, A p> or |r|^2 is not a positive finite number
+  CG_NROWS = 10
 };
 
 }  // namespace wl

@@ -284,7 +284,8 @@ class WilsonLattice:
 
     def hmc_trajectory(self, terms: List[Term], nsteps: Sequence[int], P: torch.Tensor, chi: torch.Tensor,
                        u: float, beta: float = 5.6, tau: float = 1.0, integrator: str = "omelyan",
-                       no_metropolis: bool = False, omelyan_lambda: float = 0.0) -> W.HmcResult:
+                       no_metropolis: bool = False, omelyan_lambda: float = 0.0,
+                       phi_given: bool = False) -> W.HmcResult:
         prm = W.HmcParams()
         prm.beta, prm.tau, prm.omelyan_lambda = beta, tau, omelyan_lambda
         prm.integrator = W.WL_INT_OMELYAN if integrator == "omelyan" else W.WL_INT_LEAPFROG
@@ -293,12 +294,28 @@ class WilsonLattice:
             prm.terms[i] = t.c()
         for i, n in enumerate(nsteps):
             prm.nsteps[i] = int(n)
-        prm.flags = W.WL_HMC_NO_METROPOLIS if no_metropolis else 0
+        prm.flags = (W.WL_HMC_NO_METROPOLIS if no_metropolis else 0) | (W.WL_HMC_PHI_GIVEN if phi_given else 0)
         _need(P, 256 * self.V, "momenta")
         _need(chi, sum(self.field_bytes("f64") * (2 if t.full else 1) for t in terms), "noise")
         res = W.HmcResult()
         W.check(self.lib.hmc_trajectory(self.h, C.byref(prm), _ptr(P), _ptr(chi), u, C.byref(res)))
         return res
+
+    def profile(self, enable: bool = True):
+        W.check(self.lib.wl_profile(self.h, int(enable)))
+
+    def profile_read(self):
+        """{prec: (average hop launch duration in us, samples)} of the sampled launches."""
+        us = (C.c_double * 3)()
+        n = (C.c_longlong * 3)()
+        W.check(self.lib.wl_profile_read(self.h, us, n))
+        return {name: (us[i], n[i]) for name, i in PREC.items()}
+
+    def hop_counts(self):
+        """{prec: hop applications since create} (single-rhs units)."""
+        n = (C.c_longlong * 3)()
+        W.check(self.lib.wl_hop_counts(self.h, n))
+        return {name: n[i] for name, i in PREC.items()}
 
     def counters(self):
         a, b = C.c_longlong(), C.c_longlong()

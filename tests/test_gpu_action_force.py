@@ -1,0 +1,196 @@
+"""GPU parity: polynomial filter, action terms (heatbath, value, force), gauge and
+link kernels, and the HMC trajectory, against the FP64 oracle.
+
+Deterministic operator chains (polynomial, bilinear, gauge force, link
+update) meet the FP64 bar 1e-12.  Results that go through a solve are
+compared at solver tolerance 1e-13 on both sides (error <= cond * 2e-13 with
+cond < 100 here), asserted at 1e-9 / 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+from oracle import action as oact, force as oforce, gauge as ogauge, hmc as ohmc
+from oracle import lattice as olat, poly as opoly, su3 as osu3, wilson as ow
+from paper_1702_00124_amd.lattice import CG, Term
+from tests.gpu_common import full_noise, half_noise, make_lattice, need_gpu, rel, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+L4 = (4, 4, 4, 4)
+KAPPA, MU2 = 0.155, 0.05
+
+
+@pytest.mark.parametrize("mode", ["P", "PJ", "Q", "QDAG"])
+@pytest.mark.parametrize("n", [4, 16])
+def test_poly_filter_matches_oracle(mode, n):
+    say("poly", mode, n)
+    lat, U = make_lattice(L4)
+    psi = half_noise(L4, 61)
+    got = to_np(lat.export_spinor(lat.poly_filter_apply(lat.import_spinor(torch.from_numpy(psi)), KAPPA, MU2, n,
+                                                        0.001, 8.0, mode)))
+    J = lambda v: ow.J(U, v, L4, KAPPA, MU2)
+    ref = {"P": lambda: opoly.apply_P(J, psi, n, 0.001, 8.0),
+           "PJ": lambda: opoly.apply_PJ(J, psi, n, 0.001, 8.0),
+           "Q": lambda: opoly.apply_Q(J, psi, n, 0.001, 8.0),
+           "QDAG": lambda: opoly.apply_Q(J, psi, n, 0.001, 8.0, dagger=True)}[mode]()
+    assert rel(got, ref) <= 1e-12
+
+
+def test_bilinear_primitive_matches_oracle():
+    L = (6, 4, 4, 10)
+    say("bilinear", L)
+    lat, U = make_lattice(L)
+    A, Cf = full_noise(L, 71), full_noise(L, 72)
+    F = lat.force_bilinear(lat.import_full(torch.from_numpy(A)), lat.import_full(torch.from_numpy(Cf)))
+    assert rel(to_np(lat.export_su3(F)), oforce.bilinear_grad(U, A, Cf, L, -1)) <= 1e-12
+
+
+def test_gauge_kernels_match_oracle():
+    L = (6, 4, 4, 10)
+    say("gauge force / plaquette / link update", L)
+    lat, U = make_lattice(L)
+    assert abs(lat.plaquette() - ogauge.mean_plaquette(U, L)) <= 1e-14
+    F = lat.gauge_force(5.6)
+    assert rel(to_np(lat.export_su3(F)), ogauge.force(U, L, 5.6)) <= 1e-12
+    p = li.gaussian_momenta(L, 5)
+    lat.link_update(lat.import_su3(torch.from_numpy(p)), 0.07)
+    ref = osu3.reunitarize(np.einsum("mxab,mxbc->mxac", osu3.expi(0.07, osu3.coeffs_to_matrix(p)), U))
+    got = to_np(lat.get_links())
+    assert np.abs(got - ref).max() <= 1e-13
+    # SU(3) to rounding
+    assert np.abs(np.einsum("mxab,mxcb->mxac", got, got.conj()) - np.eye(3)).max() < 1e-14
+
+
+def _term(kind, n=4):
+    if kind == "KINV_FULL":
+        return Term("KINV_FULL", 0.12, cg=CG(tol=1e-13)), oact.Term("KINV_FULL", 0.12, tol=1e-13)
+    return (Term(kind, KAPPA, mu2=MU2, degree=n, cg=CG(tol=1e-13)),
+            oact.Term(kind, KAPPA, mu2=MU2, n=n, tol=1e-13))
+
+
+@pytest.mark.parametrize("kind", ["KINV_FULL", "KINV", "RATIO", "POLY", "POLYK_INV"])
+def test_term_heatbath_action_force_match_oracle(kind):
+    say("term", kind)
+    a = 0.3 if kind == "KINV_FULL" else 0.447
+    lat, U = make_lattice(L4, a=a)
+    gt, ot = _term(kind)
+    full = kind == "KINV_FULL"
+    chi = full_noise(L4, 3001) if full else half_noise(L4, 3001)
+    imp = (lambda x: lat.import_full(torch.from_numpy(x))) if full else (lambda x: lat.import_spinor(torch.from_numpy(x)))
+    exp = (lambda b: to_np(lat.export_full(b))) if full else (lambda b: to_np(lat.export_spinor(b)))
+    ops = oact.Ops(U, L4)
+    # heatbath
+    phi_g = lat.heatbath(gt, imp(chi))
+    phi_r = oact.heatbath(ops, ot, chi)
+    assert rel(exp(phi_g), phi_r) <= 1e-10
+    # action at the same phi (the oracle's), and S = chi^dag chi after the heatbath
+    phi_b = imp(phi_r)
+    S_g = lat.action(gt, phi_b)
+    S_r = oact.action(ops, ot, phi_r)
+    assert abs(S_g - S_r) <= 1e-10 * abs(S_r)
+    assert abs(lat.action(gt, phi_g) - np.vdot(chi, chi).real) <= 1e-9 * abs(S_r)
+    # force
+    F = to_np(lat.export_su3(lat.fermion_force(gt, phi_b)))
+    Fr = oact.force(ops, ot, phi_r)
+    e = rel(F, Fr)
+    say(f"  force relative error {e:.2e}")
+    assert e <= 1e-9
+
+
+def test_poly_force_order16():
+    say("POLY / POLYK_INV force at order 16")
+    lat, U = make_lattice(L4)
+    ops = oact.Ops(U, L4)
+    phi = half_noise(L4, 3003)
+    for kind in ("POLY", "POLYK_INV"):
+        gt, ot = _term(kind, n=16)
+        F = to_np(lat.export_su3(lat.fermion_force(gt, lat.import_spinor(torch.from_numpy(phi)))))
+        assert rel(F, oact.force(ops, ot, phi)) <= 1e-9
+
+
+def _hmc_setup(scale=1):
+    terms_g = [Term("POLY", KAPPA, mu2=MU2, degree=4, cg=CG(tol=1e-13)),
+               Term("POLYK_INV", KAPPA, mu2=MU2, degree=4, cg=CG(tol=1e-13)),
+               Term("RATIO", KAPPA, mu2=MU2, cg=CG(tol=1e-13))]
+    terms_o = [oact.Term("POLY", KAPPA, mu2=MU2, n=4, tol=1e-13),
+               oact.Term("POLYK_INV", KAPPA, mu2=MU2, n=4, tol=1e-13),
+               oact.Term("RATIO", KAPPA, mu2=MU2, tol=1e-13)]
+    nsteps = [2 * scale, 1 * scale, 1 * scale, 3 * scale]
+    return terms_g, terms_o, nsteps
+
+
+def test_hmc_trajectory_matches_oracle():
+    say("hmc trajectory 4^4 vs oracle")
+    lat, U = make_lattice(L4)
+    terms_g, terms_o, nsteps = _hmc_setup()
+    P = li.gaussian_momenta(L4, li.seed_md(0, 15))
+    Vh = li.volume(L4) // 2
+    chis = [li.gaussian_spinor((Vh, 4, 3), li.seed_md(0, i)) for i in range(3)]
+    chi_b = torch.cat([lat.import_spinor(torch.from_numpy(c)) for c in chis])
+    Pb = lat.import_su3(torch.from_numpy(P))
+    res = lat.hmc_trajectory(terms_g, nsteps, Pb, chi_b, 0.5, beta=5.6, tau=0.2, integrator="omelyan",
+                             no_metropolis=True)
+    prm = ohmc.HMCParams(terms=terms_o, beta=5.6, nsteps=nsteps, scheme="omelyan", tau=0.2)
+    r = ohmc.trajectory(U, P, L4, prm, chis, 0.5)
+    say(f"  dH gpu {res.dH:.10f} oracle {r.dH:.10f}; n_kmat {res.n_kmat}")
+    assert abs(res.H0 - r.H0) <= 1e-9 * abs(r.H0)
+    assert abs(res.dH - r.dH) <= 1e-7
+    assert rel(to_np(lat.get_links()), r.U) <= 1e-10
+    assert rel(to_np(lat.export_su3(Pb)), r.P) <= 1e-9
+    assert res.n_kmat > 0
+
+
+def test_hmc_reversibility_on_gpu():
+    """Integrate, flip P, integrate with the same pseudofermions: back to the start."""
+    say("hmc reversibility")
+    L = (6, 4, 4, 10)
+    lat, U = make_lattice(L)
+    terms_g, _, nsteps = _hmc_setup()
+    Vh = li.volume(L) // 2
+    chis = [li.gaussian_spinor((Vh, 4, 3), li.seed_md(1, i)) for i in range(3)]
+    phis = torch.cat([lat.heatbath(t, lat.import_spinor(torch.from_numpy(c))) for t, c in zip(terms_g, chis)])
+    P0 = li.gaussian_momenta(L, li.seed_md(1, 15))
+    Pb = lat.import_su3(torch.from_numpy(P0))
+    lat.hmc_trajectory(terms_g, nsteps, Pb, phis, 0.0, tau=0.3, no_metropolis=True, phi_given=True)
+    Pb.neg_()
+    lat.hmc_trajectory(terms_g, nsteps, Pb, phis, 0.0, tau=0.3, no_metropolis=True, phi_given=True)
+    dU = np.abs(to_np(lat.get_links()) - U).max()
+    dP = np.abs(to_np(lat.export_su3(Pb)) + P0).max()
+    say(f"  max |dU| {dU:.2e}  max |dP| {dP:.2e}")
+    assert dU < 1e-11 and dP < 1e-9
+
+
+def test_hmc_energy_violation_scales_as_step_squared():
+    """dH(h) / dH(h/2) -> 4 for the second-order scheme.  Coarser steps
+    (scales 1, 2) are outside the asymptotic regime on these synthetic links;
+    the oracle gives the same dH there (-4.7608, -9.4356)."""
+    say("hmc dH ~ eps^2")
+    L = (6, 4, 4, 10)
+    dh = []
+    for k in (4, 8):
+        lat, U = make_lattice(L)
+        terms_g, _, nsteps = _hmc_setup(scale=k)
+        Vh = li.volume(L) // 2
+        chi = torch.cat([lat.import_spinor(torch.from_numpy(li.gaussian_spinor((Vh, 4, 3), li.seed_md(2, i))))
+                         for i in range(3)])
+        Pb = lat.import_su3(torch.from_numpy(li.gaussian_momenta(L, li.seed_md(2, 15))))
+        res = lat.hmc_trajectory(terms_g, nsteps, Pb, chi, 0.0, tau=0.3, integrator="leapfrog", no_metropolis=True)
+        dh.append(res.dH)
+    say(f"  dH {dh}")
+    assert 3.0 < dh[0] / dh[1] < 5.0
+
+
+def test_hmc_rejection_restores_links():
+    say("hmc rejection")
+    lat, U = make_lattice(L4)
+    terms_g, _, nsteps = _hmc_setup()
+    Vh = li.volume(L4) // 2
+    chi = torch.cat([lat.import_spinor(torch.from_numpy(li.gaussian_spinor((Vh, 4, 3), 9 + i))) for i in range(3)])
+    Pb = lat.import_su3(torch.from_numpy(li.gaussian_momenta(L4, 8)))
+    res = lat.hmc_trajectory(terms_g, nsteps, Pb, chi, 1.0 - 1e-16, tau=0.5)   # u ~ 1: reject unless dH < 0
+    if not res.accepted:
+        assert np.array_equal(to_np(lat.get_links()), U)
+    else:
+        assert res.dH <= 0
