@@ -49,6 +49,25 @@ SHIFTS = [0.0, 0.005, 0.05, 0.5, 0.0, 0.005, 0.05, 0.5]
 HOP_BYTES_PER_SITE = {"f64": 8 * 144 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8 * 24 + 2 * 48}
 
 
+# HBM traffic of one hop launch on this workload from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, `bench.py --kernels-only`),
+# scaled by the same counters' reading for a plain 1 GiB device copy
+# (FETCH_SIZE read 524300 KiB -> x2.0; WRITE_SIZE read 1048576 KiB -> x1.0).
+# Valid only for the kernel source they were taken on (hash of the hop
+# kernel sources); otherwise `traffic` is reported as null.
+PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
+PMC_COUNTERS = {"source_sha256": None, "per_launch_kib": {}}
+
+
+def hop_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dslash.hip", "wl_device.h"):
+        with open(os.path.join(ROOT, "paper_1702_00124_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -85,6 +104,30 @@ print(json.dumps({"n": n, "sec_per_hop": dt}))
                       f"({d['sec_per_hop']:.2f} s each, single-threaded NumPy)"}
 
 
+def lat_variant(lat, prec):
+    """Variant the autotuner kept for prec (the faster of its two timings)."""
+    site, dp = lat.last_tune[prec]
+    return 1 if dp <= site else 0
+
+
+def kernels_only(lat, Vh, li, torch):
+    """Hop launches for kernel-trace and counter runs, plus a plain copy of known
+    size whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    psi = li.gaussian_spinor((Vh, 4, 3), li.seed_source(0))
+    for prec in ("f64", "f32"):
+        b = lat.import_spinor(torch.from_numpy(psi), prec)
+        out = lat.new_field(prec)
+        for _ in range(50):
+            lat.dslash(b, 0, prec=prec, out=out)
+    torch.cuda.synchronize()
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("kernels-only done: 50 hop launches f64, 50 f32, 5 copies of 1 GiB")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +135,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--quick", action="store_true", help="skip the CG comparison legs")
+    ap.add_argument("--md-steps", default=",".join(map(str, NSTEPS)),
+                    help="integrator steps per scale (poly, poly-K inverse, ratio, gauge); profiling runs shorten them")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only launch the hop kernels (50 each, FP64 and FP32) and a 1 GiB copy, for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -106,6 +153,8 @@ def main():
 
     torch.cuda.set_device(0)
     Vh = L[0] * L[1] * L[2] * L[3] // 2
+    nsteps = [int(v) for v in args.md_steps.split(",")]
+    assert len(nsteps) == 4
     t0 = time.time()
     U = li.random_links(L, LINK_SPREAD, li.seed_links(1))
     log(f"links generated in {time.time() - t0:.1f}s")
@@ -113,6 +162,12 @@ def main():
     lat.set_links(torch.from_numpy(U))
     plaq0 = lat.plaquette()
     log(f"plaquette {plaq0:.4f}")
+    tune = lat.autotune()
+    lat.last_tune = tune
+    log(f"hop autotune (us per launch, site / direction-parallel): {tune}")
+    if args.kernels_only:
+        kernels_only(lat, Vh, li, torch)
+        return
 
     cg_md = CG(tol=1e-10, inner="f32", chunk=8)
     terms = [Term("POLY", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_md),
@@ -127,7 +182,7 @@ def main():
     torch.cuda.synchronize()
 
     def trajectory(k):
-        return lat.hmc_trajectory(terms, NSTEPS, P[k], chi[k], float(u[k]), beta=BETA, tau=1.0,
+        return lat.hmc_trajectory(terms, nsteps, P[k], chi[k], float(u[k]), beta=BETA, tau=1.0,
                                   integrator="omelyan")
 
     for k in range(args.warmup):
@@ -153,21 +208,30 @@ def main():
     bytes_per_hop = {p: b * Vh for p, b in HOP_BYTES_PER_SITE.items()}
     value = sum(n_hop[p] * bytes_per_hop[p] for p in n_hop) / wall / 1e9
 
-    # roofline of the dominant kernel: the hop launch with the most sampled time
-    dom = max(prof, key=lambda p: prof[p][0] * prof[p][1])
-    avg_us, nsamp = prof[dom]
-    achieved = bytes_per_hop[dom] / (avg_us * 1e-6) / 1e9 if avg_us > 0 else 0.0
+    # roofline of the dominant kernel: the hop precision with the most time in
+    # the timed steps (applications x sampled in-situ duration); its launch
+    # duration is measured on a burst of back-to-back launches with HIP events
+    # on the library's stream (in-situ event pairs add inter-kernel gaps)
+    dom = max(prof, key=lambda p: n_hop[p] * prof[p][0])
+    avg_us = lat.time_hop(dom, 1, 500)
+    achieved = bytes_per_hop[dom] / (avg_us * 1e-6) / 1e9
+    traffic = None
+    kib = PMC_COUNTERS["per_launch_kib"].get(dom)
+    if kib and PMC_COUNTERS["source_sha256"] == hop_source_hash():
+        traffic = int(1024 * (kib["fetch"] * PMC_FETCH_SCALE + kib["write"] * PMC_WRITE_SCALE))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"hop_kernel {dom}", "avg_launch_us": round(avg_us, 2), "samples": nsamp,
-                "algorithmic_bytes_per_launch": bytes_per_hop[dom]}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"hop {dom} ({['thread-per-site', 'direction-parallel'][lat_variant(lat, dom)]})",
+                "avg_launch_us": round(avg_us, 2), "in_situ_avg_us": round(prof[dom][0], 2),
+                "in_situ_samples": prof[dom][1], "algorithmic_bytes_per_launch": bytes_per_hop[dom]}
     extra = {"hop_avg_us": {p: round(v[0], 2) for p, v in prof.items()},
              "hop_gbs": {p: round(bytes_per_hop[p] / (v[0] * 1e-6) / 1e9, 1) if v[0] > 0 else None
                          for p, v in prof.items()},
              "dH": [round(r.dH, 5) for r in results], "accepted": [int(r.accepted) for r in results],
              "n_kmat_per_traj": [int(r.n_kmat) for r in results],
              "cg_iters_per_traj": [int(r.cg_iters) for r in results],
-             "plaquette_start": round(plaq0, 5), "plaquette_end": round(results[-1].plaquette, 5)}
+             "plaquette_start": round(plaq0, 5), "plaquette_end": round(results[-1].plaquette, 5),
+             "hop_autotune_us": {p: [round(v[0], 2), round(v[1], 2)] for p, v in tune.items()}}
 
     if not args.quick:
         # CG time-to-1e-10: FP64 vs mixed single rhs, 8 sequential FP64 vs one batched mixed
@@ -216,7 +280,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer", "data": "synthetic",
         "config": {"workload": "PF-MP HMC trajectory, wilson 16^3x32 kappa=0.155 beta=5.6, "
                                "cheb n=16 [0.001,8], mu2=0.05, omelyan tau=1 steps 40/20/20/80",
-                   "lattice": list(L), "kappa": KAPPA, "link_spread": LINK_SPREAD, "parallelism": "single GPU"},
+                   "lattice": list(L), "kappa": KAPPA, "link_spread": LINK_SPREAD, "md_steps": nsteps,
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "hop_applications": n_hop,
         "extra": extra,

@@ -226,8 +226,30 @@ typedef struct {
 int hmc_trajectory(wl_lattice* lat, const wl_hmc_params* params, double* P, const void* chi,
                    double u_metropolis, wl_hmc_result* result);
 
+/* The overlaid schedule used by hmc_trajectory (Sec. 3.2), host only, no
+ * device needed: nscales schemes with nsteps[i] steps; event k is
+ * kinds[k] = 0 (S update of scale terms[k], step weights[k] tau) or 1 (T step
+ * of weights[k] tau, terms[k] = -1).  Host arrays of max_events entries (any
+ * may be NULL); *n_events gets the count (WL_EINVAL if it exceeds max_events). */
+int wl_integrator_schedule(const int* nsteps, int nscales, int scheme, double lambda, int* kinds, int* terms,
+                           double* weights, int max_events, int* n_events);
+
 /* Counters: hop applications and K applications since create (single rhs units). */
 int wl_counters(const wl_lattice* lat, long long* n_hop, long long* n_kmat);
+/* Hop kernel variants: 0 = one thread per output site (all 8 directions);
+ * 1 = direction-parallel (8 wavefronts, one per direction, over 64 sites,
+ * combined through LDS).  wl_set_hop_variant picks one per precision;
+ * wl_autotune times both on this lattice for every precision and keeps the
+ * faster (us_out: optional host array [3][2] of microseconds per launch).
+ * Results are identical up to the FP summation order of the 8 directions. */
+int wl_set_hop_variant(wl_lattice* lat, wl_prec prec, int variant);
+int wl_autotune(wl_lattice* lat, double* us_out);
+/* Tracing: average duration in microseconds of nlaunch back-to-back hop
+ * launches (current variant, nrhs right-hand sides, scratch fields owned by
+ * the library), timed with HIP events on the context stream.  Not counted in
+ * the hop counters. */
+int wl_time_hop(wl_lattice* lat, wl_prec prec, int nrhs, int nlaunch, double* avg_us);
+
 /* Hop applications since create per storage precision (counts[wl_prec], single rhs units). */
 int wl_hop_counts(const wl_lattice* lat, long long* counts);
 

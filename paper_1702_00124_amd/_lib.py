@@ -78,7 +78,12 @@ SIGNATURES = {
     "wl_link_update": (I, [P, P, D]),
     "hmc_trajectory": (I, [P, C.POINTER(HmcParams), P, P, D, C.POINTER(HmcResult)]),
     "wl_counters": (I, [P, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+    "wl_integrator_schedule": (I, [C.POINTER(I), I, I, D, C.POINTER(I), C.POINTER(I), C.POINTER(D), I,
+                                   C.POINTER(I)]),
     "wl_profile": (I, [P, I]),
+    "wl_set_hop_variant": (I, [P, I, I]),
+    "wl_autotune": (I, [P, C.POINTER(D)]),
+    "wl_time_hop": (I, [P, I, I, I, C.POINTER(D)]),
     "wl_hop_counts": (I, [P, C.POINTER(C.c_longlong)]),
     "wl_profile_read": (I, [P, C.POINTER(D), C.POINTER(C.c_longlong)]),
 }

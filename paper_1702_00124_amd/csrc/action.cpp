@@ -57,7 +57,7 @@ int solve_j(wl_lattice* L, void* x, const void* b, double kappa, double mu2, con
 void solve_poly(wl_lattice* L, void* x, const void* b, const wl_term& t, int mode, long long* iters) {
   wl_cg_stats st{};
   const PolyDesc pd = pdesc(t);
-  auto apply = [&](void* out, const void* in) { poly_apply(L, mode, out, in, t.kappa, t.mu2, pd); };
+  auto apply = [&](Prec pr, void* out, const void* in) { poly_apply(L, mode, out, in, t.kappa, t.mu2, pd, pr); };
   const int rc = cg_run_generic(L, x, b, apply, t.cg, &st);
   if (iters) *iters += st.iters;
   WL_REQUIRE(rc == WL_OK, rc, "polynomial CG did not converge");

@@ -87,54 +87,57 @@ struct CaxpbyArgs {
   double b[2 * kMaxRhs];
 };
 
+template <typename P>
 __global__ __launch_bounds__(kBlock) void caxpby_kernel(Geo g, char* out, const char* x, const char* y, int g5y,
-                                                       CaxpbyArgs c) {
+                                                       size_t stride, CaxpbyArgs c) {
+  using R = typename P::real;
   const int rhs = blockIdx.y;
   const int h = blockIdx.x * kBlock + threadIdx.x;
   if (h >= g.Vh) return;
-  const size_t off = rhs * size_t(192) * g.Vh;
-  const cplx<double> ca = {c.a[2 * rhs], c.a[2 * rhs + 1]};
-  const cplx<double> cb = {c.b[2 * rhs], c.b[2 * rhs + 1]};
-  Spinor<double> o;
+  const size_t off = rhs * stride;
+  const cplx<R> ca = {R(c.a[2 * rhs]), R(c.a[2 * rhs + 1])};
+  const cplx<R> cb = {R(c.b[2 * rhs]), R(c.b[2 * rhs + 1])};
+  Spinor<R> o;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) o.c[k] = zero<double>();
+  for (int k = 0; k < 12; ++k) o.c[k] = zero<R>();
   if (x) {
-    const Spinor<double> xv = SpinorIO<PrecF64>::load(x + off, h, g.Vh);
+    const Spinor<R> xv = SpinorIO<P>::load(x + off, h, g.Vh);
 #pragma unroll
     for (int k = 0; k < 12; ++k) o.c[k] = ca * xv.c[k];
   }
   if (y) {
-    const Spinor<double> yv = SpinorIO<PrecF64>::load(y + off, h, g.Vh);
+    const Spinor<R> yv = SpinorIO<P>::load(y + off, h, g.Vh);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      const cplx<double> t = cb * yv.c[k];
+      const cplx<R> t = cb * yv.c[k];
       o.c[k] = (g5y && k >= 6) ? o.c[k] - t : o.c[k] + t;
     }
   }
-  SpinorIO<PrecF64>::store(out + off, h, g.Vh, o);
+  SpinorIO<P>::store(out + off, h, g.Vh, o);
 }
 
-// complex <x, y> = sum conj(x) y (two rows per rhs) or |x|^2 (one row per rhs)
-__global__ __launch_bounds__(kBlock) void dot_kernel(Geo g, const char* x, const char* y, double* partials,
-                                                    int pstride, int cdot) {
+// complex <x, y> = sum conj(x) y (two rows per rhs) or |x|^2 (one row per rhs), FP64 accumulation
+template <typename P>
+__global__ __launch_bounds__(kBlock) void dot_kernel(Geo g, const char* x, const char* y, size_t stride,
+                                                    double* partials, int pstride, int cdot) {
+  using R = typename P::real;
   __shared__ double lds[kBlock / 64];
   const int rhs = blockIdx.y;
   const int h = blockIdx.x * kBlock + threadIdx.x;
-  const size_t off = rhs * size_t(192) * g.Vh;
+  const size_t off = rhs * stride;
   double re = 0.0, im = 0.0;
   if (h < g.Vh) {
-    const Spinor<double> xv = SpinorIO<PrecF64>::load(x + off, h, g.Vh);
+    const Spinor<R> xv = SpinorIO<P>::load(x + off, h, g.Vh);
     if (cdot) {
-      const Spinor<double> yv = SpinorIO<PrecF64>::load(y + off, h, g.Vh);
+      const Spinor<R> yv = SpinorIO<P>::load(y + off, h, g.Vh);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
-        const cplx<double> t = cmul(xv.c[k], yv.c[k]);
-        re += t.r;
-        im += t.i;
+        re += double(xv.c[k].r) * double(yv.c[k].r) + double(xv.c[k].i) * double(yv.c[k].i);
+        im += double(xv.c[k].r) * double(yv.c[k].i) - double(xv.c[k].i) * double(yv.c[k].r);
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < 12; ++k) re += xv.c[k].r * xv.c[k].r + xv.c[k].i * xv.c[k].i;
+      for (int k = 0; k < 12; ++k) re += double(xv.c[k].r) * double(xv.c[k].r) + double(xv.c[k].i) * double(xv.c[k].i);
     }
   }
   const double sr = block_sum(re, lds);
@@ -199,27 +202,30 @@ __global__ __launch_bounds__(kBlock) void cg_beta_kernel(const double* partials,
 }
 
 
-// One step of the Chebyshev filter recurrence (F64):
+// One step of the Chebyshev filter recurrence:
 //   tprev <- ct * t + cw * w - tprev        (t_{m+1} = 2 y(J) t_m - t_{m-1}, w = J t_m)
 //   eprev <- ce * e + 2 t - eprev           (e_{m+1} = 2 y0 e_m + 2 t_m - e_{m-1})
+template <typename P>
 __global__ __launch_bounds__(kBlock) void cheb_step_kernel(Geo g, const char* t, const char* w, char* tprev,
-                                                          const char* e, char* eprev, double ct, double cw,
-                                                          double ce) {
+                                                          const char* e, char* eprev, size_t stride, double ct,
+                                                          double cw, double ce) {
+  using R = typename P::real;
   const int h = blockIdx.x * kBlock + threadIdx.x;
   if (h >= g.Vh) return;
-  const size_t off = blockIdx.y * size_t(192) * g.Vh;
-  const Spinor<double> tv = SpinorIO<PrecF64>::load(t + off, h, g.Vh);
-  const Spinor<double> wv = SpinorIO<PrecF64>::load(w + off, h, g.Vh);
-  const Spinor<double> ev = SpinorIO<PrecF64>::load(e + off, h, g.Vh);
-  Spinor<double> tp = SpinorIO<PrecF64>::load(tprev + off, h, g.Vh);
-  Spinor<double> ep = SpinorIO<PrecF64>::load(eprev + off, h, g.Vh);
+  const size_t off = blockIdx.y * stride;
+  const Spinor<R> tv = SpinorIO<P>::load(t + off, h, g.Vh);
+  const Spinor<R> wv = SpinorIO<P>::load(w + off, h, g.Vh);
+  const Spinor<R> ev = SpinorIO<P>::load(e + off, h, g.Vh);
+  Spinor<R> tp = SpinorIO<P>::load(tprev + off, h, g.Vh);
+  Spinor<R> ep = SpinorIO<P>::load(eprev + off, h, g.Vh);
+  const R rt = R(ct), rw = R(cw), re = R(ce), two = R(2);
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    tp.c[k] = ct * tv.c[k] + cw * wv.c[k] - tp.c[k];
-    ep.c[k] = ce * ev.c[k] + 2.0 * tv.c[k] - ep.c[k];
+    tp.c[k] = rt * tv.c[k] + rw * wv.c[k] - tp.c[k];
+    ep.c[k] = re * ev.c[k] + two * tv.c[k] - ep.c[k];
   }
-  SpinorIO<PrecF64>::store(tprev + off, h, g.Vh, tp);
-  SpinorIO<PrecF64>::store(eprev + off, h, g.Vh, ep);
+  SpinorIO<P>::store(tprev + off, h, g.Vh, tp);
+  SpinorIO<P>::store(eprev + off, h, g.Vh, ep);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -267,23 +273,29 @@ void launch_convert(wl_lattice* L, Prec dprec, void* dst, Prec sprec, const void
 }
 
 void launch_caxpby(wl_lattice* L, void* out, const double* a, const void* x, const double* b, const void* y,
-                   int g5y, int nrhs) {
+                   int g5y, int nrhs, Prec prec) {
   CaxpbyArgs c{};
   for (int r = 0; r < 2 * nrhs; ++r) {
     c.a[r] = a ? a[r] : 0.0;
     c.b[r] = b ? b[r] : 0.0;
   }
   dim3 grid(blas_blocks(L), nrhs);
-  hipLaunchKernelGGL(caxpby_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (char*)out, (const char*)x,
-                     (const char*)y, g5y, c);
+  by_prec(prec, [&](auto P) {
+    using PT = decltype(P);
+    hipLaunchKernelGGL((caxpby_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (char*)out, (const char*)x,
+                       (const char*)y, g5y, spinor_bytes(prec, L->Vh), c);
+  });
   WL_HIP(hipGetLastError());
 }
 
 void launch_dot_partials(wl_lattice* L, const void* x, const void* y, int nrhs, double* partials, int stride,
-                         int complex_dot) {
+                         int complex_dot, Prec prec) {
   dim3 grid(blas_blocks(L), nrhs);
-  hipLaunchKernelGGL(dot_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (const char*)x, (const char*)y,
-                     partials, stride, complex_dot);
+  by_prec(prec, [&](auto P) {
+    using PT = decltype(P);
+    hipLaunchKernelGGL((dot_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (const char*)x, (const char*)y,
+                       spinor_bytes(prec, L->Vh), partials, stride, complex_dot);
+  });
   WL_HIP(hipGetLastError());
 }
 
@@ -303,10 +315,14 @@ void launch_cg_beta(wl_lattice* L, const double* partials, int stride, int nb, d
 }
 
 void launch_cheb_step(wl_lattice* L, const void* t, const void* w, void* tprev, const void* e, void* eprev, double ct,
-                      double cw, double ce, int nrhs) {
+                      double cw, double ce, int nrhs, Prec prec) {
   dim3 grid(blas_blocks(L), nrhs);
-  hipLaunchKernelGGL(cheb_step_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (const char*)t, (const char*)w,
-                     (char*)tprev, (const char*)e, (char*)eprev, ct, cw, ce);
+  by_prec(prec, [&](auto P) {
+    using PT = decltype(P);
+    hipLaunchKernelGGL((cheb_step_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (const char*)t,
+                       (const char*)w, (char*)tprev, (const char*)e, (char*)eprev, spinor_bytes(prec, L->Vh), ct, cw,
+                       ce);
+  });
   WL_HIP(hipGetLastError());
 }
 

@@ -1,6 +1,7 @@
 // extern "C" entry points of libwilson_hmc (declared in include/wilson_hmc.h).
 // Every call validates its arguments, runs inside a guard that turns internal
 // errors into return codes, and records the message for wl_last_error().
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -10,6 +11,12 @@
 namespace wl {
 int hmc_run(wl_lattice* L, const wl_hmc_params& prm, double* P, const void* chi, double u, wl_hmc_result* res);
 double plaquette_host(wl_lattice* L);
+struct Event {
+  int kind;
+  int term;
+  double w;
+};
+std::vector<Event> merge_schedule(const std::vector<int>& nsteps, int scheme, double lam);
 }  // namespace wl
 
 using namespace wl;
@@ -424,6 +431,112 @@ int wl_hop_counts(const wl_lattice* L, long long* counts) {
     check_lat(L);
     WL_REQUIRE(counts, WL_EINVAL, "null argument");
     for (int p = 0; p < 3; ++p) counts[p] = L->n_hop_p[p];
+    return WL_OK;
+  });
+}
+
+int wl_set_hop_variant(wl_lattice* L, wl_prec prec, int variant) {
+  return guard([&]() {
+    check_lat(L);
+    check_prec_rhs(prec, 1);
+    WL_REQUIRE(variant == kHopSite || variant == kHopDirParallel, WL_EINVAL, "unknown hop variant");
+    WL_HIP(hipStreamSynchronize(L->stream));
+    L->hop_var[prec] = variant;
+    return WL_OK;
+  });
+}
+
+int wl_time_hop(wl_lattice* L, wl_prec prec, int nrhs, int nlaunch, double* avg_us) {
+  return guard([&]() {
+    check_lat(L);
+    check_prec_rhs(prec, nrhs);
+    WL_REQUIRE(avg_us && nlaunch >= 1 && nlaunch <= 100000, WL_EINVAL, "bad arguments");
+    set_device(L);
+    const size_t fb = spinor_bytes(F64, L->Vh) * nrhs;  // large enough for every precision
+    void* a = ws_get(L, "tune_a", fb);
+    void* b = ws_get(L, "tune_b", fb);
+    WL_HIP(hipMemsetAsync(a, 0, fb, L->stream));
+    hipEvent_t e0, e1;
+    WL_HIP(hipEventCreate(&e0));
+    WL_HIP(hipEventCreate(&e1));
+    HopEpi e;
+    for (int i = 0; i < 3; ++i) launch_hop(L, Prec(prec), b, a, 0, 0, nrhs, e);
+    WL_HIP(hipEventRecord(e0, L->stream));
+    for (int i = 0; i < nlaunch; ++i) launch_hop(L, Prec(prec), b, a, 0, 0, nrhs, e);
+    WL_HIP(hipEventRecord(e1, L->stream));
+    WL_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    WL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *avg_us = 1e3 * ms / nlaunch;
+    L->n_hop -= (long long)(nlaunch + 3) * nrhs;
+    L->n_hop_p[prec] -= (long long)(nlaunch + 3) * nrhs;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return WL_OK;
+  });
+}
+
+int wl_autotune(wl_lattice* L, double* us_out) {
+  return guard([&]() {
+    check_lat(L);
+    set_device(L);
+    // time each hop variant on scratch fields (best of 3 bursts of 20 launches
+    // after 5 warm-ups) and keep the faster
+    hipEvent_t e0, e1;
+    WL_HIP(hipEventCreate(&e0));
+    WL_HIP(hipEventCreate(&e1));
+    const size_t fb = spinor_bytes(F64, L->Vh);
+    void* a = ws_get(L, "tune_a", fb);
+    void* b = ws_get(L, "tune_b", fb);
+    WL_HIP(hipMemsetAsync(a, 0, fb, L->stream));
+    for (int p = 0; p < 3; ++p) {
+      double best = 1e30;
+      int best_v = L->hop_var[p];
+      for (int v = 0; v < 2; ++v) {
+        L->hop_var[p] = v;
+        HopEpi e;
+        for (int i = 0; i < 5; ++i) launch_hop(L, Prec(p), b, a, 0, 0, 1, e);
+        double us = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+          WL_HIP(hipEventRecord(e0, L->stream));
+          for (int i = 0; i < 20; ++i) launch_hop(L, Prec(p), b, a, 0, 0, 1, e);
+          WL_HIP(hipEventRecord(e1, L->stream));
+          WL_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          WL_HIP(hipEventElapsedTime(&ms, e0, e1));
+          us = std::min(us, 1e3 * ms / 20);
+        }
+        if (us_out) us_out[2 * p + v] = us;
+        if (us < best) {
+          best = us;
+          best_v = v;
+        }
+        L->n_hop -= 65;
+        L->n_hop_p[p] -= 65;
+      }
+      L->hop_var[p] = best_v;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return WL_OK;
+  });
+}
+
+int wl_integrator_schedule(const int* nsteps, int nscales, int scheme, double lambda, int* kinds, int* terms,
+                           double* weights, int max_events, int* n_events) {
+  return guard([&]() {
+    WL_REQUIRE(nsteps && n_events && nscales >= 1 && nscales <= 9, WL_EINVAL, "bad arguments");
+    WL_REQUIRE(scheme == WL_INT_LEAPFROG || scheme == WL_INT_OMELYAN, WL_EINVAL, "unknown integrator");
+    std::vector<int> ns(nsteps, nsteps + nscales);
+    for (int n : ns) WL_REQUIRE(n >= 1 && n <= 100000, WL_EINVAL, "nsteps out of range");
+    const auto ev = merge_schedule(ns, scheme, lambda > 0.0 ? lambda : 0.1931833275037836);
+    *n_events = int(ev.size());
+    WL_REQUIRE(int(ev.size()) <= max_events, WL_EINVAL, "event buffer too small");
+    for (size_t i = 0; i < ev.size(); ++i) {
+      if (kinds) kinds[i] = ev[i].kind;
+      if (terms) terms[i] = ev[i].term;
+      if (weights) weights[i] = ev[i].w;
+    }
     return WL_OK;
   });
 }

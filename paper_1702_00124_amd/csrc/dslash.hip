@@ -34,7 +34,18 @@ struct HopArgs {
   int part_stride;
   int part_off;
   int use_xcd;
+  int rows;  // rhs groups per tile
 };
+
+// Flattened grid: block b -> (tile, rhs group).  The XCD-aware renumbering
+// gives each XCD a contiguous block range, and the rhs groups of one tile are
+// adjacent inside it, so a tile's links are fetched once into that XCD's L2
+// and reused by every group.
+__device__ __forceinline__ void hop_block_coords(const HopArgs& a, int* tile, int* row) {
+  const int b = a.use_xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  *tile = b / a.rows;
+  *row = b - *tile * a.rows;
+}
 
 template <typename P, int MU, int DAG, int NR>
 __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h, int r0,
@@ -85,10 +96,11 @@ template <typename P, int DAG, int NR>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
   using R = typename P::real;
   __shared__ double lds[kBlock / 64];
-  const int b = a.use_xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  int b, row;
+  hop_block_coords(a, &b, &row);
   const int h = b * kBlock + threadIdx.x;
   const int Vh = a.g.Vh;
-  const int r0 = blockIdx.y * NR;
+  const int r0 = row * NR;
   double part[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) part[r] = 0.0;
@@ -152,25 +164,171 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
   }
 }
 
-int hop_grid_blocks(const wl_lattice* L) { return site_blocks(L->Vh); }
+// ------------------------------------------------------------------ direction-parallel variant
+// One workgroup = 8 wavefronts over the same 64 consecutive output sites;
+// wavefront d = 2 mu + (0 forward, 1 backward) loads its direction's link
+// once, projects, multiplies and writes the half-spinor result of every rhs
+// to LDS; after one barrier the wavefronts rebuild and sum the 8 directions
+// per 16-byte storage unit and run the epilogue.  Eight times the wavefronts
+// of the site kernel at the same coalescing (every load is 64 consecutive
+// sites), which hides memory latency on small lattices.
+constexpr int kDpSites = 64;
+constexpr int kDpThreads = 8 * kDpSites;
+
+template <typename P, int MU, int FWD, int DAG, int NR>
+__device__ __forceinline__ void dp_dir(const HopArgs& a, const Coord& c, int h, int r0,
+                                       cplx<typename P::real>* W, int lane) {
+  using R = typename P::real;
+  constexpr int S = FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1);  // projector sign (1 + S g_mu)
+  constexpr int D = 2 * MU + (FWD ? 0 : 1);
+  const int Vh = a.g.Vh;
+  const size_t lb = LinkIO<P>::bytes * size_t(Vh);
+  bool wrap;
+  const int hn = neighbour<MU>(a.g, c, FWD ? +1 : -1, &wrap);
+  const SU3<R> U = FWD ? LinkIO<P>::load(a.links + (a.parity * 4 + MU) * lb, h, Vh)
+                       : LinkIO<P>::load(a.links + ((1 - a.parity) * 4 + MU) * lb, hn, Vh);
+  const R ph = wrap ? R(a.g.tbc) : R(1);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const Spinor<R> s = SpinorIO<P>::load(a.in + (r0 + r) * a.rhs_stride, hn, Vh);
+    const Half<R> hp = project<MU, S>(s);
+    Half<R> w;
+    if (FWD) {
+      su3_mul(U, hp.c, w.c);
+      su3_mul(U, hp.c + 3, w.c + 3);
+    } else {
+      su3_dag_mul(U, hp.c, w.c);
+      su3_dag_mul(U, hp.c + 3, w.c + 3);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) W[((r * 8 + D) * 6 + k) * kDpSites + lane] = ph * w.c[k];
+  }
+}
+
+// sum over the 8 directions of the rebuilt spinor component (spin s, colour col)
+// from the half-spinor results W[d][3 k + col]; the lower spin rows carry the
+// projector's phases, which flip sign between forward and backward terms
+template <int DAG, typename R>
+__device__ __forceinline__ cplx<R> dp_recon(const cplx<R>* W, int s, int col, int lane) {
+  auto w = [&](int d, int k) { return W[(d * 6 + 3 * k + col) * kDpSites + lane]; };
+  if (s < 2) {
+    cplx<R> acc = w(0, s);
+#pragma unroll
+    for (int d = 1; d < 8; ++d) acc = acc + w(d, s);
+    return acc;
+  }
+  const R sf = DAG ? R(1) : R(-1);  // forward projector sign
+  auto df = [&](int mu, int k) { return w(2 * mu, k) - w(2 * mu + 1, k); };
+  cplx<R> acc;
+  if (s == 2)  // x: +i h1, y: +h1, z: +i h0, t: +h0
+    acc = times_i(df(0, 1)) + df(1, 1) + times_i(df(2, 0)) + df(3, 0);
+  else         // x: +i h0, y: -h0, z: -i h1, t: +h1
+    acc = times_i(df(0, 0)) - df(1, 0) - times_i(df(2, 1)) + df(3, 1);
+  return sf * acc;
+}
+
+template <typename P, int DAG, int NR>
+__global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
+  using R = typename P::real;
+  using UIO = UnitIO<P>;
+  __shared__ cplx<R> W[NR * 8 * 6 * kDpSites];
+  __shared__ double red[kDpThreads / 64];
+  int tile, row;
+  hop_block_coords(a, &tile, &row);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int Vh = a.g.Vh;
+  const int h = tile * kDpSites + lane;
+  const bool active = h < Vh;
+  const int r0 = row * NR;
+  if (active) {
+    const Coord c = site_coords(a.g, h, a.parity);
+    switch (wv) {
+      case 0: dp_dir<P, 0, 1, DAG, NR>(a, c, h, r0, W, lane); break;
+      case 1: dp_dir<P, 0, 0, DAG, NR>(a, c, h, r0, W, lane); break;
+      case 2: dp_dir<P, 1, 1, DAG, NR>(a, c, h, r0, W, lane); break;
+      case 3: dp_dir<P, 1, 0, DAG, NR>(a, c, h, r0, W, lane); break;
+      case 4: dp_dir<P, 2, 1, DAG, NR>(a, c, h, r0, W, lane); break;
+      case 5: dp_dir<P, 2, 0, DAG, NR>(a, c, h, r0, W, lane); break;
+      case 6: dp_dir<P, 3, 1, DAG, NR>(a, c, h, r0, W, lane); break;
+      default: dp_dir<P, 3, 0, DAG, NR>(a, c, h, r0, W, lane); break;
+    }
+  }
+  __syncthreads();
+  double part[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) part[r] = 0.0;
+  if (active) {
+    const R ca = R(a.a), cx = R(a.cx);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const size_t off = (r0 + r) * a.rhs_stride;
+      const R cy = R(a.by[r0 + r]);
+      for (int u = wv; u < UIO::NU; u += 8) {
+        cplx<R> o[UIO::CPU], xv[UIO::CPU], yv[UIO::CPU];
+        if (a.x) UIO::load(a.x + off, u, h, Vh, xv);
+        if (a.y) UIO::load(a.y + off, u, h, Vh, yv);
+#pragma unroll
+        for (int q = 0; q < UIO::CPU; ++q) {
+          const int comp = u * UIO::CPU + q;
+          const int s = comp / 3;
+          o[q] = ca * dp_recon<DAG>(W + r * 8 * 6 * kDpSites, s, comp - 3 * s, lane);
+          if (a.x) o[q] = o[q] + cx * xv[q];
+          if (a.g5 && s >= 2) o[q] = R(-1) * o[q];
+          if (a.y) o[q] = o[q] + cy * yv[q];
+        }
+        UIO::store(a.out + off, u, h, Vh, o);
+        if (a.dot == 1) {
+          cplx<R> dv[UIO::CPU];
+          UIO::load(a.dotv + off, u, h, Vh, dv);
+#pragma unroll
+          for (int q = 0; q < UIO::CPU; ++q)
+            part[r] += double(dv[q].r) * double(o[q].r) + double(dv[q].i) * double(o[q].i);
+        } else if (a.dot == 2) {
+#pragma unroll
+          for (int q = 0; q < UIO::CPU; ++q) part[r] += double(o[q].r) * double(o[q].r) + double(o[q].i) * double(o[q].i);
+        }
+      }
+    }
+  }
+  if (a.dot) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double sum = block_sum(part[r], red);
+      if (threadIdx.x == 0) a.partials[(r0 + r) * a.part_stride + a.part_off + tile] = sum;
+    }
+  }
+}
+
+int hop_tiles(const wl_lattice* L, Prec prec) {
+  return L->hop_var[prec] == kHopDirParallel ? (L->Vh + kDpSites - 1) / kDpSites : site_blocks(L->Vh);
+}
 
 template <typename P, int DAG>
-static void dispatch_nr(const HopArgs& a, int nrhs, hipStream_t st, int nb) {
-  // rhs per thread: FP64 keeps one (the register budget of a double spinor
-  // accumulator plus hoisted loads); FP32/BF16 share each link over two
+static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, int variant, int tiles) {
+  // rhs per block: FP64 keeps one (register / LDS budget of double spinors);
+  // FP32 and BF16 share each link load over two
   int nr = 1;
   if (sizeof(typename P::real) == 4 && nrhs % 2 == 0) nr = 2;
-  dim3 grid(nb, nrhs / nr);
-  switch (nr) {
-    case 2: hipLaunchKernelGGL((hop_kernel<P, DAG, 2>), grid, dim3(kBlock), 0, st, a); break;
-    default: hipLaunchKernelGGL((hop_kernel<P, DAG, 1>), grid, dim3(kBlock), 0, st, a); break;
+  a.rows = nrhs / nr;
+  dim3 grid(tiles * a.rows);
+  if (variant == kHopDirParallel) {
+    switch (nr) {
+      case 2: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, 2>), grid, dim3(kDpThreads), 0, st, a); break;
+      default: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, 1>), grid, dim3(kDpThreads), 0, st, a); break;
+    }
+  } else {
+    switch (nr) {
+      case 2: hipLaunchKernelGGL((hop_kernel<P, DAG, 2>), grid, dim3(kBlock), 0, st, a); break;
+      default: hipLaunchKernelGGL((hop_kernel<P, DAG, 1>), grid, dim3(kBlock), 0, st, a); break;
+    }
   }
 }
 
 template <typename P>
-static void dispatch(const HopArgs& a, int dagger, int nrhs, hipStream_t st, int nb) {
-  if (dagger) dispatch_nr<P, 1>(a, nrhs, st, nb);
-  else dispatch_nr<P, 0>(a, nrhs, st, nb);
+static void dispatch(const HopArgs& a, int dagger, int nrhs, hipStream_t st, int variant, int tiles) {
+  if (dagger) dispatch_nr<P, 1>(a, nrhs, st, variant, tiles);
+  else dispatch_nr<P, 0>(a, nrhs, st, variant, tiles);
 }
 
 void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_parity, int dagger,
@@ -197,7 +355,8 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
   a.part_stride = e.part_stride;
   a.part_off = e.part_off;
   a.use_xcd = L->use_xcd;
-  const int nb = hop_grid_blocks(L);
+  const int tiles = hop_tiles(L, prec);
+  const int variant = L->hop_var[prec];
   // sampled event timing (never inside a graph capture)
   const bool timed = L->prof_on && !L->prof_capturing && nrhs == 1 && L->prof_ev[prec].size() < 2 * kProfPairs;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -207,9 +366,9 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
     WL_HIP(hipEventRecord(e0, L->stream));
   }
   switch (prec) {
-    case F64: dispatch<PrecF64>(a, dagger, nrhs, L->stream, nb); break;
-    case F32: dispatch<PrecF32>(a, dagger, nrhs, L->stream, nb); break;
-    case BF16: dispatch<PrecBF16>(a, dagger, nrhs, L->stream, nb); break;
+    case F64: dispatch<PrecF64>(a, dagger, nrhs, L->stream, variant, tiles); break;
+    case F32: dispatch<PrecF32>(a, dagger, nrhs, L->stream, variant, tiles); break;
+    case BF16: dispatch<PrecBF16>(a, dagger, nrhs, L->stream, variant, tiles); break;
   }
   WL_HIP(hipGetLastError());
   if (timed) {

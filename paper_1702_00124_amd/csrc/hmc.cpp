@@ -28,6 +28,8 @@ struct Event {
   double w;    // step in units of tau
 };
 
+std::vector<Event> merge_schedule(const std::vector<int>& nsteps, int scheme, double lam);
+
 static long long lcm_ll(long long a, long long b) { return a / std::gcd(a, b) * b; }
 
 std::vector<Event> merge_schedule(const std::vector<int>& nsteps, int scheme, double lam) {

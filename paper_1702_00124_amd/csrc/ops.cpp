@@ -90,7 +90,7 @@ void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa
   launch_hop(L, prec, oe, t + hb, 0, 1, 1, e);
   e.x = t + hb;
   e.dotv = ie + hb;
-  e.part_off = hop_grid_blocks(L);
+  e.part_off = hop_tiles(L, prec);
   launch_hop(L, prec, oe + hb, t, 1, 1, 1, e);
   L->n_kmat += 1;
 }

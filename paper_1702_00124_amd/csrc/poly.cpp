@@ -40,9 +40,9 @@ static void check_poly(const PolyDesc& pd) {
   WL_REQUIRE(pd.a > 0.0 && pd.b > pd.a, WL_EINVAL, "polynomial interval needs 0 < a < b");
 }
 
-// out = P_n(J) in by the recurrence
-static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd) {
-  const size_t fb = spinor_bytes(F64, L->Vh);
+// out = P_n(J) in by the recurrence, fields and arithmetic in storage precision pr
+static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd, Prec pr) {
+  const size_t fb = spinor_bytes(pr, L->Vh);
   void* tA = ws_get(L, "pl_tA", fb);
   void* tB = ws_get(L, "pl_tB", fb);
   void* eA = ws_get(L, "pl_eA", fb);
@@ -53,54 +53,55 @@ static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, doubl
   const double ct = 2.0 * (b + a) / (b - a), cw = -4.0 / (b - a);
   // t0 = in, t1 = y(J) in, e0 = 0, e1 = in
   copy_dev(L, tA, in, fb);
-  op_j(L, F64, w, in, kappa, &mu2, 1);
+  op_j(L, pr, w, in, kappa, &mu2, 1);
   const double c1[2] = {(b + a) / (b - a), 0.0}, c2[2] = {-2.0 / (b - a), 0.0};
-  launch_caxpby(L, tB, c1, in, c2, w, 0, 1);
+  launch_caxpby(L, tB, c1, in, c2, w, 0, 1, pr);
   zero_dev(L, eA, fb);
   copy_dev(L, eB, in, fb);
   for (int m = 1; m <= pd.n; ++m) {
     const bool need_t = m < pd.n;
-    if (need_t) op_j(L, F64, w, tB, kappa, &mu2, 1);
-    launch_cheb_step(L, tB, need_t ? w : tB, tA, eB, eA, ct, need_t ? cw : 0.0, 2.0 * y0, 1);
+    if (need_t) op_j(L, pr, w, tB, kappa, &mu2, 1);
+    launch_cheb_step(L, tB, need_t ? w : tB, tA, eB, eA, ct, need_t ? cw : 0.0, 2.0 * y0, 1, pr);
     std::swap(tA, tB);
     std::swap(eA, eB);
   }
   const double s[2] = {(2.0 / (b - a)) / cheb_T_above_one(pd.n + 1, y0), 0.0};
-  launch_caxpby(L, out, s, eB, nullptr, nullptr, 0, 1);
+  launch_caxpby(L, out, s, eB, nullptr, nullptr, 0, 1, pr);
 }
 
 // out = sqrt(c) prod_k (J - z_k) in   (conjugate roots for Q^dag)
 static void poly_Q(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
-                   int dagger) {
+                   int dagger, Prec pr) {
   WL_REQUIRE(pd.n % 2 == 0, WL_EINVAL, "P = Q^dag Q needs an even degree");
-  const size_t fb = spinor_bytes(F64, L->Vh);
+  const size_t fb = spinor_bytes(pr, L->Vh);
   void* v = ws_get(L, "pl_qv", fb);
   void* w = ws_get(L, "pl_w", fb);
   std::vector<double> zr, zi;
   poly_q_roots(pd, zr, zi);
   copy_dev(L, v, in, fb);
   for (size_t k = 0; k < zr.size(); ++k) {
-    op_j(L, F64, w, v, kappa, &mu2, 1);
+    op_j(L, pr, w, v, kappa, &mu2, 1);
     const double one[2] = {1.0, 0.0};
     const double mz[2] = {-zr[k], dagger ? zi[k] : -zi[k]};
-    launch_caxpby(L, v, one, w, mz, v, 0, 1);
+    launch_caxpby(L, v, one, w, mz, v, 0, 1, pr);
   }
   const double sc[2] = {std::sqrt(poly_lead(pd)), 0.0};
-  launch_caxpby(L, out, sc, v, nullptr, nullptr, 0, 1);
+  launch_caxpby(L, out, sc, v, nullptr, nullptr, 0, 1, pr);
 }
 
-void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd) {
+void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
+                Prec pr) {
   check_poly(pd);
   switch (mode) {
-    case WL_POLY_P: poly_P(L, out, in, kappa, mu2, pd); break;
+    case WL_POLY_P: poly_P(L, out, in, kappa, mu2, pd, pr); break;
     case WL_POLY_PJ: {
-      void* jin = ws_get(L, "pl_jin", spinor_bytes(F64, L->Vh));
-      op_j(L, F64, jin, in, kappa, &mu2, 1);
-      poly_P(L, out, jin, kappa, mu2, pd);
+      void* jin = ws_get(L, "pl_jin", spinor_bytes(pr, L->Vh));
+      op_j(L, pr, jin, in, kappa, &mu2, 1);
+      poly_P(L, out, jin, kappa, mu2, pd, pr);
       break;
     }
-    case WL_POLY_Q: poly_Q(L, out, in, kappa, mu2, pd, 0); break;
-    case WL_POLY_QDAG: poly_Q(L, out, in, kappa, mu2, pd, 1); break;
+    case WL_POLY_Q: poly_Q(L, out, in, kappa, mu2, pd, 0, pr); break;
+    case WL_POLY_QDAG: poly_Q(L, out, in, kappa, mu2, pd, 1, pr); break;
     default: throw Error(WL_EINVAL, "unknown polynomial mode");
   }
 }

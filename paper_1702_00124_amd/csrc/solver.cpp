@@ -114,12 +114,16 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   };
   push_state();
 
+  // rows of nbrow partials: the operator writes nbrow of <p, A p> per rhs;
+  // the update writes nh * blas_blocks of |r|^2 (never more than nbrow)
+  const int nb_upd = nh * blas_blocks(L);
+  WL_REQUIRE(nb_upd <= nbrow, WL_EINVAL, "cg: reduction row too narrow");
   auto issue_chunk = [&]() {
     for (int it = 0; it < chunk; ++it) {
       apply_lp(ip, Ap, p, DotOut{L->partials, nbrow});
       launch_cg_alpha(L, L->partials, nbrow, nbrow, st, nrhs);
       launch_cg_update(L, ip, x, r, p, Ap, st, nrhs, nh, L->partials, nbrow);
-      launch_cg_beta(L, L->partials, nbrow, nbrow, st, nrhs);
+      launch_cg_beta(L, L->partials, nbrow, nb_upd, st, nrhs);
       launch_cg_xpay(L, ip, p, r, st, nrhs, nh);
     }
   };
@@ -247,24 +251,26 @@ int cg_run(wl_lattice* L, void* x, const void* b, double kappa, const double* mu
     op_apply(L, op, pr, out, in, kappa, mu2, nrhs, d);
   };
   Apply64 a64 = [&](void* out, const void* in) { op_apply(L, op, F64, out, in, kappa, mu2, nrhs); };
-  return cg_core(L, x, b, nrhs, nh, op_dot_blocks(L, op), spinor_bytes(F64, L->Vh),
+  const Prec ipr = (ip == F32 || ip == BF16) ? ip : F64;
+  return cg_core(L, x, b, nrhs, nh, op_dot_blocks(L, op, ipr), spinor_bytes(F64, L->Vh),
                  spinor_bytes((ip == F32 || ip == BF16) ? ip : F64, L->Vh), lp, a64, prm, stats, true);
 }
 
-int cg_run_generic(wl_lattice* L, void* x, const void* b, const std::function<void(void*, const void*)>& apply,
-                   const wl_cg_params& prm_in, wl_cg_stats* stats) {
+int cg_run_generic(wl_lattice* L, void* x, const void* b,
+                   const std::function<void(Prec, void*, const void*)>& apply, const wl_cg_params& prm_in,
+                   wl_cg_stats* stats) {
   wl_cg_params prm = prm_in;
-  prm.inner = WL_F64;   // the polynomial operators run in FP64
-  prm.use_graph = 0;    // they synchronise the host inside (nothing to capture)
+  prm.use_graph = 0;  // the polynomial operators synchronise nothing but are host-sequenced; no capture
+  const Prec ip = Prec(prm.inner);
   const int nb = blas_blocks(L);
-  ApplyLowp lp = [&](Prec, void* out, const void* in, const DotOut& d) {
-    apply(out, in);
+  ApplyLowp lp = [&](Prec pr, void* out, const void* in, const DotOut& d) {
+    apply(pr, out, in);
     // complex <in, out>: row 0 holds the real part, which CG needs
-    launch_dot_partials(L, in, out, 1, d.partials, d.stride, 1);
+    launch_dot_partials(L, in, out, 1, d.partials, d.stride, 1, pr);
   };
-  Apply64 a64 = [&](void* out, const void* in) { apply(out, in); };
-  return cg_core(L, x, b, 1, 1, nb, spinor_bytes(F64, L->Vh), spinor_bytes(F64, L->Vh), lp, a64, prm, stats,
-                 false);
+  Apply64 a64 = [&](void* out, const void* in) { apply(F64, out, in); };
+  return cg_core(L, x, b, 1, 1, nb, spinor_bytes(F64, L->Vh),
+                 spinor_bytes((ip == F32 || ip == BF16) ? ip : F64, L->Vh), lp, a64, prm, stats, false);
 }
 
 }  // namespace wl

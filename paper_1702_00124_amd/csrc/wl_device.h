@@ -160,6 +160,54 @@ struct SpinorIO<PrecBF16> {
   }
 };
 
+// storage units of a spinor: 16-byte vectors (F64: 1 complex, F32: 2, BF16: 4)
+template <typename P>
+struct UnitIO;
+
+template <>
+struct UnitIO<PrecF64> {
+  static constexpr int NU = 12, CPU = 1;
+  static __device__ __forceinline__ void load(const void* base, int u, int h, int Vh, cplx<double>* c) {
+    const double2 v = reinterpret_cast<const double2*>(base)[u * Vh + h];
+    c[0] = {v.x, v.y};
+  }
+  static __device__ __forceinline__ void store(void* base, int u, int h, int Vh, const cplx<double>* c) {
+    reinterpret_cast<double2*>(base)[u * Vh + h] = make_double2(c[0].r, c[0].i);
+  }
+};
+
+template <>
+struct UnitIO<PrecF32> {
+  static constexpr int NU = 6, CPU = 2;
+  static __device__ __forceinline__ void load(const void* base, int u, int h, int Vh, cplx<float>* c) {
+    const float4 v = reinterpret_cast<const float4*>(base)[u * Vh + h];
+    c[0] = {v.x, v.y};
+    c[1] = {v.z, v.w};
+  }
+  static __device__ __forceinline__ void store(void* base, int u, int h, int Vh, const cplx<float>* c) {
+    reinterpret_cast<float4*>(base)[u * Vh + h] = make_float4(c[0].r, c[0].i, c[1].r, c[1].i);
+  }
+};
+
+template <>
+struct UnitIO<PrecBF16> {
+  static constexpr int NU = 3, CPU = 4;
+  static __device__ __forceinline__ void load(const void* base, int u, int h, int Vh, cplx<float>* c) {
+    const uint4 v = reinterpret_cast<const uint4*>(base)[u * Vh + h];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[q] = {bf16_to_f32(w[q] & 0xFFFFu), bf16_to_f32(w[q] >> 16)};
+  }
+  static __device__ __forceinline__ void store(void* base, int u, int h, int Vh, const cplx<float>* c) {
+    uint4 v;
+    v.x = pack_bf16x2(c[0].r, c[0].i);
+    v.y = pack_bf16x2(c[1].r, c[1].i);
+    v.z = pack_bf16x2(c[2].r, c[2].i);
+    v.w = pack_bf16x2(c[3].r, c[3].i);
+    reinterpret_cast<uint4*>(base)[u * Vh + h] = v;
+  }
+};
+
 // link load: base points at [mu] block of one parity
 template <typename T>
 __device__ __forceinline__ void third_row(SU3<T>& u) {

@@ -19,6 +19,7 @@ constexpr int kBlock = 256;  // threads per workgroup of the site kernels
 constexpr int kScal = 2048;  // device scalar slots; the CG state starts at kCgState
 constexpr int kCgState = 1024;
 constexpr int kProfPairs = 4096;  // sampled hop launches timed per precision
+enum HopVariant { kHopSite = 0, kHopDirParallel = 1 };
 
 enum Prec { F64 = WL_F64, F32 = WL_F32, BF16 = WL_BF16 };
 
@@ -67,7 +68,7 @@ struct wl_lattice {
   long long n_hop_p[3] = {0, 0, 0};          // ... per storage precision
   long long n_kmat = 0;                      // K-hat / K applications (single rhs units)
   int use_xcd = 1;
-  int hop_block = wl::kBlock;
+  int hop_var[3] = {1, 1, 0};                // hop kernel variant per precision (wl::HopVariant)
   // optional event timing of sampled hop launches, per storage precision
   int prof_on = 0;
   int prof_capturing = 0;
@@ -99,7 +100,8 @@ struct HopEpi {
   int part_stride = 0;      // per-rhs stride of partials
   int part_off = 0;         // block offset inside a rhs row
 };
-int hop_grid_blocks(const wl_lattice* L);
+// workgroups (and reduction partials per rhs) of one hop launch in precision prec
+int hop_tiles(const wl_lattice* L, Prec prec);
 // out (parity p, nrhs fields) = epilogue(D_{p,1-p} in) or its dagger
 void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_parity, int dagger,
                 int nrhs, const HopEpi& e);
@@ -115,18 +117,18 @@ void launch_cg_update(wl_lattice* L, Prec prec, void* x64, void* r, const void* 
 void launch_cg_xpay(wl_lattice* L, Prec prec, void* p, const void* r, const double* st, int nrhs, int nh);
 // dst = convert(src), both nrhs half fields
 void launch_convert(wl_lattice* L, Prec dprec, void* dst, Prec sprec, const void* src, int nrhs);
-// out = a[r] x + b[r] (g5 ? gamma5 y : y), complex coefficients, F64 fields; x or y may be null
+// out = a[r] x + b[r] (g5 ? gamma5 y : y), complex coefficients; x or y may be null
 void launch_caxpby(wl_lattice* L, void* out, const double* a /*2*nrhs host*/, const void* x,
-                   const double* b /*2*nrhs host*/, const void* y, int g5y, int nrhs);
-// partials of <x, y> (complex, 2 values per block) or |x|^2 over nrhs F64 fields
+                   const double* b /*2*nrhs host*/, const void* y, int g5y, int nrhs, Prec prec = F64);
+// partials of <x, y> (complex, 2 values per block) or |x|^2 over nrhs fields (FP64 sums)
 void launch_dot_partials(wl_lattice* L, const void* x, const void* y, int nrhs, double* partials,
-                         int stride, int complex_dot);
+                         int stride, int complex_dot, Prec prec = F64);
 // sum partials: out[r * ncomp + c] = sum_b partials[(r * ncomp + c) * stride + b], b < nb
 void launch_finish_sum(wl_lattice* L, const double* partials, int stride, int nb, int nrows,
                        double* out_dev);
-// Chebyshev recurrence step: tprev <- ct t + cw w - tprev ; eprev <- ce e + 2 t - eprev (F64)
+// Chebyshev recurrence step: tprev <- ct t + cw w - tprev ; eprev <- ce e + 2 t - eprev
 void launch_cheb_step(wl_lattice* L, const void* t, const void* w, void* tprev, const void* e, void* eprev,
-                      double ct, double cw, double ce, int nrhs);
+                      double ct, double cw, double ce, int nrhs, Prec prec = F64);
 // CG scalar steps on the device state (see solver.cpp for the layout)
 void launch_cg_alpha(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);
 void launch_cg_beta(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);

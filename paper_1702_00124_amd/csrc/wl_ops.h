@@ -15,7 +15,7 @@ struct DotOut {
 // even sites: out = M-hat in (dagger: M-hat^dag), nrhs fields of precision prec
 void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger, int nrhs);
 // even sites: out = K-hat in + mu2[r] in; optional partials of Re<in, out>
-// (one row per rhs, hop_grid_blocks(L) blocks)
+// (one row per rhs, hop_tiles(L, prec) blocks)
 void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const double* mu2, int nrhs,
           const DotOut& dot = DotOut());
 // full lattice (F64 halves back to back, nrhs = 1): M, M^dag, K = M^dag M
@@ -24,8 +24,8 @@ void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa
 // generic dispatch used by the solver; dot rows hold 2 * blocks for the full lattice
 void op_apply(wl_lattice* L, int op, Prec prec, void* out, const void* in, double kappa, const double* mu2,
               int nrhs, const DotOut& dot = DotOut());
-inline int op_dot_blocks(const wl_lattice* L, int op) {
-  return (op == WL_OP_K ? 2 : 1) * hop_grid_blocks(L);
+inline int op_dot_blocks(const wl_lattice* L, int op, Prec prec) {
+  return (op == WL_OP_K ? 2 : 1) * hop_tiles(L, prec);
 }
 inline size_t op_field_bytes(const wl_lattice* L, int op, Prec prec, int nrhs) {
   return (op == WL_OP_K ? 2 : 1) * spinor_bytes(prec, L->Vh) * size_t(nrhs);
@@ -38,17 +38,21 @@ void cdot_host(wl_lattice* L, const void* x, const void* y, int nrhs, double* ou
 // CG (solver.cpp) on J (even sites) or the full-lattice K
 int cg_run(wl_lattice* L, void* x, const void* b, double kappa, const double* mu2, int nrhs, int op,
            const wl_cg_params& prm, wl_cg_stats* stats);
-// CG on a general HPD operator on even-site F64 fields (one rhs):
-// apply(out, in) must leave out = A in.  Used for P(J) and P(J) J.
-int cg_run_generic(wl_lattice* L, void* x, const void* b, const std::function<void(void*, const void*)>& apply,
-                   const wl_cg_params& prm, wl_cg_stats* stats);
+// CG on a general HPD operator on even-site fields (one rhs, x and b F64):
+// apply(prec, out, in) must leave out = A in with fields of storage precision
+// prec (prm.inner for the iteration, F64 for true residuals).  Used for P(J)
+// and P(J) J.
+int cg_run_generic(wl_lattice* L, void* x, const void* b,
+                   const std::function<void(Prec, void*, const void*)>& apply, const wl_cg_params& prm,
+                   wl_cg_stats* stats);
 
 // polynomial filter (poly.cpp), F64, one rhs
 struct PolyDesc {
   int n;
   double a, b;
 };
-void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd);
+void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
+                Prec pr = F64);
 double poly_lead(const PolyDesc& pd);
 void poly_q_roots(const PolyDesc& pd, std::vector<double>& re, std::vector<double>& im);
 

@@ -301,6 +301,22 @@ class WilsonLattice:
         W.check(self.lib.hmc_trajectory(self.h, C.byref(prm), _ptr(P), _ptr(chi), u, C.byref(res)))
         return res
 
+    def set_hop_variant(self, prec, variant: int):
+        """0: thread per site; 1: direction-parallel (default)."""
+        W.check(self.lib.wl_set_hop_variant(self.h, _prec(prec), int(variant)))
+
+    def autotune(self):
+        """Time both hop variants per precision, keep the faster; returns {prec: (site_us, dp_us)}."""
+        us = (C.c_double * 6)()
+        W.check(self.lib.wl_autotune(self.h, us))
+        return {name: (us[2 * i], us[2 * i + 1]) for name, i in PREC.items()}
+
+    def time_hop(self, prec="f64", nrhs: int = 1, nlaunch: int = 200) -> float:
+        """Average microseconds per hop launch over a back-to-back burst."""
+        us = C.c_double()
+        W.check(self.lib.wl_time_hop(self.h, _prec(prec), nrhs, nlaunch, C.byref(us)))
+        return us.value
+
     def profile(self, enable: bool = True):
         W.check(self.lib.wl_profile(self.h, int(enable)))
 
@@ -321,3 +337,16 @@ class WilsonLattice:
         a, b = C.c_longlong(), C.c_longlong()
         W.check(self.lib.wl_counters(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+
+def integrator_schedule(nsteps: Sequence[int], integrator: str = "omelyan", omelyan_lambda: float = 0.0):
+    """The library's overlaid integrator schedule (host only): list of
+    ('S', scale, weight) and ('T', weight), weights in units of tau."""
+    lib = W.load()
+    ns = (C.c_int * len(nsteps))(*[int(n) for n in nsteps])
+    n = C.c_int()
+    cap = 4 * sum(int(v) for v in nsteps) + 8
+    kinds, terms, w = (C.c_int * cap)(), (C.c_int * cap)(), (C.c_double * cap)()
+    sch = W.WL_INT_OMELYAN if integrator == "omelyan" else W.WL_INT_LEAPFROG
+    W.check(lib.wl_integrator_schedule(ns, len(nsteps), sch, omelyan_lambda, kinds, terms, w, cap, C.byref(n)))
+    return [("T", w[k]) if kinds[k] == 1 else ("S", terms[k], w[k]) for k in range(n.value)]

@@ -19,10 +19,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make_lattice(L, a=0.447, seed=1003, unit=False):
+def make_lattice(L, a=0.447, seed=1003, unit=False, variant=None):
     from paper_1702_00124_amd.lattice import WilsonLattice
     need_gpu()
     lat = WilsonLattice(L, t_bc=-1)
+    if variant is not None:
+        for prec in ("f64", "f32", "bf16"):
+            lat.set_hop_variant(prec, variant)
     U = li.unit_links(L) if unit else li.random_links(L, a, seed)
     lat.set_links(torch.from_numpy(U))
     return lat, U

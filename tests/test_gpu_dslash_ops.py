@@ -37,12 +37,16 @@ def test_layout_roundtrips(L):
     assert np.array_equal(to_np(lat.export_su3(lat.import_su3(torch.from_numpy(p)))), p)
 
 
+VARIANTS = [0, 1]   # thread per site, direction-parallel
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("L", SHAPES)
 @pytest.mark.parametrize("parity", [0, 1])
 @pytest.mark.parametrize("dagger", [False, True])
-def test_dslash_f64_matches_oracle(L, parity, dagger):
-    say("dslash f64", L, parity, dagger)
-    lat, U = make_lattice(L)
+def test_dslash_f64_matches_oracle(L, parity, dagger, variant):
+    say("dslash f64", L, parity, dagger, "variant", variant)
+    lat, U = make_lattice(L, variant=variant)
     psi = half_noise(L, 10 + parity)
     got = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi)), parity, dagger)))
     ref = ow.hop_eo(U, psi, L, parity, t_bc=-1, dagger=dagger)
@@ -70,11 +74,12 @@ def test_dslash_free_field_plane_wave_at_full_size():
     assert rel(got_o, expect[od]) <= 1e-13
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-6), ("bf16", 2e-2)])
-def test_dslash_low_precision_error(prec, tol):
+def test_dslash_low_precision_error(prec, tol, variant):
     L = (8, 8, 8, 8)
-    say("dslash", prec, L)
-    lat, U = make_lattice(L)
+    say("dslash", prec, L, "variant", variant)
+    lat, U = make_lattice(L, variant=variant)
     psi = half_noise(L, 21, nrhs=4)
     got = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi), prec), 0, prec=prec, nrhs=4),
                                   prec, 4))
@@ -85,16 +90,36 @@ def test_dslash_low_precision_error(prec, tol):
         assert e <= tol
 
 
-@pytest.mark.parametrize("nrhs", [2, 3])
-def test_dslash_multi_rhs_equals_single(nrhs):
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [2, 3, 4])
+def test_dslash_multi_rhs_equals_single(nrhs, prec, variant):
+    """Batched rhs give bit-identical results to one-at-a-time (same arithmetic per rhs)."""
     L = (6, 4, 4, 10)
-    say("dslash multi-rhs", nrhs)
-    lat, U = make_lattice(L)
+    say("dslash multi-rhs", nrhs, prec, "variant", variant)
+    lat, U = make_lattice(L, variant=variant)
     psi = half_noise(L, 31, nrhs=nrhs)
-    multi = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi)), 1, nrhs=nrhs), "f64", nrhs))
+    multi = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi), prec), 1, prec=prec,
+                                               nrhs=nrhs), prec, nrhs))
     for r in range(nrhs):
-        single = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi[r])), 1)))
+        single = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi[r]), prec), 1, prec=prec),
+                                         prec))
         assert np.array_equal(multi[r], single)
+
+
+def test_variants_agree_and_autotune():
+    L = (8, 8, 8, 8)
+    say("variants agree / autotune")
+    lat, U = make_lattice(L)
+    psi = half_noise(L, 33)
+    outs = []
+    for v in VARIANTS:
+        lat.set_hop_variant("f64", v)
+        outs.append(to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi)), 0))))
+    assert rel(outs[0], outs[1]) <= 1e-14
+    res = lat.autotune()
+    say(f"  autotune us per launch (site, dir-parallel): {res}")
+    assert all(a > 0 and b > 0 for a, b in res.values())
 
 
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 4, 10)])
