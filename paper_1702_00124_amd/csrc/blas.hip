@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, double* x64, c
     Spinor<R> pv = SpinorIO<P>::load(p + off, h, Vh);
     Spinor<R> av = SpinorIO<P>::load(Ap + off, h, Vh);
     Spinor<R> rv = SpinorIO<P>::load(r + off, h, Vh);
-    char* xb = reinterpret_cast<char*>(x64) + f * size_t(192) * Vh;
+    char* xb = reinterpret_cast<char*>(x64) + f * size_t(192) * g.Vhp;
     Spinor<double> xv = SpinorIO<PrecF64>::load(xb, h, Vh);
     const R ar = R(alpha);
 #pragma unroll

@@ -113,14 +113,13 @@ int wl_create(wl_lattice** out, const int32_t Ls[4], int32_t t_bc, void* hip_str
       L->Vh = int(V / 2);
       L->geo.Lxh = Ls[0] / 2;
       L->geo.Vh = L->Vh;
+      L->geo.Vhp = padded_sites(L->Vh);
       L->geo.tbc = t_bc;
       L->stream = static_cast<hipStream_t>(hip_stream);
-      device_alloc(&L->U[F64], size_t(576) * L->V);
-      device_alloc(&L->U[F32], size_t(192) * L->V);
-      device_alloc(&L->U[BF16], size_t(96) * L->V);
+      for (int p = 0; p < 3; ++p) device_alloc(&L->U[p], links_bytes(Prec(p), L->Vh));
       device_alloc(reinterpret_cast<void**>(&L->dscal), kScal * sizeof(double));
       WL_HIP(hipHostMalloc(reinterpret_cast<void**>(&L->hscal), kScal * sizeof(double), hipHostMallocDefault));
-      WL_HIP(hipMemsetAsync(L->U[F64], 0, size_t(576) * L->V, L->stream));
+      WL_HIP(hipMemsetAsync(L->U[F64], 0, links_bytes(F64, L->Vh), L->stream));
       WL_HIP(hipMemsetAsync(L->dscal, 0, kScal * sizeof(double), L->stream));
       ensure_partials(L, size_t(4) * kMaxRhs * site_blocks(L->Vh) + 64);
       WL_HIP(hipStreamSynchronize(L->stream));

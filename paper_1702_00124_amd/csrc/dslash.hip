@@ -54,7 +54,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h,
   constexpr int SF = DAG ? +1 : -1;  // projector sign of the forward term
   constexpr int SB = -SF;
   const int Vh = a.g.Vh;
-  const size_t lb = LinkIO<P>::bytes * size_t(Vh);
+  const size_t lb = LinkIO<P>::bytes * size_t(a.g.Vhp);
   bool wrap;
   // forward: U_mu(x) in(x + mu)
   {
@@ -182,7 +182,7 @@ __device__ __forceinline__ void dp_dir(const HopArgs& a, const Coord& c, int h, 
   constexpr int S = FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1);  // projector sign (1 + S g_mu)
   constexpr int D = 2 * MU + (FWD ? 0 : 1);
   const int Vh = a.g.Vh;
-  const size_t lb = LinkIO<P>::bytes * size_t(Vh);
+  const size_t lb = LinkIO<P>::bytes * size_t(a.g.Vhp);
   bool wrap;
   const int hn = neighbour<MU>(a.g, c, FWD ? +1 : -1, &wrap);
   const SU3<R> U = FWD ? LinkIO<P>::load(a.links + (a.parity * 4 + MU) * lb, h, Vh)

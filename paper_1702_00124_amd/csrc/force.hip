@@ -59,15 +59,16 @@ __device__ __forceinline__ void su3_from_coeffs(const double* p, cd* H) {
   H[7] = {0.5 * p[5], 0.5 * p[6]};
 }
 
-__device__ __forceinline__ const double2* link_ptr(const void* U, int p, int mu, int Vh) {
-  return reinterpret_cast<const double2*>(U) + size_t(p * 4 + mu) * 9 * Vh;
+// F64 links in the tiled layout of wl_device.h: block (parity, mu) of 9 x Vhp
+__device__ __forceinline__ const double2* link_ptr(const void* U, int p, int mu, int Vhp) {
+  return reinterpret_cast<const double2*>(U) + size_t(p * 4 + mu) * 9 * Vhp;
 }
 
-__device__ __forceinline__ void load_link(const void* U, int p, int mu, int h, int Vh, cd* m) {
-  const double2* b = link_ptr(U, p, mu, Vh);
+__device__ __forceinline__ void load_link(const void* U, int p, int mu, int h, int Vhp, cd* m) {
+  const double2* b = link_ptr(U, p, mu, Vhp);
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const double2 v = b[k * Vh + h];
+    const double2 v = b[fidx(k, h, 9)];
     m[k] = {v.x, v.y};
   }
 }
@@ -82,7 +83,7 @@ __device__ __forceinline__ Coord step(const Geo& g, Coord c, int nu, int d) {
 
 __device__ __forceinline__ void load_link_at(const void* U, const Geo& g, Coord c, int mu, cd* m) {
   const int p = (c.x + c.y + c.z + c.t) & 1;
-  load_link(U, p, mu, half_index(g, c.x, c.y, c.z, c.t), g.Vh, m);
+  load_link(U, p, mu, half_index(g, c.x, c.y, c.z, c.t), g.Vhp, m);
 }
 
 // ------------------------------------------------------------------ fermion bilinear
@@ -111,7 +112,7 @@ __device__ __forceinline__ void bilinear_dir(const Geo& g, const Coord& c, int p
       Xi[3 * a + b] = hC.c[a] * conj(hA.c[b]) + hC.c[3 + a] * conj(hA.c[3 + b]);
       Th[3 * a + b] = gC.c[a] * conj(gA.c[b]) + gC.c[3 + a] * conj(gA.c[3 + b]);
     }
-  load_link(U, p, MU, h, g.Vh, Um);
+  load_link(U, p, MU, h, g.Vhp, Um);
   if (wrap) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) Um[k] = double(g.tbc) * Um[k];
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void gauge_force_kernel(Geo g, double* F, c
     for (int k = 0; k < 9; ++k) A[k] = A[k] + s[k];
   }
   cd Um[9], G[9];
-  load_link(U, p, mu, h, g.Vh, Um);
+  load_link(U, p, mu, h, g.Vhp, Um);
   mat_mul(Um, A, G);
   double gr[8];
   su3_grad(G, gr);
@@ -266,16 +267,16 @@ __global__ __launch_bounds__(kBlock) void link_update_kernel(Geo g, void* U, con
   for (int a = 0; a < 8; ++a) pc[a] = pp[a * g.Vh + h];
   cd E[9], Um[9], Un[9];
   su3_expi(pc, eps, E);
-  double2* b = reinterpret_cast<double2*>(U) + size_t(pm) * 9 * g.Vh;
+  double2* b = reinterpret_cast<double2*>(U) + size_t(pm) * 9 * g.Vhp;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const double2 v = b[k * g.Vh + h];
+    const double2 v = b[fidx(k, h, 9)];
     Um[k] = {v.x, v.y};
   }
   mat_mul(E, Um, Un);
   reunitarize(Un);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) b[k * g.Vh + h] = make_double2(Un[k].r, Un[k].i);
+  for (int k = 0; k < 9; ++k) b[fidx(k, h, 9)] = make_double2(Un[k].r, Un[k].i);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -289,10 +290,10 @@ __global__ __launch_bounds__(kBlock) void plaquette_kernel(Geo g, const void* U,
     for (int mu = 0; mu < 4; ++mu) {
       for (int nu = mu + 1; nu < 4; ++nu) {
         cd a[9], b[9], c[9], d[9], t1[9], t2[9];
-        load_link(U, p, mu, h, g.Vh, a);
+        load_link(U, p, mu, h, g.Vhp, a);
         load_link_at(U, g, step(g, x, mu, +1), nu, b);
         load_link_at(U, g, step(g, x, nu, +1), mu, c);
-        load_link(U, p, nu, h, g.Vh, d);
+        load_link(U, p, nu, h, g.Vhp, d);
         mat_mul(a, b, t1);  // U_mu(x) U_nu(x+mu)
         mat_mul(d, c, t2);  // U_nu(x) U_mu(x+nu)
         // Re tr(t1 t2^dag)

@@ -107,7 +107,7 @@ int hmc_run(wl_lattice* L, const wl_hmc_params& prm, double* P, const void* chi,
   long long cg_iters = 0;
 
   // keep the starting links for a rejection
-  const size_t ub = size_t(576) * L->V;
+  const size_t ub = links_bytes(F64, L->Vh);
   void* Ubak = ws_get(L, "hmc_Ubak", ub);
   copy_dev(L, Ubak, L->U[F64], ub);
 

@@ -26,9 +26,9 @@ __global__ void pack_links_kernel(Geo g, const double2* canon, double2* U) {
   int p, h;
   site_parity(g, s, &p, &h);
   const double2* src = canon + (size_t(mu) * V + s) * 9;
-  double2* dst = U + size_t(p * 4 + mu) * 9 * g.Vh;
+  double2* dst = U + size_t(p * 4 + mu) * 9 * g.Vhp;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) dst[k * g.Vh + h] = src[k];
+  for (int k = 0; k < 9; ++k) dst[fidx(k, h, 9)] = src[k];
 }
 
 __global__ void unpack_links_kernel(Geo g, double2* canon, const double2* U) {
@@ -39,9 +39,9 @@ __global__ void unpack_links_kernel(Geo g, double2* canon, const double2* U) {
   int p, h;
   site_parity(g, s, &p, &h);
   double2* dst = canon + (size_t(mu) * V + s) * 9;
-  const double2* src = U + size_t(p * 4 + mu) * 9 * g.Vh;
+  const double2* src = U + size_t(p * 4 + mu) * 9 * g.Vhp;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) dst[k] = src[k * g.Vh + h];
+  for (int k = 0; k < 9; ++k) dst[k] = src[fidx(k, h, 9)];
 }
 
 // FP32 and BF16 copies keep the first two rows only
@@ -49,18 +49,18 @@ __global__ void lowp_links_kernel(Geo g, const double2* U, float4* U32, uint2* U
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   const int pm = blockIdx.y;  // parity * 4 + mu
   if (h >= g.Vh) return;
-  const double2* src = U + size_t(pm) * 9 * g.Vh;
+  const double2* src = U + size_t(pm) * 9 * g.Vhp;
   double2 m[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) m[k] = src[k * g.Vh + h];
+  for (int k = 0; k < 6; ++k) m[k] = src[fidx(k, h, 9)];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const double2 a = m[2 * j], b = m[2 * j + 1];
-    U32[(size_t(pm) * 3 + j) * g.Vh + h] = make_float4(float(a.x), float(a.y), float(b.x), float(b.y));
+    U32[size_t(pm) * 3 * g.Vhp + fidx(j, h, 3)] = make_float4(float(a.x), float(a.y), float(b.x), float(b.y));
     uint2 v;
     v.x = pack_bf16x2(float(a.x), float(a.y));
     v.y = pack_bf16x2(float(b.x), float(b.y));
-    U16[(size_t(pm) * 3 + j) * g.Vh + h] = v;
+    U16[size_t(pm) * 3 * g.Vhp + fidx(j, h, 3)] = v;
   }
 }
 

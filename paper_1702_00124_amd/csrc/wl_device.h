@@ -6,17 +6,25 @@
 //     in lexicographic order s = x + Lx*(y + Ly*(z + Lz*t)) has h = i.
 //   * spinor component c = 3*spin + colour; chiral gamma basis with
 //     gamma_5 = diag(1, 1, -1, -1).
-//   * storage is structure-of-arrays over h so that a wavefront reads 64
-//     consecutive sites per load instruction, 16 bytes per lane:
-//       F64  spinor: double2 [12][Vh]   link: double2 [9][Vh]
-//       F32  spinor: float4  [6][Vh]    link: float4  [3][Vh]  (two rows)
-//       BF16 spinor: uint4   [3][Vh]    link: uint2   [3][Vh]  (two rows)
+//   * storage is structure-of-arrays within tiles of 64 sites, so that a
+//     wavefront reads 64 consecutive sites per load instruction (16 bytes per
+//     lane) and all components of a tile lie in one contiguous block:
+//     element (component u of NU, site h) sits at ((h/64) NU + u) 64 + h%64,
+//     and a field spans Vh rounded up to a multiple of 64 sites:
+//       F64  spinor: double2, NU = 12   link: double2, NU = 9
+//       F32  spinor: float4,  NU = 6    link: float4,  NU = 3  (two rows)
+//       BF16 spinor: uint4,   NU = 3    link: uint2,   NU = 3  (two rows)
 //     with the third link row rebuilt as conj(row0 x row1) (SU(3)).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace wl {
+
+// ------------------------------------------------------------------ tiled field index
+constexpr int kSiteTile = 64;
+__host__ __device__ constexpr int padded_sites(int n) { return (n + kSiteTile - 1) / kSiteTile * kSiteTile; }
+__device__ __forceinline__ int fidx(int u, int h, int NU) { return ((h >> 6) * NU + u) * kSiteTile + (h & 63); }
 
 // ------------------------------------------------------------------ complex
 template <typename T>
@@ -99,7 +107,7 @@ struct SpinorIO<PrecF64> {
     Spinor<double> s;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      double2 v = b[c * Vh + h];
+      double2 v = b[fidx(c, h, 12)];
       s.c[c] = {v.x, v.y};
     }
     return s;
@@ -107,7 +115,7 @@ struct SpinorIO<PrecF64> {
   static __device__ __forceinline__ void store(void* base, int h, int Vh, const Spinor<double>& s) {
     double2* b = reinterpret_cast<double2*>(base);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) b[c * Vh + h] = make_double2(s.c[c].r, s.c[c].i);
+    for (int c = 0; c < 12; ++c) b[fidx(c, h, 12)] = make_double2(s.c[c].r, s.c[c].i);
   }
 };
 
@@ -118,7 +126,7 @@ struct SpinorIO<PrecF32> {
     Spinor<float> s;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      float4 v = b[j * Vh + h];
+      float4 v = b[fidx(j, h, 6)];
       s.c[2 * j] = {v.x, v.y};
       s.c[2 * j + 1] = {v.z, v.w};
     }
@@ -128,7 +136,7 @@ struct SpinorIO<PrecF32> {
     float4* b = reinterpret_cast<float4*>(base);
 #pragma unroll
     for (int j = 0; j < 6; ++j)
-      b[j * Vh + h] = make_float4(s.c[2 * j].r, s.c[2 * j].i, s.c[2 * j + 1].r, s.c[2 * j + 1].i);
+      b[fidx(j, h, 6)] = make_float4(s.c[2 * j].r, s.c[2 * j].i, s.c[2 * j + 1].r, s.c[2 * j + 1].i);
   }
 };
 
@@ -139,7 +147,7 @@ struct SpinorIO<PrecBF16> {
     Spinor<float> s;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      uint4 v = b[j * Vh + h];
+      uint4 v = b[fidx(j, h, 3)];
       uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int q = 0; q < 4; ++q) s.c[4 * j + q] = {bf16_to_f32(w[q] & 0xFFFFu), bf16_to_f32(w[q] >> 16)};
@@ -155,7 +163,7 @@ struct SpinorIO<PrecBF16> {
       v.y = pack_bf16x2(s.c[4 * j + 1].r, s.c[4 * j + 1].i);
       v.z = pack_bf16x2(s.c[4 * j + 2].r, s.c[4 * j + 2].i);
       v.w = pack_bf16x2(s.c[4 * j + 3].r, s.c[4 * j + 3].i);
-      b[j * Vh + h] = v;
+      b[fidx(j, h, 3)] = v;
     }
   }
 };
@@ -168,11 +176,11 @@ template <>
 struct UnitIO<PrecF64> {
   static constexpr int NU = 12, CPU = 1;
   static __device__ __forceinline__ void load(const void* base, int u, int h, int Vh, cplx<double>* c) {
-    const double2 v = reinterpret_cast<const double2*>(base)[u * Vh + h];
+    const double2 v = reinterpret_cast<const double2*>(base)[fidx(u, h, 12)];
     c[0] = {v.x, v.y};
   }
   static __device__ __forceinline__ void store(void* base, int u, int h, int Vh, const cplx<double>* c) {
-    reinterpret_cast<double2*>(base)[u * Vh + h] = make_double2(c[0].r, c[0].i);
+    reinterpret_cast<double2*>(base)[fidx(u, h, 12)] = make_double2(c[0].r, c[0].i);
   }
 };
 
@@ -180,12 +188,12 @@ template <>
 struct UnitIO<PrecF32> {
   static constexpr int NU = 6, CPU = 2;
   static __device__ __forceinline__ void load(const void* base, int u, int h, int Vh, cplx<float>* c) {
-    const float4 v = reinterpret_cast<const float4*>(base)[u * Vh + h];
+    const float4 v = reinterpret_cast<const float4*>(base)[fidx(u, h, 6)];
     c[0] = {v.x, v.y};
     c[1] = {v.z, v.w};
   }
   static __device__ __forceinline__ void store(void* base, int u, int h, int Vh, const cplx<float>* c) {
-    reinterpret_cast<float4*>(base)[u * Vh + h] = make_float4(c[0].r, c[0].i, c[1].r, c[1].i);
+    reinterpret_cast<float4*>(base)[fidx(u, h, 6)] = make_float4(c[0].r, c[0].i, c[1].r, c[1].i);
   }
 };
 
@@ -193,7 +201,7 @@ template <>
 struct UnitIO<PrecBF16> {
   static constexpr int NU = 3, CPU = 4;
   static __device__ __forceinline__ void load(const void* base, int u, int h, int Vh, cplx<float>* c) {
-    const uint4 v = reinterpret_cast<const uint4*>(base)[u * Vh + h];
+    const uint4 v = reinterpret_cast<const uint4*>(base)[fidx(u, h, 3)];
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) c[q] = {bf16_to_f32(w[q] & 0xFFFFu), bf16_to_f32(w[q] >> 16)};
@@ -204,7 +212,7 @@ struct UnitIO<PrecBF16> {
     v.y = pack_bf16x2(c[1].r, c[1].i);
     v.z = pack_bf16x2(c[2].r, c[2].i);
     v.w = pack_bf16x2(c[3].r, c[3].i);
-    reinterpret_cast<uint4*>(base)[u * Vh + h] = v;
+    reinterpret_cast<uint4*>(base)[fidx(u, h, 3)] = v;
   }
 };
 
@@ -227,7 +235,7 @@ struct LinkIO<PrecF64> {
     SU3<double> u;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      double2 v = b[k * Vh + h];
+      double2 v = b[fidx(k, h, 9)];
       u.m[k] = {v.x, v.y};
     }
     return u;
@@ -242,7 +250,7 @@ struct LinkIO<PrecF32> {
     SU3<float> u;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      float4 v = b[j * Vh + h];
+      float4 v = b[fidx(j, h, 3)];
       u.m[2 * j] = {v.x, v.y};
       u.m[2 * j + 1] = {v.z, v.w};
     }
@@ -259,7 +267,7 @@ struct LinkIO<PrecBF16> {
     SU3<float> u;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      uint2 v = b[j * Vh + h];
+      uint2 v = b[fidx(j, h, 3)];
       u.m[2 * j] = {bf16_to_f32(v.x & 0xFFFFu), bf16_to_f32(v.x >> 16)};
       u.m[2 * j + 1] = {bf16_to_f32(v.y & 0xFFFFu), bf16_to_f32(v.y >> 16)};
     }
@@ -337,6 +345,7 @@ struct Geo {
   int L[4];
   int Lxh;   // Lx / 2
   int Vh;    // V / 2
+  int Vhp;   // Vh rounded up to whole 64-site tiles (field extent)
   int tbc;   // +1 periodic, -1 antiperiodic in time (fermions only)
 };
 

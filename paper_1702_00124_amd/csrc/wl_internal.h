@@ -40,8 +40,13 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::wl::Error(code, msg); \
   } while (0)
 
+// bytes of one half-lattice spinor field (padded to whole 64-site tiles)
 inline size_t spinor_bytes(Prec p, int Vh) {
-  return size_t(p == F64 ? 192 : (p == F32 ? 96 : 48)) * size_t(Vh);
+  return size_t(p == F64 ? 192 : (p == F32 ? 96 : 48)) * size_t(padded_sites(Vh));
+}
+// bytes of all packed links of one precision: 2 parities x 4 directions
+inline size_t links_bytes(Prec p, int Vh) {
+  return size_t(8) * size_t(p == F64 ? 144 : (p == F32 ? 48 : 24)) * size_t(padded_sites(Vh));
 }
 inline size_t link_bytes(Prec p) { return p == F64 ? 144 : (p == F32 ? 48 : 24); }
 
