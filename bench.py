@@ -44,9 +44,9 @@ MU2_HASENBUSCH = 0.05
 POLY_N, POLY_A, POLY_B = 16, 0.001, 8.0
 NSTEPS = [40, 20, 20, 80]
 SHIFTS = [0.0, 0.005, 0.05, 0.5, 0.0, 0.005, 0.05, 0.5]
-# algorithmic bytes of one hop application per output site: 8 links + input
+# algorithmic bytes of one hop application per output site: 8 two-row links + input
 # spinor read once + output spinor written once (perfect on-chip reuse)
-HOP_BYTES_PER_SITE = {"f64": 8 * 144 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8 * 24 + 2 * 48}
+HOP_BYTES_PER_SITE = {"f64": 8 * 96 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8 * 24 + 2 * 48}
 
 
 # HBM traffic of one hop launch on this workload from two rocprofv3 --pmc runs

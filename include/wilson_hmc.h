@@ -249,6 +249,10 @@ int wl_autotune(wl_lattice* lat, double* us_out);
  * the library), timed with HIP events on the context stream.  Not counted in
  * the hop counters. */
 int wl_time_hop(wl_lattice* lat, wl_prec prec, int nrhs, int nlaunch, double* avg_us);
+/* Tracing: the practical HBM ceiling: a plain copy of bytes (multiple of 16,
+ * at most 16 GiB) between two library buffers, reps times; *gbs = bytes read
+ * plus written per second (GB/s). */
+int wl_stream_copy(wl_lattice* lat, size_t bytes, int reps, double* gbs);
 
 /* Hop applications since create per storage precision (counts[wl_prec], single rhs units). */
 int wl_hop_counts(const wl_lattice* lat, long long* counts);

@@ -84,6 +84,7 @@ SIGNATURES = {
     "wl_set_hop_variant": (I, [P, I, I]),
     "wl_autotune": (I, [P, C.POINTER(D)]),
     "wl_time_hop": (I, [P, I, I, I, C.POINTER(D)]),
+    "wl_stream_copy": (I, [P, SZ, I, C.POINTER(D)]),
     "wl_hop_counts": (I, [P, C.POINTER(C.c_longlong)]),
     "wl_profile_read": (I, [P, C.POINTER(D), C.POINTER(C.c_longlong)]),
 }

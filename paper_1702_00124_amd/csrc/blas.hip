@@ -228,6 +228,24 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(Geo g, const char* t,
   SpinorIO<P>::store(eprev + off, h, g.Vh, ep);
 }
 
+// STREAM-style copy (the practical bandwidth ceiling): every thread moves four
+// 16-byte vectors, loads issued before stores
+__global__ __launch_bounds__(kBlock) void stream_copy_kernel(const float4* __restrict__ a, float4* __restrict__ b,
+                                                            size_t n) {
+  const size_t base = (size_t(blockIdx.x) * kBlock * 4) + threadIdx.x;
+  float4 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const size_t i = base + size_t(k) * kBlock;
+    if (i < n) v[k] = a[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const size_t i = base + size_t(k) * kBlock;
+    if (i < n) b[i] = v[k];
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 template <typename F>
 static void by_prec(Prec p, F&& f) {
@@ -323,6 +341,13 @@ void launch_cheb_step(wl_lattice* L, const void* t, const void* w, void* tprev, 
                        (const char*)w, (char*)tprev, (const char*)e, (char*)eprev, spinor_bytes(prec, L->Vh), ct, cw,
                        ce);
   });
+  WL_HIP(hipGetLastError());
+}
+
+void launch_stream_copy(wl_lattice* L, const void* a, void* b, size_t bytes) {
+  const size_t n = bytes / 16;
+  const size_t nb = (n + 4 * kBlock - 1) / (4 * kBlock);
+  hipLaunchKernelGGL(stream_copy_kernel, dim3(unsigned(nb)), dim3(kBlock), 0, L->stream, (const float4*)a, (float4*)b, n);
   WL_HIP(hipGetLastError());
 }
 

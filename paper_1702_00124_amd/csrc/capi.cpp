@@ -116,10 +116,11 @@ int wl_create(wl_lattice** out, const int32_t Ls[4], int32_t t_bc, void* hip_str
       L->geo.Vhp = padded_sites(L->Vh);
       L->geo.tbc = t_bc;
       L->stream = static_cast<hipStream_t>(hip_stream);
+      device_alloc(&L->Ufull, full_links_bytes(L->Vh));
       for (int p = 0; p < 3; ++p) device_alloc(&L->U[p], links_bytes(Prec(p), L->Vh));
       device_alloc(reinterpret_cast<void**>(&L->dscal), kScal * sizeof(double));
       WL_HIP(hipHostMalloc(reinterpret_cast<void**>(&L->hscal), kScal * sizeof(double), hipHostMallocDefault));
-      WL_HIP(hipMemsetAsync(L->U[F64], 0, links_bytes(F64, L->Vh), L->stream));
+      WL_HIP(hipMemsetAsync(L->Ufull, 0, full_links_bytes(L->Vh), L->stream));
       WL_HIP(hipMemsetAsync(L->dscal, 0, kScal * sizeof(double), L->stream));
       ensure_partials(L, size_t(4) * kMaxRhs * site_blocks(L->Vh) + 64);
       WL_HIP(hipStreamSynchronize(L->stream));
@@ -139,6 +140,7 @@ int wl_destroy(wl_lattice* L) {
   for (auto& kv : L->ws) (void)hipFree(kv.second.first);
   for (int p = 0; p < 3; ++p)
     if (L->U[p]) (void)hipFree(L->U[p]);
+  if (L->Ufull) (void)hipFree(L->Ufull);
   if (L->partials) (void)hipFree(L->partials);
   if (L->dscal) (void)hipFree(L->dscal);
   if (L->hscal) (void)hipHostFree(L->hscal);
@@ -471,6 +473,39 @@ int wl_time_hop(wl_lattice* L, wl_prec prec, int nrhs, int nlaunch, double* avg_
     L->n_hop_p[prec] -= (long long)(nlaunch + 3) * nrhs;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    return WL_OK;
+  });
+}
+
+int wl_stream_copy(wl_lattice* L, size_t bytes, int reps, double* gbs) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(gbs && reps >= 1 && bytes >= 16 && bytes % 16 == 0 && bytes <= (size_t(1) << 34), WL_EINVAL,
+               "bad arguments");
+    set_device(L);
+    void* a = ws_get(L, "stream_a", bytes);
+    void* b = ws_get(L, "stream_b", bytes);
+    WL_HIP(hipMemsetAsync(a, 0, bytes, L->stream));
+    hipEvent_t e0, e1;
+    WL_HIP(hipEventCreate(&e0));
+    WL_HIP(hipEventCreate(&e1));
+    launch_stream_copy(L, a, b, bytes);
+    WL_HIP(hipEventRecord(e0, L->stream));
+    for (int i = 0; i < reps; ++i) launch_stream_copy(L, a, b, bytes);
+    WL_HIP(hipEventRecord(e1, L->stream));
+    WL_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    WL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *gbs = 2.0 * double(bytes) * reps / (1e-3 * ms) / 1e9;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // release the two buffers (they can be large)
+    for (const char* n : {"stream_a", "stream_b"}) {
+      auto it = L->ws.find(n);
+      WL_HIP(hipStreamSynchronize(L->stream));
+      WL_HIP(hipFree(it->second.first));
+      L->ws.erase(it);
+    }
     return WL_OK;
   });
 }

@@ -335,7 +335,7 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
                 int nrhs, const HopEpi& e) {
   WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs, WL_EINVAL, "nrhs out of range");
   WL_REQUIRE(out != in, WL_EINVAL, "hop output must not alias its input");
-  if (prec != F64) ensure_lowp_links(L);
+  ensure_lowp_links(L);
   HopArgs a;
   a.g = L->geo;
   a.parity = out_parity;

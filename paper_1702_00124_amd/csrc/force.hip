@@ -320,26 +320,26 @@ void launch_bilinear(wl_lattice* L, double* F, const void* Ae, const void* Ao, c
                      double coeff) {
   dim3 grid(site_blocks(L->Vh), 2);
   hipLaunchKernelGGL(bilinear_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, F, (const char*)Ae,
-                     (const char*)Ao, (const char*)Ce, (const char*)Co, L->U[F64], coeff);
+                     (const char*)Ao, (const char*)Ce, (const char*)Co, L->Ufull, coeff);
   WL_HIP(hipGetLastError());
 }
 
 void launch_gauge_force(wl_lattice* L, double* F, double coeff) {
   dim3 grid(site_blocks(L->Vh), 8);
-  hipLaunchKernelGGL(gauge_force_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, F, L->U[F64], coeff);
+  hipLaunchKernelGGL(gauge_force_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, F, L->Ufull, coeff);
   WL_HIP(hipGetLastError());
 }
 
 void launch_link_update(wl_lattice* L, const double* P, double eps) {
   dim3 grid(site_blocks(L->Vh), 8);
-  hipLaunchKernelGGL(link_update_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, L->U[F64], P, eps);
+  hipLaunchKernelGGL(link_update_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, L->Ufull, P, eps);
   WL_HIP(hipGetLastError());
   L->lowp_valid = false;
 }
 
 void launch_plaquette_partials(wl_lattice* L, double* partials) {
   dim3 grid(site_blocks(L->Vh), 2);
-  hipLaunchKernelGGL(plaquette_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, L->U[F64], partials);
+  hipLaunchKernelGGL(plaquette_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, L->Ufull, partials);
   WL_HIP(hipGetLastError());
 }
 

@@ -107,9 +107,9 @@ int hmc_run(wl_lattice* L, const wl_hmc_params& prm, double* P, const void* chi,
   long long cg_iters = 0;
 
   // keep the starting links for a rejection
-  const size_t ub = links_bytes(F64, L->Vh);
+  const size_t ub = full_links_bytes(L->Vh);
   void* Ubak = ws_get(L, "hmc_Ubak", ub);
-  copy_dev(L, Ubak, L->U[F64], ub);
+  copy_dev(L, Ubak, L->Ufull, ub);
 
   // heatbath
   std::vector<void*> phi(nt);
@@ -151,7 +151,7 @@ int hmc_run(wl_lattice* L, const wl_hmc_params& prm, double* P, const void* chi,
   r.H1 = hamiltonian(r.S1);
   r.dH = r.H1 - r.H0;
   r.accepted = (prm.flags & WL_HMC_NO_METROPOLIS) ? 1 : (u < std::exp(-r.dH) ? 1 : 0);
-  if (!r.accepted) copy_dev(L, L->U[F64], Ubak, ub);
+  if (!r.accepted) copy_dev(L, L->Ufull, Ubak, ub);
   L->lowp_valid = false;
   r.plaquette = plaquette_host(L);
   r.n_kmat = L->n_kmat - kmat0;

@@ -44,8 +44,8 @@ __global__ void unpack_links_kernel(Geo g, double2* canon, const double2* U) {
   for (int k = 0; k < 9; ++k) dst[k] = src[fidx(k, h, 9)];
 }
 
-// FP32 and BF16 copies keep the first two rows only
-__global__ void lowp_links_kernel(Geo g, const double2* U, float4* U32, uint2* U16) {
+// hop copies of the links (FP64, FP32, BF16) keep the first two rows only
+__global__ void lowp_links_kernel(Geo g, const double2* U, double2* U64, float4* U32, uint2* U16) {
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   const int pm = blockIdx.y;  // parity * 4 + mu
   if (h >= g.Vh) return;
@@ -53,6 +53,8 @@ __global__ void lowp_links_kernel(Geo g, const double2* U, float4* U32, uint2* U
   double2 m[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) m[k] = src[fidx(k, h, 9)];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) U64[size_t(pm) * 6 * g.Vhp + fidx(k, h, 6)] = m[k];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const double2 a = m[2 * j], b = m[2 * j + 1];
@@ -127,7 +129,7 @@ __global__ void su3_io_kernel(Geo g, double* internal, double* canon, int to_can
 void launch_pack_links(wl_lattice* L, const void* canon) {
   dim3 grid(site_blocks(L->V), 4);
   hipLaunchKernelGGL(pack_links_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (const double2*)canon,
-                     (double2*)L->U[F64]);
+                     (double2*)L->Ufull);
   WL_HIP(hipGetLastError());
   L->lowp_valid = false;
 }
@@ -135,14 +137,14 @@ void launch_pack_links(wl_lattice* L, const void* canon) {
 void launch_unpack_links(wl_lattice* L, void* canon) {
   dim3 grid(site_blocks(L->V), 4);
   hipLaunchKernelGGL(unpack_links_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (double2*)canon,
-                     (const double2*)L->U[F64]);
+                     (const double2*)L->Ufull);
   WL_HIP(hipGetLastError());
 }
 
 void launch_lowp_links(wl_lattice* L) {
   dim3 grid(site_blocks(L->Vh), 8);
-  hipLaunchKernelGGL(lowp_links_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (const double2*)L->U[F64],
-                     (float4*)L->U[F32], (uint2*)L->U[BF16]);
+  hipLaunchKernelGGL(lowp_links_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (const double2*)L->Ufull,
+                     (double2*)L->U[F64], (float4*)L->U[F32], (uint2*)L->U[BF16]);
   WL_HIP(hipGetLastError());
   L->lowp_valid = true;
 }

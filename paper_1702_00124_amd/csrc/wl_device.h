@@ -11,7 +11,7 @@
 //     lane) and all components of a tile lie in one contiguous block:
 //     element (component u of NU, site h) sits at ((h/64) NU + u) 64 + h%64,
 //     and a field spans Vh rounded up to a multiple of 64 sites:
-//       F64  spinor: double2, NU = 12   link: double2, NU = 9
+//       F64  spinor: double2, NU = 12   link: double2, NU = 6  (two rows)
 //       F32  spinor: float4,  NU = 6    link: float4,  NU = 3  (two rows)
 //       BF16 spinor: uint4,   NU = 3    link: uint2,   NU = 3  (two rows)
 //     with the third link row rebuilt as conj(row0 x row1) (SU(3)).
@@ -229,15 +229,16 @@ struct LinkIO;
 
 template <>
 struct LinkIO<PrecF64> {
-  static constexpr int bytes = 144;  // per link
+  static constexpr int bytes = 96;  // per link: two rows of double2
   static __device__ __forceinline__ SU3<double> load(const void* base, int h, int Vh) {
     const double2* b = reinterpret_cast<const double2*>(base);
     SU3<double> u;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      double2 v = b[fidx(k, h, 9)];
+    for (int k = 0; k < 6; ++k) {
+      double2 v = b[fidx(k, h, 6)];
       u.m[k] = {v.x, v.y};
     }
+    third_row(u);
     return u;
   }
 };

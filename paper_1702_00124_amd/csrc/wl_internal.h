@@ -44,11 +44,13 @@ struct Error : std::runtime_error {
 inline size_t spinor_bytes(Prec p, int Vh) {
   return size_t(p == F64 ? 192 : (p == F32 ? 96 : 48)) * size_t(padded_sites(Vh));
 }
-// bytes of all packed links of one precision: 2 parities x 4 directions
+// bytes of the two-row hop links of one precision: 2 parities x 4 directions
 inline size_t links_bytes(Prec p, int Vh) {
-  return size_t(8) * size_t(p == F64 ? 144 : (p == F32 ? 48 : 24)) * size_t(padded_sites(Vh));
+  return size_t(8) * size_t(p == F64 ? 96 : (p == F32 ? 48 : 24)) * size_t(padded_sites(Vh));
 }
-inline size_t link_bytes(Prec p) { return p == F64 ? 144 : (p == F32 ? 48 : 24); }
+// bytes of the full FP64 links (3 rows)
+inline size_t full_links_bytes(int Vh) { return size_t(8) * 144 * size_t(padded_sites(Vh)); }
+inline size_t link_bytes(Prec p) { return p == F64 ? 96 : (p == F32 ? 48 : 24); }
 
 }  // namespace wl
 
@@ -61,8 +63,9 @@ struct wl_lattice {
   int V, Vh;
   hipStream_t stream;
   int device;
-  void* U[3] = {nullptr, nullptr, nullptr};  // F64, F32, BF16 packed links
-  bool lowp_valid = false;                   // U[F32], U[BF16] match U[F64]
+  void* Ufull = nullptr;                     // FP64 links, all 3 rows (forces, gauge, updates)
+  void* U[3] = {nullptr, nullptr, nullptr};  // hop links F64 / F32 / BF16, first two rows
+  bool lowp_valid = false;                   // U[*] match Ufull
   double* partials = nullptr;                // reduction partials
   size_t partials_len = 0;
   double* dscal = nullptr;                   // device scalars [kScal]: results, then CG state
@@ -131,6 +134,8 @@ void launch_dot_partials(wl_lattice* L, const void* x, const void* y, int nrhs, 
 // sum partials: out[r * ncomp + c] = sum_b partials[(r * ncomp + c) * stride + b], b < nb
 void launch_finish_sum(wl_lattice* L, const double* partials, int stride, int nb, int nrows,
                        double* out_dev);
+// plain device copy of bytes (multiple of 16) from a to b
+void launch_stream_copy(wl_lattice* L, const void* a, void* b, size_t bytes);
 // Chebyshev recurrence step: tprev <- ct t + cw w - tprev ; eprev <- ce e + 2 t - eprev
 void launch_cheb_step(wl_lattice* L, const void* t, const void* w, void* tprev, const void* e, void* eprev,
                       double ct, double cw, double ce, int nrhs, Prec prec = F64);

@@ -317,6 +317,12 @@ class WilsonLattice:
         W.check(self.lib.wl_time_hop(self.h, _prec(prec), nrhs, nlaunch, C.byref(us)))
         return us.value
 
+    def stream_copy(self, nbytes: int = 1 << 30, reps: int = 10) -> float:
+        """GB/s (read + write) of a plain device copy: the practical HBM ceiling."""
+        g = C.c_double()
+        W.check(self.lib.wl_stream_copy(self.h, nbytes, reps, C.byref(g)))
+        return g.value
+
     def profile(self, enable: bool = True):
         W.check(self.lib.wl_profile(self.h, int(enable)))
 
