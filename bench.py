@@ -56,7 +56,15 @@ HOP_BYTES_PER_SITE = {"f64": 8 * 96 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8
 # Valid only for the kernel source they were taken on (hash of the hop
 # kernel sources); otherwise `traffic` is reported as null.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
-PMC_COUNTERS = {"source_sha256": None, "per_launch_kib": {}}
+PMC_COUNTERS = {
+    "source_sha256": "5076290b9fe40b2503959a5207769692e5599437e91cb9e7fc70179b81e9a5d1",
+    # (precision, variant): KiB per dispatch on the 16^3x32 workload, median of 65-115 dispatches
+    "per_launch_kib": {
+        "f64:site": {"fetch": 34229.4, "write": 12288.0}, "f64:dp": {"fetch": 34014.3, "write": 12288.0},
+        "f32:site": {"fetch": 16999.0, "write": 6144.0}, "f32:dp": {"fetch": 17002.5, "write": 6144.0},
+        "bf16:site": {"fetch": 8566.5, "write": 3072.0}, "bf16:dp": {"fetch": 8576.5, "write": 3072.0},
+    },
+}
 
 
 def hop_source_hash() -> str:
@@ -216,12 +224,13 @@ def main():
     avg_us = lat.time_hop(dom, 1, 500)
     achieved = bytes_per_hop[dom] / (avg_us * 1e-6) / 1e9
     traffic = None
-    kib = PMC_COUNTERS["per_launch_kib"].get(dom)
+    variant = lat_variant(lat, dom)
+    kib = PMC_COUNTERS["per_launch_kib"].get(f"{dom}:{['site', 'dp'][variant]}")
     if kib and PMC_COUNTERS["source_sha256"] == hop_source_hash():
         traffic = int(1024 * (kib["fetch"] * PMC_FETCH_SCALE + kib["write"] * PMC_WRITE_SCALE))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"hop {dom} ({['thread-per-site', 'direction-parallel'][lat_variant(lat, dom)]})",
+                "kernel": f"hop {dom} ({['thread-per-site', 'direction-parallel'][variant]})",
                 "avg_launch_us": round(avg_us, 2), "in_situ_avg_us": round(prof[dom][0], 2),
                 "in_situ_samples": prof[dom][1], "algorithmic_bytes_per_launch": bytes_per_hop[dom]}
     extra = {"hop_avg_us": {p: round(v[0], 2) for p, v in prof.items()},

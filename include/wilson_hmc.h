@@ -244,9 +244,10 @@ int wl_counters(const wl_lattice* lat, long long* n_hop, long long* n_kmat);
  * Results are identical up to the FP summation order of the 8 directions. */
 int wl_set_hop_variant(wl_lattice* lat, wl_prec prec, int variant);
 int wl_autotune(wl_lattice* lat, double* us_out);
-/* Tracing: average duration in microseconds of nlaunch back-to-back hop
- * launches (current variant, nrhs right-hand sides, scratch fields owned by
- * the library), timed with HIP events on the context stream.  Not counted in
+/* Tracing: average duration in microseconds of back-to-back hop launches
+ * (current variant, nrhs right-hand sides, scratch fields owned by the
+ * library), timed with HIP events on the context stream: 100 warm-up
+ * launches, then the median over 5 sub-bursts of nlaunch/5.  Not counted in
  * the hop counters. */
 int wl_time_hop(wl_lattice* lat, wl_prec prec, int nrhs, int nlaunch, double* avg_us);
 /* Tracing: the practical HBM ceiling: a plain copy of bytes (multiple of 16,

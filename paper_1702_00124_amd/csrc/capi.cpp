@@ -461,16 +461,24 @@ int wl_time_hop(wl_lattice* L, wl_prec prec, int nrhs, int nlaunch, double* avg_
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
     HopEpi e;
-    for (int i = 0; i < 3; ++i) launch_hop(L, Prec(prec), b, a, 0, 0, nrhs, e);
-    WL_HIP(hipEventRecord(e0, L->stream));
-    for (int i = 0; i < nlaunch; ++i) launch_hop(L, Prec(prec), b, a, 0, 0, nrhs, e);
-    WL_HIP(hipEventRecord(e1, L->stream));
-    WL_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    WL_HIP(hipEventElapsedTime(&ms, e0, e1));
-    *avg_us = 1e3 * ms / nlaunch;
-    L->n_hop -= (long long)(nlaunch + 3) * nrhs;
-    L->n_hop_p[prec] -= (long long)(nlaunch + 3) * nrhs;
+    // warm-up long enough for the clocks to leave any idle state, then the
+    // median of 5 sub-bursts
+    const int warm = 100, nsub = 5, per = std::max(1, nlaunch / nsub);
+    for (int i = 0; i < warm; ++i) launch_hop(L, Prec(prec), b, a, 0, 0, nrhs, e);
+    std::vector<double> sub;
+    for (int k = 0; k < nsub; ++k) {
+      WL_HIP(hipEventRecord(e0, L->stream));
+      for (int i = 0; i < per; ++i) launch_hop(L, Prec(prec), b, a, 0, 0, nrhs, e);
+      WL_HIP(hipEventRecord(e1, L->stream));
+      WL_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      WL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      sub.push_back(1e3 * ms / per);
+    }
+    std::sort(sub.begin(), sub.end());
+    *avg_us = sub[nsub / 2];
+    L->n_hop -= (long long)(warm + nsub * per) * nrhs;
+    L->n_hop_p[prec] -= (long long)(warm + nsub * per) * nrhs;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return WL_OK;
