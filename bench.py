@@ -112,6 +112,69 @@ print(json.dumps({"n": n, "sec_per_hop": dt}))
                       f"({d['sec_per_hop']:.2f} s each, single-threaded NumPy)"}
 
 
+def large_volume(li, torch, np, CG, WilsonLattice):
+    """32^3 x 64, kappa = 0.156, links with plaquette ~0.60, 4 Gaussian rhs:
+    hop bandwidth per precision, CG to true residual 1e-10 with FP64 single rhs
+    vs BF16-storage / FP32-arithmetic inner iterations on the 4-rhs batch (FP64
+    reliable updates), and the force bilinear's throughput."""
+    Lg, kappa = (32, 32, 32, 64), 0.156
+    Vh = Lg[0] * Lg[1] * Lg[2] * Lg[3] // 2
+    t0 = time.time()
+    U = li.random_links(Lg, 0.432, li.seed_links(4))
+    log(f"large volume: links in {time.time() - t0:.1f}s")
+    lat = WilsonLattice(Lg, t_bc=-1)
+    lat.set_links(torch.from_numpy(U))
+    del U
+    out = {"lattice": list(Lg), "kappa": kappa, "plaquette": round(lat.plaquette(), 5)}
+    tune = lat.autotune()
+    out["hop"] = {}
+    for p in ("f64", "f32", "bf16"):
+        for nrhs in (1, 4):
+            us = lat.time_hop(p, nrhs, 200)
+            byt = (HOP_BYTES_PER_SITE[p] + (nrhs - 1) * 2 * {"f64": 192, "f32": 96, "bf16": 48}[p]) * Vh
+            out["hop"][f"{p}_x{nrhs}"] = {"us": round(us, 1), "us_per_rhs": round(us / nrhs, 1),
+                                          "GBs": round(byt / (us * 1e-6) / 1e9, 1)}
+    log("large volume hop", json.dumps(out["hop"]))
+    bs = [li.gaussian_spinor((Vh, 4, 3), li.seed_source(100 + j)) for j in range(4)]
+    b1 = lat.import_spinor(torch.from_numpy(bs[0]))
+    b4 = lat.import_spinor(torch.from_numpy(np.stack(bs)))
+    res = {}
+    for name, b, nrhs, inner in (("f64_x1", b1, 1, "f64"), ("bf16_x4", b4, 4, "bf16"), ("f32_x4", b4, 4, "f32")):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st, rc = lat.cg_solve(b, kappa, "J", mu2=[0.0] * nrhs, nrhs=nrhs,
+                                 params=CG(tol=1e-10, inner=inner, maxiter=20000))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        res[name] = {"ms": round(dt * 1e3, 1), "ms_per_rhs": round(dt * 1e3 / nrhs, 1),
+                     "iters": [s.iters for s in st], "reliable_updates": st[0].reliable_updates,
+                     "max_true_rel_res": max(s.true_rel_res for s in st), "rc": rc}
+        log("large volume cg", name, json.dumps(res[name]))
+    res["bf16_x4_speedup_per_rhs"] = round(res["f64_x1"]["ms"] / res["bf16_x4"]["ms_per_rhs"], 3)
+    res["f32_x4_speedup_per_rhs"] = round(res["f64_x1"]["ms"] / res["f32_x4"]["ms_per_rhs"], 3)
+    out["cg"] = res
+    # force bilinear: 2 full spinors + 4 links + read/write of 32 coefficients per site
+    A = lat.new_field("f64", 1, full=True)
+    A.zero_()
+    F = lat.new_su3()
+    for _ in range(2):
+        lat.force_bilinear(A, A, F)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        lat.force_bilinear(A, A, F)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / 10 * 1e3
+    fb = 1472 * 2 * Vh
+    out["force_bilinear"] = {"us": round(us, 1), "GBs": round(fb / (us * 1e-6) / 1e9, 1),
+                             "algorithmic_bytes": fb}
+    out["hop_autotune_us"] = {p: [round(v[0], 1), round(v[1], 1)] for p, v in tune.items()}
+    lat.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def lat_variant(lat, prec):
     """Variant the autotuner kept for prec (the faster of its two timings)."""
     site, dp = lat.last_tune[prec]
@@ -282,6 +345,9 @@ def main():
             "eight_rhs_true_res_max": max(s.true_rel_res for s in sbat),
         }
         log("cg", json.dumps(extra["cg"]))
+        lat.close()
+        torch.cuda.empty_cache()
+        extra["large_volume"] = large_volume(li, torch, np, CG, WilsonLattice)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -301,7 +367,8 @@ def main():
         except Exception as e:  # the baseline must not hide the GPU result
             out["cpu_baseline"] = {"error": str(e)[:200]}
     print(json.dumps(out), flush=True)
-    lat.close()
+    if args.quick:
+        lat.close()
 
 
 if __name__ == "__main__":
