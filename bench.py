@@ -169,34 +169,38 @@ def large_volume(li, torch, np, CG, WilsonLattice):
     fb = 1472 * 2 * Vh
     out["force_bilinear"] = {"us": round(us, 1), "GBs": round(fb / (us * 1e-6) / 1e9, 1),
                              "algorithmic_bytes": fb}
-    out["hop_autotune_us"] = {p: [round(v[0], 1), round(v[1], 1)] for p, v in tune.items()}
+    out["hop_config"] = {p: [lat.hop_config(p, k) for k in range(3)] for p in ("f64", "f32", "bf16")}
+    log("large volume hop autotune (us per launch, C API order):", json.dumps(
+        {p: [round(x, 1) for x in v] for p, v in tune.items()}))
     lat.close()
     torch.cuda.empty_cache()
     return out
 
 
-def lat_variant(lat, prec):
-    """Variant the autotuner kept for prec (the faster of its two timings)."""
-    site, dp = lat.last_tune[prec]
-    return 1 if dp <= site else 0
+KERNELS_ONLY_CONFIGS = [(v, x) for v in (0, 1) for x in (1, 0)]   # (variant, use_xcd)
 
 
 def kernels_only(lat, Vh, li, torch):
-    """Hop launches for kernel-trace and counter runs, plus a plain copy of known
-    size whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    """Hop launches for kernel-trace and counter runs: 50 one-rhs launches of
+    every (variant, workgroup order) in KERNELS_ONLY_CONFIGS for f64, f32,
+    bf16, in that order, then a plain copy of known size whose FETCH_SIZE /
+    WRITE_SIZE calibrate the counters."""
     psi = li.gaussian_spinor((Vh, 4, 3), li.seed_source(0))
-    for prec in ("f64", "f32"):
+    for prec in ("f64", "f32", "bf16"):
         b = lat.import_spinor(torch.from_numpy(psi), prec)
         out = lat.new_field(prec)
-        for _ in range(50):
-            lat.dslash(b, 0, prec=prec, out=out)
+        for variant, xcd in KERNELS_ONLY_CONFIGS:
+            lat.set_hop_config(prec, 0, variant=variant, npass=1, use_xcd=xcd)
+            for _ in range(50):
+                lat.dslash(b, 0, prec=prec, out=out)
     torch.cuda.synchronize()
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
     dst = torch.empty_like(src)
     for _ in range(5):
         dst.copy_(src)
     torch.cuda.synchronize()
-    log("kernels-only done: 50 hop launches f64, 50 f32, 5 copies of 1 GiB")
+    log("kernels-only done: per precision (f64, f32, bf16) 50 hop launches of each (variant, use_xcd) in",
+        KERNELS_ONLY_CONFIGS, "then 5 copies of 1 GiB")
 
 
 def main():
@@ -209,7 +213,8 @@ def main():
     ap.add_argument("--md-steps", default=",".join(map(str, NSTEPS)),
                     help="integrator steps per scale (poly, poly-K inverse, ratio, gauge); profiling runs shorten them")
     ap.add_argument("--kernels-only", action="store_true",
-                    help="only launch the hop kernels (50 each, FP64 and FP32) and a 1 GiB copy, for counter runs")
+                    help="only launch the hop kernels (50 per configuration and precision) and a 1 GiB copy, "
+                         "for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -233,12 +238,13 @@ def main():
     lat.set_links(torch.from_numpy(U))
     plaq0 = lat.plaquette()
     log(f"plaquette {plaq0:.4f}")
-    tune = lat.autotune()
-    lat.last_tune = tune
-    log(f"hop autotune (us per launch, site / direction-parallel): {tune}")
     if args.kernels_only:
         kernels_only(lat, Vh, li, torch)
         return
+    tune = lat.autotune()
+    log(f"hop autotune (us per launch, candidates in the C API order): {tune}")
+    log("hop configurations kept (variant, npass, use_xcd) for 1, 2-4, 5-16 rhs:",
+        {p: [lat.hop_config(p, k) for k in range(3)] for p in ("f64", "f32", "bf16")})
 
     cg_md = CG(tol=1e-10, inner="f32", chunk=8)
     terms = [Term("POLY", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_md),
@@ -287,13 +293,14 @@ def main():
     avg_us = lat.time_hop(dom, 1, 500)
     achieved = bytes_per_hop[dom] / (avg_us * 1e-6) / 1e9
     traffic = None
-    variant = lat_variant(lat, dom)
-    kib = PMC_COUNTERS["per_launch_kib"].get(f"{dom}:{['site', 'dp'][variant]}")
+    variant, _, use_xcd = lat.hop_config(dom, 0)
+    kib = PMC_COUNTERS["per_launch_kib"].get(f"{dom}:{['site', 'dp'][variant]}:xcd{use_xcd}")
     if kib and PMC_COUNTERS["source_sha256"] == hop_source_hash():
         traffic = int(1024 * (kib["fetch"] * PMC_FETCH_SCALE + kib["write"] * PMC_WRITE_SCALE))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"hop {dom} ({['thread-per-site', 'direction-parallel'][variant]})",
+                "kernel": f"hop {dom} ({['thread-per-site', 'direction-parallel'][variant]}, "
+                          f"{'XCD-contiguous' if use_xcd else 'round-robin'} workgroup order)",
                 "avg_launch_us": round(avg_us, 2), "in_situ_avg_us": round(prof[dom][0], 2),
                 "in_situ_samples": prof[dom][1], "algorithmic_bytes_per_launch": bytes_per_hop[dom]}
     extra = {"hop_avg_us": {p: round(v[0], 2) for p, v in prof.items()},
@@ -303,7 +310,7 @@ def main():
              "n_kmat_per_traj": [int(r.n_kmat) for r in results],
              "cg_iters_per_traj": [int(r.cg_iters) for r in results],
              "plaquette_start": round(plaq0, 5), "plaquette_end": round(results[-1].plaquette, 5),
-             "hop_autotune_us": {p: [round(v[0], 2), round(v[1], 2)] for p, v in tune.items()}}
+             "hop_config": {p: [lat.hop_config(p, k) for k in range(3)] for p in ("f64", "f32", "bf16")}}
 
     if not args.quick:
         # CG time-to-1e-10: FP64 vs mixed single rhs, 8 sequential FP64 vs one batched mixed

@@ -236,13 +236,32 @@ int wl_integrator_schedule(const int* nsteps, int nscales, int scheme, double la
 
 /* Counters: hop applications and K applications since create (single rhs units). */
 int wl_counters(const wl_lattice* lat, long long* n_hop, long long* n_kmat);
-/* Hop kernel variants: 0 = one thread per output site (all 8 directions);
- * 1 = direction-parallel (8 wavefronts, one per direction, over 64 sites,
- * combined through LDS).  wl_set_hop_variant picks one per precision;
- * wl_autotune times both on this lattice for every precision and keeps the
- * faster (us_out: optional host array [3][2] of microseconds per launch).
- * Results are identical up to the FP summation order of the 8 directions. */
-int wl_set_hop_variant(wl_lattice* lat, wl_prec prec, int variant);
+/* Hop launch configuration, kept per storage precision and per rhs-count
+ * class (kind 0: one rhs; 1: 2-4 rhs; 2: 5-16 rhs):
+ *   variant  0 = one thread per output site (all 8 directions);
+ *            1 = direction-parallel (8 wavefronts, one per direction, over 64
+ *                sites, combined through LDS);
+ *   npass    direction-parallel: up to npass (1, 2, 4) passes of 1 (FP64) or
+ *            2 (FP32, BF16, even rhs counts) rhs reuse each link held in
+ *            registers; site: 2 = two rhs per thread (FP32, BF16, even rhs
+ *            counts), else one;
+ *   use_xcd  1 = workgroups renumbered so that each of the 8 XCDs walks a
+ *            contiguous range of sites; 0 = the hardware's round-robin order.
+ * Results are identical for every npass and use_xcd, and agree between the
+ * two variants up to the FP summation order of the 8 directions.
+ * wl_set_hop_config sets one class (kind = -1: all three); WL_EINVAL for
+ * values outside these sets.  wl_get_hop_config reads one class (outputs may
+ * be NULL).
+ * wl_autotune times on this lattice, for every precision, class 0 at 1 rhs
+ * over {site, direction-parallel}, classes 1 and 2 at 4 and 8 rhs over
+ * {site npass 1, 2; direction-parallel npass 1, 2, 4}, each candidate with
+ * use_xcd 1 then 0 (best of 3 bursts of 20 launches), and keeps the fastest
+ * of every class.  us_out: optional host array of 3 x 24 microseconds per
+ * launch, per precision (F64, F32, BF16): the 4 class-0 candidates
+ * (site, dp with use_xcd 1, then with 0), then 10 for class 1 and 10 for
+ * class 2 (site 1, site 2, dp 1, dp 2, dp 4 with use_xcd 1, then with 0). */
+int wl_set_hop_config(wl_lattice* lat, wl_prec prec, int kind, int variant, int npass, int use_xcd);
+int wl_get_hop_config(const wl_lattice* lat, wl_prec prec, int kind, int* variant, int* npass, int* use_xcd);
 int wl_autotune(wl_lattice* lat, double* us_out);
 /* Tracing: average duration in microseconds of back-to-back hop launches
  * (current variant, nrhs right-hand sides, scratch fields owned by the

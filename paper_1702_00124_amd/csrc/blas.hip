@@ -18,7 +18,7 @@ int blas_blocks(const wl_lattice* L) { return site_blocks(L->Vh); }
 template <typename P>
 __global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, double* x64, char* r, const char* p,
                                                           const char* Ap, const double* st, size_t stride,
-                                                          double* partials, int pstride, int nh) {
+                                                          size_t stride64, double* partials, int pstride, int nh) {
   using R = typename P::real;
   __shared__ double lds[kBlock / 64];
   const int f = blockIdx.y;
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, double* x64, c
     Spinor<R> pv = SpinorIO<P>::load(p + off, h, Vh);
     Spinor<R> av = SpinorIO<P>::load(Ap + off, h, Vh);
     Spinor<R> rv = SpinorIO<P>::load(r + off, h, Vh);
-    char* xb = reinterpret_cast<char*>(x64) + f * size_t(192) * g.Vhp;
+    char* xb = reinterpret_cast<char*>(x64) + f * stride64;
     Spinor<double> xv = SpinorIO<PrecF64>::load(xb, h, Vh);
     const R ar = R(alpha);
 #pragma unroll
@@ -262,7 +262,8 @@ void launch_cg_update(wl_lattice* L, Prec prec, void* x64, void* r, const void* 
   by_prec(prec, [&](auto P) {
     using PT = decltype(P);
     hipLaunchKernelGGL((cg_update_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (double*)x64, (char*)r,
-                       (const char*)p, (const char*)Ap, st, spinor_bytes(prec, L->Vh), partials, stride, nh);
+                       (const char*)p, (const char*)Ap, st, spinor_bytes(prec, L->Vh), spinor_bytes(F64, L->Vh), partials,
+                       stride, nh);
   });
   WL_HIP(hipGetLastError());
 }

@@ -436,13 +436,30 @@ int wl_hop_counts(const wl_lattice* L, long long* counts) {
   });
 }
 
-int wl_set_hop_variant(wl_lattice* L, wl_prec prec, int variant) {
+int wl_set_hop_config(wl_lattice* L, wl_prec prec, int kind, int variant, int npass, int use_xcd) {
   return guard([&]() {
     check_lat(L);
     check_prec_rhs(prec, 1);
+    WL_REQUIRE(kind >= -1 && kind < kHopKinds, WL_EINVAL, "hop class must be -1, 0, 1 or 2");
     WL_REQUIRE(variant == kHopSite || variant == kHopDirParallel, WL_EINVAL, "unknown hop variant");
+    WL_REQUIRE(npass == 1 || npass == 2 || npass == 4, WL_EINVAL, "npass must be 1, 2 or 4");
+    WL_REQUIRE(use_xcd == 0 || use_xcd == 1, WL_EINVAL, "use_xcd must be 0 or 1");
     WL_HIP(hipStreamSynchronize(L->stream));
-    L->hop_var[prec] = variant;
+    for (int k = 0; k < kHopKinds; ++k)
+      if (kind == -1 || kind == k) L->hop_cfg[prec][k] = HopConfig{variant, npass, use_xcd};
+    return WL_OK;
+  });
+}
+
+int wl_get_hop_config(const wl_lattice* L, wl_prec prec, int kind, int* variant, int* npass, int* use_xcd) {
+  return guard([&]() {
+    check_lat(L);
+    check_prec_rhs(prec, 1);
+    WL_REQUIRE(kind >= 0 && kind < kHopKinds, WL_EINVAL, "hop class must be 0, 1 or 2");
+    const HopConfig& c = L->hop_cfg[prec][kind];
+    if (variant) *variant = c.variant;
+    if (npass) *npass = c.npass;
+    if (use_xcd) *use_xcd = c.use_xcd;
     return WL_OK;
   });
 }
@@ -518,45 +535,66 @@ int wl_stream_copy(wl_lattice* L, size_t bytes, int reps, double* gbs) {
   });
 }
 
+// best of 3 bursts of 20 hop launches (after 5 warm-ups), microseconds per
+// launch, on scratch fields; not counted in the hop counters
+static double tune_burst(wl_lattice* L, Prec p, void* out, const void* in, int nrhs, hipEvent_t e0, hipEvent_t e1) {
+  HopEpi e;
+  for (int i = 0; i < 5; ++i) launch_hop(L, p, out, in, 0, 0, nrhs, e);
+  double us = 1e30;
+  for (int rep = 0; rep < 3; ++rep) {
+    WL_HIP(hipEventRecord(e0, L->stream));
+    for (int i = 0; i < 20; ++i) launch_hop(L, p, out, in, 0, 0, nrhs, e);
+    WL_HIP(hipEventRecord(e1, L->stream));
+    WL_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    WL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    us = std::min(us, 1e3 * ms / 20);
+  }
+  L->n_hop -= 65LL * nrhs;
+  L->n_hop_p[p] -= 65LL * nrhs;
+  return us;
+}
+
 int wl_autotune(wl_lattice* L, double* us_out) {
   return guard([&]() {
     check_lat(L);
     set_device(L);
-    // time each hop variant on scratch fields (best of 3 bursts of 20 launches
-    // after 5 warm-ups) and keep the faster
     hipEvent_t e0, e1;
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
-    const size_t fb = spinor_bytes(F64, L->Vh);
+    const size_t fb = spinor_bytes(F64, L->Vh) * kTuneRhs[kHopKinds - 1];
     void* a = ws_get(L, "tune_a", fb);
     void* b = ws_get(L, "tune_b", fb);
     WL_HIP(hipMemsetAsync(a, 0, fb, L->stream));
+    int slot = 0;
     for (int p = 0; p < 3; ++p) {
-      double best = 1e30;
-      int best_v = L->hop_var[p];
-      for (int v = 0; v < 2; ++v) {
-        L->hop_var[p] = v;
-        HopEpi e;
-        for (int i = 0; i < 5; ++i) launch_hop(L, Prec(p), b, a, 0, 0, 1, e);
-        double us = 1e30;
-        for (int rep = 0; rep < 3; ++rep) {
-          WL_HIP(hipEventRecord(e0, L->stream));
-          for (int i = 0; i < 20; ++i) launch_hop(L, Prec(p), b, a, 0, 0, 1, e);
-          WL_HIP(hipEventRecord(e1, L->stream));
-          WL_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          WL_HIP(hipEventElapsedTime(&ms, e0, e1));
-          us = std::min(us, 1e3 * ms / 20);
+      for (int k = 0; k < kHopKinds; ++k) {
+        // one rhs: both variants; several: site with 1 or 2 rhs per thread and
+        // direction-parallel with 1, 2 or 4 passes; each in both workgroup orders
+        std::vector<HopConfig> cand;
+        for (int xcd = 1; xcd >= 0; --xcd) {
+          if (k == 0) {
+            cand.push_back({kHopSite, 1, xcd});
+            cand.push_back({kHopDirParallel, 1, xcd});
+          } else {
+            for (int np : {1, 2}) cand.push_back({kHopSite, np, xcd});
+            for (int np : {1, 2, 4}) cand.push_back({kHopDirParallel, np, xcd});
+          }
         }
-        if (us_out) us_out[2 * p + v] = us;
-        if (us < best) {
-          best = us;
-          best_v = v;
+        double best = 1e30;
+        HopConfig keep = L->hop_cfg[p][k];
+        for (const HopConfig& c : cand) {
+          L->hop_cfg[p][k] = c;
+          const double us = tune_burst(L, Prec(p), b, a, kTuneRhs[k], e0, e1);
+          if (us_out) us_out[slot] = us;
+          ++slot;
+          if (us < best) {
+            best = us;
+            keep = c;
+          }
         }
-        L->n_hop -= 65;
-        L->n_hop_p[p] -= 65;
+        L->hop_cfg[p][k] = keep;
       }
-      L->hop_var[p] = best_v;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

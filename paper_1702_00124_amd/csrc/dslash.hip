@@ -95,7 +95,6 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h,
 template <typename P, int DAG, int NR>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
   using R = typename P::real;
-  __shared__ double lds[kBlock / 64];
   int b, row;
   hop_block_coords(a, &b, &row);
   const int h = b * kBlock + threadIdx.x;
@@ -125,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) o.c[k] = ca * acc[r].c[k];
       if (a.x) {
-        const Spinor<R> xv = SpinorIO<P>::load(a.x + off, h, Vh);
+        const Spinor<R> xv = SpinorIO<P>::load_nt(a.x + off, h, Vh);
         const R cx = R(a.cx);
 #pragma unroll
         for (int k = 0; k < 12; ++k) o.c[k] = o.c[k] + cx * xv.c[k];
@@ -135,14 +134,14 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
         for (int k = 6; k < 12; ++k) o.c[k] = R(-1) * o.c[k];
       }
       if (a.y) {
-        const Spinor<R> yv = SpinorIO<P>::load(a.y + off, h, Vh);
+        const Spinor<R> yv = SpinorIO<P>::load_nt(a.y + off, h, Vh);
         const R cy = R(a.by[r0 + r]);
 #pragma unroll
         for (int k = 0; k < 12; ++k) o.c[k] = o.c[k] + cy * yv.c[k];
       }
-      SpinorIO<P>::store(a.out + off, h, Vh, o);
+      SpinorIO<P>::store_nt(a.out + off, h, Vh, o);
       if (a.dot == 1) {
-        const Spinor<R> dv = SpinorIO<P>::load(a.dotv + off, h, Vh);
+        const Spinor<R> dv = SpinorIO<P>::load_nt(a.dotv + off, h, Vh);
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) s += double(dv.c[k].r) * double(o.c[k].r) + double(dv.c[k].i) * double(o.c[k].i);
@@ -155,11 +154,13 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
       }
     }
   }
-  if (a.dot) {
+  // one partial per wavefront of 64 sites, as in the direction-parallel variant
+  const int slot = b * (kBlock / 64) + (threadIdx.x >> 6);
+  if (a.dot && slot * 64 < Vh) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const double s = block_sum(part[r], lds);
-      if (threadIdx.x == 0) a.partials[(r0 + r) * a.part_stride + a.part_off + b] = s;
+      const double s = wave_sum(part[r]);
+      if ((threadIdx.x & 63) == 0) a.partials[(r0 + r) * a.part_stride + a.part_off + slot] = s;
     }
   }
 }
@@ -175,22 +176,30 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 constexpr int kDpSites = 64;
 constexpr int kDpThreads = 8 * kDpSites;
 
-template <typename P, int MU, int FWD, int DAG, int NR>
-__device__ __forceinline__ void dp_dir(const HopArgs& a, const Coord& c, int h, int r0,
-                                       cplx<typename P::real>* W, int lane) {
+// the wavefront's direction: its neighbour, time-boundary phase and link
+template <typename P, int MU, int FWD>
+__device__ __forceinline__ void dp_link(const HopArgs& a, const Coord& c, int h, SU3<typename P::real>* U, int* hn,
+                                        typename P::real* ph) {
   using R = typename P::real;
-  constexpr int S = FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1);  // projector sign (1 + S g_mu)
-  constexpr int D = 2 * MU + (FWD ? 0 : 1);
   const int Vh = a.g.Vh;
   const size_t lb = LinkIO<P>::bytes * size_t(a.g.Vhp);
   bool wrap;
-  const int hn = neighbour<MU>(a.g, c, FWD ? +1 : -1, &wrap);
-  const SU3<R> U = FWD ? LinkIO<P>::load(a.links + (a.parity * 4 + MU) * lb, h, Vh)
-                       : LinkIO<P>::load(a.links + ((1 - a.parity) * 4 + MU) * lb, hn, Vh);
-  const R ph = wrap ? R(a.g.tbc) : R(1);
+  *hn = neighbour<MU>(a.g, c, FWD ? +1 : -1, &wrap);
+  *U = FWD ? LinkIO<P>::load(a.links + (a.parity * 4 + MU) * lb, h, Vh)
+           : LinkIO<P>::load(a.links + ((1 - a.parity) * 4 + MU) * lb, *hn, Vh);
+  *ph = wrap ? R(a.g.tbc) : R(1);
+}
+
+// project, multiply and store to LDS the half-spinor results of NRP rhs
+template <typename P, int MU, int FWD, int DAG, int NRP>
+__device__ __forceinline__ void dp_spin(const HopArgs& a, const SU3<typename P::real>& U, int hn,
+                                        typename P::real ph, int r0, cplx<typename P::real>* W, int lane) {
+  using R = typename P::real;
+  constexpr int S = FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1);  // projector sign (1 + S g_mu)
+  constexpr int D = 2 * MU + (FWD ? 0 : 1);
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const Spinor<R> s = SpinorIO<P>::load(a.in + (r0 + r) * a.rhs_stride, hn, Vh);
+  for (int r = 0; r < NRP; ++r) {
+    const Spinor<R> s = SpinorIO<P>::load(a.in + (r0 + r) * a.rhs_stride, hn, a.g.Vh);
     const Half<R> hp = project<MU, S>(s);
     Half<R> w;
     if (FWD) {
@@ -227,11 +236,14 @@ __device__ __forceinline__ cplx<R> dp_recon(const cplx<R>* W, int s, int col, in
   return sf * acc;
 }
 
-template <typename P, int DAG, int NR>
+// NRP rhs share one LDS pass; NPASS passes reuse the link held in registers,
+// so each link is read once for NRP * NPASS rhs
+template <typename P, int DAG, int NRP, int NPASS>
 __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
   using R = typename P::real;
   using UIO = UnitIO<P>;
-  __shared__ cplx<R> W[NR * 8 * 6 * kDpSites];
+  constexpr int NR = NRP * NPASS;
+  __shared__ cplx<R> W[NRP * 8 * 6 * kDpSites];
   __shared__ double red[kDpThreads / 64];
   int tile, row;
   hop_block_coords(a, &tile, &row);
@@ -241,55 +253,76 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
   const int h = tile * kDpSites + lane;
   const bool active = h < Vh;
   const int r0 = row * NR;
+  SU3<R> U;
+  int hn = 0;
+  R ph = R(1);
   if (active) {
     const Coord c = site_coords(a.g, h, a.parity);
     switch (wv) {
-      case 0: dp_dir<P, 0, 1, DAG, NR>(a, c, h, r0, W, lane); break;
-      case 1: dp_dir<P, 0, 0, DAG, NR>(a, c, h, r0, W, lane); break;
-      case 2: dp_dir<P, 1, 1, DAG, NR>(a, c, h, r0, W, lane); break;
-      case 3: dp_dir<P, 1, 0, DAG, NR>(a, c, h, r0, W, lane); break;
-      case 4: dp_dir<P, 2, 1, DAG, NR>(a, c, h, r0, W, lane); break;
-      case 5: dp_dir<P, 2, 0, DAG, NR>(a, c, h, r0, W, lane); break;
-      case 6: dp_dir<P, 3, 1, DAG, NR>(a, c, h, r0, W, lane); break;
-      default: dp_dir<P, 3, 0, DAG, NR>(a, c, h, r0, W, lane); break;
+      case 0: dp_link<P, 0, 1>(a, c, h, &U, &hn, &ph); break;
+      case 1: dp_link<P, 0, 0>(a, c, h, &U, &hn, &ph); break;
+      case 2: dp_link<P, 1, 1>(a, c, h, &U, &hn, &ph); break;
+      case 3: dp_link<P, 1, 0>(a, c, h, &U, &hn, &ph); break;
+      case 4: dp_link<P, 2, 1>(a, c, h, &U, &hn, &ph); break;
+      case 5: dp_link<P, 2, 0>(a, c, h, &U, &hn, &ph); break;
+      case 6: dp_link<P, 3, 1>(a, c, h, &U, &hn, &ph); break;
+      default: dp_link<P, 3, 0>(a, c, h, &U, &hn, &ph); break;
     }
   }
-  __syncthreads();
   double part[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) part[r] = 0.0;
-  if (active) {
-    const R ca = R(a.a), cx = R(a.cx);
+  const R ca = R(a.a), cx = R(a.cx);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const size_t off = (r0 + r) * a.rhs_stride;
-      const R cy = R(a.by[r0 + r]);
-      for (int u = wv; u < UIO::NU; u += 8) {
-        cplx<R> o[UIO::CPU], xv[UIO::CPU], yv[UIO::CPU];
-        if (a.x) UIO::load(a.x + off, u, h, Vh, xv);
-        if (a.y) UIO::load(a.y + off, u, h, Vh, yv);
+  for (int pass = 0; pass < NPASS; ++pass) {
+    const int rp = r0 + pass * NRP;
+    if (active) {
+      switch (wv) {
+        case 0: dp_spin<P, 0, 1, DAG, NRP>(a, U, hn, ph, rp, W, lane); break;
+        case 1: dp_spin<P, 0, 0, DAG, NRP>(a, U, hn, ph, rp, W, lane); break;
+        case 2: dp_spin<P, 1, 1, DAG, NRP>(a, U, hn, ph, rp, W, lane); break;
+        case 3: dp_spin<P, 1, 0, DAG, NRP>(a, U, hn, ph, rp, W, lane); break;
+        case 4: dp_spin<P, 2, 1, DAG, NRP>(a, U, hn, ph, rp, W, lane); break;
+        case 5: dp_spin<P, 2, 0, DAG, NRP>(a, U, hn, ph, rp, W, lane); break;
+        case 6: dp_spin<P, 3, 1, DAG, NRP>(a, U, hn, ph, rp, W, lane); break;
+        default: dp_spin<P, 3, 0, DAG, NRP>(a, U, hn, ph, rp, W, lane); break;
+      }
+    }
+    __syncthreads();
+    if (active) {
 #pragma unroll
-        for (int q = 0; q < UIO::CPU; ++q) {
-          const int comp = u * UIO::CPU + q;
-          const int s = comp / 3;
-          o[q] = ca * dp_recon<DAG>(W + r * 8 * 6 * kDpSites, s, comp - 3 * s, lane);
-          if (a.x) o[q] = o[q] + cx * xv[q];
-          if (a.g5 && s >= 2) o[q] = R(-1) * o[q];
-          if (a.y) o[q] = o[q] + cy * yv[q];
-        }
-        UIO::store(a.out + off, u, h, Vh, o);
-        if (a.dot == 1) {
-          cplx<R> dv[UIO::CPU];
-          UIO::load(a.dotv + off, u, h, Vh, dv);
+      for (int r = 0; r < NRP; ++r) {
+        const size_t off = (rp + r) * a.rhs_stride;
+        const R cy = R(a.by[rp + r]);
+        for (int u = wv; u < UIO::NU; u += 8) {
+          cplx<R> o[UIO::CPU], xv[UIO::CPU], yv[UIO::CPU];
+          if (a.x) UIO::load_nt(a.x + off, u, h, Vh, xv);
+          if (a.y) UIO::load_nt(a.y + off, u, h, Vh, yv);
 #pragma unroll
-          for (int q = 0; q < UIO::CPU; ++q)
-            part[r] += double(dv[q].r) * double(o[q].r) + double(dv[q].i) * double(o[q].i);
-        } else if (a.dot == 2) {
+          for (int q = 0; q < UIO::CPU; ++q) {
+            const int comp = u * UIO::CPU + q;
+            const int s = comp / 3;
+            o[q] = ca * dp_recon<DAG>(W + r * 8 * 6 * kDpSites, s, comp - 3 * s, lane);
+            if (a.x) o[q] = o[q] + cx * xv[q];
+            if (a.g5 && s >= 2) o[q] = R(-1) * o[q];
+            if (a.y) o[q] = o[q] + cy * yv[q];
+          }
+          UIO::store_nt(a.out + off, u, h, Vh, o);
+          if (a.dot == 1) {
+            cplx<R> dv[UIO::CPU];
+            UIO::load_nt(a.dotv + off, u, h, Vh, dv);
 #pragma unroll
-          for (int q = 0; q < UIO::CPU; ++q) part[r] += double(o[q].r) * double(o[q].r) + double(o[q].i) * double(o[q].i);
+            for (int q = 0; q < UIO::CPU; ++q)
+              part[pass * NRP + r] += double(dv[q].r) * double(o[q].r) + double(dv[q].i) * double(o[q].i);
+          } else if (a.dot == 2) {
+#pragma unroll
+            for (int q = 0; q < UIO::CPU; ++q)
+              part[pass * NRP + r] += double(o[q].r) * double(o[q].r) + double(o[q].i) * double(o[q].i);
+          }
         }
       }
     }
+    if (pass + 1 < NPASS) __syncthreads();  // W is rewritten by the next pass
   }
   if (a.dot) {
 #pragma unroll
@@ -300,35 +333,53 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
   }
 }
 
-int hop_tiles(const wl_lattice* L, Prec prec) {
-  return L->hop_var[prec] == kHopDirParallel ? (L->Vh + kDpSites - 1) / kDpSites : site_blocks(L->Vh);
-}
+int hop_tiles(const wl_lattice* L, Prec) { return (L->Vh + kDpSites - 1) / kDpSites; }
 
-template <typename P, int DAG>
-static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, int variant, int tiles) {
-  // rhs per block: FP64 keeps one (register / LDS budget of double spinors);
-  // FP32 and BF16 share each link load over two
-  int nr = 1;
-  if (sizeof(typename P::real) == 4 && nrhs % 2 == 0) nr = 2;
-  a.rows = nrhs / nr;
-  dim3 grid(tiles * a.rows);
-  if (variant == kHopDirParallel) {
-    switch (nr) {
-      case 2: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, 2>), grid, dim3(kDpThreads), 0, st, a); break;
-      default: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, 1>), grid, dim3(kDpThreads), 0, st, a); break;
-    }
-  } else {
-    switch (nr) {
-      case 2: hipLaunchKernelGGL((hop_kernel<P, DAG, 2>), grid, dim3(kBlock), 0, st, a); break;
-      default: hipLaunchKernelGGL((hop_kernel<P, DAG, 1>), grid, dim3(kBlock), 0, st, a); break;
-    }
+template <typename P, int DAG, int NRP>
+static void dispatch_dp(HopArgs a, int nrhs, hipStream_t st, int max_pass) {
+  // passes per block: the largest of 4, 2, 1 within max_pass dividing the rhs groups
+  const int groups = nrhs / NRP;
+  const int npass = (max_pass >= 4 && groups % 4 == 0) ? 4 : ((max_pass >= 2 && groups % 2 == 0) ? 2 : 1);
+  a.rows = groups / npass;
+  dim3 grid(((a.g.Vh + kDpSites - 1) / kDpSites) * a.rows);
+  switch (npass) {
+    case 4: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 4>), grid, dim3(kDpThreads), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 2>), grid, dim3(kDpThreads), 0, st, a); break;
+    default: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 1>), grid, dim3(kDpThreads), 0, st, a); break;
   }
 }
 
+template <typename P, int DAG>
+static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, const HopConfig& c) {
+  // rhs per LDS pass (direction-parallel) or per thread (site): two for FP32
+  // and BF16 with an even rhs count when the configuration allows, else one
+  constexpr bool narrow = sizeof(typename P::real) == 4;
+  const bool two = narrow && nrhs % 2 == 0 && (c.variant == kHopDirParallel || c.npass >= 2);
+  if (c.variant == kHopDirParallel) {
+    if constexpr (narrow) {
+      if (two) {
+        dispatch_dp<P, DAG, 2>(a, nrhs, st, c.npass);
+        return;
+      }
+    }
+    dispatch_dp<P, DAG, 1>(a, nrhs, st, c.npass);
+    return;
+  }
+  if constexpr (narrow) {
+    if (two) {
+      a.rows = nrhs / 2;
+      hipLaunchKernelGGL((hop_kernel<P, DAG, 2>), dim3(site_blocks(a.g.Vh) * a.rows), dim3(kBlock), 0, st, a);
+      return;
+    }
+  }
+  a.rows = nrhs;
+  hipLaunchKernelGGL((hop_kernel<P, DAG, 1>), dim3(site_blocks(a.g.Vh) * a.rows), dim3(kBlock), 0, st, a);
+}
+
 template <typename P>
-static void dispatch(const HopArgs& a, int dagger, int nrhs, hipStream_t st, int variant, int tiles) {
-  if (dagger) dispatch_nr<P, 1>(a, nrhs, st, variant, tiles);
-  else dispatch_nr<P, 0>(a, nrhs, st, variant, tiles);
+static void dispatch(const HopArgs& a, int dagger, int nrhs, hipStream_t st, const HopConfig& c) {
+  if (dagger) dispatch_nr<P, 1>(a, nrhs, st, c);
+  else dispatch_nr<P, 0>(a, nrhs, st, c);
 }
 
 void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_parity, int dagger,
@@ -354,9 +405,8 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
   a.partials = e.partials;
   a.part_stride = e.part_stride;
   a.part_off = e.part_off;
-  a.use_xcd = L->use_xcd;
-  const int tiles = hop_tiles(L, prec);
-  const int variant = L->hop_var[prec];
+  const HopConfig& cfg = L->hop_cfg[prec][hop_kind(nrhs)];
+  a.use_xcd = cfg.use_xcd;
   // sampled event timing (never inside a graph capture)
   const bool timed = L->prof_on && !L->prof_capturing && nrhs == 1 && L->prof_ev[prec].size() < 2 * kProfPairs;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -366,9 +416,9 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
     WL_HIP(hipEventRecord(e0, L->stream));
   }
   switch (prec) {
-    case F64: dispatch<PrecF64>(a, dagger, nrhs, L->stream, variant, tiles); break;
-    case F32: dispatch<PrecF32>(a, dagger, nrhs, L->stream, variant, tiles); break;
-    case BF16: dispatch<PrecBF16>(a, dagger, nrhs, L->stream, variant, tiles); break;
+    case F64: dispatch<PrecF64>(a, dagger, nrhs, L->stream, cfg); break;
+    case F32: dispatch<PrecF32>(a, dagger, nrhs, L->stream, cfg); break;
+    case BF16: dispatch<PrecBF16>(a, dagger, nrhs, L->stream, cfg); break;
   }
   WL_HIP(hipGetLastError());
   if (timed) {

@@ -96,6 +96,42 @@ struct SU3 {
   cplx<T> m[9];  // row-major
 };
 
+// ------------------------------------------------------------------ streaming access
+// Non-temporal loads and stores for data a hop touches exactly once (links:
+// each link serves one output site forward and one backward; the epilogue's
+// operands; the output), so that they do not push the neighbour spinors, which
+// are read 8 times, out of L2.
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef unsigned v2u_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const v2d_t v = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+  const v4f_t v = __builtin_nontemporal_load(reinterpret_cast<const v4f_t*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint2 ld_stream(const uint2* p) {
+  const v2u_t v = __builtin_nontemporal_load(reinterpret_cast<const v2u_t*>(p));
+  return make_uint2(v.x, v.y);
+}
+typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+  const v4u_t v = __builtin_nontemporal_load(reinterpret_cast<const v4u_t*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+// non-temporal stores for hop outputs: the hop never reads them back
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+  __builtin_nontemporal_store(v2d_t{v.x, v.y}, reinterpret_cast<v2d_t*>(p));
+}
+__device__ __forceinline__ void st_stream(float4* p, float4 v) {
+  __builtin_nontemporal_store(v4f_t{v.x, v.y, v.z, v.w}, reinterpret_cast<v4f_t*>(p));
+}
+__device__ __forceinline__ void st_stream(uint4* p, uint4 v) {
+  __builtin_nontemporal_store(v4u_t{v.x, v.y, v.z, v.w}, reinterpret_cast<v4u_t*>(p));
+}
+
 // spinor load/store: base points at one rhs of one parity
 template <typename P>
 struct SpinorIO;
@@ -117,6 +153,21 @@ struct SpinorIO<PrecF64> {
 #pragma unroll
     for (int c = 0; c < 12; ++c) b[fidx(c, h, 12)] = make_double2(s.c[c].r, s.c[c].i);
   }
+  static __device__ __forceinline__ Spinor<double> load_nt(const void* base, int h, int Vh) {
+    const double2* b = reinterpret_cast<const double2*>(base);
+    Spinor<double> s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const double2 v = ld_stream(b + fidx(c, h, 12));
+      s.c[c] = {v.x, v.y};
+    }
+    return s;
+  }
+  static __device__ __forceinline__ void store_nt(void* base, int h, int Vh, const Spinor<double>& s) {
+    double2* b = reinterpret_cast<double2*>(base);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st_stream(b + fidx(c, h, 12), make_double2(s.c[c].r, s.c[c].i));
+  }
 };
 
 template <>
@@ -137,6 +188,23 @@ struct SpinorIO<PrecF32> {
 #pragma unroll
     for (int j = 0; j < 6; ++j)
       b[fidx(j, h, 6)] = make_float4(s.c[2 * j].r, s.c[2 * j].i, s.c[2 * j + 1].r, s.c[2 * j + 1].i);
+  }
+  static __device__ __forceinline__ Spinor<float> load_nt(const void* base, int h, int Vh) {
+    const float4* b = reinterpret_cast<const float4*>(base);
+    Spinor<float> s;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const float4 v = ld_stream(b + fidx(j, h, 6));
+      s.c[2 * j] = {v.x, v.y};
+      s.c[2 * j + 1] = {v.z, v.w};
+    }
+    return s;
+  }
+  static __device__ __forceinline__ void store_nt(void* base, int h, int Vh, const Spinor<float>& s) {
+    float4* b = reinterpret_cast<float4*>(base);
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      st_stream(b + fidx(j, h, 6), make_float4(s.c[2 * j].r, s.c[2 * j].i, s.c[2 * j + 1].r, s.c[2 * j + 1].i));
   }
 };
 
@@ -166,6 +234,30 @@ struct SpinorIO<PrecBF16> {
       b[fidx(j, h, 3)] = v;
     }
   }
+  static __device__ __forceinline__ Spinor<float> load_nt(const void* base, int h, int Vh) {
+    const uint4* b = reinterpret_cast<const uint4*>(base);
+    Spinor<float> s;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const uint4 v = ld_stream(b + fidx(j, h, 3));
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s.c[4 * j + q] = {bf16_to_f32(w[q] & 0xFFFFu), bf16_to_f32(w[q] >> 16)};
+    }
+    return s;
+  }
+  static __device__ __forceinline__ void store_nt(void* base, int h, int Vh, const Spinor<float>& s) {
+    uint4* b = reinterpret_cast<uint4*>(base);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      uint4 v;
+      v.x = pack_bf16x2(s.c[4 * j + 0].r, s.c[4 * j + 0].i);
+      v.y = pack_bf16x2(s.c[4 * j + 1].r, s.c[4 * j + 1].i);
+      v.z = pack_bf16x2(s.c[4 * j + 2].r, s.c[4 * j + 2].i);
+      v.w = pack_bf16x2(s.c[4 * j + 3].r, s.c[4 * j + 3].i);
+      st_stream(b + fidx(j, h, 3), v);
+    }
+  }
 };
 
 // storage units of a spinor: 16-byte vectors (F64: 1 complex, F32: 2, BF16: 4)
@@ -182,6 +274,13 @@ struct UnitIO<PrecF64> {
   static __device__ __forceinline__ void store(void* base, int u, int h, int Vh, const cplx<double>* c) {
     reinterpret_cast<double2*>(base)[fidx(u, h, 12)] = make_double2(c[0].r, c[0].i);
   }
+  static __device__ __forceinline__ void load_nt(const void* base, int u, int h, int Vh, cplx<double>* c) {
+    const double2 v = ld_stream(reinterpret_cast<const double2*>(base) + fidx(u, h, 12));
+    c[0] = {v.x, v.y};
+  }
+  static __device__ __forceinline__ void store_nt(void* base, int u, int h, int Vh, const cplx<double>* c) {
+    st_stream(reinterpret_cast<double2*>(base) + fidx(u, h, 12), make_double2(c[0].r, c[0].i));
+  }
 };
 
 template <>
@@ -194,6 +293,14 @@ struct UnitIO<PrecF32> {
   }
   static __device__ __forceinline__ void store(void* base, int u, int h, int Vh, const cplx<float>* c) {
     reinterpret_cast<float4*>(base)[fidx(u, h, 6)] = make_float4(c[0].r, c[0].i, c[1].r, c[1].i);
+  }
+  static __device__ __forceinline__ void load_nt(const void* base, int u, int h, int Vh, cplx<float>* c) {
+    const float4 v = ld_stream(reinterpret_cast<const float4*>(base) + fidx(u, h, 6));
+    c[0] = {v.x, v.y};
+    c[1] = {v.z, v.w};
+  }
+  static __device__ __forceinline__ void store_nt(void* base, int u, int h, int Vh, const cplx<float>* c) {
+    st_stream(reinterpret_cast<float4*>(base) + fidx(u, h, 6), make_float4(c[0].r, c[0].i, c[1].r, c[1].i));
   }
 };
 
@@ -213,6 +320,20 @@ struct UnitIO<PrecBF16> {
     v.z = pack_bf16x2(c[2].r, c[2].i);
     v.w = pack_bf16x2(c[3].r, c[3].i);
     reinterpret_cast<uint4*>(base)[fidx(u, h, 3)] = v;
+  }
+  static __device__ __forceinline__ void load_nt(const void* base, int u, int h, int Vh, cplx<float>* c) {
+    const uint4 v = ld_stream(reinterpret_cast<const uint4*>(base) + fidx(u, h, 3));
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[q] = {bf16_to_f32(w[q] & 0xFFFFu), bf16_to_f32(w[q] >> 16)};
+  }
+  static __device__ __forceinline__ void store_nt(void* base, int u, int h, int Vh, const cplx<float>* c) {
+    uint4 v;
+    v.x = pack_bf16x2(c[0].r, c[0].i);
+    v.y = pack_bf16x2(c[1].r, c[1].i);
+    v.z = pack_bf16x2(c[2].r, c[2].i);
+    v.w = pack_bf16x2(c[3].r, c[3].i);
+    st_stream(reinterpret_cast<uint4*>(base) + fidx(u, h, 3), v);
   }
 };
 
@@ -235,7 +356,7 @@ struct LinkIO<PrecF64> {
     SU3<double> u;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      double2 v = b[fidx(k, h, 6)];
+      const double2 v = ld_stream(b + fidx(k, h, 6));
       u.m[k] = {v.x, v.y};
     }
     third_row(u);
@@ -251,7 +372,7 @@ struct LinkIO<PrecF32> {
     SU3<float> u;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      float4 v = b[fidx(j, h, 3)];
+      const float4 v = ld_stream(b + fidx(j, h, 3));
       u.m[2 * j] = {v.x, v.y};
       u.m[2 * j + 1] = {v.z, v.w};
     }
@@ -268,7 +389,7 @@ struct LinkIO<PrecBF16> {
     SU3<float> u;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      uint2 v = b[fidx(j, h, 3)];
+      const uint2 v = ld_stream(b + fidx(j, h, 3));
       u.m[2 * j] = {bf16_to_f32(v.x & 0xFFFFu), bf16_to_f32(v.x >> 16)};
       u.m[2 * j + 1] = {bf16_to_f32(v.y & 0xFFFFu), bf16_to_f32(v.y >> 16)};
     }

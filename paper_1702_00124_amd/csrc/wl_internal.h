@@ -15,11 +15,21 @@
 namespace wl {
 
 constexpr int kMaxRhs = 16;
+constexpr int kTuneRhs[3] = {1, 4, 8};  // rhs counts the autotuner times each hop class at
 constexpr int kBlock = 256;  // threads per workgroup of the site kernels
 constexpr int kScal = 2048;  // device scalar slots; the CG state starts at kCgState
 constexpr int kCgState = 1024;
 constexpr int kProfPairs = 4096;  // sampled hop launches timed per precision
 enum HopVariant { kHopSite = 0, kHopDirParallel = 1 };
+// how a hop is launched: kernel variant; npass = direction-parallel: most rhs
+// passes per link held in registers (1, 2, 4), site: rhs per thread (1, 2);
+// use_xcd = XCD-contiguous workgroup numbering (else hardware round-robin)
+struct HopConfig {
+  int variant, npass, use_xcd;
+};
+// rhs-count classes with their own configuration: 1, 2-4, 5-16
+constexpr int kHopKinds = 3;
+inline int hop_kind(int nrhs) { return nrhs <= 1 ? 0 : (nrhs <= 4 ? 1 : 2); }
 
 enum Prec { F64 = WL_F64, F32 = WL_F32, BF16 = WL_BF16 };
 
@@ -41,8 +51,15 @@ struct Error : std::runtime_error {
   } while (0)
 
 // bytes of one half-lattice spinor field (padded to whole 64-site tiles)
+// Bytes of one rhs of an even-odd spinor field: the tiled sites, rounded up to
+// 4 KiB, plus a stagger so that the rhs of a batch (and the halves of a full
+// field) do not start at addresses congruent modulo the L2 set span: a stride
+// that is a multiple of a large power of two maps the same site of every rhs
+// to one L2 set and one memory channel.
+constexpr size_t kFieldStagger = size_t(37) << 12;  // 148 KiB: odd multiple of 4 KiB
 inline size_t spinor_bytes(Prec p, int Vh) {
-  return size_t(p == F64 ? 192 : (p == F32 ? 96 : 48)) * size_t(padded_sites(Vh));
+  const size_t raw = size_t(p == F64 ? 192 : (p == F32 ? 96 : 48)) * size_t(padded_sites(Vh));
+  return ((raw + 4095) & ~size_t(4095)) + kFieldStagger;
 }
 // bytes of the two-row hop links of one precision: 2 parities x 4 directions
 inline size_t links_bytes(Prec p, int Vh) {
@@ -75,8 +92,11 @@ struct wl_lattice {
   long long n_hop = 0;                       // hop applications (single rhs units)
   long long n_hop_p[3] = {0, 0, 0};          // ... per storage precision
   long long n_kmat = 0;                      // K-hat / K applications (single rhs units)
-  int use_xcd = 1;
-  int hop_var[3] = {1, 1, 0};                // hop kernel variant per precision (wl::HopVariant)
+  // hop launch configuration per storage precision and rhs-count class
+  wl::HopConfig hop_cfg[3][wl::kHopKinds] = {
+      {{wl::kHopDirParallel, 1, 1}, {wl::kHopDirParallel, 4, 1}, {wl::kHopDirParallel, 4, 1}},
+      {{wl::kHopDirParallel, 1, 1}, {wl::kHopDirParallel, 4, 1}, {wl::kHopDirParallel, 4, 1}},
+      {{wl::kHopSite, 1, 1}, {wl::kHopDirParallel, 4, 1}, {wl::kHopDirParallel, 4, 1}}};
   // optional event timing of sampled hop launches, per storage precision
   int prof_on = 0;
   int prof_capturing = 0;

@@ -301,15 +301,34 @@ class WilsonLattice:
         W.check(self.lib.hmc_trajectory(self.h, C.byref(prm), _ptr(P), _ptr(chi), u, C.byref(res)))
         return res
 
+    HOP_KINDS = (1, 4, 8)  # rhs counts the autotuner times classes 0, 1, 2 at (1, 2-4, 5-16 rhs)
+
+    def hop_config(self, prec, kind: int):
+        """(variant, npass, use_xcd) of one precision and rhs class (0: 1 rhs, 1: 2-4, 2: 5-16)."""
+        v, n, x = C.c_int(), C.c_int(), C.c_int()
+        W.check(self.lib.wl_get_hop_config(self.h, _prec(prec), int(kind), C.byref(v), C.byref(n), C.byref(x)))
+        return v.value, n.value, x.value
+
+    def set_hop_config(self, prec, kind: int = -1, variant=None, npass=None, use_xcd=None):
+        """Set fields of the hop configuration (None keeps a field) of one rhs class or all (-1)."""
+        for k in (range(3) if kind == -1 else (kind,)):
+            cur = self.hop_config(prec, k)
+            new = [cur[i] if v is None else int(v) for i, v in enumerate((variant, npass, use_xcd))]
+            W.check(self.lib.wl_set_hop_config(self.h, _prec(prec), k, *new))
+
     def set_hop_variant(self, prec, variant: int):
-        """0: thread per site; 1: direction-parallel (default)."""
-        W.check(self.lib.wl_set_hop_variant(self.h, _prec(prec), int(variant)))
+        """0: thread per site; 1: direction-parallel; for every rhs class."""
+        self.set_hop_config(prec, -1, variant=variant)
 
     def autotune(self):
-        """Time both hop variants per precision, keep the faster; returns {prec: (site_us, dp_us)}."""
-        us = (C.c_double * 6)()
+        """Time the hop configurations per precision and rhs class and keep the fastest.
+
+        Returns {prec: [24 microsecond timings]} in the order the C API documents:
+        class 0 (site, dp) x (xcd on, off); classes 1 and 2
+        (site 1, site 2, dp 1, dp 2, dp 4) x (xcd on, off)."""
+        us = (C.c_double * 72)()
         W.check(self.lib.wl_autotune(self.h, us))
-        return {name: (us[2 * i], us[2 * i + 1]) for name, i in PREC.items()}
+        return {name: list(us[24 * i:24 * i + 24]) for name, i in PREC.items()}
 
     def time_hop(self, prec="f64", nrhs: int = 1, nlaunch: int = 200) -> float:
         """Average microseconds per hop launch over a back-to-back burst."""

@@ -12,6 +12,7 @@ import torch
 
 import lattice_inputs as li
 from oracle import wilson as ow
+from paper_1702_00124_amd.lattice import CG
 from tests.gpu_common import full_noise, half_noise, make_lattice, need_gpu, rel, say, to_np
 
 pytestmark = pytest.mark.gpu
@@ -118,8 +119,15 @@ def test_variants_agree_and_autotune():
         outs.append(to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi)), 0))))
     assert rel(outs[0], outs[1]) <= 1e-14
     res = lat.autotune()
-    say(f"  autotune us per launch (site, dir-parallel): {res}")
-    assert all(a > 0 and b > 0 for a, b in res.values())
+    say(f"  autotune us per launch: {res}")
+    assert all(len(v) == 24 and min(v) > 0 for v in res.values())
+    for prec in ("f64", "f32", "bf16"):
+        say(f"  kept {prec}: {[lat.hop_config(prec, k) for k in range(3)]}")
+    # the tuned choice still gives the oracle's hop, one rhs and several
+    psi4 = half_noise(L, 34, nrhs=4)
+    got = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi4)), 0, nrhs=4), "f64", 4))
+    for r in range(4):
+        assert rel(got[r], ow.hop_eo(U, psi4[r], L, 0)) <= 1e-12
 
 
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 4, 10)])
@@ -167,3 +175,53 @@ def test_errors_are_reported():
         lat.dslash(b, 0, nrhs=17)
     with pytest.raises(WilsonError):
         lat.apply_K(b, 0.1, "J", out=b)
+
+
+@pytest.mark.parametrize("passes", [1, 2, 4])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [5, 8, 12, 16])
+def test_dslash_link_reuse_passes_equal_single(nrhs, prec, passes):
+    """Direction-parallel kernel holding each link across 1, 2 or 4 rhs passes:
+    bit-identical to one rhs at a time, dagger included; 16 = the rhs limit."""
+    L = (6, 4, 4, 10)
+    say("dslash link-reuse passes", passes, prec, "nrhs", nrhs)
+    lat, U = make_lattice(L, variant=1)
+    lat.set_hop_config(prec, -1, npass=passes)
+    psi = half_noise(L, 35, nrhs=nrhs)
+    for dagger in (False, True):
+        multi = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi), prec), 0, dagger,
+                                                   prec=prec, nrhs=nrhs), prec, nrhs))
+        for r in range(nrhs):
+            single = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi[r]), prec), 0, dagger,
+                                                        prec=prec), prec))
+            assert np.array_equal(multi[r], single), (r, dagger)
+        if prec == "f64":
+            assert rel(multi[nrhs - 1], ow.hop_eo(U, psi[nrhs - 1], L, 0, t_bc=-1, dagger=dagger)) <= 1e-12
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_dslash_launch_config_invariance(variant):
+    """Rhs per pass or thread, passes per link load and workgroup order change
+    no output bit of a variant; 8^4 spans eight 64-site tiles per parity."""
+    L = (8, 8, 8, 8)
+    say("dslash launch configurations", "variant", variant)
+    lat, U = make_lattice(L, variant=variant)
+    psi = half_noise(L, 36, nrhs=4)
+    outs = {}
+    for npass in (1, 2, 4):
+        for xcd in (1, 0):
+            lat.set_hop_config("f64", -1, npass=npass, use_xcd=xcd)
+            lat.set_hop_config("bf16", -1, npass=npass, use_xcd=xcd)
+            for prec in ("f64", "bf16"):
+                outs[(npass, xcd, prec)] = to_np(lat.export_spinor(
+                    lat.dslash(lat.import_spinor(torch.from_numpy(psi), prec), 1, prec=prec, nrhs=4), prec, 4))
+    for k, v in outs.items():
+        assert np.array_equal(v, outs[(1, 1, k[2])]), k
+    assert rel(outs[(1, 1, "f64")][2], ow.hop_eo(U, psi[2], L, 1)) <= 1e-12
+    lat.set_hop_config("f32", -1, npass=2, use_xcd=0)
+    b = half_noise(L, 37)
+    x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), 0.155, "J", params=CG(tol=1e-10, inner="f32"))
+    assert rc == 0 and st[0].true_rel_res <= 1e-10
+    assert rel(ow.J(U, to_np(lat.export_spinor(x)), L, 0.155, 0.0), b) <= 1.01e-10
+    with pytest.raises(Exception):
+        lat.set_hop_config("f64", 0, npass=3)

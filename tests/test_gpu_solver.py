@@ -30,12 +30,14 @@ def test_cg_full_lattice_small_workload():
     assert rel(ow.K(U, xg, L, kappa), b) <= 1e-11
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("inner", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("graph", [False, True])
-def test_cg_even_odd_precisions(inner, graph):
+def test_cg_even_odd_precisions(inner, graph, variant):
+    """Both hop variants: the fused <p, J p> partials of each feed the CG."""
     L, kappa, mu2 = (8, 8, 8, 8), 0.155, 0.0
-    say("cg J", inner, "graph" if graph else "eager")
-    lat, U = make_lattice(L)
+    say("cg J", inner, "graph" if graph else "eager", "variant", variant)
+    lat, U = make_lattice(L, variant=variant)
     b = half_noise(L, 2002)
     x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), kappa, "J", mu2=[mu2],
                              params=CG(tol=1e-10, inner=inner, use_graph=graph))
@@ -47,12 +49,18 @@ def test_cg_even_odd_precisions(inner, graph):
     assert rel(xg, xr) <= 200 * 2e-10
 
 
-def test_cg_batched_shifts_match_single():
-    """8 rhs, rhs j with shift mu2[j mod 4] (the batched multi-rhs workload's pairing)."""
+@pytest.mark.parametrize("variant,passes", [(0, 1), (0, 2), (1, 1), (1, 2), (1, 4)])
+def test_cg_batched_shifts_match_single(variant, passes):
+    """8 rhs, rhs j with shift mu2[j mod 4] (the batched multi-rhs workload's
+    pairing), for each multi-rhs hop layout: thread per site, and the
+    direction-parallel kernel with 1, 2 or 4 rhs passes per link load (for the
+    site kernel, passes >= 2 means two rhs per thread)."""
     L, kappa = (6, 4, 4, 10), 0.155
     mu2 = [0.0, 0.005, 0.05, 0.5] * 2
-    say("cg batched 8 rhs")
-    lat, U = make_lattice(L)
+    say("cg batched 8 rhs, variant", variant, "passes", passes)
+    lat, U = make_lattice(L, variant=variant)
+    for prec in ("f64", "f32", "bf16"):
+        lat.set_hop_config(prec, -1, npass=passes)
     b = half_noise(L, 2010, nrhs=8)
     for inner in ("f64", "f32"):
         x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), kappa, "J", mu2=mu2, nrhs=8,
