@@ -57,12 +57,34 @@ HOP_BYTES_PER_SITE = {"f64": 8 * 96 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8
 # kernel sources); otherwise `traffic` is reported as null.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_COUNTERS = {
-    "source_sha256": "5076290b9fe40b2503959a5207769692e5599437e91cb9e7fc70179b81e9a5d1",
-    # (precision, variant): KiB per dispatch on the 16^3x32 workload, median of 65-115 dispatches
+    "source_sha256": "8ee86695bc9c28f21f027846c72774dd4faa49ac09e60e21d20661a3a0d4c136",
+    # "precision:variant:workgroup order:streaming": KiB per dispatch on the 16^3x32
+    # workload, median of 45 dispatches per configuration
     "per_launch_kib": {
-        "f64:site": {"fetch": 34229.4, "write": 12288.0}, "f64:dp": {"fetch": 34014.3, "write": 12288.0},
-        "f32:site": {"fetch": 16999.0, "write": 6144.0}, "f32:dp": {"fetch": 17002.5, "write": 6144.0},
-        "bf16:site": {"fetch": 8566.5, "write": 3072.0}, "bf16:dp": {"fetch": 8576.5, "write": 3072.0},
+        "f64:site:xcd1:st0": {"fetch": 34202.3, "write": 12288.0},
+        "f64:site:xcd1:st1": {"fetch": 33935.0, "write": 12299.9},
+        "f64:site:xcd0:st0": {"fetch": 40056.4, "write": 12288.0},
+        "f64:site:xcd0:st1": {"fetch": 37113.2, "write": 12289.0},
+        "f64:dp:xcd1:st0": {"fetch": 34185.1, "write": 12288.0},
+        "f64:dp:xcd1:st1": {"fetch": 33926.5, "write": 12288.0},
+        "f64:dp:xcd0:st0": {"fetch": 45173.4, "write": 12288.0},
+        "f64:dp:xcd0:st1": {"fetch": 45009.5, "write": 12288.0},
+        "f32:site:xcd1:st0": {"fetch": 16998.0, "write": 6144.0},
+        "f32:site:xcd1:st1": {"fetch": 17001.0, "write": 6144.0},
+        "f32:site:xcd0:st0": {"fetch": 18617.2, "write": 6144.0},
+        "f32:site:xcd0:st1": {"fetch": 18537.0, "write": 6144.0},
+        "f32:dp:xcd1:st0": {"fetch": 17001.0, "write": 6144.0},
+        "f32:dp:xcd1:st1": {"fetch": 17001.0, "write": 6144.0},
+        "f32:dp:xcd0:st0": {"fetch": 22377.3, "write": 6144.0},
+        "f32:dp:xcd0:st1": {"fetch": 22377.0, "write": 6144.0},
+        "bf16:site:xcd1:st0": {"fetch": 8561.5, "write": 3072.0},
+        "bf16:site:xcd1:st1": {"fetch": 8563.0, "write": 3072.0},
+        "bf16:site:xcd0:st0": {"fetch": 9329.5, "write": 3072.0},
+        "bf16:site:xcd0:st1": {"fetch": 9331.0, "write": 3072.0},
+        "bf16:dp:xcd1:st0": {"fetch": 8568.0, "write": 3072.0},
+        "bf16:dp:xcd1:st1": {"fetch": 8572.5, "write": 3072.0},
+        "bf16:dp:xcd0:st0": {"fetch": 11448.0, "write": 3072.0},
+        "bf16:dp:xcd0:st1": {"fetch": 11452.5, "write": 3072.0},
     },
 }
 
@@ -177,7 +199,7 @@ def large_volume(li, torch, np, CG, WilsonLattice):
     return out
 
 
-KERNELS_ONLY_CONFIGS = [(v, x) for v in (0, 1) for x in (1, 0)]   # (variant, use_xcd)
+KERNELS_ONLY_CONFIGS = [(v, x, st) for v in (0, 1) for x in (1, 0) for st in (0, 1)]   # (variant, use_xcd, stream)
 
 
 def kernels_only(lat, Vh, li, torch):
@@ -189,8 +211,8 @@ def kernels_only(lat, Vh, li, torch):
     for prec in ("f64", "f32", "bf16"):
         b = lat.import_spinor(torch.from_numpy(psi), prec)
         out = lat.new_field(prec)
-        for variant, xcd in KERNELS_ONLY_CONFIGS:
-            lat.set_hop_config(prec, 0, variant=variant, npass=1, use_xcd=xcd)
+        for variant, xcd, stream in KERNELS_ONLY_CONFIGS:
+            lat.set_hop_config(prec, 0, variant=variant, npass=1, use_xcd=xcd, stream=stream)
             for _ in range(50):
                 lat.dslash(b, 0, prec=prec, out=out)
     torch.cuda.synchronize()
@@ -199,7 +221,7 @@ def kernels_only(lat, Vh, li, torch):
     for _ in range(5):
         dst.copy_(src)
     torch.cuda.synchronize()
-    log("kernels-only done: per precision (f64, f32, bf16) 50 hop launches of each (variant, use_xcd) in",
+    log("kernels-only done: per precision (f64, f32, bf16) 50 hop launches of each (variant, use_xcd, stream) in",
         KERNELS_ONLY_CONFIGS, "then 5 copies of 1 GiB")
 
 
@@ -215,6 +237,9 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch the hop kernels (50 per configuration and precision) and a 1 GiB copy, "
                          "for counter runs")
+    ap.add_argument("--kernels-volume", default=None,
+                    help="Lx,Ly,Lz,Lt of the --kernels-only lattice (default the trajectory's 16,16,16,32; "
+                         "32,32,32,64 is the large-volume lattice with plaquette ~0.60 links)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -228,6 +253,14 @@ def main():
     from paper_1702_00124_amd.lattice import CG, Term, WilsonLattice
 
     torch.cuda.set_device(0)
+    if args.kernels_only and args.kernels_volume:
+        Lk = tuple(int(v) for v in args.kernels_volume.split(","))
+        assert len(Lk) == 4
+        lat = WilsonLattice(Lk, t_bc=-1)
+        lat.set_links(torch.from_numpy(li.random_links(Lk, 0.432, li.seed_links(4))))
+        log(f"kernels-only lattice {Lk}, plaquette {lat.plaquette():.4f}")
+        kernels_only(lat, li.volume(Lk) // 2, li, torch)
+        return
     Vh = L[0] * L[1] * L[2] * L[3] // 2
     nsteps = [int(v) for v in args.md_steps.split(",")]
     assert len(nsteps) == 4
@@ -243,7 +276,7 @@ def main():
         return
     tune = lat.autotune()
     log(f"hop autotune (us per launch, candidates in the C API order): {tune}")
-    log("hop configurations kept (variant, npass, use_xcd) for 1, 2-4, 5-16 rhs:",
+    log("hop configurations kept (variant, npass, use_xcd, stream) for 1, 2-4, 5-16 rhs:",
         {p: [lat.hop_config(p, k) for k in range(3)] for p in ("f64", "f32", "bf16")})
 
     cg_md = CG(tol=1e-10, inner="f32", chunk=8)
@@ -293,14 +326,15 @@ def main():
     avg_us = lat.time_hop(dom, 1, 500)
     achieved = bytes_per_hop[dom] / (avg_us * 1e-6) / 1e9
     traffic = None
-    variant, _, use_xcd = lat.hop_config(dom, 0)
-    kib = PMC_COUNTERS["per_launch_kib"].get(f"{dom}:{['site', 'dp'][variant]}:xcd{use_xcd}")
+    variant, _, use_xcd, stream = lat.hop_config(dom, 0)
+    kib = PMC_COUNTERS["per_launch_kib"].get(f"{dom}:{['site', 'dp'][variant]}:xcd{use_xcd}:st{stream}")
     if kib and PMC_COUNTERS["source_sha256"] == hop_source_hash():
         traffic = int(1024 * (kib["fetch"] * PMC_FETCH_SCALE + kib["write"] * PMC_WRITE_SCALE))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"hop {dom} ({['thread-per-site', 'direction-parallel'][variant]}, "
-                          f"{'XCD-contiguous' if use_xcd else 'round-robin'} workgroup order)",
+                          f"{'XCD-contiguous' if use_xcd else 'round-robin'} workgroup order, "
+                          f"{'streaming' if stream else 'cached'} access)",
                 "avg_launch_us": round(avg_us, 2), "in_situ_avg_us": round(prof[dom][0], 2),
                 "in_situ_samples": prof[dom][1], "algorithmic_bytes_per_launch": bytes_per_hop[dom]}
     extra = {"hop_avg_us": {p: round(v[0], 2) for p, v in prof.items()},

@@ -246,28 +246,36 @@ int wl_counters(const wl_lattice* lat, long long* n_hop, long long* n_kmat);
  *            registers; site: 2 = two rhs per thread (FP32, BF16, even rhs
  *            counts), else one;
  *   use_xcd  1 = workgroups renumbered so that each of the 8 XCDs walks a
- *            contiguous range of sites; 0 = the hardware's round-robin order.
- * Results are identical for every npass and use_xcd, and agree between the
- * two variants up to the FP summation order of the 8 directions.
+ *            contiguous range of sites; 0 = the hardware's round-robin order;
+ *   stream   1 = non-temporal loads of links and epilogue operands and
+ *            non-temporal output stores (pays on volumes beyond the caches),
+ *            0 = ordinary cached access.
+ * Results are identical for every npass and use_xcd; stream and the variant
+ * change them by rounding only (stream: the compiler's contraction of products
+ * into FMAs may differ; variant: the summation order of the 8 directions).
  * wl_set_hop_config sets one class (kind = -1: all three); WL_EINVAL for
  * values outside these sets.  wl_get_hop_config reads one class (outputs may
  * be NULL).
  * wl_autotune times on this lattice, for every precision, class 0 at 1 rhs
  * over {site, direction-parallel}, classes 1 and 2 at 4 and 8 rhs over
  * {site npass 1, 2; direction-parallel npass 1, 2, 4}, each candidate with
- * use_xcd 1 then 0 (best of 3 bursts of 20 launches), and keeps the fastest
- * of every class.  us_out: optional host array of 3 x 24 microseconds per
- * launch, per precision (F64, F32, BF16): the 4 class-0 candidates
- * (site, dp with use_xcd 1, then with 0), then 10 for class 1 and 10 for
- * class 2 (site 1, site 2, dp 1, dp 2, dp 4 with use_xcd 1, then with 0). */
-int wl_set_hop_config(wl_lattice* lat, wl_prec prec, int kind, int variant, int npass, int use_xcd);
-int wl_get_hop_config(const wl_lattice* lat, wl_prec prec, int kind, int* variant, int* npass, int* use_xcd);
+ * (stream, use_xcd) = (0, 1), (0, 0), (1, 1), (1, 0), as bursts in which each
+ * launch reads the previous launch's output (best of 3 bursts of 20), and
+ * keeps the fastest of every class.  stream = 1 is a candidate only where the
+ * hop's working set (links and two fields of that class) exceeds the 256 MiB
+ * last-level cache.  us_out: optional host array of 3 x 48 microseconds per
+ * launch (0 for candidates not timed), per precision (F64, F32, BF16): 8 for
+ * class 0 (site, dp per (stream, use_xcd) in that order), then 20 for class 1
+ * and 20 for class 2 (site 1, site 2, dp 1, dp 2, dp 4 per (stream, use_xcd)). */
+int wl_set_hop_config(wl_lattice* lat, wl_prec prec, int kind, int variant, int npass, int use_xcd, int stream);
+int wl_get_hop_config(const wl_lattice* lat, wl_prec prec, int kind, int* variant, int* npass, int* use_xcd,
+                      int* stream);
 int wl_autotune(wl_lattice* lat, double* us_out);
 /* Tracing: average duration in microseconds of back-to-back hop launches
- * (current variant, nrhs right-hand sides, scratch fields owned by the
- * library), timed with HIP events on the context stream: 100 warm-up
- * launches, then the median over 5 sub-bursts of nlaunch/5.  Not counted in
- * the hop counters. */
+ * (current configuration for nrhs right-hand sides, two scratch fields owned
+ * by the library, each launch reading the previous one's output), timed with
+ * HIP events on the context stream: 100 warm-up launches, then the median
+ * over 5 sub-bursts of nlaunch/5.  Not counted in the hop counters. */
 int wl_time_hop(wl_lattice* lat, wl_prec prec, int nrhs, int nlaunch, double* avg_us);
 /* Tracing: the practical HBM ceiling: a plain copy of bytes (multiple of 16,
  * at most 16 GiB) between two library buffers, reps times; *gbs = bytes read

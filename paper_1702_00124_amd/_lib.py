@@ -81,8 +81,8 @@ SIGNATURES = {
     "wl_integrator_schedule": (I, [C.POINTER(I), I, I, D, C.POINTER(I), C.POINTER(I), C.POINTER(D), I,
                                    C.POINTER(I)]),
     "wl_profile": (I, [P, I]),
-    "wl_set_hop_config": (I, [P, I, I, I, I, I]),
-    "wl_get_hop_config": (I, [P, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
+    "wl_set_hop_config": (I, [P, I, I, I, I, I, I]),
+    "wl_get_hop_config": (I, [P, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
     "wl_autotune": (I, [P, C.POINTER(D)]),
     "wl_time_hop": (I, [P, I, I, I, C.POINTER(D)]),
     "wl_stream_copy": (I, [P, SZ, I, C.POINTER(D)]),

@@ -436,7 +436,7 @@ int wl_hop_counts(const wl_lattice* L, long long* counts) {
   });
 }
 
-int wl_set_hop_config(wl_lattice* L, wl_prec prec, int kind, int variant, int npass, int use_xcd) {
+int wl_set_hop_config(wl_lattice* L, wl_prec prec, int kind, int variant, int npass, int use_xcd, int stream) {
   return guard([&]() {
     check_lat(L);
     check_prec_rhs(prec, 1);
@@ -444,14 +444,16 @@ int wl_set_hop_config(wl_lattice* L, wl_prec prec, int kind, int variant, int np
     WL_REQUIRE(variant == kHopSite || variant == kHopDirParallel, WL_EINVAL, "unknown hop variant");
     WL_REQUIRE(npass == 1 || npass == 2 || npass == 4, WL_EINVAL, "npass must be 1, 2 or 4");
     WL_REQUIRE(use_xcd == 0 || use_xcd == 1, WL_EINVAL, "use_xcd must be 0 or 1");
+    WL_REQUIRE(stream == 0 || stream == 1, WL_EINVAL, "stream must be 0 or 1");
     WL_HIP(hipStreamSynchronize(L->stream));
     for (int k = 0; k < kHopKinds; ++k)
-      if (kind == -1 || kind == k) L->hop_cfg[prec][k] = HopConfig{variant, npass, use_xcd};
+      if (kind == -1 || kind == k) L->hop_cfg[prec][k] = HopConfig{variant, npass, use_xcd, stream};
     return WL_OK;
   });
 }
 
-int wl_get_hop_config(const wl_lattice* L, wl_prec prec, int kind, int* variant, int* npass, int* use_xcd) {
+int wl_get_hop_config(const wl_lattice* L, wl_prec prec, int kind, int* variant, int* npass, int* use_xcd,
+                      int* stream) {
   return guard([&]() {
     check_lat(L);
     check_prec_rhs(prec, 1);
@@ -460,6 +462,7 @@ int wl_get_hop_config(const wl_lattice* L, wl_prec prec, int kind, int* variant,
     if (variant) *variant = c.variant;
     if (npass) *npass = c.npass;
     if (use_xcd) *use_xcd = c.use_xcd;
+    if (stream) *stream = c.stream;
     return WL_OK;
   });
 }
@@ -474,18 +477,21 @@ int wl_time_hop(wl_lattice* L, wl_prec prec, int nrhs, int nlaunch, double* avg_
     void* a = ws_get(L, "tune_a", fb);
     void* b = ws_get(L, "tune_b", fb);
     WL_HIP(hipMemsetAsync(a, 0, fb, L->stream));
+    WL_HIP(hipMemsetAsync(b, 0, fb, L->stream));
     hipEvent_t e0, e1;
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
     HopEpi e;
     // warm-up long enough for the clocks to leave any idle state, then the
-    // median of 5 sub-bursts
+    // median of 5 sub-bursts; launches alternate between the two fields, so
+    // each reads the previous one's output, as in a solver
     const int warm = 100, nsub = 5, per = std::max(1, nlaunch / nsub);
-    for (int i = 0; i < warm; ++i) launch_hop(L, Prec(prec), b, a, 0, 0, nrhs, e);
+    auto hop = [&](int i) { launch_hop(L, Prec(prec), i & 1 ? a : b, i & 1 ? b : a, i & 1, 0, nrhs, e); };
+    for (int i = 0; i < warm; ++i) hop(i);
     std::vector<double> sub;
     for (int k = 0; k < nsub; ++k) {
       WL_HIP(hipEventRecord(e0, L->stream));
-      for (int i = 0; i < per; ++i) launch_hop(L, Prec(prec), b, a, 0, 0, nrhs, e);
+      for (int i = 0; i < per; ++i) hop(i);
       WL_HIP(hipEventRecord(e1, L->stream));
       WL_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -537,13 +543,14 @@ int wl_stream_copy(wl_lattice* L, size_t bytes, int reps, double* gbs) {
 
 // best of 3 bursts of 20 hop launches (after 5 warm-ups), microseconds per
 // launch, on scratch fields; not counted in the hop counters
-static double tune_burst(wl_lattice* L, Prec p, void* out, const void* in, int nrhs, hipEvent_t e0, hipEvent_t e1) {
+static double tune_burst(wl_lattice* L, Prec p, void* fa, void* fb, int nrhs, hipEvent_t e0, hipEvent_t e1) {
   HopEpi e;
-  for (int i = 0; i < 5; ++i) launch_hop(L, p, out, in, 0, 0, nrhs, e);
+  // ping-pong: each launch reads the previous one's output, as in a solver
+  for (int i = 0; i < 5; ++i) launch_hop(L, p, i & 1 ? fa : fb, i & 1 ? fb : fa, i & 1, 0, nrhs, e);
   double us = 1e30;
   for (int rep = 0; rep < 3; ++rep) {
     WL_HIP(hipEventRecord(e0, L->stream));
-    for (int i = 0; i < 20; ++i) launch_hop(L, p, out, in, 0, 0, nrhs, e);
+    for (int i = 0; i < 20; ++i) launch_hop(L, p, i & 1 ? fa : fb, i & 1 ? fb : fa, i & 1, 0, nrhs, e);
     WL_HIP(hipEventRecord(e1, L->stream));
     WL_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -566,24 +573,37 @@ int wl_autotune(wl_lattice* L, double* us_out) {
     void* a = ws_get(L, "tune_a", fb);
     void* b = ws_get(L, "tune_b", fb);
     WL_HIP(hipMemsetAsync(a, 0, fb, L->stream));
+    WL_HIP(hipMemsetAsync(b, 0, fb, L->stream));
     int slot = 0;
     for (int p = 0; p < 3; ++p) {
       for (int k = 0; k < kHopKinds; ++k) {
         // one rhs: both variants; several: site with 1 or 2 rhs per thread and
-        // direction-parallel with 1, 2 or 4 passes; each in both workgroup orders
+        // direction-parallel with 1, 2 or 4 passes; each in both workgroup
+        // orders, cached then streaming
+        // streaming access only where the hop's working set (links and two
+        // fields) exceeds the last-level cache: below it the next kernel reads
+        // this hop's output from the cache, which a burst of hops cannot show
+        const size_t wset = links_bytes(Prec(p), L->Vh) + 2 * spinor_bytes(Prec(p), L->Vh) * kTuneRhs[k];
+        const int max_stream = wset > kLastLevelCache ? 1 : 0;
         std::vector<HopConfig> cand;
-        for (int xcd = 1; xcd >= 0; --xcd) {
-          if (k == 0) {
-            cand.push_back({kHopSite, 1, xcd});
-            cand.push_back({kHopDirParallel, 1, xcd});
-          } else {
-            for (int np : {1, 2}) cand.push_back({kHopSite, np, xcd});
-            for (int np : {1, 2, 4}) cand.push_back({kHopDirParallel, np, xcd});
+        for (int stm = 0; stm <= 1; ++stm)
+          for (int xcd = 1; xcd >= 0; --xcd) {
+            if (k == 0) {
+              cand.push_back({kHopSite, 1, xcd, stm});
+              cand.push_back({kHopDirParallel, 1, xcd, stm});
+            } else {
+              for (int np : {1, 2}) cand.push_back({kHopSite, np, xcd, stm});
+              for (int np : {1, 2, 4}) cand.push_back({kHopDirParallel, np, xcd, stm});
+            }
           }
-        }
         double best = 1e30;
         HopConfig keep = L->hop_cfg[p][k];
         for (const HopConfig& c : cand) {
+          if (c.stream > max_stream) {  // not a candidate on this volume
+            if (us_out) us_out[slot] = 0.0;
+            ++slot;
+            continue;
+          }
           L->hop_cfg[p][k] = c;
           const double us = tune_burst(L, Prec(p), b, a, kTuneRhs[k], e0, e1);
           if (us_out) us_out[slot] = us;

@@ -47,7 +47,7 @@ __device__ __forceinline__ void hop_block_coords(const HopArgs& a, int* tile, in
   *row = b - *tile * a.rows;
 }
 
-template <typename P, int MU, int DAG, int NR>
+template <typename P, int MU, int DAG, int NR, bool ST>
 __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h, int r0,
                                         Spinor<typename P::real>* acc) {
   using R = typename P::real;
@@ -59,7 +59,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h,
   // forward: U_mu(x) in(x + mu)
   {
     const int hf = neighbour<MU>(a.g, c, +1, &wrap);
-    const SU3<R> U = LinkIO<P>::load(a.links + (a.parity * 4 + MU) * lb, h, Vh);
+    const SU3<R> U = LinkIO<P>::template load<ST>(a.links + (a.parity * 4 + MU) * lb, h, Vh);
     const R ph = wrap ? R(a.g.tbc) : R(1);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -76,7 +76,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h,
   // backward: U_mu(x - mu)^dag in(x - mu)
   {
     const int hb = neighbour<MU>(a.g, c, -1, &wrap);
-    const SU3<R> U = LinkIO<P>::load(a.links + ((1 - a.parity) * 4 + MU) * lb, hb, Vh);
+    const SU3<R> U = LinkIO<P>::template load<ST>(a.links + ((1 - a.parity) * 4 + MU) * lb, hb, Vh);
     const R ph = wrap ? R(a.g.tbc) : R(1);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -92,7 +92,29 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h,
   }
 }
 
-template <typename P, int DAG, int NR>
+// epilogue field access, streaming or cached
+template <typename P, bool ST>
+__device__ __forceinline__ Spinor<typename P::real> epi_load(const char* base, int h, int Vh) {
+  if constexpr (ST) return SpinorIO<P>::load_nt(base, h, Vh);
+  else return SpinorIO<P>::load(base, h, Vh);
+}
+template <typename P, bool ST>
+__device__ __forceinline__ void epi_store(char* base, int h, int Vh, const Spinor<typename P::real>& v) {
+  if constexpr (ST) SpinorIO<P>::store_nt(base, h, Vh, v);
+  else SpinorIO<P>::store(base, h, Vh, v);
+}
+template <typename P, bool ST>
+__device__ __forceinline__ void epi_load_unit(const char* base, int u, int h, int Vh, cplx<typename P::real>* c) {
+  if constexpr (ST) UnitIO<P>::load_nt(base, u, h, Vh, c);
+  else UnitIO<P>::load(base, u, h, Vh, c);
+}
+template <typename P, bool ST>
+__device__ __forceinline__ void epi_store_unit(char* base, int u, int h, int Vh, const cplx<typename P::real>* c) {
+  if constexpr (ST) UnitIO<P>::store_nt(base, u, h, Vh, c);
+  else UnitIO<P>::store(base, u, h, Vh, c);
+}
+
+template <typename P, int DAG, int NR, bool ST>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
   using R = typename P::real;
   int b, row;
@@ -111,10 +133,10 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
     for (int r = 0; r < NR; ++r)
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[r].c[k] = zero<R>();
-    hop_dir<P, 0, DAG, NR>(a, c, h, r0, acc);
-    hop_dir<P, 1, DAG, NR>(a, c, h, r0, acc);
-    hop_dir<P, 2, DAG, NR>(a, c, h, r0, acc);
-    hop_dir<P, 3, DAG, NR>(a, c, h, r0, acc);
+    hop_dir<P, 0, DAG, NR, ST>(a, c, h, r0, acc);
+    hop_dir<P, 1, DAG, NR, ST>(a, c, h, r0, acc);
+    hop_dir<P, 2, DAG, NR, ST>(a, c, h, r0, acc);
+    hop_dir<P, 3, DAG, NR, ST>(a, c, h, r0, acc);
 
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -124,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) o.c[k] = ca * acc[r].c[k];
       if (a.x) {
-        const Spinor<R> xv = SpinorIO<P>::load_nt(a.x + off, h, Vh);
+        const Spinor<R> xv = epi_load<P, ST>(a.x + off, h, Vh);
         const R cx = R(a.cx);
 #pragma unroll
         for (int k = 0; k < 12; ++k) o.c[k] = o.c[k] + cx * xv.c[k];
@@ -134,14 +156,14 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
         for (int k = 6; k < 12; ++k) o.c[k] = R(-1) * o.c[k];
       }
       if (a.y) {
-        const Spinor<R> yv = SpinorIO<P>::load_nt(a.y + off, h, Vh);
+        const Spinor<R> yv = epi_load<P, ST>(a.y + off, h, Vh);
         const R cy = R(a.by[r0 + r]);
 #pragma unroll
         for (int k = 0; k < 12; ++k) o.c[k] = o.c[k] + cy * yv.c[k];
       }
-      SpinorIO<P>::store_nt(a.out + off, h, Vh, o);
+      epi_store<P, ST>(a.out + off, h, Vh, o);
       if (a.dot == 1) {
-        const Spinor<R> dv = SpinorIO<P>::load_nt(a.dotv + off, h, Vh);
+        const Spinor<R> dv = epi_load<P, ST>(a.dotv + off, h, Vh);
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) s += double(dv.c[k].r) * double(o.c[k].r) + double(dv.c[k].i) * double(o.c[k].i);
@@ -177,7 +199,7 @@ constexpr int kDpSites = 64;
 constexpr int kDpThreads = 8 * kDpSites;
 
 // the wavefront's direction: its neighbour, time-boundary phase and link
-template <typename P, int MU, int FWD>
+template <typename P, int MU, int FWD, bool ST>
 __device__ __forceinline__ void dp_link(const HopArgs& a, const Coord& c, int h, SU3<typename P::real>* U, int* hn,
                                         typename P::real* ph) {
   using R = typename P::real;
@@ -185,8 +207,8 @@ __device__ __forceinline__ void dp_link(const HopArgs& a, const Coord& c, int h,
   const size_t lb = LinkIO<P>::bytes * size_t(a.g.Vhp);
   bool wrap;
   *hn = neighbour<MU>(a.g, c, FWD ? +1 : -1, &wrap);
-  *U = FWD ? LinkIO<P>::load(a.links + (a.parity * 4 + MU) * lb, h, Vh)
-           : LinkIO<P>::load(a.links + ((1 - a.parity) * 4 + MU) * lb, *hn, Vh);
+  *U = FWD ? LinkIO<P>::template load<ST>(a.links + (a.parity * 4 + MU) * lb, h, Vh)
+           : LinkIO<P>::template load<ST>(a.links + ((1 - a.parity) * 4 + MU) * lb, *hn, Vh);
   *ph = wrap ? R(a.g.tbc) : R(1);
 }
 
@@ -238,7 +260,7 @@ __device__ __forceinline__ cplx<R> dp_recon(const cplx<R>* W, int s, int col, in
 
 // NRP rhs share one LDS pass; NPASS passes reuse the link held in registers,
 // so each link is read once for NRP * NPASS rhs
-template <typename P, int DAG, int NRP, int NPASS>
+template <typename P, int DAG, int NRP, int NPASS, bool ST>
 __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
   using R = typename P::real;
   using UIO = UnitIO<P>;
@@ -259,14 +281,14 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
   if (active) {
     const Coord c = site_coords(a.g, h, a.parity);
     switch (wv) {
-      case 0: dp_link<P, 0, 1>(a, c, h, &U, &hn, &ph); break;
-      case 1: dp_link<P, 0, 0>(a, c, h, &U, &hn, &ph); break;
-      case 2: dp_link<P, 1, 1>(a, c, h, &U, &hn, &ph); break;
-      case 3: dp_link<P, 1, 0>(a, c, h, &U, &hn, &ph); break;
-      case 4: dp_link<P, 2, 1>(a, c, h, &U, &hn, &ph); break;
-      case 5: dp_link<P, 2, 0>(a, c, h, &U, &hn, &ph); break;
-      case 6: dp_link<P, 3, 1>(a, c, h, &U, &hn, &ph); break;
-      default: dp_link<P, 3, 0>(a, c, h, &U, &hn, &ph); break;
+      case 0: dp_link<P, 0, 1, ST>(a, c, h, &U, &hn, &ph); break;
+      case 1: dp_link<P, 0, 0, ST>(a, c, h, &U, &hn, &ph); break;
+      case 2: dp_link<P, 1, 1, ST>(a, c, h, &U, &hn, &ph); break;
+      case 3: dp_link<P, 1, 0, ST>(a, c, h, &U, &hn, &ph); break;
+      case 4: dp_link<P, 2, 1, ST>(a, c, h, &U, &hn, &ph); break;
+      case 5: dp_link<P, 2, 0, ST>(a, c, h, &U, &hn, &ph); break;
+      case 6: dp_link<P, 3, 1, ST>(a, c, h, &U, &hn, &ph); break;
+      default: dp_link<P, 3, 0, ST>(a, c, h, &U, &hn, &ph); break;
     }
   }
   double part[NR];
@@ -296,8 +318,8 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
         const R cy = R(a.by[rp + r]);
         for (int u = wv; u < UIO::NU; u += 8) {
           cplx<R> o[UIO::CPU], xv[UIO::CPU], yv[UIO::CPU];
-          if (a.x) UIO::load_nt(a.x + off, u, h, Vh, xv);
-          if (a.y) UIO::load_nt(a.y + off, u, h, Vh, yv);
+          if (a.x) epi_load_unit<P, ST>(a.x + off, u, h, Vh, xv);
+          if (a.y) epi_load_unit<P, ST>(a.y + off, u, h, Vh, yv);
 #pragma unroll
           for (int q = 0; q < UIO::CPU; ++q) {
             const int comp = u * UIO::CPU + q;
@@ -307,10 +329,10 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
             if (a.g5 && s >= 2) o[q] = R(-1) * o[q];
             if (a.y) o[q] = o[q] + cy * yv[q];
           }
-          UIO::store_nt(a.out + off, u, h, Vh, o);
+          epi_store_unit<P, ST>(a.out + off, u, h, Vh, o);
           if (a.dot == 1) {
             cplx<R> dv[UIO::CPU];
-            UIO::load_nt(a.dotv + off, u, h, Vh, dv);
+            epi_load_unit<P, ST>(a.dotv + off, u, h, Vh, dv);
 #pragma unroll
             for (int q = 0; q < UIO::CPU; ++q)
               part[pass * NRP + r] += double(dv[q].r) * double(o[q].r) + double(dv[q].i) * double(o[q].i);
@@ -335,7 +357,7 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
 
 int hop_tiles(const wl_lattice* L, Prec) { return (L->Vh + kDpSites - 1) / kDpSites; }
 
-template <typename P, int DAG, int NRP>
+template <typename P, int DAG, int NRP, bool ST>
 static void dispatch_dp(HopArgs a, int nrhs, hipStream_t st, int max_pass) {
   // passes per block: the largest of 4, 2, 1 within max_pass dividing the rhs groups
   const int groups = nrhs / NRP;
@@ -343,13 +365,13 @@ static void dispatch_dp(HopArgs a, int nrhs, hipStream_t st, int max_pass) {
   a.rows = groups / npass;
   dim3 grid(((a.g.Vh + kDpSites - 1) / kDpSites) * a.rows);
   switch (npass) {
-    case 4: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 4>), grid, dim3(kDpThreads), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 2>), grid, dim3(kDpThreads), 0, st, a); break;
-    default: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 1>), grid, dim3(kDpThreads), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 4, ST>), grid, dim3(kDpThreads), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 2, ST>), grid, dim3(kDpThreads), 0, st, a); break;
+    default: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 1, ST>), grid, dim3(kDpThreads), 0, st, a); break;
   }
 }
 
-template <typename P, int DAG>
+template <typename P, int DAG, bool ST>
 static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, const HopConfig& c) {
   // rhs per LDS pass (direction-parallel) or per thread (site): two for FP32
   // and BF16 with an even rhs count when the configuration allows, else one
@@ -358,28 +380,33 @@ static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, const HopConfig& c)
   if (c.variant == kHopDirParallel) {
     if constexpr (narrow) {
       if (two) {
-        dispatch_dp<P, DAG, 2>(a, nrhs, st, c.npass);
+        dispatch_dp<P, DAG, 2, ST>(a, nrhs, st, c.npass);
         return;
       }
     }
-    dispatch_dp<P, DAG, 1>(a, nrhs, st, c.npass);
+    dispatch_dp<P, DAG, 1, ST>(a, nrhs, st, c.npass);
     return;
   }
   if constexpr (narrow) {
     if (two) {
       a.rows = nrhs / 2;
-      hipLaunchKernelGGL((hop_kernel<P, DAG, 2>), dim3(site_blocks(a.g.Vh) * a.rows), dim3(kBlock), 0, st, a);
+      hipLaunchKernelGGL((hop_kernel<P, DAG, 2, ST>), dim3(site_blocks(a.g.Vh) * a.rows), dim3(kBlock), 0, st, a);
       return;
     }
   }
   a.rows = nrhs;
-  hipLaunchKernelGGL((hop_kernel<P, DAG, 1>), dim3(site_blocks(a.g.Vh) * a.rows), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((hop_kernel<P, DAG, 1, ST>), dim3(site_blocks(a.g.Vh) * a.rows), dim3(kBlock), 0, st, a);
 }
 
 template <typename P>
 static void dispatch(const HopArgs& a, int dagger, int nrhs, hipStream_t st, const HopConfig& c) {
-  if (dagger) dispatch_nr<P, 1>(a, nrhs, st, c);
-  else dispatch_nr<P, 0>(a, nrhs, st, c);
+  if (c.stream) {
+    if (dagger) dispatch_nr<P, 1, true>(a, nrhs, st, c);
+    else dispatch_nr<P, 0, true>(a, nrhs, st, c);
+  } else {
+    if (dagger) dispatch_nr<P, 1, false>(a, nrhs, st, c);
+    else dispatch_nr<P, 0, false>(a, nrhs, st, c);
+  }
 }
 
 void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_parity, int dagger,

@@ -99,8 +99,10 @@ struct SU3 {
 // ------------------------------------------------------------------ streaming access
 // Non-temporal loads and stores for data a hop touches exactly once (links:
 // each link serves one output site forward and one backward; the epilogue's
-// operands; the output), so that they do not push the neighbour spinors, which
-// are read 8 times, out of L2.
+// operands; the output), so that on volumes beyond the caches they do not push
+// the neighbour spinors, which are read 8 times, out of L2.  On volumes that
+// fit the caches the next kernel's input is this one's output, and streaming
+// stores lose that reuse: the hop takes them as a per-launch option.
 typedef double v2d_t __attribute__((ext_vector_type(2)));
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 typedef unsigned v2u_t __attribute__((ext_vector_type(2)));
@@ -351,12 +353,13 @@ struct LinkIO;
 template <>
 struct LinkIO<PrecF64> {
   static constexpr int bytes = 96;  // per link: two rows of double2
+  template <bool ST = false>
   static __device__ __forceinline__ SU3<double> load(const void* base, int h, int Vh) {
     const double2* b = reinterpret_cast<const double2*>(base);
     SU3<double> u;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const double2 v = ld_stream(b + fidx(k, h, 6));
+      const double2 v = ST ? ld_stream(b + fidx(k, h, 6)) : b[fidx(k, h, 6)];
       u.m[k] = {v.x, v.y};
     }
     third_row(u);
@@ -367,12 +370,13 @@ struct LinkIO<PrecF64> {
 template <>
 struct LinkIO<PrecF32> {
   static constexpr int bytes = 48;
+  template <bool ST = false>
   static __device__ __forceinline__ SU3<float> load(const void* base, int h, int Vh) {
     const float4* b = reinterpret_cast<const float4*>(base);
     SU3<float> u;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const float4 v = ld_stream(b + fidx(j, h, 3));
+      const float4 v = ST ? ld_stream(b + fidx(j, h, 3)) : b[fidx(j, h, 3)];
       u.m[2 * j] = {v.x, v.y};
       u.m[2 * j + 1] = {v.z, v.w};
     }
@@ -384,12 +388,13 @@ struct LinkIO<PrecF32> {
 template <>
 struct LinkIO<PrecBF16> {
   static constexpr int bytes = 24;
+  template <bool ST = false>
   static __device__ __forceinline__ SU3<float> load(const void* base, int h, int Vh) {
     const uint2* b = reinterpret_cast<const uint2*>(base);
     SU3<float> u;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const uint2 v = ld_stream(b + fidx(j, h, 3));
+      const uint2 v = ST ? ld_stream(b + fidx(j, h, 3)) : b[fidx(j, h, 3)];
       u.m[2 * j] = {bf16_to_f32(v.x & 0xFFFFu), bf16_to_f32(v.x >> 16)};
       u.m[2 * j + 1] = {bf16_to_f32(v.y & 0xFFFFu), bf16_to_f32(v.y >> 16)};
     }

@@ -16,6 +16,7 @@ namespace wl {
 
 constexpr int kMaxRhs = 16;
 constexpr int kTuneRhs[3] = {1, 4, 8};  // rhs counts the autotuner times each hop class at
+constexpr size_t kLastLevelCache = size_t(256) << 20;  // MI355X Infinity Cache
 constexpr int kBlock = 256;  // threads per workgroup of the site kernels
 constexpr int kScal = 2048;  // device scalar slots; the CG state starts at kCgState
 constexpr int kCgState = 1024;
@@ -23,9 +24,10 @@ constexpr int kProfPairs = 4096;  // sampled hop launches timed per precision
 enum HopVariant { kHopSite = 0, kHopDirParallel = 1 };
 // how a hop is launched: kernel variant; npass = direction-parallel: most rhs
 // passes per link held in registers (1, 2, 4), site: rhs per thread (1, 2);
-// use_xcd = XCD-contiguous workgroup numbering (else hardware round-robin)
+// use_xcd = XCD-contiguous workgroup numbering (else hardware round-robin);
+// stream = non-temporal link and epilogue loads and output stores
 struct HopConfig {
-  int variant, npass, use_xcd;
+  int variant, npass, use_xcd, stream;
 };
 // rhs-count classes with their own configuration: 1, 2-4, 5-16
 constexpr int kHopKinds = 3;
@@ -94,9 +96,9 @@ struct wl_lattice {
   long long n_kmat = 0;                      // K-hat / K applications (single rhs units)
   // hop launch configuration per storage precision and rhs-count class
   wl::HopConfig hop_cfg[3][wl::kHopKinds] = {
-      {{wl::kHopDirParallel, 1, 1}, {wl::kHopDirParallel, 4, 1}, {wl::kHopDirParallel, 4, 1}},
-      {{wl::kHopDirParallel, 1, 1}, {wl::kHopDirParallel, 4, 1}, {wl::kHopDirParallel, 4, 1}},
-      {{wl::kHopSite, 1, 1}, {wl::kHopDirParallel, 4, 1}, {wl::kHopDirParallel, 4, 1}}};
+      {{wl::kHopDirParallel, 1, 1, 0}, {wl::kHopDirParallel, 4, 1, 0}, {wl::kHopDirParallel, 4, 1, 0}},
+      {{wl::kHopDirParallel, 1, 1, 0}, {wl::kHopDirParallel, 4, 1, 0}, {wl::kHopDirParallel, 4, 1, 0}},
+      {{wl::kHopSite, 1, 1, 0}, {wl::kHopSite, 1, 1, 0}, {wl::kHopSite, 1, 1, 0}}};
   // optional event timing of sampled hop launches, per storage precision
   int prof_on = 0;
   int prof_capturing = 0;

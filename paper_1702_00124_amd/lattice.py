@@ -304,16 +304,16 @@ class WilsonLattice:
     HOP_KINDS = (1, 4, 8)  # rhs counts the autotuner times classes 0, 1, 2 at (1, 2-4, 5-16 rhs)
 
     def hop_config(self, prec, kind: int):
-        """(variant, npass, use_xcd) of one precision and rhs class (0: 1 rhs, 1: 2-4, 2: 5-16)."""
-        v, n, x = C.c_int(), C.c_int(), C.c_int()
-        W.check(self.lib.wl_get_hop_config(self.h, _prec(prec), int(kind), C.byref(v), C.byref(n), C.byref(x)))
-        return v.value, n.value, x.value
+        """(variant, npass, use_xcd, stream) of one precision and rhs class (0: 1 rhs, 1: 2-4, 2: 5-16)."""
+        v = [C.c_int() for _ in range(4)]
+        W.check(self.lib.wl_get_hop_config(self.h, _prec(prec), int(kind), *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
-    def set_hop_config(self, prec, kind: int = -1, variant=None, npass=None, use_xcd=None):
+    def set_hop_config(self, prec, kind: int = -1, variant=None, npass=None, use_xcd=None, stream=None):
         """Set fields of the hop configuration (None keeps a field) of one rhs class or all (-1)."""
         for k in (range(3) if kind == -1 else (kind,)):
             cur = self.hop_config(prec, k)
-            new = [cur[i] if v is None else int(v) for i, v in enumerate((variant, npass, use_xcd))]
+            new = [cur[i] if v is None else int(v) for i, v in enumerate((variant, npass, use_xcd, stream))]
             W.check(self.lib.wl_set_hop_config(self.h, _prec(prec), k, *new))
 
     def set_hop_variant(self, prec, variant: int):
@@ -323,12 +323,12 @@ class WilsonLattice:
     def autotune(self):
         """Time the hop configurations per precision and rhs class and keep the fastest.
 
-        Returns {prec: [24 microsecond timings]} in the order the C API documents:
-        class 0 (site, dp) x (xcd on, off); classes 1 and 2
-        (site 1, site 2, dp 1, dp 2, dp 4) x (xcd on, off)."""
-        us = (C.c_double * 72)()
+        Returns {prec: [48 microsecond timings]} in the order the C API documents:
+        class 0 (site, dp), then classes 1 and 2 (site 1, site 2, dp 1, dp 2, dp 4),
+        each per (stream, use_xcd) = (0, 1), (0, 0), (1, 1), (1, 0)."""
+        us = (C.c_double * 144)()
         W.check(self.lib.wl_autotune(self.h, us))
-        return {name: list(us[24 * i:24 * i + 24]) for name, i in PREC.items()}
+        return {name: list(us[48 * i:48 * i + 48]) for name, i in PREC.items()}
 
     def time_hop(self, prec="f64", nrhs: int = 1, nlaunch: int = 200) -> float:
         """Average microseconds per hop launch over a back-to-back burst."""
