@@ -10,17 +10,24 @@ Heatbaths draw phi from Gaussian chi with density exp(-chi^dag chi).
 
 Readings (the paper prints no formulas for these):
 
-* J = K-hat + mu^2 (mu^2 form of the Hasenbusch mass shift) on the even
-  sites; W = M-hat + i mu g5 has W^dag W = J, and P(J), Q(J), J, K-hat commute;
-* the correction term J K^-1 is taken in its Hermitian form with the same
-  determinant: RATIO, phi^dag W K-hat^-1 W^dag phi;
-* P = Q^dag Q with Q = sqrt(c) prod_{k <= n/2} (J - z_k) (see ``poly``).
+* every term has its operator J = K-hat(kappa) + mu^2 on the even sites: the
+  paper's Hasenbusch matrix J = K(kappa') is kappa = kappa', mu^2 = 0; the
+  mu^2 form shifts K-hat instead.  W = M-hat(kappa) + i mu g5 has W^dag W = J,
+  and P(J), Q(J), J commute;
+* a correction term J_n J_d^-1 (Sec. 2: J K^-1; Sec. 3.3: J_1 J_2^-1,
+  J_2 K^-1) is taken in its Hermitian form with the same determinant:
+  RATIO, phi^dag W_n J^-1 W_n^dag phi, with the numerator W_n = M-hat(kappa_n)
+  + i mu_n g5 (kappa_n = kappa_num, or kappa when 0; mu_n^2 = mu2_num) and
+  the term's J as denominator;
+* P is P_n, or the quotient P_n / P_{n_div} of the two-filter actions
+  (Sec. 3.3 Q(K) = P_2/P_1, Sec. 4.2 Q(J)); P = Q^dag Q with Q = sqrt(c)
+  prod (J - z_k) over P's roots of negative imaginary part (see ``poly``).
 
-Term kinds and heatbaths (given chi):
+Term kinds and heatbaths (given chi), W_d = W of the term's J:
 
     KINV_FULL  phi^dag K^-1 phi, full lattice     phi = M^dag chi
     KINV       phi^dag J^-1 phi                    phi = W^dag chi
-    RATIO      phi^dag W K-hat^-1 W^dag phi        phi = W J^-1 M-hat^dag chi
+    RATIO      phi^dag W_n J^-1 W_n^dag phi        phi = W_n J_n^-1 W_d^dag chi
     POLY       phi^dag P(J) phi                    phi = Q^dag P(J)^-1 chi
     POLYK_INV  phi^dag [P(J) J]^-1 phi             phi = Q^dag W^dag chi
 
@@ -50,6 +57,13 @@ class Term:
     a: float = 0.001          # polynomial interval [a, b]
     b: float = 8.0
     tol: float = 1e-12        # CG tolerance of the solves inside the term
+    n_div: int = 0            # P = P_n / P_{n_div} (0: P_n)
+    kappa_num: float = 0.0    # RATIO numerator kappa (0: kappa)
+    mu2_num: float = 0.0      # RATIO numerator shift
+
+    @property
+    def kn(self) -> float:
+        return self.kappa_num or self.kappa
 
 
 class Ops:
@@ -111,12 +125,12 @@ def action(ops: Ops, t: Term, phi) -> float:
     if t.kind == "KINV":
         return solver.vdot(phi, _inv(J, phi, t.tol)).real
     if t.kind == "RATIO":
-        v = ops.W(phi, k, m2, dagger=True)
-        return solver.vdot(v, _inv(lambda w: ops.Khat(w, k), v, t.tol)).real
+        v = ops.W(phi, t.kn, t.mu2_num, dagger=True)
+        return solver.vdot(v, _inv(J, v, t.tol)).real
     if t.kind == "POLY":
-        return solver.vdot(phi, poly.apply_P(J, phi, t.n, t.a, t.b)).real
+        return solver.vdot(phi, poly.apply_P(J, phi, t.n, t.a, t.b, t.n_div)).real
     if t.kind == "POLYK_INV":
-        Pi = lambda v: poly.apply_PJ(J, v, t.n, t.a, t.b)
+        Pi = lambda v: poly.apply_PJ(J, v, t.n, t.a, t.b, t.n_div)
         return solver.vdot(phi, _inv(Pi, phi, t.tol)).real
     raise ValueError(t.kind)
 
@@ -130,12 +144,13 @@ def heatbath(ops: Ops, t: Term, chi):
     if t.kind == "KINV":
         return ops.W(chi, k, m2, dagger=True)
     if t.kind == "RATIO":
-        return ops.W(_inv(J, ops.Mhat(chi, k, dagger=True), t.tol), k, m2)
+        Jn = lambda v: ops.J(v, t.kn, t.mu2_num)
+        return ops.W(_inv(Jn, ops.W(chi, k, m2, dagger=True), t.tol), t.kn, t.mu2_num)
     if t.kind == "POLY":
-        Pinv_chi = _inv(lambda v: poly.apply_P(J, v, t.n, t.a, t.b), chi, t.tol)
-        return poly.apply_Q(J, Pinv_chi, t.n, t.a, t.b, dagger=True)
+        Pinv_chi = _inv(lambda v: poly.apply_P(J, v, t.n, t.a, t.b, t.n_div), chi, t.tol)
+        return poly.apply_Q(J, Pinv_chi, t.n, t.a, t.b, dagger=True, n_div=t.n_div)
     if t.kind == "POLYK_INV":
-        return poly.apply_Q(J, ops.W(chi, k, m2, dagger=True), t.n, t.a, t.b, dagger=True)
+        return poly.apply_Q(J, ops.W(chi, k, m2, dagger=True), t.n, t.a, t.b, dagger=True, n_div=t.n_div)
     raise ValueError(t.kind)
 
 
@@ -145,7 +160,7 @@ def _chain_grad(ops, t, right, left_top):
     R_k = prod_{j<k} (J - z_j) right,  L_k = prod_{j>k} (J - conj z_j) left_top."""
     k, m2 = t.kappa, t.mu2
     J = lambda v: ops.J(v, k, m2)
-    z = poly.q_roots(t.n, t.a, t.b)
+    z = poly.q_roots(t.n, t.a, t.b, t.n_div)
     m = len(z)
     R = [right]
     for j in range(m - 1):
@@ -171,18 +186,20 @@ def force(ops: Ops, t: Term, phi) -> np.ndarray:
         X = _inv(J, phi, t.tol)
         return -2.0 * ops.grad_re_dMhat(ops.Mhat(X, k), X, k)
     if t.kind == "RATIO":
-        v = ops.W(phi, k, m2, dagger=True)
-        X = _inv(lambda w: ops.Khat(w, k), v, t.tol)
-        # dS = 2 Re(phi^dag dM-hat X) - 2 Re(Y^dag dM-hat X), Y = M-hat X
-        return 2.0 * ops.grad_re_dMhat(phi - ops.Mhat(X, k), X, k)
+        v = ops.W(phi, t.kn, t.mu2_num, dagger=True)
+        X = _inv(J, v, t.tol)
+        # S = v^dag X, v = W_n^dag phi:
+        # dS = 2 Re(phi^dag dM-hat(kappa_n) X) - 2 Re(Y^dag dM-hat(kappa) X), Y = W X
+        return (2.0 * ops.grad_re_dMhat(phi, X, t.kn)
+                - 2.0 * ops.grad_re_dMhat(ops.W(X, k, m2), X, k))
     if t.kind == "POLY":
-        sc = np.sqrt(poly.lead_coeff(t.n, t.a, t.b))
-        psi = poly.apply_Q(J, phi, t.n, t.a, t.b)
+        sc = np.sqrt(poly.lead_of(t.n, t.a, t.b, t.n_div))
+        psi = poly.apply_Q(J, phi, t.n, t.a, t.b, n_div=t.n_div)
         return 2.0 * sc * _chain_grad(ops, t, phi, psi)
     if t.kind == "POLYK_INV":
-        sc = np.sqrt(poly.lead_coeff(t.n, t.a, t.b))
-        X = _inv(lambda v: poly.apply_PJ(J, v, t.n, t.a, t.b), phi, t.tol)
-        QX = poly.apply_Q(J, X, t.n, t.a, t.b)
+        sc = np.sqrt(poly.lead_of(t.n, t.a, t.b, t.n_div))
+        X = _inv(lambda v: poly.apply_PJ(J, v, t.n, t.a, t.b, t.n_div), phi, t.tol)
+        QX = poly.apply_Q(J, X, t.n, t.a, t.b, n_div=t.n_div)
         g = 2.0 * sc * _chain_grad(ops, t, X, J(QX)) + ops.grad_re_dJ(QX, QX, k)
         return -g
     raise ValueError(t.kind)

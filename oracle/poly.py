@@ -15,6 +15,11 @@ z_k = ((b+a)/2)(1 - cos t_k) - i sqrt(ab) sin t_k, t_k = 2 pi k / (n+1),
 k = 1..n (they depend on n only through n+1, hence P_{n1} | P_{n2} whenever
 (n1+1) | (n2+1), matching the nested orders 4 -> 24/34/54 of Sec. 3.3).
 
+The intermediate filter of the two-filter actions (Sec. 3.3, Q(K) = P_2/P_1;
+Sec. 4.2, Q(J)) is the quotient P_{n2}/P_{n1}: the polynomial whose roots are
+those of P_{n2} that are not roots of P_{n1}, with leading coefficient
+c_{n2}/c_{n1}.  The functions below take n_div = n1 (0: no divisor).
+
 Three evaluations are provided (closed form, real recurrence, root product) so
 that they can be checked against each other; operator application uses the root
 product, the direct consequence of the definition.
@@ -92,28 +97,61 @@ def max_rel_error(n, a, b) -> float:
     return 1.0 / float(cheb_T(n + 1, np.array(y0)))
 
 
+# ---------------------------------------------------------------- quotients P_n / P_{n_div}
+def roots_of(n, a, b, n_div=0) -> np.ndarray:
+    """Roots of P_n / P_{n_div}: the roots of P_n that are not roots of P_{n_div}."""
+    z = roots(n, a, b)
+    if not n_div:
+        return z
+    if n_div >= n or (n + 1) % (n_div + 1):
+        raise ValueError("P_n_div divides P_n only when (n_div + 1) | (n + 1)")
+    zd = roots(n_div, a, b)
+    keep = np.array([w for w in z if np.abs(zd - w).min() > 1e-9 * b])
+    if len(keep) != n - n_div:
+        raise ValueError("root sets do not nest")
+    return keep
+
+
+def lead_of(n, a, b, n_div=0) -> float:
+    """Leading coefficient of P_n / P_{n_div}."""
+    return lead_coeff(n, a, b) / (lead_coeff(n_div, a, b) if n_div else 1.0)
+
+
+def p_quotient_roots(x, n, a, b, n_div=0):
+    """P_n(x) / P_{n_div}(x) as lead * prod (x - z) over roots_of (real x)."""
+    x = np.asarray(x, dtype=float)
+    out = lead_of(n, a, b, n_div) * np.ones_like(x, dtype=complex)
+    for z in roots_of(n, a, b, n_div):
+        out = out * (x - z)
+    return out.real
+
+
 # ---------------------------------------------------------------- operators
-def q_roots(n, a, b) -> np.ndarray:
-    """Roots of Q with P = Q^dag Q: the n/2 roots with negative imaginary part."""
-    if n % 2:
-        raise ValueError("P = Q^dag Q needs an even order")
-    return roots(n, a, b)[: n // 2]
+def q_roots(n, a, b, n_div=0) -> np.ndarray:
+    """Roots of Q with P = Q^dag Q (P = P_n / P_{n_div}): those with negative imaginary part."""
+    z = roots_of(n, a, b, n_div)
+    if len(z) % 2:
+        raise ValueError("P = Q^dag Q needs an even number of roots")
+    q = z[z.imag < 0]
+    if 2 * len(q) != len(z):
+        raise ValueError("roots do not come in conjugate pairs")
+    return q
 
 
-def apply_P(apply_J, psi, n, a, b):
+def apply_P(apply_J, psi, n, a, b, n_div=0):
     out = psi.astype(np.complex128)
-    for z in roots(n, a, b):
+    for z in roots_of(n, a, b, n_div):
         out = apply_J(out) - z * out
-    return lead_coeff(n, a, b) * out
+    return lead_of(n, a, b, n_div) * out
 
 
-def apply_Q(apply_J, psi, n, a, b, dagger=False):
+def apply_Q(apply_J, psi, n, a, b, dagger=False, n_div=0):
     out = psi.astype(np.complex128)
-    for z in q_roots(n, a, b):
+    for z in q_roots(n, a, b, n_div):
         zz = np.conj(z) if dagger else z
         out = apply_J(out) - zz * out
-    return np.sqrt(lead_coeff(n, a, b)) * out
+    return np.sqrt(lead_of(n, a, b, n_div)) * out
 
 
-def apply_PJ(apply_J, psi, n, a, b):
-    return apply_P(apply_J, apply_J(psi), n, a, b)
+def apply_PJ(apply_J, psi, n, a, b, n_div=0):
+    return apply_P(apply_J, apply_J(psi), n, a, b, n_div)

@@ -27,9 +27,15 @@ def _rotate(U, omega, eps):
 
 TERMS = {
     "KINV": act.Term("KINV", 0.155, mu2=0.05, tol=1e-14),
-    "RATIO": act.Term("RATIO", 0.155, mu2=0.05, tol=1e-14),
+    "RATIO": act.Term("RATIO", 0.155, mu2_num=0.05, tol=1e-14),
     "POLY": act.Term("POLY", 0.155, mu2=0.05, n=4, tol=1e-14),
     "POLYK_INV": act.Term("POLYK_INV", 0.155, mu2=0.05, n=4, tol=1e-14),
+    # the paper's kappa' form J = K-hat(kappa') and the nested / two-filter terms
+    "RATIO_KAPPA": act.Term("RATIO", 0.155, kappa_num=0.150, tol=1e-14),        # J K^-1
+    "RATIO_NESTED": act.Term("RATIO", 0.150, kappa_num=0.145, tol=1e-14),       # J_1 J_2^-1
+    "RATIO_SHIFTS": act.Term("RATIO", 0.155, mu2=0.005, mu2_num=0.05, tol=1e-14),
+    "POLY_QUOTIENT": act.Term("POLY", 0.150, n=24, n_div=4, tol=1e-12),         # Q(J) = P_24 / P_4
+    "POLYK_INV_KAPPA": act.Term("POLYK_INV", 0.150, n=4, tol=1e-14),
 }
 
 
@@ -40,7 +46,7 @@ def _phi(term, L=L4):
     return li.gaussian_spinor((V // 2, 4, 3), 2001)
 
 
-@pytest.mark.parametrize("name", ["KINV_FULL", "KINV", "RATIO", "POLY", "POLYK_INV"])
+@pytest.mark.parametrize("name", ["KINV_FULL"] + list(TERMS))
 def test_force_matches_finite_differences(name):
     if name == "KINV_FULL":
         term = act.Term("KINV_FULL", 0.12, tol=1e-14)
@@ -81,7 +87,7 @@ def test_force_gauge_covariance():
     """U -> G U G(x+mu)^dag, phi -> G phi: F_mu(x) -> G(x) F_mu(x) G(x)^dag."""
     L = (4, 4, 2, 4)
     U = _links(L)
-    term = act.Term("RATIO", 0.155, mu2=0.05, tol=1e-14)
+    term = act.Term("RATIO", 0.155, mu2_num=0.05, tol=1e-14)
     phi = _phi(term, L)
     V = li.volume(L)
     G = li.random_su3_field(V, 12)
@@ -93,12 +99,13 @@ def test_force_gauge_covariance():
     assert np.abs(F1 - rot).max() < 1e-10 * np.abs(F0).max()
 
 
-@pytest.mark.parametrize("name", ["KINV", "RATIO", "POLY", "POLYK_INV"])
+@pytest.mark.parametrize("name", list(TERMS))
 def test_heatbath_gives_S_equal_chi_norm(name):
     term = TERMS[name]
-    U = _links()
-    ops = act.Ops(U, L4)
-    chi = li.gaussian_spinor((li.volume(L4) // 2, 4, 3), 3001)
+    L = L4 if name in ("KINV", "RATIO", "POLY", "POLYK_INV") else (4, 2, 2, 4)
+    U = _links(L)
+    ops = act.Ops(U, L)
+    chi = li.gaussian_spinor((li.volume(L) // 2, 4, 3), 3001)
     phi = act.heatbath(ops, term, chi)
     S = act.action(ops, term, phi)
     assert abs(S - np.vdot(chi, chi).real) < 1e-10 * S
@@ -131,3 +138,84 @@ def test_filtered_actions_reproduce_det_Khat():
     # W^dag W = J
     Jd = wl.dense(J, Vh)
     assert np.abs(Wd.conj().T @ Wd - Jd).max() < 1e-13
+
+
+# ---------------------------------------------------------------- the paper's actions
+K, KP, K1, K2, MU2 = 0.155, 0.150, 0.145, 0.150, 0.05
+
+
+def T(kind, kappa, **kw):
+    return act.Term(kind, kappa, tol=1e-13, **kw)
+
+
+# Sec. 2 (MP, PF), Sec. 3.3 (2PF, 2MP), Sec. 4.1 (PF-MP, kappa' and mu^2 forms),
+# Sec. 4.2 (1PF-2MP, 2PF-1MP); kappa' < kappa (the reading of Sec. 4.1's sign)
+PAPER_ACTIONS = {
+    "MP": [T("KINV", KP), T("RATIO", K, kappa_num=KP)],
+    "PF": [T("POLY", K, n=4), T("POLYK_INV", K, n=4)],
+    "2PF": [T("POLY", K, n=4), T("POLY", K, n=24, n_div=4), T("POLYK_INV", K, n=24)],
+    "2MP": [T("KINV", K1), T("RATIO", K2, kappa_num=K1), T("RATIO", K, kappa_num=K2)],
+    "PF-MP": [T("POLY", KP, n=4), T("POLYK_INV", KP, n=4), T("RATIO", K, kappa_num=KP)],
+    "PF-MP-mu2": [T("POLY", K, mu2=MU2, n=4), T("POLYK_INV", K, mu2=MU2, n=4), T("RATIO", K, mu2_num=MU2)],
+    "1PF-2MP": [T("POLY", K1, n=4), T("POLYK_INV", K1, n=4), T("RATIO", K2, kappa_num=K1),
+                T("RATIO", K, kappa_num=K2)],
+    "2PF-1MP": [T("POLY", KP, n=4), T("POLY", KP, n=24, n_div=4), T("POLYK_INV", KP, n=24),
+                T("RATIO", K, kappa_num=KP)],
+}
+
+
+def _dense_term(ops, t, Vh):
+    """The term's kernel A (S = phi^dag A phi) from dense operator matrices; polynomials
+    through the eigendecomposition of J and the closed form of P_n (not its roots)."""
+    Jd = wl.dense(lambda v: ops.J(v, t.kappa, t.mu2), Vh)
+    if t.kind == "KINV":
+        return np.linalg.inv(Jd)
+    if t.kind == "RATIO":
+        Wn = wl.dense(lambda v: ops.W(v, t.kappa_num or t.kappa, t.mu2_num), Vh)
+        return Wn @ np.linalg.inv(Jd) @ Wn.conj().T
+    lam, Vec = np.linalg.eigh(Jd)
+    p = poly.p_closed(lam, t.n, t.a, t.b)
+    if t.n_div:
+        p = p / poly.p_closed(lam, t.n_div, t.a, t.b)
+    if t.kind == "POLY":
+        return (Vec * p) @ Vec.conj().T
+    if t.kind == "POLYK_INV":
+        return (Vec / (p * lam)) @ Vec.conj().T
+    raise ValueError(t.kind)
+
+
+@pytest.mark.parametrize("name", list(PAPER_ACTIONS))
+def test_paper_actions_reproduce_det_Khat(name):
+    """Each action's Gaussian integral gives det K-hat(kappa): sum_i log det A_i = -log det K-hat,
+    and the oracle's matrix-free action values equal phi^dag A_i phi."""
+    L = (2, 2, 2, 4)
+    U = _links(L, seed=77)
+    Vh = li.volume(L) // 2
+    ops = act.Ops(U, L)
+    dK = np.linalg.slogdet(wl.dense(lambda v: ops.Khat(v, K), Vh))[1]
+    total = 0.0
+    phi = li.gaussian_spinor((Vh, 4, 3), 2101)
+    for t in PAPER_ACTIONS[name]:
+        A = _dense_term(ops, t, Vh)
+        sign, ld = np.linalg.slogdet(A)
+        assert abs(sign - 1) < 1e-9          # Hermitian positive definite
+        total += ld
+        S_dense = np.vdot(phi.reshape(-1), A @ phi.reshape(-1)).real
+        assert abs(act.action(ops, t, phi) - S_dense) <= 1e-9 * abs(S_dense), (name, t.kind)
+    assert abs(total + dK) <= 1e-8 * abs(dK), (total, -dK)
+
+
+def test_quotient_polynomial_closed_form_and_roots():
+    """P_24 / P_4 (Sec. 3.3 nesting): 20 roots, in conjugate pairs, values equal the quotient
+    of the closed forms, and |Q(x)|^2 = P(x) on the real axis."""
+    a, b = 0.001, 8.0
+    z = poly.roots_of(24, a, b, 4)
+    assert len(z) == 20 and len(poly.q_roots(24, a, b, 4)) == 10
+    assert max(np.abs(z - np.conj(w)).min() for w in z) < 1e-12
+    x = np.geomspace(2e-3, 7.9, 401)
+    ref = poly.p_closed(x, 24, a, b) / poly.p_closed(x, 4, a, b)
+    assert np.abs(poly.p_quotient_roots(x, 24, a, b, 4) / ref - 1).max() < 1e-10
+    q = np.sqrt(poly.lead_of(24, a, b, 4)) * np.prod([x - w for w in poly.q_roots(24, a, b, 4)], axis=0)
+    assert np.abs(np.abs(q) ** 2 / ref - 1).max() < 1e-10
+    with pytest.raises(ValueError):
+        poly.roots_of(24, a, b, 6)       # 7 does not divide 25

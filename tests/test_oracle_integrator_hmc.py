@@ -58,7 +58,7 @@ L4 = (4, 4, 4, 4)
 def _setup(nsteps, scheme="omelyan", tau=1.0):
     terms = [act.Term("POLY", 0.155, mu2=0.05, n=4, tol=1e-14),
              act.Term("POLYK_INV", 0.155, mu2=0.05, n=4, tol=1e-14),
-             act.Term("RATIO", 0.155, mu2=0.05, tol=1e-14)]
+             act.Term("RATIO", 0.155, mu2_num=0.05, tol=1e-14)]
     params = hmc.HMCParams(terms=terms, beta=5.6, nsteps=nsteps, scheme=scheme, tau=tau)
     U = li.random_links(L4, 0.447, 1003)
     P = li.gaussian_momenta(L4, li.seed_md(0, 15))
