@@ -282,7 +282,7 @@ def main():
     cg_md = CG(tol=1e-10, inner="f32", chunk=8)
     terms = [Term("POLY", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_md),
              Term("POLYK_INV", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_md),
-             Term("RATIO", KAPPA, mu2=MU2_HASENBUSCH, cg=cg_md)]
+             Term("RATIO", KAPPA, mu2_num=MU2_HASENBUSCH, cg=cg_md)]
     ntraj = args.warmup + args.steps
     P, chi, u = [], [], li.uniforms(ntraj, li.seed_metropolis(0))
     for k in range(ntraj):

@@ -131,12 +131,20 @@ int cg_solve(wl_lattice* lat, void* x, const void* b, double kappa, const double
              wl_op op, const wl_cg_params* params, wl_cg_stats* stats);
 
 /* Chebyshev filter polynomial (Sec. 2, polynomial filtering): order degree on
- * [a, b] approximating 1/x; applied to J = K-hat + mu2 on even sites.
- * P = Q^dag Q with Q built from the degree/2 roots of negative imaginary part
- * (degree even for the Q modes).  F64 internal fields, nrhs = 1. */
+ * [a, b] approximating 1/x, 1 - x P(x) = T_{degree+1}(y(x)) / T_{degree+1}(y(0)),
+ * y(x) = (b + a - 2x)/(b - a), or its quotient by a lower order (degree_div);
+ * applied to J = K-hat(kappa) + mu2 on even sites.  P = Q^dag Q with Q built
+ * from P's roots of negative imaginary part (degree and degree_div even for
+ * the Q modes).  F64 internal fields, nrhs = 1.  WL_EINVAL for a degree
+ * outside 1..512, an interval without 0 < a < b, or a divisor order that
+ * does not divide. */
 typedef struct {
   int degree;
   double a, b;
+  int degree_div; /* 0: P = P_degree; else the quotient P_degree / P_degree_div of the
+                     two-filter actions (Sec. 3.3 Q(K) = P_2 / P_1, Sec. 4.2 Q(J)): its
+                     roots are those of P_degree that are not roots of P_degree_div,
+                     which needs (degree_div + 1) | (degree + 1) and both even */
 } wl_poly;
 
 typedef enum { WL_POLY_P = 0, WL_POLY_PJ = 1, WL_POLY_Q = 2, WL_POLY_QDAG = 3 } wl_poly_mode;
@@ -144,14 +152,22 @@ typedef enum { WL_POLY_P = 0, WL_POLY_PJ = 1, WL_POLY_Q = 2, WL_POLY_QDAG = 3 } 
 int poly_filter_apply(wl_lattice* lat, void* out, const void* in, double kappa, double mu2,
                       const wl_poly* poly, wl_poly_mode mode);
 
-/* Pseudofermion action terms (Sec. 2 and 4.1), mu2 form of the Hasenbusch shift:
+/* Pseudofermion action terms (Sec. 2, 3.3, 4.1, 4.2).  Every term has its
+ * operator J = K-hat(kappa) + mu2 on the even sites: the paper's Hasenbusch
+ * matrix J = K(kappa') is kappa = kappa', mu2 = 0; mu2 > 0 is the shifted
+ * form.  W = M-hat(kappa) + i sqrt(mu2) g5, so W^dag W = J.
  *   WL_TERM_KINV_FULL  phi^dag K^-1 phi, full lattice (two-flavour action, Sec. 2)
  *   WL_TERM_KINV       phi^dag J^-1 phi
- *   WL_TERM_RATIO      phi^dag W K-hat^-1 W^dag phi, W = M-hat + i mu g5
- *                      (Hermitian form of the J K^-1 correction term)
- *   WL_TERM_POLY       phi^dag P(J) phi
+ *   WL_TERM_RATIO      phi^dag W_n J^-1 W_n^dag phi: the Hermitian form of a
+ *                      correction term J_n J^-1 (Sec. 2 J K^-1; Sec. 3.3
+ *                      J_1 J_2^-1, J_2 K^-1), numerator W_n = M-hat(kappa_num)
+ *                      + i sqrt(mu2_num) g5 (kappa_num = 0: kappa)
+ *   WL_TERM_POLY       phi^dag P(J) phi  (P = P_n, or the quotient filter
+ *                      P_n / P_n_div when poly.degree_div > 0)
  *   WL_TERM_POLYK_INV  phi^dag [P(J) J]^-1 phi
- * phi / chi: internal F64 fields (FULL for KINV_FULL, even half otherwise). */
+ * phi / chi: internal F64 fields (FULL for KINV_FULL, even half otherwise).
+ * WL_EINVAL for negative shifts or kappas, WL_EUNSUPPORTED for a shifted
+ * full-lattice term. */
 typedef enum {
   WL_TERM_KINV_FULL = 0,
   WL_TERM_KINV = 1,
@@ -166,6 +182,8 @@ typedef struct {
   double mu2;
   wl_poly poly;
   wl_cg_params cg;
+  double kappa_num; /* RATIO numerator (0: kappa) */
+  double mu2_num;   /* RATIO numerator shift */
 } wl_term;
 
 /* phi drawn from Gaussian chi so that S(phi) = chi^dag chi (Sec. 2 heatbath). */

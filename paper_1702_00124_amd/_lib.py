@@ -30,11 +30,12 @@ class CgStats(C.Structure):
 
 
 class Poly(C.Structure):
-    _fields_ = [("degree", C.c_int), ("a", C.c_double), ("b", C.c_double)]
+    _fields_ = [("degree", C.c_int), ("a", C.c_double), ("b", C.c_double), ("degree_div", C.c_int)]
 
 
 class Term(C.Structure):
-    _fields_ = [("kind", C.c_int), ("kappa", C.c_double), ("mu2", C.c_double), ("poly", Poly), ("cg", CgParams)]
+    _fields_ = [("kind", C.c_int), ("kappa", C.c_double), ("mu2", C.c_double), ("poly", Poly), ("cg", CgParams),
+                ("kappa_num", C.c_double), ("mu2_num", C.c_double)]
 
 
 class HmcParams(C.Structure):

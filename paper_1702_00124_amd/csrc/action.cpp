@@ -1,14 +1,17 @@
 // Pseudofermion action terms: heatbath, action value and force (Sec. 2: the
 // two-flavour action phi^dag (M^dag M)^-1 phi and its force; mass
 // preconditioning phi1^dag J^-1 phi1 + phi2^dag J K^-1 phi2; polynomial
-// filtering phi1^dag P phi1 + phi2^dag [P K]^-1 phi2; Sec. 4.1: PF-MP).
+// filtering phi1^dag P phi1 + phi2^dag [P K]^-1 phi2; Sec. 3.3: two filters;
+// Sec. 4.1: PF-MP; Sec. 4.2: three filters).
 //
-// J = K-hat + mu2 and W = M-hat + i mu g5 (W^dag W = J by gamma5-hermiticity).
+// Each term's J = K-hat(kappa) + mu2 and W = M-hat(kappa) + i mu g5 (W^dag W = J
+// by gamma5-hermiticity); RATIO's numerator W_n = M-hat(kappa_n) + i mu_n g5,
+// J_n = W_n^dag W_n; P may be the quotient P_n / P_m of the two-filter actions.
 //
 //   term        S(phi)                        heatbath from chi
 //   KINV_FULL   phi^dag K^-1 phi (full)       phi = M^dag chi
 //   KINV        phi^dag J^-1 phi              phi = W^dag chi
-//   RATIO       phi^dag W K-hat^-1 W^dag phi  phi = W J^-1 M-hat^dag chi
+//   RATIO       phi^dag W_n J^-1 W_n^dag phi  phi = W_n J_n^-1 W^dag chi
 //   POLY        phi^dag P(J) phi              phi = Q^dag P(J)^-1 chi
 //   POLYK_INV   phi^dag [P(J) J]^-1 phi       phi = Q^dag W^dag chi
 //
@@ -28,12 +31,17 @@ namespace {
 
 size_t hbytes(const wl_lattice* L) { return spinor_bytes(F64, L->Vh); }
 
-PolyDesc pdesc(const wl_term& t) { return PolyDesc{t.poly.degree, t.poly.a, t.poly.b}; }
+PolyDesc pdesc(const wl_term& t) { return PolyDesc{t.poly.degree, t.poly.a, t.poly.b, t.poly.degree_div}; }
+
+// RATIO numerator kappa
+double kappa_n(const wl_term& t) { return t.kappa_num > 0.0 ? t.kappa_num : t.kappa; }
 
 void check_term(const wl_term& t) {
   WL_REQUIRE(t.kind >= WL_TERM_KINV_FULL && t.kind <= WL_TERM_POLYK_INV, WL_EINVAL, "unknown term kind");
-  WL_REQUIRE(t.mu2 >= 0.0, WL_EINVAL, "mu2 must be non-negative");
+  WL_REQUIRE(t.kappa > 0.0 && t.kappa_num >= 0.0, WL_EINVAL, "kappa must be positive");
+  WL_REQUIRE(t.mu2 >= 0.0 && t.mu2_num >= 0.0, WL_EINVAL, "mu2 must be non-negative");
   WL_REQUIRE(t.kind != WL_TERM_KINV_FULL || t.mu2 == 0.0, WL_EUNSUPPORTED, "full-lattice term takes mu2 = 0");
+  if (t.kind == WL_TERM_POLY || t.kind == WL_TERM_POLYK_INV) check_poly(pdesc(t));
 }
 
 // out = W in (dagger: W^dag in), W = M-hat + i mu g5
@@ -129,9 +137,9 @@ void term_heatbath(wl_lattice* L, const wl_term& t, void* phi, const void* chi) 
     case WL_TERM_RATIO: {
       void* a = ws_get(L, "hb_a", fb);
       void* x = ws_get(L, "hb_x", fb);
-      op_mhat(L, F64, a, chi, t.kappa, 1, 1);
-      solve_j(L, x, a, t.kappa, t.mu2, t.cg, nullptr);
-      op_w(L, phi, x, t.kappa, t.mu2, 0);
+      op_w(L, a, chi, t.kappa, t.mu2, 1);
+      solve_j(L, x, a, kappa_n(t), t.mu2_num, t.cg, nullptr);
+      op_w(L, phi, x, kappa_n(t), t.mu2_num, 0);
       break;
     }
     case WL_TERM_POLY: {
@@ -169,8 +177,8 @@ double term_action(wl_lattice* L, const wl_term& t, const void* phi, long long* 
     case WL_TERM_RATIO: {
       void* v = ws_get(L, "ac_v", fb);
       void* x = ws_get(L, "ac_x", fb);
-      op_w(L, v, phi, t.kappa, t.mu2, 1);
-      solve_j(L, x, v, t.kappa, 0.0, t.cg, iters);
+      op_w(L, v, phi, kappa_n(t), t.mu2_num, 1);
+      solve_j(L, x, v, t.kappa, t.mu2, t.cg, iters);
       return re_dot(L, v, x);
     }
     case WL_TERM_POLY: {
@@ -213,16 +221,24 @@ void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, dou
       break;
     }
     case WL_TERM_RATIO: {
-      // dS = 2 Re((phi - Y)^dag dM-hat X), v = W^dag phi, X = K-hat^-1 v, Y = M-hat X
+      // S = v^dag X, v = W_n^dag phi, X = J^-1 v:
+      // dS = 2 Re(phi^dag dM-hat(kappa_n) X) - 2 Re(Y^dag dM-hat(kappa) X), Y = M-hat X
+      // (the i mu g5 parts of W_n and W drop out of both real parts); with
+      // kappa_n = kappa the two bilinears merge into one
       void* v = ws_get(L, "fo_v", fb);
       void* x = ws_get(L, "fo_x", fb);
       void* y = ws_get(L, "fo_y", fb);
-      op_w(L, v, phi, t.kappa, t.mu2, 1);
-      solve_j(L, x, v, t.kappa, 0.0, t.cg, iters);
+      op_w(L, v, phi, kappa_n(t), t.mu2_num, 1);
+      solve_j(L, x, v, t.kappa, t.mu2, t.cg, iters);
       op_mhat(L, F64, y, x, t.kappa, 0, 1);
-      const double one[2] = {1.0, 0.0}, mone[2] = {-1.0, 0.0};
-      launch_caxpby(L, y, one, phi, mone, y, 0, 1);
-      grad_re_dmhat(L, F, y, x, t.kappa, 2.0 * coeff);
+      if (kappa_n(t) == t.kappa) {
+        const double one[2] = {1.0, 0.0}, mone[2] = {-1.0, 0.0};
+        launch_caxpby(L, y, one, phi, mone, y, 0, 1);
+        grad_re_dmhat(L, F, y, x, t.kappa, 2.0 * coeff);
+      } else {
+        grad_re_dmhat(L, F, phi, x, kappa_n(t), 2.0 * coeff);
+        grad_re_dmhat(L, F, y, x, t.kappa, -2.0 * coeff);
+      }
       break;
     }
     case WL_TERM_POLY: {

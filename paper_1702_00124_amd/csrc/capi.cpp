@@ -300,7 +300,7 @@ int poly_filter_apply(wl_lattice* L, void* out, const void* in, double kappa, do
     check_lat(L);
     WL_REQUIRE(out && in && poly, WL_EINVAL, "null argument");
     set_device(L);
-    poly_apply(L, mode, out, in, kappa, mu2, PolyDesc{poly->degree, poly->a, poly->b});
+    poly_apply(L, mode, out, in, kappa, mu2, PolyDesc{poly->degree, poly->a, poly->b, poly->degree_div});
     return WL_OK;
   });
 }

@@ -11,6 +11,11 @@
 // one fused vector kernel per order.  Q(J), with P = Q^dag Q, is the product
 // over the n/2 roots z_k = ((b+a)/2)(1 - cos t_k) - i sqrt(ab) sin t_k,
 // t_k = 2 pi k/(n+1), times sqrt(c), c the leading coefficient of P_n.
+//
+// The quotient P_n / P_m of the two-filter actions (Sec. 3.3, 4.2; (m+1) | (n+1)):
+// the roots of P_m are those of P_n at the indices k divisible by
+// r = (n+1)/(m+1), so the quotient's Q runs over k = 1..n/2 with k % r != 0,
+// its leading coefficient is c_n / c_m, and P = Q^dag Q is applied as such.
 #include <cmath>
 
 #include "wl_ops.h"
@@ -19,25 +24,38 @@ namespace wl {
 
 static double cheb_T_above_one(int m, double y) { return std::cosh(m * std::acosh(y)); }
 
+// leading coefficient of P_n (Chebyshev form above)
+static double lead_n(int n, double a, double b) {
+  const double y0 = (b + a) / (b - a);
+  const double sgn = (n % 2) ? -1.0 : 1.0;
+  return sgn * std::pow(2.0, n) * std::pow(2.0 / (b - a), n + 1) / cheb_T_above_one(n + 1, y0);
+}
+
 double poly_lead(const PolyDesc& pd) {
-  const double y0 = (pd.b + pd.a) / (pd.b - pd.a);
-  const double sgn = (pd.n % 2) ? -1.0 : 1.0;
-  return sgn * std::pow(2.0, pd.n) * std::pow(2.0 / (pd.b - pd.a), pd.n + 1) / cheb_T_above_one(pd.n + 1, y0);
+  return lead_n(pd.n, pd.a, pd.b) / (pd.ndiv > 0 ? lead_n(pd.ndiv, pd.a, pd.b) : 1.0);
 }
 
 void poly_q_roots(const PolyDesc& pd, std::vector<double>& re, std::vector<double>& im) {
   re.clear();
   im.clear();
+  const int r = pd.ndiv > 0 ? (pd.n + 1) / (pd.ndiv + 1) : 0;
   for (int k = 1; k <= pd.n / 2; ++k) {
+    if (r > 0 && k % r == 0) continue;  // a root of the divisor
     const double th = 2.0 * M_PI * k / (pd.n + 1);
     re.push_back(0.5 * (pd.b + pd.a) * (1.0 - std::cos(th)));
     im.push_back(-std::sqrt(pd.a * pd.b) * std::sin(th));
   }
 }
 
-static void check_poly(const PolyDesc& pd) {
+void check_poly(const PolyDesc& pd) {
   WL_REQUIRE(pd.n >= 1 && pd.n <= 512, WL_EINVAL, "polynomial degree out of range");
   WL_REQUIRE(pd.a > 0.0 && pd.b > pd.a, WL_EINVAL, "polynomial interval needs 0 < a < b");
+  WL_REQUIRE(pd.ndiv >= 0, WL_EINVAL, "negative divisor order");
+  if (pd.ndiv > 0) {
+    WL_REQUIRE(pd.ndiv < pd.n && (pd.n + 1) % (pd.ndiv + 1) == 0, WL_EINVAL,
+               "divisor order m needs (m + 1) | (degree + 1)");
+    WL_REQUIRE(pd.n % 2 == 0 && pd.ndiv % 2 == 0, WL_EINVAL, "quotient filters need even orders");
+  }
 }
 
 // out = P_n(J) in by the recurrence, fields and arithmetic in storage precision pr
@@ -89,15 +107,27 @@ static void poly_Q(wl_lattice* L, void* out, const void* in, double kappa, doubl
   launch_caxpby(L, out, sc, v, nullptr, nullptr, 0, 1, pr);
 }
 
+// P(J) in: the recurrence for P_n, Q^dag Q for a quotient
+static void poly_full(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
+                      Prec pr) {
+  if (pd.ndiv == 0) {
+    poly_P(L, out, in, kappa, mu2, pd, pr);
+    return;
+  }
+  void* q = ws_get(L, "pl_qq", spinor_bytes(pr, L->Vh));
+  poly_Q(L, q, in, kappa, mu2, pd, 0, pr);
+  poly_Q(L, out, q, kappa, mu2, pd, 1, pr);
+}
+
 void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
                 Prec pr) {
   check_poly(pd);
   switch (mode) {
-    case WL_POLY_P: poly_P(L, out, in, kappa, mu2, pd, pr); break;
+    case WL_POLY_P: poly_full(L, out, in, kappa, mu2, pd, pr); break;
     case WL_POLY_PJ: {
       void* jin = ws_get(L, "pl_jin", spinor_bytes(pr, L->Vh));
       op_j(L, pr, jin, in, kappa, &mu2, 1);
-      poly_P(L, out, jin, kappa, mu2, pd, pr);
+      poly_full(L, out, jin, kappa, mu2, pd, pr);
       break;
     }
     case WL_POLY_Q: poly_Q(L, out, in, kappa, mu2, pd, 0, pr); break;

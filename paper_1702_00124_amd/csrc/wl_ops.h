@@ -50,10 +50,12 @@ int cg_run_generic(wl_lattice* L, void* x, const void* b,
 struct PolyDesc {
   int n;
   double a, b;
+  int ndiv = 0;  // > 0: the quotient P_n / P_ndiv
 };
 void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
                 Prec pr = F64);
 double poly_lead(const PolyDesc& pd);
+void check_poly(const PolyDesc& pd);
 void poly_q_roots(const PolyDesc& pd, std::vector<double>& re, std::vector<double>& im);
 
 // action terms (action.cpp)

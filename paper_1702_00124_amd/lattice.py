@@ -61,7 +61,11 @@ class CG:
 
 @dataclass
 class Term:
-    """A pseudofermion action term (kinds: KINV_FULL, KINV, RATIO, POLY, POLYK_INV)."""
+    """A pseudofermion action term (kinds: KINV_FULL, KINV, RATIO, POLY, POLYK_INV).
+
+    (kappa, mu2) define the term's J = K-hat(kappa) + mu2; RATIO's numerator is
+    M-hat(kappa_num or kappa) + i sqrt(mu2_num) g5; degree_div > 0 makes the
+    polynomial the quotient P_degree / P_degree_div."""
     kind: str
     kappa: float
     mu2: float = 0.0
@@ -69,9 +73,13 @@ class Term:
     a: float = 0.001
     b: float = 8.0
     cg: CG = field(default_factory=CG)
+    degree_div: int = 0
+    kappa_num: float = 0.0
+    mu2_num: float = 0.0
 
     def c(self) -> W.Term:
-        return W.Term(TERM_KIND[self.kind], self.kappa, self.mu2, W.Poly(self.degree, self.a, self.b), self.cg.c())
+        return W.Term(TERM_KIND[self.kind], self.kappa, self.mu2, W.Poly(self.degree, self.a, self.b, self.degree_div),
+                      self.cg.c(), self.kappa_num, self.mu2_num)
 
     @property
     def full(self) -> bool:
@@ -226,11 +234,11 @@ class WilsonLattice:
         return x, res, rc
 
     def poly_filter_apply(self, buf: torch.Tensor, kappa: float, mu2: float, degree: int, a: float, b: float,
-                          mode: str = "P", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                          mode: str = "P", out: Optional[torch.Tensor] = None, degree_div: int = 0) -> torch.Tensor:
         out = self.new_field("f64") if out is None else out
         _need(buf, self.field_bytes("f64"), "input")
         _need(out, self.field_bytes("f64"), "output")
-        p = W.Poly(degree, a, b)
+        p = W.Poly(degree, a, b, degree_div)
         W.check(self.lib.poly_filter_apply(self.h, _ptr(out), _ptr(buf), kappa, mu2, C.byref(p), POLY_MODE[mode]))
         return out
 

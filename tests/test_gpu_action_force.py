@@ -63,14 +63,58 @@ def test_gauge_kernels_match_oracle():
     assert np.abs(np.einsum("mxab,mxcb->mxac", got, got.conj()) - np.eye(3)).max() < 1e-14
 
 
-def _term(kind, n=4):
-    if kind == "KINV_FULL":
+@pytest.mark.parametrize("mode", ["P", "PJ", "Q", "QDAG"])
+def test_quotient_filter_matches_oracle(mode):
+    """P_24 / P_4 (the intermediate filter of the two-filter actions) on J = K-hat(kappa')."""
+    say("quotient poly", mode)
+    lat, U = make_lattice(L4)
+    psi = half_noise(L4, 62)
+    kp = 0.150
+    got = to_np(lat.export_spinor(lat.poly_filter_apply(lat.import_spinor(torch.from_numpy(psi)), kp, 0.0, 24,
+                                                        0.001, 8.0, mode, degree_div=4)))
+    J = lambda v: ow.J(U, v, L4, kp, 0.0)
+    ref = {"P": lambda: opoly.apply_P(J, psi, 24, 0.001, 8.0, 4),
+           "PJ": lambda: opoly.apply_PJ(J, psi, 24, 0.001, 8.0, 4),
+           "Q": lambda: opoly.apply_Q(J, psi, 24, 0.001, 8.0, n_div=4),
+           "QDAG": lambda: opoly.apply_Q(J, psi, 24, 0.001, 8.0, dagger=True, n_div=4)}[mode]()
+    assert rel(got, ref) <= 1e-12
+    with pytest.raises(Exception):
+        lat.poly_filter_apply(lat.import_spinor(torch.from_numpy(psi)), kp, 0.0, 24, 0.001, 8.0, mode, degree_div=6)
+
+
+# name -> (kind, kappa, extra fields); the last five are the paper's kappa' form and the
+# nested / two-filter terms of Secs. 3.3, 4.1, 4.2
+TERM_CASES = {
+    "KINV": ("KINV", KAPPA, dict(mu2=MU2)),
+    "RATIO": ("RATIO", KAPPA, dict(mu2_num=MU2)),
+    "POLY": ("POLY", KAPPA, dict(mu2=MU2, n=4)),
+    "POLYK_INV": ("POLYK_INV", KAPPA, dict(mu2=MU2, n=4)),
+    "RATIO_KAPPA": ("RATIO", KAPPA, dict(kappa_num=0.150)),
+    "RATIO_NESTED": ("RATIO", 0.150, dict(kappa_num=0.145)),
+    "RATIO_SHIFTS": ("RATIO", KAPPA, dict(mu2=0.005, mu2_num=MU2)),
+    "POLY_QUOTIENT": ("POLY", 0.150, dict(n=24, n_div=4)),
+    "POLYK_INV_KAPPA": ("POLYK_INV", 0.150, dict(n=4)),
+}
+
+
+def _pair(kind, kappa, n=0, n_div=0, mu2=0.0, kappa_num=0.0, mu2_num=0.0, tol=1e-13):
+    g = Term(kind, kappa, mu2=mu2, degree=n, degree_div=n_div, kappa_num=kappa_num, mu2_num=mu2_num,
+             cg=CG(tol=tol))
+    o = oact.Term(kind, kappa, mu2=mu2, n=n, n_div=n_div, kappa_num=kappa_num, mu2_num=mu2_num, tol=tol)
+    return g, o
+
+
+def _term(name, n=None):
+    if name == "KINV_FULL":
         return Term("KINV_FULL", 0.12, cg=CG(tol=1e-13)), oact.Term("KINV_FULL", 0.12, tol=1e-13)
-    return (Term(kind, KAPPA, mu2=MU2, degree=n, cg=CG(tol=1e-13)),
-            oact.Term(kind, KAPPA, mu2=MU2, n=n, tol=1e-13))
+    kind, kappa, kw = TERM_CASES[name]
+    kw = dict(kw)
+    if n is not None:
+        kw["n"] = n
+    return _pair(kind, kappa, **kw)
 
 
-@pytest.mark.parametrize("kind", ["KINV_FULL", "KINV", "RATIO", "POLY", "POLYK_INV"])
+@pytest.mark.parametrize("kind", ["KINV_FULL"] + list(TERM_CASES))
 def test_term_heatbath_action_force_match_oracle(kind):
     say("term", kind)
     a = 0.3 if kind == "KINV_FULL" else 0.447
@@ -113,10 +157,10 @@ def test_poly_force_order16():
 def _hmc_setup(scale=1):
     terms_g = [Term("POLY", KAPPA, mu2=MU2, degree=4, cg=CG(tol=1e-13)),
                Term("POLYK_INV", KAPPA, mu2=MU2, degree=4, cg=CG(tol=1e-13)),
-               Term("RATIO", KAPPA, mu2=MU2, cg=CG(tol=1e-13))]
+               Term("RATIO", KAPPA, mu2_num=MU2, cg=CG(tol=1e-13))]
     terms_o = [oact.Term("POLY", KAPPA, mu2=MU2, n=4, tol=1e-13),
                oact.Term("POLYK_INV", KAPPA, mu2=MU2, n=4, tol=1e-13),
-               oact.Term("RATIO", KAPPA, mu2=MU2, tol=1e-13)]
+               oact.Term("RATIO", KAPPA, mu2_num=MU2, tol=1e-13)]
     nsteps = [2 * scale, 1 * scale, 1 * scale, 3 * scale]
     return terms_g, terms_o, nsteps
 
@@ -194,3 +238,34 @@ def test_hmc_rejection_restores_links():
         assert np.array_equal(to_np(lat.get_links()), U)
     else:
         assert res.dH <= 0
+
+
+@pytest.mark.parametrize("action", ["2PF-1MP", "2MP"])
+def test_paper_action_trajectory_matches_oracle(action):
+    """A short trajectory of a three-filter / two-preconditioner action of Secs. 3.3
+    and 4.2 in the kappa' form (kappa' = 0.150, kappa_1 = 0.145, kappa_2 = 0.150):
+    energies, dH and the end links against the oracle."""
+    say("paper action trajectory", action)
+    lat, U = make_lattice(L4)
+    kp, k1, k2 = 0.150, 0.145, 0.150
+    if action == "2PF-1MP":
+        spec = [("POLY", kp, dict(n=4)), ("POLY", kp, dict(n=24, n_div=4)), ("POLYK_INV", kp, dict(n=24)),
+                ("RATIO", KAPPA, dict(kappa_num=kp))]
+        nsteps = [2, 1, 1, 1, 3]
+    else:
+        spec = [("KINV", k1, {}), ("RATIO", k2, dict(kappa_num=k1)), ("RATIO", KAPPA, dict(kappa_num=k2))]
+        nsteps = [2, 1, 1, 3]
+    pairs = [_pair(kind, kappa, **kw) for kind, kappa, kw in spec]
+    terms_g, terms_o = [p[0] for p in pairs], [p[1] for p in pairs]
+    P = li.gaussian_momenta(L4, li.seed_md(1, 15))
+    Vh = li.volume(L4) // 2
+    chis = [li.gaussian_spinor((Vh, 4, 3), li.seed_md(1, i)) for i in range(len(spec))]
+    chi_b = torch.cat([lat.import_spinor(torch.from_numpy(c)) for c in chis])
+    res = lat.hmc_trajectory(terms_g, nsteps, lat.import_su3(torch.from_numpy(P)), chi_b, 0.5, beta=5.6, tau=0.2,
+                             integrator="omelyan", no_metropolis=True)
+    prm = ohmc.HMCParams(terms=terms_o, beta=5.6, nsteps=nsteps, scheme="omelyan", tau=0.2)
+    r = ohmc.trajectory(U, P, L4, prm, chis, 0.0)   # u = 0 accepts: compare the end points
+    say(f"  dH gpu {res.dH:.10f} oracle {r.dH:.10f}; n_kmat {res.n_kmat}")
+    assert abs(res.H0 - r.H0) <= 1e-9 * abs(r.H0)
+    assert abs(res.dH - r.dH) <= 1e-7
+    assert r.accepted and rel(to_np(lat.get_links()), r.U) <= 1e-10
