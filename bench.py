@@ -134,6 +134,53 @@ print(json.dumps({"n": n, "sec_per_hop": dt}))
                       f"({d['sec_per_hop']:.2f} s each, single-threaded NumPy)"}
 
 
+# the paper's actions (Sec. 2 MP, PF; Sec. 3.3 2PF, 2MP; Sec. 4.1 PF-MP; Sec. 4.2
+# 1PF-2MP, 2PF-1MP) in the kappa' form of the Hasenbusch matrix J = K-hat(kappa'),
+# kappa_1 = 0.145 < kappa' = kappa_2 = 0.150 < kappa = 0.155; polynomial orders as
+# the paper fixes them (p = 4, q = 20, p_2 = 24); terms listed from the cheapest
+# (finest scale) to the most expensive
+KP, K1, K2 = 0.150, 0.145, 0.150
+PAPER_ACTIONS = {
+    "MP": [("KINV", KP, {}), ("RATIO", KAPPA, {"kappa_num": KP})],
+    "PF": [("POLY", KAPPA, {"degree": 16}), ("POLYK_INV", KAPPA, {"degree": 16})],
+    "2PF": [("POLY", KAPPA, {"degree": 4}), ("POLY", KAPPA, {"degree": 24, "degree_div": 4}),
+            ("POLYK_INV", KAPPA, {"degree": 24})],
+    "2MP": [("KINV", K1, {}), ("RATIO", K2, {"kappa_num": K1}), ("RATIO", KAPPA, {"kappa_num": K2})],
+    "PF-MP": [("POLY", KP, {"degree": 4}), ("POLYK_INV", KP, {"degree": 4}), ("RATIO", KAPPA, {"kappa_num": KP})],
+    "1PF-2MP": [("POLY", K1, {"degree": 4}), ("POLYK_INV", K1, {"degree": 4}), ("RATIO", K2, {"kappa_num": K1}),
+                ("RATIO", KAPPA, {"kappa_num": K2})],
+    "2PF-1MP": [("POLY", KP, {"degree": 4}), ("POLY", KP, {"degree": 24, "degree_div": 4}),
+                ("POLYK_INV", KP, {"degree": 24}), ("RATIO", KAPPA, {"kappa_num": KP})],
+}
+
+
+def paper_actions(lat, U, li, torch, Term, CG, L, Vh):
+    """One trajectory of each of the paper's actions on the bench lattice: Omelyan,
+    tau = 1, 40 steps for the first (cheapest) term, 20 for every other, 80 for the
+    gauge action; MD solves FP32 inner / FP64 reliable updates to 1e-10.  Reports the
+    paper's cost numerator N_mat (K-hat and J applications per trajectory), CG
+    iterations, dH and the wall time (acceptance needs an equilibrated ensemble)."""
+    cg = CG(tol=1e-10, inner="f32", chunk=8)
+    out = {}
+    for name, spec in PAPER_ACTIONS.items():
+        lat.set_links(torch.from_numpy(U))
+        terms = [Term(kind, kappa, cg=cg, **kw) for kind, kappa, kw in spec]
+        nsteps = [40] + [20] * (len(terms) - 1) + [80]
+        P = lat.import_su3(torch.from_numpy(li.gaussian_momenta(L, li.seed_md(50, 15))))
+        chi = torch.cat([lat.import_spinor(torch.from_numpy(li.gaussian_spinor((Vh, 4, 3), li.seed_md(50, i))))
+                         for i in range(len(terms))])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lat.hmc_trajectory(terms, nsteps, P, chi, 0.5, beta=BETA, tau=1.0, integrator="omelyan")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"n_mat": int(r.n_kmat), "cg_iters": int(r.cg_iters), "dH": round(r.dH, 4),
+                     "seconds": round(dt, 3), "nsteps": nsteps}
+        log("paper action", name, json.dumps(out[name]))
+    lat.set_links(torch.from_numpy(U))
+    return out
+
+
 def large_volume(li, torch, np, CG, WilsonLattice):
     """32^3 x 64, kappa = 0.156, links with plaquette ~0.60, 4 Gaussian rhs:
     hop bandwidth per precision, CG to true residual 1e-10 with FP64 single rhs
@@ -386,6 +433,7 @@ def main():
             "eight_rhs_true_res_max": max(s.true_rel_res for s in sbat),
         }
         log("cg", json.dumps(extra["cg"]))
+        extra["paper_actions"] = paper_actions(lat, U, li, torch, Term, CG, L, Vh)
         lat.close()
         torch.cuda.empty_cache()
         extra["large_volume"] = large_volume(li, torch, np, CG, WilsonLattice)
