@@ -420,6 +420,20 @@ def main():
         tseq, sseq = timed(seq64, reps=2)
         tbat, (_, sbat, _) = timed(lambda: lat.cg_solve(b8, KAPPA, "J", mu2=SHIFTS, nrhs=8,
                                                         params=CG(tol=1e-10, inner="f32")), reps=2)
+        # 8 sources x the 4 shifts = 32 systems: one multi-shift FP64 solve (one Krylov
+        # space per source) vs two batched FP32-inner solves of 16 systems each
+        SH4 = SHIFTS[:4]
+        tms, (_, sms, rcms) = timed(lambda: lat.cg_multishift(b8, KAPPA, SH4, 8, CG(tol=1e-10)), reps=2)
+        mu16 = [m for m in SH4 for _ in range(4)]
+
+        def two_batches():
+            out = []
+            for h in range(2):
+                # systems (source j, shift k) for j in 4h..4h+3, every k: 16 rhs
+                src = torch.cat([bj[4 * h + j] for k in range(4) for j in range(4)])
+                out += lat.cg_solve(src, KAPPA, "J", mu2=mu16, nrhs=16, params=CG(tol=1e-10, inner="f32"))[1]
+            return out
+        t32x, s32x = timed(two_batches, reps=2)
         extra["cg"] = {
             "single_rhs_f64_ms": round(t64 * 1e3, 2), "single_rhs_f64_iters": s64[0].iters,
             "single_rhs_mixed_f32_ms": round(t32 * 1e3, 2), "single_rhs_mixed_iters": s32[0].iters,
@@ -431,6 +445,13 @@ def main():
             "multi_rhs_speedup": round(tseq / tbat, 3),
             "eight_rhs_iters_f64": [s.iters for s in sseq], "eight_rhs_iters_batched": [s.iters for s in sbat],
             "eight_rhs_true_res_max": max(s.true_rel_res for s in sbat),
+            "multishift_32_systems_f64_ms": round(tms * 1e3, 2),
+            "multishift_base_iters": max(c.iters for c in sms[0]),
+            "multishift_true_res_max": max(c.true_rel_res for row in sms for c in row),
+            "multishift_refined": sum(c.reliable_updates for row in sms for c in row),
+            "batched_32_systems_mixed_ms": round(t32x * 1e3, 2),
+            "batched_32_true_res_max": max(c.true_rel_res for c in s32x),
+            "multishift_speedup_vs_batched": round(t32x / tms, 3),
         }
         log("cg", json.dumps(extra["cg"]))
         extra["paper_actions"] = paper_actions(lat, U, li, torch, Term, CG, L, Vh)

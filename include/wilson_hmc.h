@@ -130,6 +130,23 @@ typedef struct {
 int cg_solve(wl_lattice* lat, void* x, const void* b, double kappa, const double* mu2, int nrhs,
              wl_op op, const wl_cg_params* params, wl_cg_stats* stats);
 
+/* Multi-shift CG: x_s = J(mu2[s])^-1 b for nshift Hasenbusch shifts of
+ * K-hat(kappa) at once (the shifted systems share the Krylov space of the
+ * smallest shift; Sec. 2 Hasenbusch mass preconditioning in its mu2 form).
+ * b: nrhs even-site F64 fields; x: nshift * nrhs fields, x[s * nrhs + r]
+ * solves shift s for source r.  FP64 arithmetic; each system stops at
+ * |zeta|^2 |r|^2 <= tol^2 |b|^2 and is then checked by its FP64 true residual,
+ * a miss refined by an ordinary CG (params.inner) on its residual.
+ * params: tol, maxiter (base iterations; a refinement may take up to
+ * max(maxiter, 10000)), chunk; inner only for the refinement; use_graph
+ * ignored.  stats: host array [nshift * nrhs], same
+ * order as x (iters = base iterations until the system froze, plus any
+ * refinement iterations; reliable_updates = 1 if refined).  WL_EINVAL for
+ * nrhs outside 1..16, nshift * nrhs > 64, negative shifts; WL_ENOCONV if a
+ * system misses tol (outputs valid). */
+int cg_multishift(wl_lattice* lat, void* x, const void* b, double kappa, const double* mu2, int nshift, int nrhs,
+                  const wl_cg_params* params, wl_cg_stats* stats);
+
 /* Chebyshev filter polynomial (Sec. 2, polynomial filtering): order degree on
  * [a, b] approximating 1/x, 1 - x P(x) = T_{degree+1}(y(x)) / T_{degree+1}(y(0)),
  * y(x) = (b + a - 2x)/(b - a), or its quotient by a lower order (degree_div);

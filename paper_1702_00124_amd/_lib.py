@@ -69,6 +69,7 @@ SIGNATURES = {
     "wilson_dslash": (I, [P, P, P, I, I, I, I]),
     "apply_K": (I, [P, P, P, D, C.POINTER(D), I, I, I]),
     "cg_solve": (I, [P, P, P, D, C.POINTER(D), I, I, C.POINTER(CgParams), C.POINTER(CgStats)]),
+    "cg_multishift": (I, [P, P, P, D, C.POINTER(D), I, I, C.POINTER(CgParams), C.POINTER(CgStats)]),
     "poly_filter_apply": (I, [P, P, P, D, D, C.POINTER(Poly), I]),
     "wl_heatbath": (I, [P, P, C.POINTER(Term), P]),
     "wl_action": (I, [P, C.POINTER(Term), P, C.POINTER(D)]),

@@ -202,6 +202,106 @@ __global__ __launch_bounds__(kBlock) void cg_beta_kernel(const double* partials,
 }
 
 
+// ------------------------------------------------------------------ multi-shift CG
+// State pointers: st = CG rows of the base system (kMaxRhs columns), ms = the
+// multi-shift rows (kMaxSys columns), mr = per-rhs multi-shift rows.
+// Shifted-system scalars for iteration i, after the base alpha_i is known:
+// rotate zeta, freeze converged systems, then
+//   zeta_{i+1} = zeta_i zeta_{i-1} alpha_{i-1}
+//                / (alpha_i beta_{i-1} (zeta_{i-1} - zeta_i) + zeta_{i-1} alpha_{i-1} (1 + d alpha_i)),
+//   alpha_s = alpha_i zeta_{i+1} / zeta_i.
+__global__ __launch_bounds__(kMaxSys) void ms_scalars_kernel(double* st, double* ms, double* mr, int nrhs, int nsys) {
+  const int q = threadIdx.x;
+  double alpha_keep = 0.0;
+  const bool active = q < nsys;
+  const int r = active ? q % nrhs : 0;
+  if (active) {
+    double* row = ms + q;
+    const double zprev = row[MS_ZCUR * kMaxSys];
+    const double zcur = row[MS_ZNEXT * kMaxSys];
+    row[MS_ZPREV * kMaxSys] = zprev;
+    row[MS_ZCUR * kMaxSys] = zcur;
+    const double alpha = st[CG_ALPHA * kMaxRhs + r];
+    alpha_keep = alpha;
+    const bool base_stop = st[CG_DONE * kMaxRhs + r] != 0.0 || st[CG_BREAK * kMaxRhs + r] != 0.0;
+    bool done = row[MS_DONE * kMaxSys] != 0.0;
+    if (!done && zcur * zcur * st[CG_RR * kMaxRhs + r] <= st[CG_TOL2 * kMaxRhs + r] * st[CG_BB * kMaxRhs + r]) {
+      done = true;
+      row[MS_DONE * kMaxSys] = 1.0;
+      row[MS_ITERS * kMaxSys] = st[CG_ITERS * kMaxRhs + r];
+    }
+    if (done || base_stop || alpha == 0.0) {
+      row[MS_ASHIFT * kMaxSys] = 0.0;
+      row[MS_ZNEXT * kMaxSys] = zcur;
+    } else {
+      const double aprev = mr[MS_APREV * kMaxRhs + r];
+      const double bprev = st[CG_BETA * kMaxRhs + r];
+      const double d = row[MS_DELTA * kMaxSys];
+      const double den = alpha * bprev * (zprev - zcur) + zprev * aprev * (1.0 + d * alpha);
+      const double znext = zcur * zprev * aprev / den;
+      row[MS_ZNEXT * kMaxSys] = znext;
+      row[MS_ASHIFT * kMaxSys] = alpha * znext / zcur;
+    }
+  }
+  __syncthreads();  // every system has read alpha_{i-1}
+  if (active && q < nrhs && alpha_keep != 0.0) mr[MS_APREV * kMaxRhs + r] = alpha_keep;
+}
+
+// r -= alpha Ap (base, with |r|^2 partials); x_s += alpha_s p_s for every shift.
+// Fields [nshift][nrhs] of stride bytes, FP64.
+__global__ __launch_bounds__(kBlock) void ms_update_kernel(Geo g, char* r, const char* Ap, const char* p, char* x,
+                                                          const double* st, const double* ms, size_t stride,
+                                                          int nrhs, int nshift, double* partials, int pstride) {
+  __shared__ double lds[kBlock / 64];
+  const int rhs = blockIdx.y;
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int Vh = g.Vh;
+  const double alpha = st[CG_ALPHA * kMaxRhs + rhs];
+  double part = 0.0;
+  if (h < Vh) {
+    Spinor<double> rv = SpinorIO<PrecF64>::load(r + rhs * stride, h, Vh);
+    if (alpha != 0.0) {
+      const Spinor<double> av = SpinorIO<PrecF64>::load(Ap + rhs * stride, h, Vh);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) rv.c[k] = rv.c[k] - alpha * av.c[k];
+      SpinorIO<PrecF64>::store(r + rhs * stride, h, Vh, rv);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part += rv.c[k].r * rv.c[k].r + rv.c[k].i * rv.c[k].i;
+    for (int s = 0; s < nshift; ++s) {
+      const double as = ms[MS_ASHIFT * kMaxSys + s * nrhs + rhs];
+      if (as == 0.0) continue;
+      const size_t off = (size_t(s) * nrhs + rhs) * stride;
+      const Spinor<double> pv = SpinorIO<PrecF64>::load(p + off, h, Vh);
+      Spinor<double> xv = SpinorIO<PrecF64>::load(x + off, h, Vh);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) xv.c[k] = xv.c[k] + as * pv.c[k];
+      SpinorIO<PrecF64>::store(x + off, h, Vh, xv);
+    }
+  }
+  const double sum = block_sum(part, lds);
+  if (threadIdx.x == 0) partials[rhs * pstride + blockIdx.x] = sum;
+}
+
+// p_s = zeta_{i+1} r + beta_i (zeta_{i+1} / zeta_i)^2 p_s for every unfrozen system
+__global__ __launch_bounds__(kBlock) void ms_xpay_kernel(Geo g, char* p, const char* r, const double* st,
+                                                        const double* ms, size_t stride, int nrhs) {
+  const int q = blockIdx.y;
+  const int rhs = q % nrhs;
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int Vh = g.Vh;
+  if (h >= Vh || ms[MS_ASHIFT * kMaxSys + q] == 0.0) return;
+  const double zn = ms[MS_ZNEXT * kMaxSys + q], zc = ms[MS_ZCUR * kMaxSys + q];
+  const double ratio = zn / zc;
+  const double bs = st[CG_BETA * kMaxRhs + rhs] * ratio * ratio;
+  const size_t off = size_t(q) * stride;
+  Spinor<double> pv = SpinorIO<PrecF64>::load(p + off, h, Vh);
+  const Spinor<double> rv = SpinorIO<PrecF64>::load(r + rhs * stride, h, Vh);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) pv.c[k] = zn * rv.c[k] + bs * pv.c[k];
+  SpinorIO<PrecF64>::store(p + off, h, Vh, pv);
+}
+
 // One step of the Chebyshev filter recurrence:
 //   tprev <- ct * t + cw * w - tprev        (t_{m+1} = 2 y(J) t_m - t_{m-1}, w = J t_m)
 //   eprev <- ce * e + 2 t - eprev           (e_{m+1} = 2 y0 e_m + 2 t_m - e_{m-1})
@@ -330,6 +430,26 @@ void launch_cg_alpha(wl_lattice* L, const double* partials, int stride, int nb, 
 
 void launch_cg_beta(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs) {
   hipLaunchKernelGGL(cg_beta_kernel, dim3(nrhs), dim3(kBlock), 0, L->stream, partials, stride, nb, st);
+  WL_HIP(hipGetLastError());
+}
+
+void launch_ms_scalars(wl_lattice* L, double* st, double* ms, double* mr, int nrhs, int nshift) {
+  hipLaunchKernelGGL(ms_scalars_kernel, dim3(1), dim3(kMaxSys), 0, L->stream, st, ms, mr, nrhs, nrhs * nshift);
+  WL_HIP(hipGetLastError());
+}
+
+void launch_ms_update(wl_lattice* L, void* r, const void* Ap, const void* p, void* x, const double* st,
+                      const double* ms, int nrhs, int nshift, double* partials, int pstride) {
+  hipLaunchKernelGGL(ms_update_kernel, dim3(blas_blocks(L), nrhs), dim3(kBlock), 0, L->stream, L->geo, (char*)r,
+                     (const char*)Ap, (const char*)p, (char*)x, st, ms, spinor_bytes(F64, L->Vh), nrhs, nshift,
+                     partials, pstride);
+  WL_HIP(hipGetLastError());
+}
+
+void launch_ms_xpay(wl_lattice* L, void* p, const void* r, const double* st, const double* ms, int nrhs,
+                    int nshift) {
+  hipLaunchKernelGGL(ms_xpay_kernel, dim3(blas_blocks(L), nrhs * nshift), dim3(kBlock), 0, L->stream, L->geo,
+                     (char*)p, (const char*)r, st, ms, spinor_bytes(F64, L->Vh), nrhs);
   WL_HIP(hipGetLastError());
 }
 

@@ -294,6 +294,16 @@ int cg_solve(wl_lattice* L, void* x, const void* b, double kappa, const double* 
   });
 }
 
+int cg_multishift(wl_lattice* L, void* x, const void* b, double kappa, const double* mu2, int nshift, int nrhs,
+                  const wl_cg_params* params, wl_cg_stats* stats) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(x && b && params && mu2 && x != b, WL_EINVAL, "null or aliased argument");
+    set_device(L);
+    return cg_multishift_run(L, x, b, kappa, mu2, nshift, nrhs, *params, stats);
+  });
+}
+
 int poly_filter_apply(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const wl_poly* poly,
                       wl_poly_mode mode) {
   return guard([&]() {

@@ -273,4 +273,165 @@ int cg_run_generic(wl_lattice* L, void* x, const void* b,
                  spinor_bytes((ip == F32 || ip == BF16) ? ip : F64, L->Vh), lp, a64, prm, stats, false);
 }
 
+// ------------------------------------------------------------------ multi-shift CG
+// (J(mu2_s) ) x_s = b for nshift shifts of K-hat at once: CG on the smallest
+// shift, the others from the collinear-residual recurrences (see
+// ms_scalars_kernel).  FP64 throughout; every (rhs, shift) system freezes once
+// its residual |zeta|^2 |r|^2 meets the tolerance, the iteration ends with the
+// base system, and every solution is then checked by its FP64 true residual;
+// a system that misses it is refined by an ordinary CG on its residual.
+int cg_multishift_run(wl_lattice* L, void* x_out, const void* b, double kappa, const double* shifts, int nshift,
+                      int nrhs, const wl_cg_params& prm, wl_cg_stats* stats) {
+  static_assert(kMsRhsRows + MS_RHS_NROWS * kMaxRhs <= kScal, "multi-shift state exceeds the scalar area");
+  WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs, WL_EINVAL, "nrhs out of range");
+  WL_REQUIRE(nshift >= 1 && nshift * nrhs <= kMaxSys, WL_EINVAL, "nshift * nrhs must be at most 64");
+  WL_REQUIRE(shifts, WL_EINVAL, "null shifts");
+  WL_REQUIRE(prm.tol > 0.0 && prm.maxiter > 0, WL_EINVAL, "cg: tol and maxiter must be positive");
+  for (int s = 0; s < nshift; ++s) WL_REQUIRE(shifts[s] >= 0.0, WL_EINVAL, "shifts must be non-negative");
+  const int chunk = prm.chunk > 0 ? prm.chunk : 8;
+  const size_t fb = spinor_bytes(F64, L->Vh);
+  const int nsys = nshift * nrhs;
+  // internal order: ascending shifts, the smallest is the base system
+  std::vector<int> order(nshift);
+  for (int s = 0; s < nshift; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return shifts[i] < shifts[j]; });
+  const double s0 = shifts[order[0]];
+
+  char* r = static_cast<char*>(ws_get(L, "ms_r", fb * nrhs));
+  char* Ap = static_cast<char*>(ws_get(L, "ms_Ap", fb * nrhs));
+  char* p = static_cast<char*>(ws_get(L, "ms_p", fb * nsys));
+  char* x = static_cast<char*>(ws_get(L, "ms_x", fb * nsys));
+  char* r64 = static_cast<char*>(ws_get(L, "ms_r64", fb * nrhs));
+  const int nbrow = op_dot_blocks(L, WL_OP_J, F64);
+  WL_REQUIRE(blas_blocks(L) <= nbrow, WL_EINVAL, "cg: reduction row too narrow");
+  ensure_partials(L, size_t(nrhs) * nbrow * 2 + 64);
+  double* st = L->dscal + kCgState;
+  double* ms = L->dscal + kMsState;
+  double* mr = L->dscal + kMsRhsRows;
+
+  std::vector<double> bb(nrhs);
+  norm2_host(L, b, nrhs, bb.data());
+  zero_dev(L, x, fb * nsys);
+  copy_dev(L, r, b, fb * nrhs);
+  for (int s = 0; s < nshift; ++s) copy_dev(L, p + size_t(s) * nrhs * fb, b, fb * nrhs);
+
+  // host mirrors of the three state blocks
+  std::vector<double> hs(CG_NROWS * kMaxRhs, 0.0), hm(MS_NROWS * kMaxSys, 0.0), hr(MS_RHS_NROWS * kMaxRhs, 0.0);
+  auto S = [&](int row, int i) -> double& { return hs[row * kMaxRhs + i]; };
+  auto M = [&](int row, int q) -> double& { return hm[row * kMaxSys + q]; };
+  for (int i = 0; i < nrhs; ++i) {
+    S(CG_RR, i) = bb[i];
+    S(CG_BB, i) = bb[i];
+    S(CG_TOL2, i) = prm.tol * prm.tol;
+    S(CG_MAXRR, i) = bb[i];
+    if (bb[i] == 0.0) S(CG_DONE, i) = 1.0;
+    hr[MS_APREV * kMaxRhs + i] = 1.0;
+  }
+  for (int s = 0; s < nshift; ++s)
+    for (int i = 0; i < nrhs; ++i) {
+      const int q = s * nrhs + i;
+      M(MS_ZPREV, q) = M(MS_ZCUR, q) = M(MS_ZNEXT, q) = 1.0;
+      M(MS_DELTA, q) = shifts[order[s]] - s0;
+      if (bb[i] == 0.0) M(MS_DONE, q) = 1.0;
+    }
+  std::memcpy(L->hscal + kCgState, hs.data(), sizeof(double) * hs.size());
+  std::memcpy(L->hscal + kMsState, hm.data(), sizeof(double) * hm.size());
+  std::memcpy(L->hscal + kMsRhsRows, hr.data(), sizeof(double) * hr.size());
+  WL_HIP(hipMemcpyAsync(st, L->hscal + kCgState, sizeof(double) * (kMsRhsRows + hr.size() - kCgState),
+                        hipMemcpyHostToDevice, L->stream));
+
+  std::vector<double> mu_base(nrhs, s0);
+  const long long kmat0 = L->n_kmat;
+  while (true) {
+    for (int it = 0; it < chunk; ++it) {
+      op_j(L, F64, Ap, p, kappa, mu_base.data(), nrhs, DotOut{L->partials, nbrow});
+      launch_cg_alpha(L, L->partials, nbrow, nbrow, st, nrhs);
+      launch_ms_scalars(L, st, ms, mr, nrhs, nshift);
+      launch_ms_update(L, r, Ap, p, x, st, ms, nrhs, nshift, L->partials, nbrow);
+      launch_cg_beta(L, L->partials, nbrow, blas_blocks(L), st, nrhs);
+      launch_ms_xpay(L, p, r, st, ms, nrhs, nshift);
+    }
+    WL_HIP(hipMemcpyAsync(L->hscal + kCgState, st, sizeof(double) * (kMsRhsRows + hr.size() - kCgState),
+                          hipMemcpyDeviceToHost, L->stream));
+    WL_HIP(hipStreamSynchronize(L->stream));
+    std::memcpy(hs.data(), L->hscal + kCgState, sizeof(double) * hs.size());
+    std::memcpy(hm.data(), L->hscal + kMsState, sizeof(double) * hm.size());
+    bool all = true;
+    int max_it = 0;
+    for (int i = 0; i < nrhs; ++i) {
+      all = all && (S(CG_DONE, i) != 0.0 || S(CG_BREAK, i) != 0.0);
+      max_it = std::max(max_it, int(S(CG_ITERS, i)));
+    }
+    if (all || max_it >= prm.maxiter) break;
+  }
+  long long base_iters = 0;
+  for (int i = 0; i < nrhs; ++i) base_iters += (long long)S(CG_ITERS, i);
+  L->n_kmat = kmat0 + base_iters;
+
+  // true residuals per shift (batched over rhs), refinement of any miss
+  std::vector<double> rr(nsys), rr1(nrhs);
+  std::vector<int> refined_iters(nsys, 0);
+  const double one[2] = {1.0, 0.0}, mone[2] = {-1.0, 0.0};
+  auto residual = [&](int s) {
+    std::vector<double> mu(nrhs, shifts[order[s]]);
+    op_j(L, F64, r64, x + size_t(s) * nrhs * fb, kappa, mu.data(), nrhs);
+    L->n_kmat += nrhs;
+    double ca[2 * kMaxRhs], cb[2 * kMaxRhs];
+    for (int i = 0; i < nrhs; ++i) {
+      ca[2 * i] = 1.0, ca[2 * i + 1] = 0.0;
+      cb[2 * i] = -1.0, cb[2 * i + 1] = 0.0;
+    }
+    launch_caxpby(L, r64, ca, b, cb, r64, 0, nrhs);
+    norm2_host(L, r64, nrhs, rr1.data());
+  };
+  bool all_ok = true;  // decided by the final true residuals (a base run cut by maxiter is refined)
+  for (int s = 0; s < nshift; ++s) {
+    residual(s);
+    for (int i = 0; i < nrhs; ++i) {
+      const int q = s * nrhs + i;
+      rr[q] = rr1[i];
+      if (bb[i] == 0.0 || rr1[i] <= prm.tol * prm.tol * bb[i]) continue;
+      // refine: x_s += J_s^-1 (b - J_s x_s), to the tolerance relative to |b|
+      // (with a margin, so that the recomputed residual of x + e meets it too,
+      // and its own iteration limit: maxiter bounds the base iteration)
+      wl_cg_params rp = prm;
+      rp.tol = std::min(0.5, 0.5 * prm.tol * std::sqrt(bb[i] / rr1[i]));
+      rp.maxiter = std::max(prm.maxiter, 10000);
+      rp.use_graph = 0;
+      char* e = static_cast<char*>(ws_get(L, "ms_e", fb));
+      const double mu = shifts[order[s]];
+      wl_cg_stats est{};
+      const int rc = cg_run(L, e, r64 + size_t(i) * fb, kappa, &mu, 1, WL_OP_J, rp, &est);
+      refined_iters[q] = est.iters;
+      char* xs = x + size_t(q) * fb;
+      launch_caxpby(L, xs, one, xs, one, e, 0, 1);
+      if (rc != WL_OK) all_ok = false;
+    }
+    bool any_refined = false;
+    for (int i = 0; i < nrhs; ++i) any_refined = any_refined || refined_iters[s * nrhs + i] > 0;
+    if (any_refined) {
+      residual(s);
+      for (int i = 0; i < nrhs; ++i) rr[s * nrhs + i] = rr1[i];
+    }
+  }
+  (void)mone;
+  // results in the caller's shift order
+  for (int s = 0; s < nshift; ++s)
+    copy_dev(L, static_cast<char*>(x_out) + size_t(order[s]) * nrhs * fb, x + size_t(s) * nrhs * fb, fb * nrhs);
+  for (int s = 0; s < nshift; ++s)
+    for (int i = 0; i < nrhs; ++i) {
+      const int q = s * nrhs + i;
+      const bool ok = bb[i] == 0.0 || rr[q] <= prm.tol * prm.tol * bb[i] * (1.0 + 1e-12);
+      all_ok = all_ok && ok;
+      if (stats) {
+        wl_cg_stats& o = stats[order[s] * nrhs + i];
+        o.iters = (M(MS_DONE, q) != 0.0 ? int(M(MS_ITERS, q)) : int(S(CG_ITERS, i))) + refined_iters[q];
+        o.reliable_updates = refined_iters[q] > 0 ? 1 : 0;
+        o.converged = ok ? 1 : 0;
+        o.true_rel_res = bb[i] > 0 ? std::sqrt(rr[q] / bb[i]) : 0.0;
+      }
+    }
+  return all_ok ? WL_OK : WL_ENOCONV;
+}
+
 }  // namespace wl

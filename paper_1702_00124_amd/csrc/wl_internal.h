@@ -164,6 +164,11 @@ void launch_cheb_step(wl_lattice* L, const void* t, const void* w, void* tprev, 
 // CG scalar steps on the device state (see solver.cpp for the layout)
 void launch_cg_alpha(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);
 void launch_cg_beta(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);
+// multi-shift CG steps (FP64 fields [nshift][nrhs]; state layout in wl_solver_state.h)
+void launch_ms_scalars(wl_lattice* L, double* st, double* ms, double* mr, int nrhs, int nshift);
+void launch_ms_update(wl_lattice* L, void* r, const void* Ap, const void* p, void* x, const double* st,
+                      const double* ms, int nrhs, int nshift, double* partials, int pstride);
+void launch_ms_xpay(wl_lattice* L, void* p, const void* r, const double* st, const double* ms, int nrhs, int nshift);
 
 // ------------------------------------------------------------------ pack (pack.hip)
 void launch_pack_links(wl_lattice* L, const void* canon);

@@ -42,6 +42,10 @@ int cg_run(wl_lattice* L, void* x, const void* b, double kappa, const double* mu
 // apply(prec, out, in) must leave out = A in with fields of storage precision
 // prec (prm.inner for the iteration, F64 for true residuals).  Used for P(J)
 // and P(J) J.
+// multi-shift CG on J(mu2 = shifts[s]) for nshift shifts and nrhs sources (FP64);
+// x: [nshift][nrhs] fields in the order of shifts; stats [nshift * nrhs]
+int cg_multishift_run(wl_lattice* L, void* x, const void* b, double kappa, const double* shifts, int nshift,
+                      int nrhs, const wl_cg_params& prm, wl_cg_stats* stats);
 int cg_run_generic(wl_lattice* L, void* x, const void* b,
                    const std::function<void(Prec, void*, const void*)>& apply, const wl_cg_params& prm,
                    wl_cg_stats* stats);

@@ -17,4 +17,21 @@ enum CgStateRow {
   CG_NROWS = 10
 };
 
+// Multi-shift CG state (after the CG rows): per shifted system q = s * nrhs + r
+// rows of kMaxSys doubles, then per-rhs rows of kMaxRhs.
+constexpr int kMaxSys = 64;
+constexpr int kMsState = 1280;  // offset in the device scalar area
+enum MsStateRow {
+  MS_ZPREV = 0,   // zeta_{i-1}
+  MS_ZCUR = 1,    // zeta_i
+  MS_ZNEXT = 2,   // zeta_{i+1}
+  MS_ASHIFT = 3,  // alpha of the shifted system this iteration (0: frozen)
+  MS_DONE = 4,    // 1 once |zeta|^2 |r|^2 <= tol^2 |b|^2
+  MS_DELTA = 5,   // shift minus the base shift
+  MS_ITERS = 6,   // base iterations when the system froze
+  MS_NROWS = 7
+};
+constexpr int kMsRhsRows = kMsState + MS_NROWS * kMaxSys;  // per-rhs rows follow
+enum MsRhsRow { MS_APREV = 0, MS_RHS_NROWS = 1 };
+
 }  // namespace wl

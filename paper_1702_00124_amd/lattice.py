@@ -233,6 +233,27 @@ class WilsonLattice:
         res = [CgResult(s.iters, s.reliable_updates, bool(s.converged), s.true_rel_res) for s in st]
         return x, res, rc
 
+    def cg_multishift(self, b: torch.Tensor, kappa: float, shifts: Sequence[float], nrhs: int = 1,
+                      params: Optional[CG] = None):
+        """x[s * nrhs + r] = (K-hat + shifts[s])^-1 b_r for every shift at once (FP64);
+        returns (x, [[CgResult per rhs] per shift], rc)."""
+        params = params or CG()
+        ns = len(shifts)
+        x = torch.empty(self.field_bytes("f64") * ns * nrhs, dtype=torch.uint8, device=self.device)
+        _need(b, self.field_bytes("f64", nrhs), "rhs")
+        sh = (C.c_double * ns)(*[float(v) for v in shifts])
+        st = (W.CgStats * (ns * nrhs))()
+        prm = params.c()
+        rc = W.check(self.lib.cg_multishift(self.h, _ptr(x), _ptr(b), kappa, sh, ns, nrhs, C.byref(prm), st))
+        res = [[CgResult(st[s * nrhs + r].iters, st[s * nrhs + r].reliable_updates, bool(st[s * nrhs + r].converged),
+                         st[s * nrhs + r].true_rel_res) for r in range(nrhs)] for s in range(ns)]
+        return x, res, rc
+
+    def shift_block(self, x: torch.Tensor, s: int, nrhs: int) -> torch.Tensor:
+        """The nrhs solutions of shift s inside a cg_multishift result."""
+        fb = self.field_bytes("f64")
+        return x[s * nrhs * fb:(s + 1) * nrhs * fb]
+
     def poly_filter_apply(self, buf: torch.Tensor, kappa: float, mu2: float, degree: int, a: float, b: float,
                           mode: str = "P", out: Optional[torch.Tensor] = None, degree_div: int = 0) -> torch.Tensor:
         out = self.new_field("f64") if out is None else out

@@ -86,3 +86,49 @@ def test_cg_nonconvergence_and_zero_rhs():
     z = np.zeros_like(b)
     x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(z)), 0.155, "J")
     assert rc == 0 and st[0].iters == 0 and np.abs(to_np(lat.export_spinor(x))).max() == 0.0
+
+
+def test_multishift_cg_matches_oracle():
+    """8 sources x 4 Hasenbusch shifts (given unsorted) in one Krylov space per source:
+    every solution against the oracle's multi-shift CG and its own true residual."""
+    from oracle import solver as osl
+    L, kappa = (6, 4, 4, 10), 0.155
+    shifts = [0.5, 0.0, 0.05, 0.005]
+    nrhs = 8
+    say("multi-shift cg", nrhs, "sources", shifts)
+    lat, U = make_lattice(L)
+    b = half_noise(L, 2020, nrhs=nrhs)
+    x, st, rc = lat.cg_multishift(lat.import_spinor(torch.from_numpy(b)), kappa, shifts, nrhs,
+                                  CG(tol=1e-11, chunk=4))
+    assert rc == 0
+    A = lambda v: ow.Khat(U, v, L, kappa)
+    for s, sh in enumerate(shifts):
+        xg = to_np(lat.export_spinor(lat.shift_block(x, s, nrhs), "f64", nrhs))
+        say(f"  shift {sh}: iterations {[c.iters for c in st[s]]}")
+        for r in range(nrhs):
+            assert st[s][r].converged and st[s][r].true_rel_res <= 1e-11
+            assert rel(ow.J(U, xg[r], L, kappa, sh), b[r]) <= 1.01e-11
+        xr, _, _ = osl.cg_multishift(A, b[0], shifts, tol=1e-11)
+        assert rel(xg[0], xr[s]) <= 100 * 2e-11
+    # heavier shifts freeze earlier
+    assert st[0][0].iters < st[1][0].iters
+
+
+def test_multishift_refinement_and_edges():
+    """A base run cut short by maxiter is finished by per-system refinement; a zero
+    source gives zero solutions; too many systems is an error."""
+    L, kappa = (4, 4, 4, 4), 0.155
+    lat, U = make_lattice(L)
+    b = half_noise(L, 2021, nrhs=2)
+    b[1] = 0.0
+    shifts = [0.0, 0.05]
+    x, st, rc = lat.cg_multishift(lat.import_spinor(torch.from_numpy(b)), kappa, shifts, 2,
+                                  CG(tol=1e-10, maxiter=8, chunk=4))
+    assert rc == 0
+    for s, sh in enumerate(shifts):
+        xg = to_np(lat.export_spinor(lat.shift_block(x, s, 2), "f64", 2))
+        assert st[s][0].reliable_updates == 1 and st[s][0].converged
+        assert rel(ow.J(U, xg[0], L, kappa, sh), b[0]) <= 1.01e-10
+        assert np.abs(xg[1]).max() == 0.0 and st[s][1].converged
+    with pytest.raises(Exception):
+        lat.cg_multishift(lat.import_spinor(torch.from_numpy(half_noise(L, 1, nrhs=16))), kappa, [0.0] * 5, 16)
