@@ -134,24 +134,9 @@ print(json.dumps({"n": n, "sec_per_hop": dt}))
                       f"({d['sec_per_hop']:.2f} s each, single-threaded NumPy)"}
 
 
-# the paper's actions (Sec. 2 MP, PF; Sec. 3.3 2PF, 2MP; Sec. 4.1 PF-MP; Sec. 4.2
-# 1PF-2MP, 2PF-1MP) in the kappa' form of the Hasenbusch matrix J = K-hat(kappa'),
-# kappa_1 = 0.145 < kappa' = kappa_2 = 0.150 < kappa = 0.155; polynomial orders as
-# the paper fixes them (p = 4, q = 20, p_2 = 24); terms listed from the cheapest
-# (finest scale) to the most expensive
-KP, K1, K2 = 0.150, 0.145, 0.150
-PAPER_ACTIONS = {
-    "MP": [("KINV", KP, {}), ("RATIO", KAPPA, {"kappa_num": KP})],
-    "PF": [("POLY", KAPPA, {"degree": 16}), ("POLYK_INV", KAPPA, {"degree": 16})],
-    "2PF": [("POLY", KAPPA, {"degree": 4}), ("POLY", KAPPA, {"degree": 24, "degree_div": 4}),
-            ("POLYK_INV", KAPPA, {"degree": 24})],
-    "2MP": [("KINV", K1, {}), ("RATIO", K2, {"kappa_num": K1}), ("RATIO", KAPPA, {"kappa_num": K2})],
-    "PF-MP": [("POLY", KP, {"degree": 4}), ("POLYK_INV", KP, {"degree": 4}), ("RATIO", KAPPA, {"kappa_num": KP})],
-    "1PF-2MP": [("POLY", K1, {"degree": 4}), ("POLYK_INV", K1, {"degree": 4}), ("RATIO", K2, {"kappa_num": K1}),
-                ("RATIO", KAPPA, {"kappa_num": K2})],
-    "2PF-1MP": [("POLY", KP, {"degree": 4}), ("POLY", KP, {"degree": 24, "degree_div": 4}),
-                ("POLYK_INV", KP, {"degree": 24}), ("RATIO", KAPPA, {"kappa_num": KP})],
-}
+# kappas of the paper's actions on the bench lattice: kappa_1 = 0.145 < kappa' =
+# kappa_2 = 0.150 < kappa = 0.155 (the action lists live in the package)
+ACTION_KAPPAS = {"k": KAPPA, "kp": 0.150, "k1": 0.145, "k2": 0.150}
 
 
 def paper_actions(lat, U, li, torch, Term, CG, L, Vh):
@@ -160,12 +145,13 @@ def paper_actions(lat, U, li, torch, Term, CG, L, Vh):
     gauge action; MD solves FP32 inner / FP64 reliable updates to 1e-10.  Reports the
     paper's cost numerator N_mat (K-hat and J applications per trajectory), CG
     iterations, dH and the wall time (acceptance needs an equilibrated ensemble)."""
+    from paper_1702_00124_amd.actions import PAPER_ACTIONS, build_terms, default_nsteps
     cg = CG(tol=1e-10, inner="f32", chunk=8)
     out = {}
-    for name, spec in PAPER_ACTIONS.items():
+    for name in PAPER_ACTIONS:
         lat.set_links(torch.from_numpy(U))
-        terms = [Term(kind, kappa, cg=cg, **kw) for kind, kappa, kw in spec]
-        nsteps = [40] + [20] * (len(terms) - 1) + [80]
+        terms = build_terms(name, ACTION_KAPPAS, cg)
+        nsteps = default_nsteps(len(terms))
         P = lat.import_su3(torch.from_numpy(li.gaussian_momenta(L, li.seed_md(50, 15))))
         chi = torch.cat([lat.import_spinor(torch.from_numpy(li.gaussian_spinor((Vh, 4, 3), li.seed_md(50, i))))
                          for i in range(len(terms))])
