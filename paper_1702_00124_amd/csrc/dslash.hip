@@ -35,6 +35,13 @@ struct HopArgs {
   int part_off;
   int use_xcd;
   int rows;  // rhs groups per tile
+  // fused Chebyshev step (one rhs): with w the epilogue's result,
+  //   tprev <- ct t + cw w - tprev,  eprev <- ce e + 2 t - eprev,  w not stored
+  const char* ch_t;
+  char* ch_tprev;
+  const char* ch_e;
+  char* ch_eprev;
+  double ch_ct, ch_cw, ch_ce;
 };
 
 // Flattened grid: block b -> (tile, rhs group).  The XCD-aware renumbering
@@ -114,7 +121,27 @@ __device__ __forceinline__ void epi_store_unit(char* base, int u, int h, int Vh,
   else UnitIO<P>::store(base, u, h, Vh, c);
 }
 
-template <typename P, int DAG, int NR, bool ST>
+// the fused Chebyshev step on one 16-byte unit u of site h, w = the unit's result
+template <typename P, bool ST>
+__device__ __forceinline__ void cheb_unit(const HopArgs& a, int u, int h, int Vh, const cplx<typename P::real>* w) {
+  using R = typename P::real;
+  using UIO = UnitIO<P>;
+  cplx<R> t[UIO::CPU], tp[UIO::CPU], e[UIO::CPU], ep[UIO::CPU];
+  epi_load_unit<P, ST>(a.ch_t, u, h, Vh, t);
+  epi_load_unit<P, ST>(a.ch_tprev, u, h, Vh, tp);
+  epi_load_unit<P, ST>(a.ch_e, u, h, Vh, e);
+  epi_load_unit<P, ST>(a.ch_eprev, u, h, Vh, ep);
+  const R rt = R(a.ch_ct), rw = R(a.ch_cw), re = R(a.ch_ce), two = R(2);
+#pragma unroll
+  for (int q = 0; q < UIO::CPU; ++q) {
+    tp[q] = rt * t[q] + rw * w[q] - tp[q];
+    ep[q] = re * e[q] + two * t[q] - ep[q];
+  }
+  epi_store_unit<P, ST>(a.ch_tprev, u, h, Vh, tp);
+  epi_store_unit<P, ST>(a.ch_eprev, u, h, Vh, ep);
+}
+
+template <typename P, int DAG, int NR, bool ST, bool CHEB = false>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
   using R = typename P::real;
   int b, row;
@@ -160,6 +187,12 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
         const R cy = R(a.by[r0 + r]);
 #pragma unroll
         for (int k = 0; k < 12; ++k) o.c[k] = o.c[k] + cy * yv.c[k];
+      }
+      if constexpr (CHEB) {
+        using UIO = UnitIO<P>;
+#pragma unroll
+        for (int u = 0; u < UIO::NU; ++u) cheb_unit<P, ST>(a, u, h, Vh, o.c + u * UIO::CPU);
+        continue;
       }
       epi_store<P, ST>(a.out + off, h, Vh, o);
       if (a.dot == 1) {
@@ -260,7 +293,7 @@ __device__ __forceinline__ cplx<R> dp_recon(const cplx<R>* W, int s, int col, in
 
 // NRP rhs share one LDS pass; NPASS passes reuse the link held in registers,
 // so each link is read once for NRP * NPASS rhs
-template <typename P, int DAG, int NRP, int NPASS, bool ST>
+template <typename P, int DAG, int NRP, int NPASS, bool ST, bool CHEB = false>
 __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
   using R = typename P::real;
   using UIO = UnitIO<P>;
@@ -329,6 +362,10 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
             if (a.g5 && s >= 2) o[q] = R(-1) * o[q];
             if (a.y) o[q] = o[q] + cy * yv[q];
           }
+          if constexpr (CHEB) {
+            cheb_unit<P, ST>(a, u, h, Vh, o);
+            continue;
+          }
           epi_store_unit<P, ST>(a.out + off, u, h, Vh, o);
           if (a.dot == 1) {
             cplx<R> dv[UIO::CPU];
@@ -373,6 +410,17 @@ static void dispatch_dp(HopArgs a, int nrhs, hipStream_t st, int max_pass) {
 
 template <typename P, int DAG, bool ST>
 static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, const HopConfig& c) {
+  if constexpr (DAG == 0) {
+    if (a.ch_t) {  // fused Chebyshev step: one rhs, forward hop
+      a.rows = 1;
+      if (c.variant == kHopDirParallel)
+        hipLaunchKernelGGL((hop_dp_kernel<P, 0, 1, 1, ST, true>), dim3((a.g.Vh + kDpSites - 1) / kDpSites),
+                           dim3(kDpThreads), 0, st, a);
+      else
+        hipLaunchKernelGGL((hop_kernel<P, 0, 1, ST, true>), dim3(site_blocks(a.g.Vh)), dim3(kBlock), 0, st, a);
+      return;
+    }
+  }
   // rhs per LDS pass (direction-parallel) or per thread (site): two for FP32
   // and BF16 with an even rhs count when the configuration allows, else one
   constexpr bool narrow = sizeof(typename P::real) == 4;
@@ -413,6 +461,7 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
                 int nrhs, const HopEpi& e) {
   WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs, WL_EINVAL, "nrhs out of range");
   WL_REQUIRE(out != in, WL_EINVAL, "hop output must not alias its input");
+  WL_REQUIRE(!e.cheb_t || (nrhs == 1 && !dagger && !e.dot), WL_EINVAL, "fused Chebyshev step: one rhs, forward");
   ensure_lowp_links(L);
   HopArgs a;
   a.g = L->geo;
@@ -432,6 +481,13 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
   a.partials = e.partials;
   a.part_stride = e.part_stride;
   a.part_off = e.part_off;
+  a.ch_t = static_cast<const char*>(e.cheb_t);
+  a.ch_tprev = static_cast<char*>(e.cheb_tprev);
+  a.ch_e = static_cast<const char*>(e.cheb_e);
+  a.ch_eprev = static_cast<char*>(e.cheb_eprev);
+  a.ch_ct = e.cheb_ct;
+  a.ch_cw = e.cheb_cw;
+  a.ch_ce = e.cheb_ce;
   const HopConfig& cfg = L->hop_cfg[prec][hop_kind(nrhs)];
   a.use_xcd = cfg.use_xcd;
   // sampled event timing (never inside a graph capture)

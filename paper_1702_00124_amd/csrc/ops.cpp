@@ -25,7 +25,7 @@ void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, 
 }
 
 void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const double* mu2, int nrhs,
-          const DotOut& dot) {
+          const DotOut& dot, const ChebStep* cheb) {
   const size_t fb = spinor_bytes(prec, L->Vh) * nrhs;
   void* odd = ws_get(L, "op_odd", fb);
   void* v = ws_get(L, "op_even", fb);
@@ -52,6 +52,16 @@ void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, con
     e4.dotv = in;
     e4.partials = dot.partials;
     e4.part_stride = dot.stride;
+  }
+  if (cheb) {  // the Chebyshev step consumes J in instead of storing it
+    e4.cheb_t = in;
+    e4.cheb_tprev = cheb->tprev;
+    e4.cheb_e = cheb->e;
+    e4.cheb_eprev = cheb->eprev;
+    e4.cheb_ct = cheb->ct;
+    e4.cheb_cw = cheb->cw;
+    e4.cheb_ce = cheb->ce;
+    out = cheb->tprev;  // never written in this mode
   }
   launch_hop(L, prec, out, odd, 0, 0, nrhs, e4);  // g5 M-hat v + mu2 in
   L->n_kmat += nrhs;

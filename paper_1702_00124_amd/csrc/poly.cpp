@@ -7,8 +7,8 @@
 // P_n(J) psi runs the real three-term recurrence
 //   t_{m+1} = 2 y(J) t_m - t_{m-1}        (t_m = T_m(y(J)) psi)
 //   e_{m+1} = 2 y0 e_m + 2 t_m - e_{m-1}  (e_m = (T_m(y0) - T_m(y(J)))/(y0 - y(J)) psi)
-// so that P_n(J) psi = (2/(b-a)) e_{n+1} / T_{n+1}(y0): n J applications and
-// one fused vector kernel per order.  Q(J), with P = Q^dag Q, is the product
+// so that P_n(J) psi = (2/(b-a)) e_{n+1} / T_{n+1}(y0): n J applications, each
+// step of the recurrence fused into the last hop of its J application.  Q(J), with P = Q^dag Q, is the product
 // over the n/2 roots z_k = ((b+a)/2)(1 - cos t_k) - i sqrt(ab) sin t_k,
 // t_k = 2 pi k/(n+1), times sqrt(c), c the leading coefficient of P_n.
 //
@@ -77,9 +77,13 @@ static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, doubl
   zero_dev(L, eA, fb);
   copy_dev(L, eB, in, fb);
   for (int m = 1; m <= pd.n; ++m) {
-    const bool need_t = m < pd.n;
-    if (need_t) op_j(L, pr, w, tB, kappa, &mu2, 1);
-    launch_cheb_step(L, tB, need_t ? w : tB, tA, eB, eA, ct, need_t ? cw : 0.0, 2.0 * y0, 1, pr);
+    if (m < pd.n) {
+      // J t_m and the step in one pass: tA <- t_{m+1}, eA <- e_{m+1}
+      const ChebStep cs{tA, eB, eA, ct, cw, 2.0 * y0};
+      op_j(L, pr, nullptr, tB, kappa, &mu2, 1, DotOut(), &cs);
+    } else {
+      launch_cheb_step(L, tB, tB, tA, eB, eA, ct, 0.0, 2.0 * y0, 1, pr);  // e_{n+1} only
+    }
     std::swap(tA, tB);
     std::swap(eA, eB);
   }

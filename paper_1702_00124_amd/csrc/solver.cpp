@@ -371,7 +371,7 @@ int cg_multishift_run(wl_lattice* L, void* x_out, const void* b, double kappa, c
   // true residuals per shift (batched over rhs), refinement of any miss
   std::vector<double> rr(nsys), rr1(nrhs);
   std::vector<int> refined_iters(nsys, 0);
-  const double one[2] = {1.0, 0.0}, mone[2] = {-1.0, 0.0};
+  const double one[2] = {1.0, 0.0};
   auto residual = [&](int s) {
     std::vector<double> mu(nrhs, shifts[order[s]]);
     op_j(L, F64, r64, x + size_t(s) * nrhs * fb, kappa, mu.data(), nrhs);
@@ -414,7 +414,6 @@ int cg_multishift_run(wl_lattice* L, void* x_out, const void* b, double kappa, c
       for (int i = 0; i < nrhs; ++i) rr[s * nrhs + i] = rr1[i];
     }
   }
-  (void)mone;
   // results in the caller's shift order
   for (int s = 0; s < nshift; ++s)
     copy_dev(L, static_cast<char*>(x_out) + size_t(order[s]) * nrhs * fb, x + size_t(s) * nrhs * fb, fb * nrhs);

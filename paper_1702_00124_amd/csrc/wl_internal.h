@@ -129,6 +129,14 @@ struct HopEpi {
   double* partials = nullptr;
   int part_stride = 0;      // per-rhs stride of partials
   int part_off = 0;         // block offset inside a rhs row
+  // fused Chebyshev step (one rhs, forward hop; out is not written):
+  // with w the result above, cheb_tprev <- ct t + cw w - cheb_tprev and
+  // cheb_eprev <- ce e + 2 t - cheb_eprev (t = cheb_t, e = cheb_e)
+  const void* cheb_t = nullptr;
+  void* cheb_tprev = nullptr;
+  const void* cheb_e = nullptr;
+  void* cheb_eprev = nullptr;
+  double cheb_ct = 0.0, cheb_cw = 0.0, cheb_ce = 0.0;
 };
 // workgroups (and reduction partials per rhs) of one hop launch in precision prec
 int hop_tiles(const wl_lattice* L, Prec prec);

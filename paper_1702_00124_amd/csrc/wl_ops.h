@@ -14,10 +14,19 @@ struct DotOut {
 
 // even sites: out = M-hat in (dagger: M-hat^dag), nrhs fields of precision prec
 void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger, int nrhs);
+// one step of the Chebyshev recurrence fused into J's last hop (one rhs):
+// tprev <- ct in + cw J in - tprev, eprev <- ce e + 2 in - eprev
+struct ChebStep {
+  void* tprev;
+  const void* e;
+  void* eprev;
+  double ct, cw, ce;
+};
 // even sites: out = K-hat in + mu2[r] in; optional partials of Re<in, out>
-// (one row per rhs, hop_tiles(L, prec) blocks)
+// (one row per rhs, hop_tiles(L, prec) blocks); with cheb, out is not written
+// and the Chebyshev step consumes J in
 void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const double* mu2, int nrhs,
-          const DotOut& dot = DotOut());
+          const DotOut& dot = DotOut(), const ChebStep* cheb = nullptr);
 // full lattice (F64 halves back to back, nrhs = 1): M, M^dag, K = M^dag M
 void op_m_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger);
 void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const DotOut& dot = DotOut());

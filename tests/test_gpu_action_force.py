@@ -22,11 +22,13 @@ L4 = (4, 4, 4, 4)
 KAPPA, MU2 = 0.155, 0.05
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("mode", ["P", "PJ", "Q", "QDAG"])
 @pytest.mark.parametrize("n", [4, 16])
-def test_poly_filter_matches_oracle(mode, n):
-    say("poly", mode, n)
-    lat, U = make_lattice(L4)
+def test_poly_filter_matches_oracle(mode, n, variant):
+    """Both hop kernels (the recurrence's steps are fused into J's last hop)."""
+    say("poly", mode, n, "variant", variant)
+    lat, U = make_lattice(L4, variant=variant)
     psi = half_noise(L4, 61)
     got = to_np(lat.export_spinor(lat.poly_filter_apply(lat.import_spinor(torch.from_numpy(psi)), KAPPA, MU2, n,
                                                         0.001, 8.0, mode)))
@@ -141,6 +143,21 @@ def test_term_heatbath_action_force_match_oracle(kind):
     e = rel(F, Fr)
     say(f"  force relative error {e:.2e}")
     assert e <= 1e-9
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("inner", ["f32", "bf16"])
+def test_poly_solve_low_precision_inner(inner, variant):
+    """[P(J) J]^-1 phi with FP32 / BF16 inner iterations (the recurrence and its fused
+    steps in that precision) and FP64 reliable updates: the action at solver tolerance."""
+    say("POLYK_INV action, inner", inner, "variant", variant)
+    lat, U = make_lattice(L4, variant=variant)
+    phi = half_noise(L4, 3004)
+    gt = Term("POLYK_INV", KAPPA, mu2=MU2, degree=16, cg=CG(tol=1e-12, inner=inner))
+    ot = oact.Term("POLYK_INV", KAPPA, mu2=MU2, n=16, tol=1e-12)
+    S_g = lat.action(gt, lat.import_spinor(torch.from_numpy(phi)))
+    S_r = oact.action(oact.Ops(U, L4), ot, phi)
+    assert abs(S_g - S_r) <= 1e-9 * abs(S_r)
 
 
 def test_poly_force_order16():
