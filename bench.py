@@ -57,34 +57,34 @@ HOP_BYTES_PER_SITE = {"f64": 8 * 96 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8
 # kernel sources); otherwise `traffic` is reported as null.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_COUNTERS = {
-    "source_sha256": "8ee86695bc9c28f21f027846c72774dd4faa49ac09e60e21d20661a3a0d4c136",
+    "source_sha256": "194caf85e788e8632aa6f87360e45623599c9c2d000aac074100c7eff23efcfd",
     # "precision:variant:workgroup order:streaming": KiB per dispatch on the 16^3x32
     # workload, median of 45 dispatches per configuration
     "per_launch_kib": {
-        "f64:site:xcd1:st0": {"fetch": 34202.3, "write": 12288.0},
-        "f64:site:xcd1:st1": {"fetch": 33935.0, "write": 12299.9},
-        "f64:site:xcd0:st0": {"fetch": 40056.4, "write": 12288.0},
-        "f64:site:xcd0:st1": {"fetch": 37113.2, "write": 12289.0},
-        "f64:dp:xcd1:st0": {"fetch": 34185.1, "write": 12288.0},
-        "f64:dp:xcd1:st1": {"fetch": 33926.5, "write": 12288.0},
-        "f64:dp:xcd0:st0": {"fetch": 45173.4, "write": 12288.0},
-        "f64:dp:xcd0:st1": {"fetch": 45009.5, "write": 12288.0},
-        "f32:site:xcd1:st0": {"fetch": 16998.0, "write": 6144.0},
+        "f64:site:xcd1:st0": {"fetch": 34200.8, "write": 12288.0},
+        "f64:site:xcd1:st1": {"fetch": 33935.0, "write": 12303.9},
+        "f64:site:xcd0:st0": {"fetch": 39936.1, "write": 12288.0},
+        "f64:site:xcd0:st1": {"fetch": 37112.3, "write": 12288.4},
+        "f64:dp:xcd1:st0": {"fetch": 34321.6, "write": 12288.0},
+        "f64:dp:xcd1:st1": {"fetch": 33932.0, "write": 12288.0},
+        "f64:dp:xcd0:st0": {"fetch": 45155.7, "write": 12288.0},
+        "f64:dp:xcd0:st1": {"fetch": 45010.3, "write": 12288.0},
+        "f32:site:xcd1:st0": {"fetch": 16999.0, "write": 6144.0},
         "f32:site:xcd1:st1": {"fetch": 17001.0, "write": 6144.0},
-        "f32:site:xcd0:st0": {"fetch": 18617.2, "write": 6144.0},
-        "f32:site:xcd0:st1": {"fetch": 18537.0, "write": 6144.0},
-        "f32:dp:xcd1:st0": {"fetch": 17001.0, "write": 6144.0},
-        "f32:dp:xcd1:st1": {"fetch": 17001.0, "write": 6144.0},
-        "f32:dp:xcd0:st0": {"fetch": 22377.3, "write": 6144.0},
+        "f32:site:xcd0:st0": {"fetch": 18619.4, "write": 6144.0},
+        "f32:site:xcd0:st1": {"fetch": 18536.5, "write": 6144.0},
+        "f32:dp:xcd1:st0": {"fetch": 17001.5, "write": 6144.0},
+        "f32:dp:xcd1:st1": {"fetch": 17001.5, "write": 6144.0},
+        "f32:dp:xcd0:st0": {"fetch": 22378.0, "write": 6144.0},
         "f32:dp:xcd0:st1": {"fetch": 22377.0, "write": 6144.0},
-        "bf16:site:xcd1:st0": {"fetch": 8561.5, "write": 3072.0},
-        "bf16:site:xcd1:st1": {"fetch": 8563.0, "write": 3072.0},
-        "bf16:site:xcd0:st0": {"fetch": 9329.5, "write": 3072.0},
-        "bf16:site:xcd0:st1": {"fetch": 9331.0, "write": 3072.0},
-        "bf16:dp:xcd1:st0": {"fetch": 8568.0, "write": 3072.0},
-        "bf16:dp:xcd1:st1": {"fetch": 8572.5, "write": 3072.0},
-        "bf16:dp:xcd0:st0": {"fetch": 11448.0, "write": 3072.0},
-        "bf16:dp:xcd0:st1": {"fetch": 11452.5, "write": 3072.0},
+        "bf16:site:xcd1:st0": {"fetch": 8562.5, "write": 3072.0},
+        "bf16:site:xcd1:st1": {"fetch": 8564.5, "write": 3072.0},
+        "bf16:site:xcd0:st0": {"fetch": 9330.0, "write": 3072.0},
+        "bf16:site:xcd0:st1": {"fetch": 9332.0, "write": 3072.0},
+        "bf16:dp:xcd1:st0": {"fetch": 8576.5, "write": 3072.0},
+        "bf16:dp:xcd1:st1": {"fetch": 8576.5, "write": 3072.0},
+        "bf16:dp:xcd0:st0": {"fetch": 11456.0, "write": 3072.0},
+        "bf16:dp:xcd0:st1": {"fetch": 11456.0, "write": 3072.0},
     },
 }
 
