@@ -189,7 +189,8 @@ def large_volume(li, torch, np, CG, WilsonLattice):
             byt = (HOP_BYTES_PER_SITE[p] + (nrhs - 1) * 2 * {"f64": 192, "f32": 96, "bf16": 48}[p]) * Vh
             out["hop"][f"{p}_x{nrhs}"] = {"us": round(us, 1), "us_per_rhs": round(us / nrhs, 1),
                                           "GBs": round(byt / (us * 1e-6) / 1e9, 1)}
-    log("large volume hop", json.dumps(out["hop"]))
+    out["copy_f64_hop_bytes_gbs"] = round(lat.stream_copy(HOP_BYTES_PER_SITE["f64"] * Vh // 2 // 16 * 16, 50), 1)
+    log("large volume hop", json.dumps(out["hop"]), "copy of the FP64 hop's bytes:", out["copy_f64_hop_bytes_gbs"])
     bs = [li.gaussian_spinor((Vh, 4, 3), li.seed_source(100 + j)) for j in range(4)]
     b1 = lat.import_spinor(torch.from_numpy(bs[0]))
     b4 = lat.import_spinor(torch.from_numpy(np.stack(bs)))

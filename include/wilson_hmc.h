@@ -313,8 +313,9 @@ int wl_autotune(wl_lattice* lat, double* us_out);
  * over 5 sub-bursts of nlaunch/5.  Not counted in the hop counters. */
 int wl_time_hop(wl_lattice* lat, wl_prec prec, int nrhs, int nlaunch, double* avg_us);
 /* Tracing: the practical HBM ceiling: a plain copy of bytes (multiple of 16,
- * at most 16 GiB) between two library buffers, reps times; *gbs = bytes read
- * plus written per second (GB/s). */
+ * at most 16 GiB) between two library buffers, reps times, alternating the
+ * direction so that each copy reads the previous one's output; *gbs = bytes
+ * read plus written per second (GB/s). */
 int wl_stream_copy(wl_lattice* lat, size_t bytes, int reps, double* gbs);
 
 /* Hop applications since create per storage precision (counts[wl_prec], single rhs units). */

@@ -530,9 +530,11 @@ int wl_stream_copy(wl_lattice* L, size_t bytes, int reps, double* gbs) {
     hipEvent_t e0, e1;
     WL_HIP(hipEventCreate(&e0));
     WL_HIP(hipEventCreate(&e1));
+    // alternate the direction, so that every copy reads what the previous one
+    // wrote (as a solver's kernels do), not a cache-resident constant source
     launch_stream_copy(L, a, b, bytes);
     WL_HIP(hipEventRecord(e0, L->stream));
-    for (int i = 0; i < reps; ++i) launch_stream_copy(L, a, b, bytes);
+    for (int i = 0; i < reps; ++i) launch_stream_copy(L, i & 1 ? a : b, i & 1 ? b : a, bytes);
     WL_HIP(hipEventRecord(e1, L->stream));
     WL_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
