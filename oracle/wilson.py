@@ -91,3 +91,36 @@ def dense(op, n_sites, dtype=np.complex128):
         e[j] = 1
         A[:, j] = op(e.reshape(n_sites, 4, 3)).reshape(n)
     return A
+
+
+def hop_eo_at(U, psi_h, L, out_parity, sites_h, t_bc=-1, dagger=False):
+    """hop_eo evaluated only at the listed output sites (half-lattice indices of
+    parity out_parity), from the definition of D term by term: for large
+    lattices, where a few sampled sites check a full-size result.
+    psi_h: half field of parity 1 - out_parity.  Returns [len(sites_h), 4, 3]."""
+    g = lat.gammas()
+    one = np.eye(4)
+    s = -1.0 if dagger else 1.0
+    full_out = lat.parity_sites(L, out_parity)[np.asarray(sites_h)]
+    full_in = lat.parity_sites(L, 1 - out_parity)
+    x = np.stack(np.unravel_index(full_out, tuple(reversed(L)))[::-1], axis=1)   # (x, y, z, t) per site
+
+    def flat(c):
+        return c[:, 0] + L[0] * (c[:, 1] + L[1] * (c[:, 2] + L[2] * c[:, 3]))
+
+    out = np.zeros((len(full_out), 4, 3), dtype=np.complex128)
+    for mu in range(4):
+        for sign in (+1, -1):
+            y = x.copy()
+            y[:, mu] += sign
+            wrap = (y[:, mu] < 0) | (y[:, mu] >= L[mu])
+            y[:, mu] %= L[mu]
+            ph = np.where(wrap & (mu == 3), float(t_bc), 1.0)
+            psi_y = psi_h[np.searchsorted(full_in, flat(y))]                     # psi(x +- mu)
+            if sign > 0:
+                v = np.einsum("nab,nsb->nsa", U[mu][full_out], psi_y)           # U_mu(x) psi(x + mu)
+                out += ph[:, None, None] * lat.apply_spin(one - s * g[mu], v)
+            else:
+                v = np.einsum("nba,nsb->nsa", np.conj(U[mu][flat(y)]), psi_y)   # U_mu(x - mu)^dag psi(x - mu)
+                out += ph[:, None, None] * lat.apply_spin(one + s * g[mu], v)
+    return out

@@ -138,3 +138,19 @@ def test_schur_complement_determinant_and_inverse():
     idx = (ev[:, None] * 12 + np.arange(12)[None]).reshape(-1)
     Minv_ee = np.linalg.inv(Md)[np.ix_(idx, idx)]
     assert np.abs(Minv_ee - np.linalg.inv(Mh)).max() < 1e-12
+
+
+@pytest.mark.parametrize("L", [(4, 4, 2, 6), (6, 2, 4, 4)])
+def test_hop_at_sampled_sites_equals_full_hop(L):
+    """The per-site evaluation (used at full sizes) agrees with the whole-lattice hop,
+    both parities, dagger, across the antiperiodic time wrap."""
+    U = li.random_links(L, 0.447, 5)
+    Vh = li.volume(L) // 2
+    rng = np.random.default_rng(3)
+    for p in (0, 1):
+        psi = li.gaussian_spinor((Vh, 4, 3), 40 + p)
+        sites = rng.choice(Vh, 17, replace=False)
+        for dagger in (False, True):
+            full = wl.hop_eo(U, psi, L, p, t_bc=-1, dagger=dagger)
+            at = wl.hop_eo_at(U, psi, L, p, sites, t_bc=-1, dagger=dagger)
+            assert np.abs(at - full[sites]).max() < 1e-13
