@@ -167,6 +167,29 @@ def paper_actions(lat, U, li, torch, Term, CG, L, Vh):
     return out
 
 
+def chrono_guess(lat, U, li, torch, terms, nsteps, L, Vh):
+    """The bench trajectory from the same links, momenta and noise, force solves
+    from x0 = 0 vs from each term's previous force solution (chronological
+    guess): CG iterations, K applications, wall time and dH of each."""
+    out = {}
+    for chrono in (False, True):
+        lat.set_links(torch.from_numpy(U))
+        P = lat.import_su3(torch.from_numpy(li.gaussian_momenta(L, li.seed_md(60, 15))))
+        chi = torch.cat([lat.import_spinor(torch.from_numpy(li.gaussian_spinor((Vh, 4, 3), li.seed_md(60, i))))
+                         for i in range(len(terms))])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lat.hmc_trajectory(terms, nsteps, P, chi, 0.5, beta=BETA, tau=1.0, integrator="omelyan",
+                               no_metropolis=True, chrono=chrono)
+        torch.cuda.synchronize()
+        out["chronological" if chrono else "cold"] = {
+            "cg_iters": int(r.cg_iters), "n_mat": int(r.n_kmat), "seconds": round(time.perf_counter() - t0, 3),
+            "dH": round(r.dH, 6)}
+    lat.set_links(torch.from_numpy(U))
+    log("chronological guess", json.dumps(out))
+    return out
+
+
 def large_volume(li, torch, np, CG, WilsonLattice):
     """32^3 x 64, kappa = 0.156, links with plaquette ~0.60, 4 Gaussian rhs:
     hop bandwidth per precision, CG to true residual 1e-10 with FP64 single rhs
@@ -442,6 +465,7 @@ def main():
         }
         log("cg", json.dumps(extra["cg"]))
         extra["paper_actions"] = paper_actions(lat, U, li, torch, Term, CG, L, Vh)
+        extra["chrono"] = chrono_guess(lat, U, li, torch, terms, nsteps, L, Vh)
         lat.close()
         torch.cuda.empty_cache()
         extra["large_volume"] = large_volume(li, torch, np, CG, WilsonLattice)

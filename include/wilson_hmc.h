@@ -104,7 +104,9 @@ int apply_K(wl_lattice* lat, void* out, const void* in, double kappa, const doub
 
 /* Conjugate gradient (Sec. 2: inversion of K by CG) on op = WL_OP_J (even
  * sites, nrhs right-hand sides, shifts mu2[r]) or WL_OP_K (full lattice,
- * nrhs = 1).  x0 = 0; stops when the FP64 true residual |b - A x| <= tol |b|
+ * nrhs = 1).  x0 = 0, or the contents of x when use_x0 = 1 (then r = b - A x0
+ * in FP64; a rhs whose x0 already meets tol takes 0 iterations; x of a zero
+ * source is set to 0); stops when the FP64 true residual |b - A x| <= tol |b|
  * for every rhs.  inner = WL_F64 runs plain FP64 CG; WL_F32 / WL_BF16 run the
  * inner iteration with that storage (FP32 arithmetic, FP64 dot products) and
  * FP64 reliable updates r = b - A x whenever the iterated residual fell by
@@ -118,6 +120,7 @@ typedef struct {
   double delta;    /* reliable-update threshold (0 -> 0.1) */
   int chunk;       /* iterations between host convergence checks (0 -> 8) */
   int use_graph;   /* capture each chunk as a hipGraph and replay it */
+  int use_x0;      /* 1: x holds the initial guess on entry (else x0 = 0) */
 } wl_cg_params;
 
 typedef struct {
@@ -139,7 +142,7 @@ int cg_solve(wl_lattice* lat, void* x, const void* b, double kappa, const double
  * a miss refined by an ordinary CG (params.inner) on its residual.
  * params: tol, maxiter (base iterations; a refinement may take up to
  * max(maxiter, 10000)), chunk; inner only for the refinement; use_graph
- * ignored.  stats: host array [nshift * nrhs], same
+ * ignored; use_x0 must be 0 (WL_EUNSUPPORTED otherwise).  stats: host array [nshift * nrhs], same
  * order as x (iters = base iterations until the system froze, plus any
  * refinement iterations; reliable_updates = 1 if refined).  WL_EINVAL for
  * nrhs outside 1..16, nshift * nrhs > 64, negative shifts; WL_ENOCONV if a
@@ -234,8 +237,12 @@ int wl_link_update(wl_lattice* lat, const double* P, double eps);
  * u_metropolis: caller's uniform in [0,1); accept iff u < exp(-dH).  On
  * rejection the links are restored.  flags: WL_HMC_NO_METROPOLIS always keeps
  * the end point; WL_HMC_PHI_GIVEN takes chi as the pseudofermions themselves
- * and skips the heatbath (both for reversibility tests). */
-enum { WL_HMC_NO_METROPOLIS = 1, WL_HMC_PHI_GIVEN = 2 };
+ * and skips the heatbath (both for reversibility tests); WL_HMC_CHRONO starts
+ * every force solve of a term from that term's previous force solution in the
+ * trajectory (chronological initial guess: fewer iterations; the trajectory
+ * is then reversible only to the solver tolerance, since the reverse run
+ * sees other initial guesses). */
+enum { WL_HMC_NO_METROPOLIS = 1, WL_HMC_PHI_GIVEN = 2, WL_HMC_CHRONO = 4 };
 enum { WL_INT_LEAPFROG = 0, WL_INT_OMELYAN = 1 };
 
 typedef struct {

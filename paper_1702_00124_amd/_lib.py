@@ -15,13 +15,13 @@ WL_F64, WL_F32, WL_BF16 = 0, 1, 2
 WL_OP_M, WL_OP_MDAG, WL_OP_K, WL_OP_MHAT, WL_OP_MHAT_DAG, WL_OP_J = range(6)
 WL_POLY_P, WL_POLY_PJ, WL_POLY_Q, WL_POLY_QDAG = range(4)
 WL_TERM_KINV_FULL, WL_TERM_KINV, WL_TERM_RATIO, WL_TERM_POLY, WL_TERM_POLYK_INV = range(5)
-WL_HMC_NO_METROPOLIS, WL_HMC_PHI_GIVEN = 1, 2
+WL_HMC_NO_METROPOLIS, WL_HMC_PHI_GIVEN, WL_HMC_CHRONO = 1, 2, 4
 WL_INT_LEAPFROG, WL_INT_OMELYAN = 0, 1
 
 
 class CgParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("inner", C.c_int), ("delta", C.c_double),
-                ("chunk", C.c_int), ("use_graph", C.c_int)]
+                ("chunk", C.c_int), ("use_graph", C.c_int), ("use_x0", C.c_int)]
 
 
 class CgStats(C.Structure):

@@ -53,20 +53,44 @@ void op_w(wl_lattice* L, void* out, const void* in, double kappa, double mu2, in
   launch_caxpby(L, out, one, t, imu, in, 1, 1);
 }
 
-int solve_j(wl_lattice* L, void* x, const void* b, double kappa, double mu2, const wl_cg_params& cg,
-            long long* iters) {
+// with a chrono slot, x starts from the slot's previous solution and the
+// new solution is kept there
+void chrono_in(wl_lattice* L, ChronoSlot* ch, void* x, size_t bytes, wl_cg_params& cg) {
+  if (ch && ch->valid) {
+    copy_dev(L, x, ch->x, bytes);
+    cg.use_x0 = 1;
+  }
+}
+void chrono_out(wl_lattice* L, ChronoSlot* ch, const void* x, size_t bytes) {
+  if (ch) {
+    copy_dev(L, ch->x, x, bytes);
+    ch->valid = true;
+  }
+}
+
+int solve_j(wl_lattice* L, void* x, const void* b, double kappa, double mu2, const wl_cg_params& cg_in,
+            long long* iters, ChronoSlot* ch = nullptr) {
   wl_cg_stats st{};
+  wl_cg_params cg = cg_in;
+  cg.use_x0 = 0;
+  chrono_in(L, ch, x, spinor_bytes(F64, L->Vh), cg);
   const int rc = cg_run(L, x, b, kappa, &mu2, 1, WL_OP_J, cg, &st);
+  chrono_out(L, ch, x, spinor_bytes(F64, L->Vh));
   if (iters) *iters += st.iters;
   WL_REQUIRE(rc == WL_OK, rc, "inner CG did not converge");
   return rc;
 }
 
-void solve_poly(wl_lattice* L, void* x, const void* b, const wl_term& t, int mode, long long* iters) {
+void solve_poly(wl_lattice* L, void* x, const void* b, const wl_term& t, int mode, long long* iters,
+                ChronoSlot* ch = nullptr) {
   wl_cg_stats st{};
   const PolyDesc pd = pdesc(t);
   auto apply = [&](Prec pr, void* out, const void* in) { poly_apply(L, mode, out, in, t.kappa, t.mu2, pd, pr); };
-  const int rc = cg_run_generic(L, x, b, apply, t.cg, &st);
+  wl_cg_params cg = t.cg;
+  cg.use_x0 = 0;
+  chrono_in(L, ch, x, spinor_bytes(F64, L->Vh), cg);
+  const int rc = cg_run_generic(L, x, b, apply, cg, &st);
+  chrono_out(L, ch, x, spinor_bytes(F64, L->Vh));
   if (iters) *iters += st.iters;
   WL_REQUIRE(rc == WL_OK, rc, "polynomial CG did not converge");
 }
@@ -195,7 +219,8 @@ double term_action(wl_lattice* L, const wl_term& t, const void* phi, long long* 
   return 0.0;
 }
 
-void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, double coeff, long long* iters) {
+void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, double coeff, long long* iters,
+                ChronoSlot* ch) {
   check_term(t);
   const size_t fb = hbytes(L);
   switch (t.kind) {
@@ -204,7 +229,11 @@ void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, dou
       char* x = static_cast<char*>(ws_get(L, "fo_xf", 2 * fb));
       char* y = static_cast<char*>(ws_get(L, "fo_yf", 2 * fb));
       wl_cg_stats st{};
-      const int rc = cg_run(L, x, phi, t.kappa, nullptr, 1, WL_OP_K, t.cg, &st);
+      wl_cg_params cg = t.cg;
+      cg.use_x0 = 0;
+      chrono_in(L, ch, x, 2 * fb, cg);
+      const int rc = cg_run(L, x, phi, t.kappa, nullptr, 1, WL_OP_K, cg, &st);
+      chrono_out(L, ch, x, 2 * fb);
       if (iters) *iters += st.iters;
       WL_REQUIRE(rc == WL_OK, rc, "inner CG did not converge");
       op_m_full(L, F64, y, x, t.kappa, 0);
@@ -215,7 +244,7 @@ void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, dou
       // dS = -2 Re(Y^dag dM-hat X), X = J^-1 phi, Y = M-hat X
       void* x = ws_get(L, "fo_x", fb);
       void* y = ws_get(L, "fo_y", fb);
-      solve_j(L, x, phi, t.kappa, t.mu2, t.cg, iters);
+      solve_j(L, x, phi, t.kappa, t.mu2, t.cg, iters, ch);
       op_mhat(L, F64, y, x, t.kappa, 0, 1);
       grad_re_dmhat(L, F, y, x, t.kappa, -2.0 * coeff);
       break;
@@ -229,7 +258,7 @@ void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, dou
       void* x = ws_get(L, "fo_x", fb);
       void* y = ws_get(L, "fo_y", fb);
       op_w(L, v, phi, kappa_n(t), t.mu2_num, 1);
-      solve_j(L, x, v, t.kappa, t.mu2, t.cg, iters);
+      solve_j(L, x, v, t.kappa, t.mu2, t.cg, iters, ch);
       op_mhat(L, F64, y, x, t.kappa, 0, 1);
       if (kappa_n(t) == t.kappa) {
         const double one[2] = {1.0, 0.0}, mone[2] = {-1.0, 0.0};
@@ -254,7 +283,7 @@ void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, dou
       void* x = ws_get(L, "fo_x", fb);
       void* qx = ws_get(L, "fo_qx", fb);
       void* jqx = ws_get(L, "fo_jqx", fb);
-      solve_poly(L, x, phi, t, WL_POLY_PJ, iters);
+      solve_poly(L, x, phi, t, WL_POLY_PJ, iters, ch);
       poly_apply(L, WL_POLY_Q, qx, x, t.kappa, t.mu2, pdesc(t));
       op_j(L, F64, jqx, qx, t.kappa, &t.mu2, 1);
       chain_grad(L, F, t, x, jqx, -2.0 * std::sqrt(poly_lead(pdesc(t))) * coeff);

@@ -135,13 +135,20 @@ int hmc_run(wl_lattice* L, const wl_hmc_params& prm, double* P, const void* chi,
   wl_hmc_result r{};
   r.H0 = hamiltonian(r.S0);
 
+  // chronological initial guesses: one slot per term, empty at the start
+  std::vector<ChronoSlot> chrono(nt);
+  if (prm.flags & WL_HMC_CHRONO)
+    for (int i = 0; i < nt; ++i)
+      chrono[i].x = ws_get(L, "hmc_chrono" + std::to_string(i), (prm.terms[i].kind == WL_TERM_KINV_FULL ? 2 : 1) * hb);
+
   std::vector<int> ns(prm.nsteps, prm.nsteps + nt + 1);
   for (const Event& e : merge_schedule(ns, prm.integrator, lam)) {
     const double eps = e.w * prm.tau;
     if (e.kind == 1) {
       launch_link_update(L, P, eps);
     } else if (e.term < nt) {
-      term_force(L, prm.terms[e.term], P, phi[e.term], -eps, &cg_iters);
+      term_force(L, prm.terms[e.term], P, phi[e.term], -eps, &cg_iters,
+                 (prm.flags & WL_HMC_CHRONO) ? &chrono[e.term] : nullptr);
     } else {
       // grad S_G = -(beta/3) Re(i tr(T^a U A)); P -= eps grad S_G
       launch_gauge_force(L, P, eps * prm.beta / 3.0);

@@ -2,7 +2,7 @@
 // full-lattice K = M^dag M (Sec. 2: K is inverted by an iterative solver such
 // as CG; Sec. 3.1: even-odd preconditioning).
 //
-// Textbook CG with x0 = 0; every scalar (alpha, beta, |r|^2, the per-rhs
+// Textbook CG from x0 = 0 (or a given initial guess); every scalar (alpha, beta, |r|^2, the per-rhs
 // convergence flag) lives on the device, so an iteration is five kernels and
 // no host round trip.  The host looks at the state once per chunk of
 // iterations; a converged rhs is frozen on the device (alpha = 0) while the
@@ -83,24 +83,33 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
     norm2_host(L, r64, nrhs, rr_true.data(), nh);
   };
 
-  // ---- initial state: x = 0, r = b, p = r
-  zero_dev(L, x, fb64);
+  // ---- initial state: x = x0 (0 unless given), r = b - A x0, p = r
   norm2_host(L, b, nrhs, bb.data(), nh);
-  if (mixed) launch_convert(L, ip, r, F64, b, nrhs * nh);
-  else copy_dev(L, r, b, fb64);
+  if (prm.use_x0) {
+    for (int i = 0; i < nrhs; ++i)  // a zero source has the zero solution
+      if (bb[i] == 0.0) zero_dev(L, static_cast<char*>(x) + size_t(i) * nh * hb64, nh * hb64);
+    true_residual();
+    if (mixed) launch_convert(L, ip, r, F64, r64, nrhs * nh);
+    else copy_dev(L, r, r64, fb64);
+  } else {
+    zero_dev(L, x, fb64);
+    if (mixed) launch_convert(L, ip, r, F64, b, nrhs * nh);
+    else copy_dev(L, r, b, fb64);
+    for (int i = 0; i < nrhs; ++i) rr_true[i] = bb[i];
+  }
   copy_dev(L, p, r, fbi);
   std::vector<double> hs(CG_NROWS * kMaxRhs, 0.0);
   auto S = [&](int row, int rr) -> double& { return hs[row * kMaxRhs + rr]; };
   std::vector<char> verified(nrhs, 0);
   for (int i = 0; i < nrhs; ++i) {
-    S(CG_RR, i) = bb[i];
+    S(CG_RR, i) = rr_true[i];
     S(CG_BB, i) = bb[i];
     S(CG_TOL2, i) = prm.tol * prm.tol;
-    S(CG_MAXRR, i) = bb[i];
-    if (bb[i] == 0.0) {
+    S(CG_MAXRR, i) = rr_true[i];
+    if (bb[i] == 0.0 || rr_true[i] <= prm.tol * prm.tol * bb[i]) {
       S(CG_DONE, i) = 1.0;
       verified[i] = 1;
-      rr_true[i] = 0.0;
+      if (bb[i] == 0.0) rr_true[i] = 0.0;
     }
   }
   auto push_state = [&]() {
@@ -132,9 +141,10 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   long long hops_per_chunk = 0, hops_p_chunk[3] = {0, 0, 0};
   int chunks = 0;
   int reliable = 0;
-  bool all_verified = false;
+  bool all_verified = true;  // an initial guess can already be a solution
+  for (int i = 0; i < nrhs; ++i) all_verified = all_verified && verified[i];
   bool out_of_iters = false;
-  while (true) {
+  while (!all_verified) {
     if (prm.use_graph && chunks > 0) {
       if (!cg_graph.exec) {
         if (!L->capture_stream) WL_HIP(hipStreamCreateWithFlags(&L->capture_stream, hipStreamNonBlocking));
@@ -286,6 +296,7 @@ int cg_multishift_run(wl_lattice* L, void* x_out, const void* b, double kappa, c
   WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs, WL_EINVAL, "nrhs out of range");
   WL_REQUIRE(nshift >= 1 && nshift * nrhs <= kMaxSys, WL_EINVAL, "nshift * nrhs must be at most 64");
   WL_REQUIRE(shifts, WL_EINVAL, "null shifts");
+  WL_REQUIRE(!prm.use_x0, WL_EUNSUPPORTED, "multi-shift CG shares one Krylov space and starts from x = 0");
   WL_REQUIRE(prm.tol > 0.0 && prm.maxiter > 0, WL_EINVAL, "cg: tol and maxiter must be positive");
   for (int s = 0; s < nshift; ++s) WL_REQUIRE(shifts[s] >= 0.0, WL_EINVAL, "shifts must be non-negative");
   const int chunk = prm.chunk > 0 ? prm.chunk : 8;
@@ -398,6 +409,7 @@ int cg_multishift_run(wl_lattice* L, void* x_out, const void* b, double kappa, c
       rp.tol = std::min(0.5, 0.5 * prm.tol * std::sqrt(bb[i] / rr1[i]));
       rp.maxiter = std::max(prm.maxiter, 10000);
       rp.use_graph = 0;
+      rp.use_x0 = 0;
       char* e = static_cast<char*>(ws_get(L, "ms_e", fb));
       const double mu = shifts[order[s]];
       wl_cg_stats est{};

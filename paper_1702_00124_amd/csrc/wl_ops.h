@@ -74,7 +74,13 @@ void poly_q_roots(const PolyDesc& pd, std::vector<double>& re, std::vector<doubl
 // action terms (action.cpp)
 void term_heatbath(wl_lattice* L, const wl_term& t, void* phi, const void* chi);
 double term_action(wl_lattice* L, const wl_term& t, const void* phi, long long* cg_iters);
-void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, double coeff, long long* cg_iters);
+// chronological initial guess of one term's force solves: the previous solution
+struct ChronoSlot {
+  void* x = nullptr;  // F64 field (full for KINV_FULL)
+  bool valid = false;
+};
+void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, double coeff, long long* cg_iters,
+                ChronoSlot* chrono = nullptr);
 
 // field copies on the context stream
 void copy_dev(wl_lattice* L, void* dst, const void* src, size_t bytes);

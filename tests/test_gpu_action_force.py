@@ -286,3 +286,27 @@ def test_paper_action_trajectory_matches_oracle(action):
     assert abs(res.H0 - r.H0) <= 1e-9 * abs(r.H0)
     assert abs(res.dH - r.dH) <= 1e-7
     assert r.accepted and rel(to_np(lat.get_links()), r.U) <= 1e-10
+
+
+def test_hmc_chronological_guess_matches_cold_start():
+    """WL_HMC_CHRONO: each force solve starts from its term's previous
+    solution.  Same end point as x0 = 0 up to the solver tolerance (1e-13:
+    the forces differ by <= cond * 2e-13), in fewer CG iterations."""
+    say("hmc chronological initial guess")
+    L = (6, 4, 4, 10)
+    terms_g, _, nsteps = _hmc_setup(scale=2)
+    Vh = li.volume(L) // 2
+    P0 = li.gaussian_momenta(L, li.seed_md(3, 15))
+    out = []
+    for chrono in (False, True):
+        lat, U = make_lattice(L)
+        chi = torch.cat([lat.import_spinor(torch.from_numpy(li.gaussian_spinor((Vh, 4, 3), li.seed_md(3, i))))
+                         for i in range(3)])
+        Pb = lat.import_su3(torch.from_numpy(P0))
+        res = lat.hmc_trajectory(terms_g, nsteps, Pb, chi, 0.0, tau=0.3, no_metropolis=True, chrono=chrono)
+        out.append((res.dH, res.cg_iters, to_np(lat.get_links()), to_np(lat.export_su3(Pb))))
+    (dh0, it0, U0, P0g), (dh1, it1, U1, P1g) = out
+    say(f"  dH cold {dh0:.12f} chrono {dh1:.12f}; cg iterations {it0} -> {it1}")
+    assert abs(dh1 - dh0) <= 1e-8
+    assert rel(U1, U0) <= 1e-10 and rel(P1g, P0g) <= 1e-9
+    assert it1 < it0

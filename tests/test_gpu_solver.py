@@ -132,3 +132,83 @@ def test_multishift_refinement_and_edges():
         assert np.abs(xg[1]).max() == 0.0 and st[s][1].converged
     with pytest.raises(Exception):
         lat.cg_multishift(lat.import_spinor(torch.from_numpy(half_noise(L, 1, nrhs=16))), kappa, [0.0] * 5, 16)
+
+
+@pytest.mark.parametrize("inner", ["f64", "bf16"])
+def test_cg_initial_guess(inner):
+    """use_x0: the solution itself as x0 takes no iteration and is kept; a
+    perturbed solution converges to the same tolerance in fewer iterations
+    than x0 = 0; a zero source with a non-zero x0 returns x = 0."""
+    L, kappa, mu2 = (8, 8, 8, 8), 0.155, 0.0
+    say("cg initial guess", inner)
+    lat, U = make_lattice(L)
+    b = half_noise(L, 2101)
+    bg = lat.import_spinor(torch.from_numpy(b))
+    x, st, rc = lat.cg_solve(bg, kappa, "J", mu2=[mu2], params=CG(tol=1e-10, inner=inner))
+    cold = st[0].iters
+    assert rc == 0 and st[0].converged
+    xs = to_np(lat.export_spinor(x))
+    # exact solution as the guess
+    x1 = x.clone()
+    _, st1, rc1 = lat.cg_solve(bg, kappa, "J", mu2=[mu2], params=CG(tol=1e-10, inner=inner, use_x0=True), x=x1)
+    assert rc1 == 0 and st1[0].converged and st1[0].iters == 0
+    assert torch.equal(x1, x)
+    # perturbed guess
+    pert = xs + 1e-4 * np.linalg.norm(xs) / np.sqrt(xs.size) * half_noise(L, 2102)
+    x2 = lat.import_spinor(torch.from_numpy(pert))
+    _, st2, rc2 = lat.cg_solve(bg, kappa, "J", mu2=[mu2], params=CG(tol=1e-10, inner=inner, use_x0=True), x=x2)
+    say(f"  iters cold {cold}, from perturbed guess {st2[0].iters}")
+    assert rc2 == 0 and st2[0].converged and st2[0].true_rel_res <= 1e-10
+    assert 0 < st2[0].iters < cold
+    xg = to_np(lat.export_spinor(x2))
+    assert rel(ow.J(U, xg, L, kappa, mu2), b) <= 1e-10 * 1.01
+    # zero source
+    x3 = x.clone()
+    _, st3, rc3 = lat.cg_solve(lat.new_field("f64").zero_(), kappa, "J", mu2=[mu2],
+                               params=CG(tol=1e-10, inner=inner, use_x0=True), x=x3)
+    assert rc3 == 0 and st3[0].iters == 0 and not torch.any(x3)
+
+
+def test_cg_initial_guess_full_lattice_and_batched():
+    """use_x0 on the full-lattice K and on a 4-rhs batch whose guesses are
+    mixed: exact, perturbed, zero, exact."""
+    L, kappa = (4, 4, 4, 4), 0.12
+    say("cg initial guess, full K and batched J")
+    lat, U = make_lattice(L, a=0.3, seed=1001)
+    b = full_noise(L, 2103)
+    bg = lat.import_full(torch.from_numpy(b))
+    x, st, _ = lat.cg_solve(bg, kappa, "K", params=CG(tol=1e-12))
+    x1 = x.clone()
+    _, st1, rc1 = lat.cg_solve(bg, kappa, "K", params=CG(tol=1e-12, use_x0=True), x=x1)
+    assert rc1 == 0 and st1[0].iters == 0 and torch.equal(x1, x)
+
+    L, kappa = (6, 4, 4, 10), 0.155
+    lat, U = make_lattice(L)
+    bs = [half_noise(L, 2110 + j) for j in range(4)]
+    bg = torch.cat([lat.import_spinor(torch.from_numpy(v)) for v in bs])
+    mu2 = [0.0, 0.01, 0.05, 0.2]
+    x, st, rc = lat.cg_solve(bg, kappa, "J", mu2=mu2, nrhs=4, params=CG(tol=1e-11))
+    assert rc == 0
+    fb = lat.field_bytes("f64")
+    x0 = x.clone()
+    xs1 = to_np(lat.export_spinor(x[fb:2 * fb]))
+    x0[fb:2 * fb] = lat.import_spinor(torch.from_numpy(xs1 + 1e-3 * half_noise(L, 2120)))
+    x0[2 * fb:3 * fb] = 0
+    _, st0, rc0 = lat.cg_solve(bg, kappa, "J", mu2=mu2, nrhs=4, params=CG(tol=1e-11, use_x0=True), x=x0)
+    say(f"  iters cold {[s.iters for s in st]}, guessed {[s.iters for s in st0]}")
+    assert rc0 == 0 and all(s.converged for s in st0)
+    assert st0[0].iters == 0 and st0[3].iters == 0
+    assert 0 < st0[1].iters < st[1].iters and st0[2].iters == st[2].iters
+    assert torch.equal(x0[:fb], x[:fb]) and torch.equal(x0[3 * fb:], x[3 * fb:])
+    for j in range(4):
+        xg = to_np(lat.export_spinor(x0[j * fb:(j + 1) * fb]))
+        assert rel(ow.J(U, xg, L, kappa, mu2[j]), bs[j]) <= 1e-11 * 1.01
+
+
+def test_multishift_rejects_initial_guess():
+    from paper_1702_00124_amd import _lib as W
+    L = (4, 4, 4, 4)
+    lat, U = make_lattice(L)
+    b = lat.import_spinor(torch.from_numpy(half_noise(L, 2130)))
+    with pytest.raises(W.WilsonError):
+        lat.cg_multishift(b, 0.155, [0.0, 0.1], params=CG(use_x0=True))
