@@ -238,10 +238,12 @@ int wl_link_update(wl_lattice* lat, const double* P, double eps);
  * rejection the links are restored.  flags: WL_HMC_NO_METROPOLIS always keeps
  * the end point; WL_HMC_PHI_GIVEN takes chi as the pseudofermions themselves
  * and skips the heatbath (both for reversibility tests); WL_HMC_CHRONO starts
- * every force solve of a term from that term's previous force solution in the
- * trajectory (chronological initial guess: fewer iterations; the trajectory
- * is then reversible only to the solver tolerance, since the reverse run
- * sees other initial guesses). */
+ * every force solve of a term from the chronological guess over that term's
+ * last chrono_depth force solutions in the trajectory: the vector of their
+ * span with the least A-norm error (minimal-residual extrapolation; chrono_depth
+ * extra operator applications per solve).  Fewer iterations; the solutions
+ * still meet the solver tolerance, so the trajectory is reversible to that
+ * tolerance (the reverse run sees other guesses) rather than exactly. */
 enum { WL_HMC_NO_METROPOLIS = 1, WL_HMC_PHI_GIVEN = 2, WL_HMC_CHRONO = 4 };
 enum { WL_INT_LEAPFROG = 0, WL_INT_OMELYAN = 1 };
 
@@ -254,6 +256,7 @@ typedef struct {
   wl_term terms[8];
   int nsteps[9];         /* per term, then the gauge action */
   int flags;
+  int chrono_depth;      /* WL_HMC_CHRONO: solutions kept per term, 1..8 (0 -> 4) */
 } wl_hmc_params;
 
 typedef struct {

@@ -41,7 +41,7 @@ class Term(C.Structure):
 class HmcParams(C.Structure):
     _fields_ = [("beta", C.c_double), ("tau", C.c_double), ("omelyan_lambda", C.c_double),
                 ("integrator", C.c_int), ("nterms", C.c_int), ("terms", Term * 8), ("nsteps", C.c_int * 9),
-                ("flags", C.c_int)]
+                ("flags", C.c_int), ("chrono_depth", C.c_int)]
 
 
 class HmcResult(C.Structure):

@@ -21,7 +21,11 @@
 // with Re(A^dag dM-hat B) = -kappa^2 grad Re(A'^dag D B'),
 //   A' = (A, (D^dag)_oe A),  B' = (B, D_oe B),
 // and Re(L^dag dJ R) = Re((M-hat R)^dag dM-hat L) + Re((M-hat L)^dag dM-hat R).
+#include <algorithm>
 #include <cmath>
+#include <complex>
+#include <functional>
+#include <vector>
 
 #include "wl_ops.h"
 
@@ -53,29 +57,109 @@ void op_w(wl_lattice* L, void* out, const void* in, double kappa, double mu2, in
   launch_caxpby(L, out, one, t, imu, in, 1, 1);
 }
 
-// with a chrono slot, x starts from the slot's previous solution and the
-// new solution is kept there
-void chrono_in(wl_lattice* L, ChronoSlot* ch, void* x, size_t bytes, wl_cg_params& cg) {
-  if (ch && ch->valid) {
-    copy_dev(L, x, ch->x, bytes);
-    cg.use_x0 = 1;
+using ApplyF64 = std::function<void(void* out, const void* in)>;
+
+// Cholesky solve of the m x m Hermitian system G c = r (G row-major, c holds r
+// on entry); false if G is not numerically positive definite.
+bool hpd_solve(int m, std::vector<std::complex<double>>& G, std::vector<std::complex<double>>& c) {
+  for (int j = 0; j < m; ++j) {
+    double d = G[j * m + j].real();
+    for (int k = 0; k < j; ++k) d -= std::norm(G[j * m + k]);
+    if (!(d > 1e-14 * std::abs(G[j * m + j].real()))) return false;
+    d = std::sqrt(d);
+    G[j * m + j] = d;
+    for (int i = j + 1; i < m; ++i) {
+      std::complex<double> s = G[i * m + j];
+      for (int k = 0; k < j; ++k) s -= G[i * m + k] * std::conj(G[j * m + k]);
+      G[i * m + j] = s / d;
+    }
   }
+  for (int i = 0; i < m; ++i) {  // L y = r
+    for (int k = 0; k < i; ++k) c[i] -= G[i * m + k] * c[k];
+    c[i] /= G[i * m + i].real();
+  }
+  for (int i = m - 1; i >= 0; --i) {  // L^dag c = y
+    for (int k = i + 1; k < m; ++k) c[i] -= std::conj(G[k * m + i]) * c[k];
+    c[i] /= G[i * m + i].real();
+  }
+  return true;
 }
-void chrono_out(wl_lattice* L, ChronoSlot* ch, const void* x, size_t bytes) {
-  if (ch) {
-    copy_dev(L, ch->x, x, bytes);
-    ch->valid = true;
+
+// Chronological initial guess (minimal-residual extrapolation): x0 is the
+// vector of the span S of the term's stored solutions that minimises the
+// A-norm of the error, i.e. x0 = V (V^dag A V)^-1 V^dag b with V an
+// orthonormal basis of S (modified Gram-Schmidt, newest solution first;
+// vectors already in the span are dropped).  No stored solution, or a basis
+// whose Gram matrix is not positive definite, leaves x0 = 0.
+void chrono_in(wl_lattice* L, ChronoSlot* ch, void* x, const void* b, const ApplyF64& A, wl_cg_params& cg) {
+  cg.use_x0 = 0;
+  if (!ch || ch->count == 0) return;
+  const size_t fb = ch->fb;
+  const int nh = ch->nh;
+  auto fld = [&](char* base, int i) { return base + size_t(i) * fb; };
+  auto axpy = [&](void* out, std::complex<double> a, const void* y, std::complex<double> bc, const void* z) {
+    double ca[2 * 2], cb[2 * 2];
+    for (int q = 0; q < nh; ++q) {
+      ca[2 * q] = a.real();
+      ca[2 * q + 1] = a.imag();
+      cb[2 * q] = bc.real();
+      cb[2 * q + 1] = bc.imag();
+    }
+    launch_caxpby(L, out, ca, y, z ? cb : nullptr, z, 0, nh);
+  };
+  int m = 0;
+  for (int k = 0; k < ch->count; ++k) {
+    const int j = (ch->next - 1 - k + 2 * ch->depth) % ch->depth;
+    char* v = fld(ch->basis, m);
+    copy_dev(L, v, fld(ch->ring, j), fb);
+    double n0 = 0.0, n1 = 0.0;
+    norm2_host(L, v, 1, &n0, nh);
+    if (!(n0 > 0.0)) continue;
+    for (int i = 0; i < m; ++i) {
+      double c[2];
+      cdot_host(L, fld(ch->basis, i), v, 1, c, nh);
+      axpy(v, 1.0, v, std::complex<double>(-c[0], -c[1]), fld(ch->basis, i));
+    }
+    norm2_host(L, v, 1, &n1, nh);
+    if (!(n1 > 1e-20 * n0)) continue;
+    axpy(v, 1.0 / std::sqrt(n1), v, 0.0, nullptr);
+    ++m;
   }
+  if (m == 0) return;
+  std::vector<std::complex<double>> G(m * m), c(m);
+  for (int j = 0; j < m; ++j) A(fld(ch->abasis, j), fld(ch->basis, j));
+  for (int i = 0; i < m; ++i) {
+    double d[2];
+    for (int j = i; j < m; ++j) {
+      cdot_host(L, fld(ch->basis, i), fld(ch->abasis, j), 1, d, nh);
+      G[i * m + j] = std::complex<double>(d[0], d[1]);
+      G[j * m + i] = std::conj(G[i * m + j]);
+    }
+    G[i * m + i] = G[i * m + i].real();
+    cdot_host(L, fld(ch->basis, i), b, 1, d, nh);
+    c[i] = std::complex<double>(d[0], d[1]);
+  }
+  if (!hpd_solve(m, G, c)) return;
+  axpy(x, c[0], fld(ch->basis, 0), 0.0, nullptr);
+  for (int i = 1; i < m; ++i) axpy(x, 1.0, x, c[i], fld(ch->basis, i));
+  cg.use_x0 = 1;
+}
+
+// keep the new solution, dropping the oldest once depth are stored
+void chrono_out(wl_lattice* L, ChronoSlot* ch, const void* x) {
+  if (!ch) return;
+  copy_dev(L, ch->ring + size_t(ch->next) * ch->fb, x, ch->fb);
+  ch->next = (ch->next + 1) % ch->depth;
+  ch->count = std::min(ch->count + 1, ch->depth);
 }
 
 int solve_j(wl_lattice* L, void* x, const void* b, double kappa, double mu2, const wl_cg_params& cg_in,
             long long* iters, ChronoSlot* ch = nullptr) {
   wl_cg_stats st{};
   wl_cg_params cg = cg_in;
-  cg.use_x0 = 0;
-  chrono_in(L, ch, x, spinor_bytes(F64, L->Vh), cg);
+  chrono_in(L, ch, x, b, [&](void* out, const void* in) { op_j(L, F64, out, in, kappa, &mu2, 1); }, cg);
   const int rc = cg_run(L, x, b, kappa, &mu2, 1, WL_OP_J, cg, &st);
-  chrono_out(L, ch, x, spinor_bytes(F64, L->Vh));
+  chrono_out(L, ch, x);
   if (iters) *iters += st.iters;
   WL_REQUIRE(rc == WL_OK, rc, "inner CG did not converge");
   return rc;
@@ -87,10 +171,9 @@ void solve_poly(wl_lattice* L, void* x, const void* b, const wl_term& t, int mod
   const PolyDesc pd = pdesc(t);
   auto apply = [&](Prec pr, void* out, const void* in) { poly_apply(L, mode, out, in, t.kappa, t.mu2, pd, pr); };
   wl_cg_params cg = t.cg;
-  cg.use_x0 = 0;
-  chrono_in(L, ch, x, spinor_bytes(F64, L->Vh), cg);
+  chrono_in(L, ch, x, b, [&](void* out, const void* in) { apply(F64, out, in); }, cg);
   const int rc = cg_run_generic(L, x, b, apply, cg, &st);
-  chrono_out(L, ch, x, spinor_bytes(F64, L->Vh));
+  chrono_out(L, ch, x);
   if (iters) *iters += st.iters;
   WL_REQUIRE(rc == WL_OK, rc, "polynomial CG did not converge");
 }
@@ -230,10 +313,10 @@ void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, dou
       char* y = static_cast<char*>(ws_get(L, "fo_yf", 2 * fb));
       wl_cg_stats st{};
       wl_cg_params cg = t.cg;
-      cg.use_x0 = 0;
-      chrono_in(L, ch, x, 2 * fb, cg);
+      chrono_in(L, ch, x, phi, [&](void* out, const void* in) { op_k_full(L, F64, out, in, t.kappa, DotOut()); },
+                cg);
       const int rc = cg_run(L, x, phi, t.kappa, nullptr, 1, WL_OP_K, cg, &st);
-      chrono_out(L, ch, x, 2 * fb);
+      chrono_out(L, ch, x);
       if (iters) *iters += st.iters;
       WL_REQUIRE(rc == WL_OK, rc, "inner CG did not converge");
       op_m_full(L, F64, y, x, t.kappa, 0);

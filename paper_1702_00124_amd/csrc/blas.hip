@@ -13,6 +13,11 @@ namespace wl {
 
 int blas_blocks(const wl_lattice* L) { return site_blocks(L->Vh); }
 
+// block of an elementwise site kernel in the same XCD-contiguous order, so
+// that each XCD touches the site range it handles in the hop kernels; the
+// per-block partial sums are indexed by it too (same order, same sums)
+__device__ __forceinline__ int site_block() { return xcd_block(blockIdx.x, gridDim.x); }
+
 // ------------------------------------------------------------------ CG update
 // fields are indexed f = rhs * nh + half (nh = 2 for full-lattice fields)
 template <typename P>
@@ -23,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, double* x64, c
   __shared__ double lds[kBlock / 64];
   const int f = blockIdx.y;
   const int rhs = f / nh;
-  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int h = site_block() * kBlock + threadIdx.x;
   const int Vh = g.Vh;
   const double alpha = st[CG_ALPHA * kMaxRhs + rhs];
   const bool done = st[CG_DONE * kMaxRhs + rhs] != 0.0;
@@ -48,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, double* x64, c
     for (int k = 0; k < 12; ++k) part += double(rv.c[k].r) * double(rv.c[k].r) + double(rv.c[k].i) * double(rv.c[k].i);
   }
   const double s = block_sum(part, lds);
-  if (threadIdx.x == 0) partials[rhs * pstride + (f % nh) * gridDim.x + blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[rhs * pstride + (f % nh) * gridDim.x + site_block()] = s;
 }
 
 template <typename P>
@@ -57,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void cg_xpay_kernel(Geo g, char* p, const c
   using R = typename P::real;
   const int f = blockIdx.y;
   const int rhs = f / nh;
-  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int h = site_block() * kBlock + threadIdx.x;
   const int Vh = g.Vh;
   if (h >= Vh || st[CG_DONE * kMaxRhs + rhs] != 0.0) return;
   const R beta = R(st[CG_BETA * kMaxRhs + rhs]);
@@ -73,7 +78,7 @@ template <typename PD, typename PS>
 __global__ __launch_bounds__(kBlock) void convert_kernel(Geo g, char* dst, size_t dstride, const char* src,
                                                         size_t sstride) {
   const int rhs = blockIdx.y;
-  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int h = site_block() * kBlock + threadIdx.x;
   if (h >= g.Vh) return;
   const auto s = SpinorIO<PS>::load(src + rhs * sstride, h, g.Vh);
   Spinor<typename PD::real> d;
@@ -92,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void caxpby_kernel(Geo g, char* out, const 
                                                        size_t stride, CaxpbyArgs c) {
   using R = typename P::real;
   const int rhs = blockIdx.y;
-  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int h = site_block() * kBlock + threadIdx.x;
   if (h >= g.Vh) return;
   const size_t off = rhs * stride;
   const cplx<R> ca = {R(c.a[2 * rhs]), R(c.a[2 * rhs + 1])};
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(Geo g, const char* x, const
   using R = typename P::real;
   __shared__ double lds[kBlock / 64];
   const int rhs = blockIdx.y;
-  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int h = site_block() * kBlock + threadIdx.x;
   const size_t off = rhs * stride;
   double re = 0.0, im = 0.0;
   if (h < g.Vh) {
@@ -144,11 +149,11 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(Geo g, const char* x, const
   if (cdot) {
     const double si = block_sum(im, lds);
     if (threadIdx.x == 0) {
-      partials[(2 * rhs) * pstride + blockIdx.x] = sr;
-      partials[(2 * rhs + 1) * pstride + blockIdx.x] = si;
+      partials[(2 * rhs) * pstride + site_block()] = sr;
+      partials[(2 * rhs + 1) * pstride + site_block()] = si;
     }
   } else if (threadIdx.x == 0) {
-    partials[rhs * pstride + blockIdx.x] = sr;
+    partials[rhs * pstride + site_block()] = sr;
   }
 }
 
@@ -254,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void ms_update_kernel(Geo g, char* r, const
                                                           int nrhs, int nshift, double* partials, int pstride) {
   __shared__ double lds[kBlock / 64];
   const int rhs = blockIdx.y;
-  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int h = site_block() * kBlock + threadIdx.x;
   const int Vh = g.Vh;
   const double alpha = st[CG_ALPHA * kMaxRhs + rhs];
   double part = 0.0;
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void ms_update_kernel(Geo g, char* r, const
     }
   }
   const double sum = block_sum(part, lds);
-  if (threadIdx.x == 0) partials[rhs * pstride + blockIdx.x] = sum;
+  if (threadIdx.x == 0) partials[rhs * pstride + site_block()] = sum;
 }
 
 // p_s = zeta_{i+1} r + beta_i (zeta_{i+1} / zeta_i)^2 p_s for every unfrozen system
@@ -288,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void ms_xpay_kernel(Geo g, char* p, const c
                                                         const double* ms, size_t stride, int nrhs) {
   const int q = blockIdx.y;
   const int rhs = q % nrhs;
-  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int h = site_block() * kBlock + threadIdx.x;
   const int Vh = g.Vh;
   if (h >= Vh || ms[MS_ASHIFT * kMaxSys + q] == 0.0) return;
   const double zn = ms[MS_ZNEXT * kMaxSys + q], zc = ms[MS_ZCUR * kMaxSys + q];
@@ -310,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(Geo g, const char* t,
                                                           const char* e, char* eprev, size_t stride, double ct,
                                                           double cw, double ce) {
   using R = typename P::real;
-  const int h = blockIdx.x * kBlock + threadIdx.x;
+  const int h = site_block() * kBlock + threadIdx.x;
   if (h >= g.Vh) return;
   const size_t off = blockIdx.y * stride;
   const Spinor<R> tv = SpinorIO<P>::load(t + off, h, g.Vh);

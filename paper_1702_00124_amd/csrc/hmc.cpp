@@ -137,9 +137,20 @@ int hmc_run(wl_lattice* L, const wl_hmc_params& prm, double* P, const void* chi,
 
   // chronological initial guesses: one slot per term, empty at the start
   std::vector<ChronoSlot> chrono(nt);
-  if (prm.flags & WL_HMC_CHRONO)
-    for (int i = 0; i < nt; ++i)
-      chrono[i].x = ws_get(L, "hmc_chrono" + std::to_string(i), (prm.terms[i].kind == WL_TERM_KINV_FULL ? 2 : 1) * hb);
+  if (prm.flags & WL_HMC_CHRONO) {
+    const int depth = prm.chrono_depth > 0 ? prm.chrono_depth : 4;
+    WL_REQUIRE(depth <= 8, WL_EINVAL, "chrono_depth must be at most 8");
+    for (int i = 0; i < nt; ++i) {
+      ChronoSlot& c = chrono[i];
+      c.nh = prm.terms[i].kind == WL_TERM_KINV_FULL ? 2 : 1;
+      c.fb = c.nh * hb;
+      c.depth = depth;
+      char* buf = static_cast<char*>(ws_get(L, "hmc_chrono" + std::to_string(i), 3 * size_t(depth) * c.fb));
+      c.ring = buf;
+      c.basis = buf + size_t(depth) * c.fb;
+      c.abasis = buf + 2 * size_t(depth) * c.fb;
+    }
+  }
 
   std::vector<int> ns(prm.nsteps, prm.nsteps + nt + 1);
   for (const Event& e : merge_schedule(ns, prm.integrator, lam)) {

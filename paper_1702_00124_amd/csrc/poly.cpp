@@ -69,13 +69,15 @@ static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, doubl
   const double a = pd.a, b = pd.b;
   const double y0 = (b + a) / (b - a);
   const double ct = 2.0 * (b + a) / (b - a), cw = -4.0 / (b - a);
-  // t0 = in, t1 = y(J) in, e0 = 0, e1 = in
-  copy_dev(L, tA, in, fb);
+  // t0 = in, t1 = y(J) in, e0 = 0, e1 = in (copies by the site kernels, in
+  // their XCD order)
+  const double one[2] = {1.0, 0.0};
+  launch_caxpby(L, tA, one, in, nullptr, nullptr, 0, 1, pr);
   op_j(L, pr, w, in, kappa, &mu2, 1);
   const double c1[2] = {(b + a) / (b - a), 0.0}, c2[2] = {-2.0 / (b - a), 0.0};
   launch_caxpby(L, tB, c1, in, c2, w, 0, 1, pr);
-  zero_dev(L, eA, fb);
-  copy_dev(L, eB, in, fb);
+  launch_caxpby(L, eA, nullptr, nullptr, nullptr, nullptr, 0, 1, pr);  // zero
+  launch_caxpby(L, eB, one, in, nullptr, nullptr, 0, 1, pr);
   for (int m = 1; m <= pd.n; ++m) {
     if (m < pd.n) {
       // J t_m and the step in one pass: tA <- t_{m+1}, eA <- e_{m+1}

@@ -74,10 +74,16 @@ void poly_q_roots(const PolyDesc& pd, std::vector<double>& re, std::vector<doubl
 // action terms (action.cpp)
 void term_heatbath(wl_lattice* L, const wl_term& t, void* phi, const void* chi);
 double term_action(wl_lattice* L, const wl_term& t, const void* phi, long long* cg_iters);
-// chronological initial guess of one term's force solves: the previous solution
+// chronological initial guess of one term's force solves: the last `depth`
+// solutions of the term, and scratch for the minimal-residual extrapolation
+// over their span (three blocks of depth F64 fields, both halves for KINV_FULL)
 struct ChronoSlot {
-  void* x = nullptr;  // F64 field (full for KINV_FULL)
-  bool valid = false;
+  char* ring = nullptr;    // previous solutions; ring[next] is overwritten next
+  char* basis = nullptr;   // orthonormal basis of their span
+  char* abasis = nullptr;  // the solve's operator applied to the basis
+  size_t fb = 0;           // bytes of one field
+  int nh = 1;              // halves per field
+  int depth = 0, count = 0, next = 0;
 };
 void term_force(wl_lattice* L, const wl_term& t, double* F, const void* phi, double coeff, long long* cg_iters,
                 ChronoSlot* chrono = nullptr);

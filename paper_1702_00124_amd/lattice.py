@@ -316,7 +316,7 @@ class WilsonLattice:
     def hmc_trajectory(self, terms: List[Term], nsteps: Sequence[int], P: torch.Tensor, chi: torch.Tensor,
                        u: float, beta: float = 5.6, tau: float = 1.0, integrator: str = "omelyan",
                        no_metropolis: bool = False, omelyan_lambda: float = 0.0,
-                       phi_given: bool = False, chrono: bool = False) -> W.HmcResult:
+                       phi_given: bool = False, chrono: bool = False, chrono_depth: int = 0) -> W.HmcResult:
         prm = W.HmcParams()
         prm.beta, prm.tau, prm.omelyan_lambda = beta, tau, omelyan_lambda
         prm.integrator = W.WL_INT_OMELYAN if integrator == "omelyan" else W.WL_INT_LEAPFROG
@@ -327,6 +327,7 @@ class WilsonLattice:
             prm.nsteps[i] = int(n)
         prm.flags = ((W.WL_HMC_NO_METROPOLIS if no_metropolis else 0) | (W.WL_HMC_PHI_GIVEN if phi_given else 0)
                      | (W.WL_HMC_CHRONO if chrono else 0))
+        prm.chrono_depth = int(chrono_depth)
         _need(P, 256 * self.V, "momenta")
         _need(chi, sum(self.field_bytes("f64") * (2 if t.full else 1) for t in terms), "noise")
         res = W.HmcResult()

@@ -182,8 +182,11 @@ def _hmc_setup(scale=1):
     return terms_g, terms_o, nsteps
 
 
-def test_hmc_trajectory_matches_oracle():
-    say("hmc trajectory 4^4 vs oracle")
+@pytest.mark.parametrize("chrono", [False, True])
+def test_hmc_trajectory_matches_oracle(chrono):
+    """The oracle solves from x0 = 0; the chronological guesses reach the same
+    tolerance, so the bounds hold for both."""
+    say("hmc trajectory 4^4 vs oracle, chrono", chrono)
     lat, U = make_lattice(L4)
     terms_g, terms_o, nsteps = _hmc_setup()
     P = li.gaussian_momenta(L4, li.seed_md(0, 15))
@@ -192,7 +195,7 @@ def test_hmc_trajectory_matches_oracle():
     chi_b = torch.cat([lat.import_spinor(torch.from_numpy(c)) for c in chis])
     Pb = lat.import_su3(torch.from_numpy(P))
     res = lat.hmc_trajectory(terms_g, nsteps, Pb, chi_b, 0.5, beta=5.6, tau=0.2, integrator="omelyan",
-                             no_metropolis=True)
+                             no_metropolis=True, chrono=chrono)
     prm = ohmc.HMCParams(terms=terms_o, beta=5.6, nsteps=nsteps, scheme="omelyan", tau=0.2)
     r = ohmc.trajectory(U, P, L4, prm, chis, 0.5)
     say(f"  dH gpu {res.dH:.10f} oracle {r.dH:.10f}; n_kmat {res.n_kmat}")
@@ -288,11 +291,13 @@ def test_paper_action_trajectory_matches_oracle(action):
     assert r.accepted and rel(to_np(lat.get_links()), r.U) <= 1e-10
 
 
-def test_hmc_chronological_guess_matches_cold_start():
-    """WL_HMC_CHRONO: each force solve starts from its term's previous
-    solution.  Same end point as x0 = 0 up to the solver tolerance (1e-13:
-    the forces differ by <= cond * 2e-13), in fewer CG iterations."""
-    say("hmc chronological initial guess")
+@pytest.mark.parametrize("depth", [1, 4])
+def test_hmc_chronological_guess_matches_cold_start(depth):
+    """WL_HMC_CHRONO: each force solve starts from the minimal-residual
+    extrapolation over its term's last `depth` solutions.  Same end point as
+    x0 = 0 up to the solver tolerance (1e-13: the forces differ by <= cond *
+    2e-13), in fewer CG iterations."""
+    say("hmc chronological initial guess, depth", depth)
     L = (6, 4, 4, 10)
     terms_g, _, nsteps = _hmc_setup(scale=2)
     Vh = li.volume(L) // 2
@@ -303,10 +308,51 @@ def test_hmc_chronological_guess_matches_cold_start():
         chi = torch.cat([lat.import_spinor(torch.from_numpy(li.gaussian_spinor((Vh, 4, 3), li.seed_md(3, i))))
                          for i in range(3)])
         Pb = lat.import_su3(torch.from_numpy(P0))
-        res = lat.hmc_trajectory(terms_g, nsteps, Pb, chi, 0.0, tau=0.3, no_metropolis=True, chrono=chrono)
+        res = lat.hmc_trajectory(terms_g, nsteps, Pb, chi, 0.0, tau=0.3, no_metropolis=True, chrono=chrono,
+                                 chrono_depth=depth)
         out.append((res.dH, res.cg_iters, to_np(lat.get_links()), to_np(lat.export_su3(Pb))))
     (dh0, it0, U0, P0g), (dh1, it1, U1, P1g) = out
     say(f"  dH cold {dh0:.12f} chrono {dh1:.12f}; cg iterations {it0} -> {it1}")
     assert abs(dh1 - dh0) <= 1e-8
     assert rel(U1, U0) <= 1e-10 and rel(P1g, P0g) <= 1e-9
     assert it1 < it0
+
+
+def test_hmc_chronological_guess_reversible_to_tolerance():
+    """Forward, flip P, backward with chronological guesses (each direction
+    with its own history): back at the start to the solver tolerance."""
+    say("hmc reversibility with chronological guesses")
+    L = (6, 4, 4, 10)
+    lat, U = make_lattice(L)
+    terms_g, _, nsteps = _hmc_setup()
+    Vh = li.volume(L) // 2
+    chis = [li.gaussian_spinor((Vh, 4, 3), li.seed_md(1, i)) for i in range(3)]
+    phis = torch.cat([lat.heatbath(t, lat.import_spinor(torch.from_numpy(c))) for t, c in zip(terms_g, chis)])
+    P0 = li.gaussian_momenta(L, li.seed_md(1, 15))
+    Pb = lat.import_su3(torch.from_numpy(P0))
+    kw = dict(tau=0.3, no_metropolis=True, phi_given=True, chrono=True)
+    lat.hmc_trajectory(terms_g, nsteps, Pb, phis, 0.0, **kw)
+    Pb.neg_()
+    lat.hmc_trajectory(terms_g, nsteps, Pb, phis, 0.0, **kw)
+    dU = np.abs(to_np(lat.get_links()) - U).max()
+    dP = np.abs(to_np(lat.export_su3(Pb)) + P0).max()
+    say(f"  max |dU| {dU:.2e}  max |dP| {dP:.2e}")
+    assert dU < 1e-10 and dP < 1e-8
+
+
+def test_hmc_chronological_guess_full_lattice_term():
+    """The chronological guess on the full-lattice two-flavour term (both
+    halves of each stored solution): same end point as x0 = 0."""
+    say("hmc chronological guess, KINV_FULL")
+    terms_g = [Term("KINV_FULL", 0.12, cg=CG(tol=1e-13))]
+    P0 = li.gaussian_momenta(L4, li.seed_md(4, 15))
+    out = []
+    for chrono in (False, True):
+        lat, U = make_lattice(L4, a=0.3, seed=1001)
+        chi = lat.import_full(torch.from_numpy(full_noise(L4, 2201)))
+        Pb = lat.import_su3(torch.from_numpy(P0))
+        res = lat.hmc_trajectory(terms_g, [6, 12], Pb, chi, 0.0, tau=0.5, no_metropolis=True, chrono=chrono)
+        out.append((res.dH, res.cg_iters, to_np(lat.get_links())))
+    say(f"  dH {out[0][0]:.12f} / {out[1][0]:.12f}; cg iterations {out[0][1]} -> {out[1][1]}")
+    assert abs(out[1][0] - out[0][0]) <= 1e-8 and rel(out[1][2], out[0][2]) <= 1e-10
+    assert out[1][1] < out[0][1]
