@@ -289,6 +289,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--quick", action="store_true", help="skip the CG comparison legs")
+    ap.add_argument("--cg-graph", action="store_true",
+                    help="the trajectory's solves replay each chunk of CG iterations as a captured HIP graph")
     ap.add_argument("--md-steps", default=",".join(map(str, NSTEPS)),
                     help="integrator steps per scale (poly, poly-K inverse, ratio, gauge); profiling runs shorten them")
     ap.add_argument("--kernels-only", action="store_true",
@@ -336,7 +338,7 @@ def main():
     log("hop configurations kept (variant, npass, use_xcd, stream) for 1, 2-4, 5-16 rhs:",
         {p: [lat.hop_config(p, k) for k in range(3)] for p in ("f64", "f32", "bf16")})
 
-    cg_md = CG(tol=1e-10, inner="f32", chunk=8)
+    cg_md = CG(tol=1e-10, inner="f32", chunk=8, use_graph=args.cg_graph)
     terms = [Term("POLY", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_md),
              Term("POLYK_INV", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_md),
              Term("RATIO", KAPPA, mu2_num=MU2_HASENBUSCH, cg=cg_md)]

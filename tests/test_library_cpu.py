@@ -90,3 +90,29 @@ def test_library_schedule_matches_oracle(kind):
             assert a[1] == b[1] and abs(a[2] - float(b[2])) < 1e-15
         else:
             assert abs(a[1] - float(b[1])) < 1e-15
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every ctypes struct of the binding has the header struct's size and
+    member offsets (a C probe compiled against the header prints them)."""
+    from paper_1702_00124_amd import _lib as W
+    structs = {"wl_cg_params": W.CgParams, "wl_cg_stats": W.CgStats, "wl_poly": W.Poly, "wl_term": W.Term,
+               "wl_hmc_params": W.HmcParams, "wl_hmc_result": W.HmcResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "wilson_hmc.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
