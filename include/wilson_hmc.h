@@ -271,6 +271,32 @@ typedef struct {
 int hmc_trajectory(wl_lattice* lat, const wl_hmc_params* params, double* P, const void* chi,
                    double u_metropolis, wl_hmc_result* result);
 
+/* Mixed-volume batches: several lattices (different extents, links and kappa;
+ * one device and one stream) whose hops run as ONE persistent launch, with the
+ * even-odd J and a CG over the batch on top (the multi-rhs CG of Sec. 2 with
+ * one system per lattice).  The batch keeps pointers to the lattices: destroy
+ * it before them.  A batch field is nlat slots of wl_batch_slot_bytes each;
+ * slot l holds lattice l's internal even-site field (as wl_import_spinor
+ * writes it) followed by zeros: allocate batch fields zeroed, the library only
+ * writes the lattices' own sites.  Calls run on the lattices' stream, use the
+ * largest lattice's workspace and CG state, and synchronise like their
+ * single-lattice counterparts; batch hops are not counted by wl_hop_counts.
+ * WL_EINVAL for nlat outside 1..8 or lattices on other devices or streams. */
+typedef struct wl_batch wl_batch;
+int wl_batch_create(wl_batch** out, wl_lattice* const* lats, int nlat);
+int wl_batch_destroy(wl_batch* batch);
+int wl_batch_slot_bytes(const wl_batch* batch, wl_prec prec, size_t* bytes);
+/* slot l of out = D_{p,1-p} (dagger: its adjoint) of slot l of in, every
+ * lattice in one launch (p = out_parity) */
+int wl_batch_dslash(wl_batch* batch, void* out, const void* in, int out_parity, int dagger, wl_prec prec);
+/* slot l of out = (K-hat(kappa[l]) + mu2[l]) slot l of in (mu2 may be NULL) */
+int wl_batch_apply_J(wl_batch* batch, void* out, const void* in, const double* kappa, const double* mu2,
+                     wl_prec prec);
+/* CG on every slot's J as in cg_solve (params.inner, reliable updates, graph
+ * chunks, use_x0 = 0 only): stats[nlat]; WL_ENOCONV if some lattice misses tol. */
+int wl_batch_cg_solve(wl_batch* batch, void* x, const void* b, const double* kappa, const double* mu2,
+                      const wl_cg_params* params, wl_cg_stats* stats);
+
 /* The overlaid schedule used by hmc_trajectory (Sec. 3.2), host only, no
  * device needed: nscales schemes with nsteps[i] steps; event k is
  * kinds[k] = 0 (S update of scale terms[k], step weights[k] tau) or 1 (T step

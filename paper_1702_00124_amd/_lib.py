@@ -80,6 +80,12 @@ SIGNATURES = {
     "wl_link_update": (I, [P, P, D]),
     "hmc_trajectory": (I, [P, C.POINTER(HmcParams), P, P, D, C.POINTER(HmcResult)]),
     "wl_counters": (I, [P, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+    "wl_batch_create": (I, [C.POINTER(P), C.POINTER(P), I]),
+    "wl_batch_destroy": (I, [P]),
+    "wl_batch_slot_bytes": (I, [P, I, C.POINTER(SZ)]),
+    "wl_batch_dslash": (I, [P, P, P, I, I, I]),
+    "wl_batch_apply_J": (I, [P, P, P, C.POINTER(D), C.POINTER(D), I]),
+    "wl_batch_cg_solve": (I, [P, P, P, C.POINTER(D), C.POINTER(D), C.POINTER(CgParams), C.POINTER(CgStats)]),
     "wl_integrator_schedule": (I, [C.POINTER(I), I, I, D, C.POINTER(I), C.POINTER(I), C.POINTER(D), I,
                                    C.POINTER(I)]),
     "wl_profile": (I, [P, I]),

@@ -653,6 +653,61 @@ int wl_integrator_schedule(const int* nsteps, int nscales, int scheme, double la
   });
 }
 
+int wl_batch_create(wl_batch** out, wl_lattice* const* lats, int nlat) {
+  return guard([&]() {
+    WL_REQUIRE(out, WL_EINVAL, "null argument");
+    *out = nullptr;
+    *out = batch_create(lats, nlat);
+    return WL_OK;
+  });
+}
+
+int wl_batch_destroy(wl_batch* B) {
+  batch_destroy(B);
+  return WL_OK;
+}
+
+int wl_batch_slot_bytes(const wl_batch* B, wl_prec prec, size_t* bytes) {
+  return guard([&]() {
+    WL_REQUIRE(B && bytes, WL_EINVAL, "null argument");
+    WL_REQUIRE(prec >= WL_F64 && prec <= WL_BF16, WL_EINVAL, "unknown precision");
+    *bytes = batch_slot_bytes(B, Prec(prec));
+    return WL_OK;
+  });
+}
+
+int wl_batch_dslash(wl_batch* B, void* out, const void* in, int out_parity, int dagger, wl_prec prec) {
+  return guard([&]() {
+    WL_REQUIRE(B && out && in && out != in, WL_EINVAL, "null or aliased argument");
+    WL_REQUIRE(out_parity == 0 || out_parity == 1, WL_EINVAL, "parity must be 0 or 1");
+    WL_REQUIRE(prec >= WL_F64 && prec <= WL_BF16, WL_EINVAL, "unknown precision");
+    set_device(batch_big(B));
+    batch_hop(B, Prec(prec), out, in, out_parity, dagger ? 1 : 0);
+    return WL_OK;
+  });
+}
+
+int wl_batch_apply_J(wl_batch* B, void* out, const void* in, const double* kappa, const double* mu2, wl_prec prec) {
+  return guard([&]() {
+    WL_REQUIRE(B && out && in && kappa && out != in, WL_EINVAL, "null or aliased argument");
+    WL_REQUIRE(prec >= WL_F64 && prec <= WL_BF16, WL_EINVAL, "unknown precision");
+    set_device(batch_big(B));
+    batch_prepare(B, Prec(prec));
+    batch_j(B, Prec(prec), out, in, kappa, mu2, DotOut());
+    return WL_OK;
+  });
+}
+
+int wl_batch_cg_solve(wl_batch* B, void* x, const void* b, const double* kappa, const double* mu2,
+                      const wl_cg_params* params, wl_cg_stats* stats) {
+  return guard([&]() {
+    WL_REQUIRE(B && x && b && kappa && params && x != b, WL_EINVAL, "null or aliased argument");
+    WL_REQUIRE(!params->use_x0, WL_EUNSUPPORTED, "batch CG starts from x = 0");
+    set_device(batch_big(B));
+    return batch_cg(B, x, b, kappa, mu2, *params, stats);
+  });
+}
+
 int wl_counters(const wl_lattice* L, long long* n_hop, long long* n_kmat) {
   return guard([&]() {
     check_lat(L);

@@ -11,6 +11,8 @@
 // product and rebuilt after it.  The stencil is HBM-bound (about 0.9 flop per
 // byte in FP64), so the kernel is written for coalesced 16-byte loads and an
 // L2-friendly, XCD-aware tile order; no MFMA.
+#include <algorithm>
+
 #include "wl_internal.h"
 
 namespace wl {
@@ -455,6 +457,181 @@ static void dispatch(const HopArgs& a, int dagger, int nrhs, hipStream_t st, con
     if (dagger) dispatch_nr<P, 1, false>(a, nrhs, st, c);
     else dispatch_nr<P, 0, false>(a, nrhs, st, c);
   }
+}
+
+// ------------------------------------------------------------------ mixed-volume batch
+// One launch over the hops of several lattices of different volumes (one rhs
+// each; its own geometry, links, fields and epilogue).  Lattice l owns tiles
+// [tile0[l], tile0[l + 1]) of the batch's tile range.  Fields are tiled by 64
+// sites, so a site's address does not depend on the lattice's extent and each
+// lattice's fields can sit in equal slots sized for the largest lattice.
+// Persistent: the grid holds at most the workgroups resident at once, each
+// walking the tile range with stride gridDim.x.
+struct BatchDesc {
+  Geo g;
+  int parity;
+  const char* links;
+  const char* in;
+  char* out;
+  const char* x;  // epilogue: out = g5^g5 (cx x + a hop) + by y
+  const char* y;
+  double cx, a, by;
+  int g5;
+  int dot;  // 1: Re<dotv, out> partial sums into partials[tile], zero up to part_len
+  const char* dotv;
+  double* partials;
+};
+struct BatchArgs {
+  BatchDesc d[kMaxBatch];
+  int tile0[kMaxBatch + 1];
+  int nlat;
+  int part_len;
+};
+
+// one wavefront's direction of a batch tile: link, neighbour, projected product into LDS
+template <typename P, int MU, int FWD, int DAG>
+__device__ __forceinline__ void dp_dir(const HopArgs& a, const Coord& c, int h, cplx<typename P::real>* W, int lane) {
+  SU3<typename P::real> U;
+  int hn = 0;
+  typename P::real ph;
+  dp_link<P, MU, FWD, false>(a, c, h, &U, &hn, &ph);
+  dp_spin<P, MU, FWD, DAG, 1>(a, U, hn, ph, 0, W, lane);
+}
+
+template <typename P, int DAG>
+__global__ __launch_bounds__(kDpThreads) void hop_dp_batch_kernel(BatchArgs ba) {
+  using R = typename P::real;
+  using UIO = UnitIO<P>;
+  __shared__ cplx<R> W[8 * 6 * kDpSites];
+  __shared__ double red[kDpThreads / 64];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  // each row of partial sums is summed whole: clear what the lattice's tiles leave
+  for (int l = blockIdx.x; l < ba.nlat; l += gridDim.x)
+    if (ba.d[l].dot)
+      for (int i = ba.tile0[l + 1] - ba.tile0[l] + int(threadIdx.x); i < ba.part_len; i += kDpThreads)
+        ba.d[l].partials[i] = 0.0;
+  const int total = ba.tile0[ba.nlat];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int l = 0;
+    while (l + 1 < ba.nlat && t >= ba.tile0[l + 1]) ++l;
+    const BatchDesc& d = ba.d[l];
+    HopArgs a;  // the fields the direction helpers read
+    a.g = d.g;
+    a.parity = d.parity;
+    a.links = d.links;
+    a.in = d.in;
+    a.rhs_stride = 0;
+    const int tile = t - ba.tile0[l];
+    const int h = tile * kDpSites + lane;
+    const int Vh = d.g.Vh;
+    const bool active = h < Vh;
+    if (active) {
+      const Coord c = site_coords(a.g, h, a.parity);
+      switch (wv) {
+        case 0: dp_dir<P, 0, 1, DAG>(a, c, h, W, lane); break;
+        case 1: dp_dir<P, 0, 0, DAG>(a, c, h, W, lane); break;
+        case 2: dp_dir<P, 1, 1, DAG>(a, c, h, W, lane); break;
+        case 3: dp_dir<P, 1, 0, DAG>(a, c, h, W, lane); break;
+        case 4: dp_dir<P, 2, 1, DAG>(a, c, h, W, lane); break;
+        case 5: dp_dir<P, 2, 0, DAG>(a, c, h, W, lane); break;
+        case 6: dp_dir<P, 3, 1, DAG>(a, c, h, W, lane); break;
+        default: dp_dir<P, 3, 0, DAG>(a, c, h, W, lane); break;
+      }
+    }
+    __syncthreads();
+    double part = 0.0;
+    if (active) {
+      const R ca = R(d.a), cx = R(d.cx), cy = R(d.by);
+      for (int u = wv; u < UIO::NU; u += 8) {
+        cplx<R> o[UIO::CPU], xv[UIO::CPU], yv[UIO::CPU];
+        if (d.x) UIO::load(d.x, u, h, Vh, xv);
+        if (d.y) UIO::load(d.y, u, h, Vh, yv);
+#pragma unroll
+        for (int q = 0; q < UIO::CPU; ++q) {
+          const int comp = u * UIO::CPU + q;
+          const int sp = comp / 3;
+          o[q] = ca * dp_recon<DAG>(W, sp, comp - 3 * sp, lane);
+          if (d.x) o[q] = o[q] + cx * xv[q];
+          if (d.g5 && sp >= 2) o[q] = R(-1) * o[q];
+          if (d.y) o[q] = o[q] + cy * yv[q];
+        }
+        UIO::store(d.out, u, h, Vh, o);
+        if (d.dot) {
+          cplx<R> dv[UIO::CPU];
+          UIO::load(d.dotv, u, h, Vh, dv);
+#pragma unroll
+          for (int q = 0; q < UIO::CPU; ++q) part += double(dv[q].r) * double(o[q].r) + double(dv[q].i) * double(o[q].i);
+        }
+      }
+    }
+    if (d.dot) {
+      const double sum = block_sum(part, red);
+      if (threadIdx.x == 0) d.partials[tile] = sum;
+    }
+    __syncthreads();  // W and red are rewritten by the next tile
+  }
+}
+
+template <typename P, int DAG>
+static int batch_grid(int total) {
+  // workgroups resident at once on the whole device (cached per instantiation)
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, cus = 0, per_cu = 0;
+    WL_HIP(hipGetDevice(&dev));
+    WL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    WL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hop_dp_batch_kernel<P, DAG>, kDpThreads, 0));
+    resident = std::max(1, cus * per_cu);
+  }
+  return std::min(total, resident);
+}
+
+void launch_hop_batch(hipStream_t st, Prec prec, int out_parity, int dagger, const BatchHop* hops, int nlat,
+                      int part_len) {
+  WL_REQUIRE(nlat >= 1 && nlat <= kMaxBatch, WL_EINVAL, "batch: 1 to 8 lattices");
+  BatchArgs ba{};
+  ba.nlat = nlat;
+  ba.part_len = part_len;
+  ba.tile0[0] = 0;
+  for (int l = 0; l < nlat; ++l) {
+    const BatchHop& b = hops[l];
+    wl_lattice* L = b.L;
+    WL_REQUIRE(b.out != b.in, WL_EINVAL, "hop output must not alias its input");
+    WL_REQUIRE(!b.e.dot || (b.e.dot == 1 && b.e.partials && hop_tiles(L, prec) <= part_len), WL_EINVAL,
+               "batch: dot partials need a row of at least the lattice's tiles");
+    ensure_lowp_links(L);
+    BatchDesc& d = ba.d[l];
+    d.g = L->geo;
+    d.parity = out_parity;
+    d.links = static_cast<const char*>(L->U[prec]);
+    d.in = static_cast<const char*>(b.in);
+    d.out = static_cast<char*>(b.out);
+    d.x = static_cast<const char*>(b.e.x);
+    d.y = static_cast<const char*>(b.e.y);
+    d.cx = b.e.cx;
+    d.a = b.e.a;
+    d.by = b.e.by[0];
+    d.g5 = b.e.g5;
+    d.dot = b.e.dot;
+    d.dotv = static_cast<const char*>(b.e.dotv);
+    d.partials = b.e.partials;
+    ba.tile0[l + 1] = ba.tile0[l] + hop_tiles(L, prec);
+  }
+  const int total = ba.tile0[nlat];
+  auto go = [&](auto P) {
+    using PT = decltype(P);
+    if (dagger)
+      hipLaunchKernelGGL((hop_dp_batch_kernel<PT, 1>), dim3(batch_grid<PT, 1>(total)), dim3(kDpThreads), 0, st, ba);
+    else
+      hipLaunchKernelGGL((hop_dp_batch_kernel<PT, 0>), dim3(batch_grid<PT, 0>(total)), dim3(kDpThreads), 0, st, ba);
+  };
+  switch (prec) {
+    case F64: go(PrecF64{}); break;
+    case F32: go(PrecF32{}); break;
+    case BF16: go(PrecBF16{}); break;
+  }
+  WL_HIP(hipGetLastError());
 }
 
 void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_parity, int dagger,

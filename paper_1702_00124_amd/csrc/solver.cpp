@@ -40,8 +40,6 @@ struct CgGraph {
 
 }  // namespace
 
-using ApplyLowp = std::function<void(Prec, void*, const void*, const DotOut&)>;
-using Apply64 = std::function<void(void*, const void*)>;
 
 // CG core.  apply_lp: inner-precision operator with fused Re<in, out>
 // partials (rows of nbrow); apply64: FP64 operator for true residuals.
@@ -264,6 +262,18 @@ int cg_run(wl_lattice* L, void* x, const void* b, double kappa, const double* mu
   const Prec ipr = (ip == F32 || ip == BF16) ? ip : F64;
   return cg_core(L, x, b, nrhs, nh, op_dot_blocks(L, op, ipr), spinor_bytes(F64, L->Vh),
                  spinor_bytes((ip == F32 || ip == BF16) ? ip : F64, L->Vh), lp, a64, prm, stats, true);
+}
+
+int cg_run_batch(wl_lattice* L, void* x, const void* b, int nrhs, int nbrow, const ApplyLowp& lp, const Apply64& a64,
+                 const wl_cg_params& prm, wl_cg_stats* stats) {
+  const Prec ip = Prec(prm.inner);
+  const Prec ipr = (ip == F32 || ip == BF16) ? ip : F64;
+  const size_t hb64 = spinor_bytes(F64, L->Vh), hbi = spinor_bytes(ipr, L->Vh);
+  WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs, WL_EINVAL, "nrhs out of range");
+  // the operator outputs are written at the lattices' sites only: clear the rest
+  zero_dev(L, ws_get(L, "cg_Ap", hbi * nrhs), hbi * nrhs);
+  zero_dev(L, ws_get(L, "cg_Ax64", hb64 * nrhs), hb64 * nrhs);
+  return cg_core(L, x, b, nrhs, 1, nbrow, hb64, hbi, lp, a64, prm, stats, false);
 }
 
 int cg_run_generic(wl_lattice* L, void* x, const void* b,

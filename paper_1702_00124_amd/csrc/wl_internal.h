@@ -140,6 +140,20 @@ struct HopEpi {
 };
 // workgroups (and reduction partials per rhs) of one hop launch in precision prec
 int hop_tiles(const wl_lattice* L, Prec prec);
+
+// mixed-volume batch: one hop per lattice (one rhs each) in a single launch;
+// with e.dot = 1, e.partials is the lattice's row of part_len partial sums
+// (entries past its tiles are cleared).  Only x, cx, a, g5, y, by[0], dot,
+// dotv and partials of the epilogue apply.  Not counted in the hop counters.
+constexpr int kMaxBatch = 8;
+struct BatchHop {
+  wl_lattice* L;
+  void* out;
+  const void* in;
+  HopEpi e;
+};
+void launch_hop_batch(hipStream_t st, Prec prec, int out_parity, int dagger, const BatchHop* hops, int nlat,
+                      int part_len);
 // out (parity p, nrhs fields) = epilogue(D_{p,1-p} in) or its dagger
 void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_parity, int dagger,
                 int nrhs, const HopEpi& e);

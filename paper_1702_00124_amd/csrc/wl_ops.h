@@ -47,17 +47,40 @@ void cdot_host(wl_lattice* L, const void* x, const void* y, int nrhs, double* ou
 // CG (solver.cpp) on J (even sites) or the full-lattice K
 int cg_run(wl_lattice* L, void* x, const void* b, double kappa, const double* mu2, int nrhs, int op,
            const wl_cg_params& prm, wl_cg_stats* stats);
-// CG on a general HPD operator on even-site fields (one rhs, x and b F64):
-// apply(prec, out, in) must leave out = A in with fields of storage precision
-// prec (prm.inner for the iteration, F64 for true residuals).  Used for P(J)
-// and P(J) J.
 // multi-shift CG on J(mu2 = shifts[s]) for nshift shifts and nrhs sources (FP64);
 // x: [nshift][nrhs] fields in the order of shifts; stats [nshift * nrhs]
 int cg_multishift_run(wl_lattice* L, void* x, const void* b, double kappa, const double* shifts, int nshift,
                       int nrhs, const wl_cg_params& prm, wl_cg_stats* stats);
+// CG on a general HPD operator on even-site fields (one rhs, x and b F64):
+// apply(prec, out, in) must leave out = A in with fields of storage precision
+// prec (prm.inner for the iteration, F64 for true residuals).  Used for P(J)
+// and P(J) J.
 int cg_run_generic(wl_lattice* L, void* x, const void* b,
                    const std::function<void(Prec, void*, const void*)>& apply, const wl_cg_params& prm,
                    wl_cg_stats* stats);
+// the solver core's operators: the inner-precision one with fused Re<in, out>
+// partial sums (a row of DotOut.stride entries per rhs), and the FP64 one
+using ApplyLowp = std::function<void(Prec, void*, const void*, const DotOut&)>;
+using Apply64 = std::function<void(void*, const void*)>;
+// CG over nrhs even-site fields of lattice L's size with the given operators
+// (the mixed-volume batch): the operators must leave zero wherever they write
+// nothing, and nbrow partial sums per rhs row
+int cg_run_batch(wl_lattice* L, void* x, const void* b, int nrhs, int nbrow, const ApplyLowp& lp, const Apply64& a64,
+                 const wl_cg_params& prm, wl_cg_stats* stats);
+
+// mixed-volume batches (batch.cpp): slots of the largest lattice's field size
+wl_batch* batch_create(wl_lattice* const* lats, int nlat);
+void batch_destroy(wl_batch* B);
+size_t batch_slot_bytes(const wl_batch* B, Prec prec);
+int batch_count(const wl_batch* B);
+wl_lattice* batch_big(const wl_batch* B);
+// allocate the batch's intermediates of one precision and pack every lattice's links
+void batch_prepare(wl_batch* B, Prec prec);
+void batch_hop(wl_batch* B, Prec prec, void* out, const void* in, int out_parity, int dagger);
+void batch_j(wl_batch* B, Prec prec, void* out, const void* in, const double* kappa, const double* mu2,
+             const DotOut& dot);
+int batch_cg(wl_batch* B, void* x, const void* b, const double* kappa, const double* mu2, const wl_cg_params& prm,
+             wl_cg_stats* stats);
 
 // polynomial filter (poly.cpp), F64, one rhs
 struct PolyDesc {

@@ -397,6 +397,94 @@ class WilsonLattice:
         return a.value, b.value
 
 
+class WilsonBatch:
+    """Mixed-volume batch of lattices (one device, one stream) whose hops run as
+    one launch: batch fields are one slot per lattice, slot l holding lattice
+    l's internal even-site field and zeros past it.  Keep the lattices alive
+    while the batch is in use."""
+
+    def __init__(self, lattices: Sequence[WilsonLattice]):
+        self.lib = W.load()
+        self.lattices = list(lattices)
+        arr = (C.c_void_p * len(self.lattices))(*[lat.h for lat in self.lattices])
+        h = C.c_void_p()
+        W.check(self.lib.wl_batch_create(C.byref(h), arr, len(self.lattices)))
+        self.h = h
+        self.device = self.lattices[0].device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.wl_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def slot_bytes(self, prec="f64") -> int:
+        n = C.c_size_t()
+        W.check(self.lib.wl_batch_slot_bytes(self.h, _prec(prec), C.byref(n)))
+        return n.value
+
+    def new_field(self, prec="f64") -> torch.Tensor:
+        return torch.zeros(self.slot_bytes(prec) * len(self.lattices), dtype=torch.uint8, device=self.device)
+
+    def slot(self, buf: torch.Tensor, l: int, prec="f64") -> torch.Tensor:
+        sb = self.slot_bytes(prec)
+        return buf[l * sb:(l + 1) * sb]
+
+    def pack(self, fields: Sequence[torch.Tensor], prec="f64") -> torch.Tensor:
+        """Batch field from one canonical (V_h, 4, 3) even-site field per lattice
+        (imported into the zeroed slots: the import writes the lattice's sites only)."""
+        out = self.new_field(prec)
+        for l, (lat, f) in enumerate(zip(self.lattices, fields)):
+            f = f.to(device=self.device, dtype=torch.complex128).contiguous()
+            assert f.shape == (lat.Vh, 4, 3)
+            W.check(self.lib.wl_import_spinor(lat.h, _ptr(self.slot(out, l, prec)), _ptr(f), _prec(prec), 1))
+        return out
+
+    def unpack(self, buf: torch.Tensor, prec="f64") -> List[torch.Tensor]:
+        """Canonical (V_h, 4, 3) field of every lattice from a batch field."""
+        res = []
+        for l, lat in enumerate(self.lattices):
+            out = torch.empty((lat.Vh, 4, 3), dtype=torch.complex128, device=self.device)
+            W.check(self.lib.wl_export_spinor(lat.h, _ptr(out), _ptr(self.slot(buf, l, prec)), _prec(prec), 1))
+            res.append(out)
+        return res
+
+    def dslash(self, buf: torch.Tensor, out_parity: int, dagger: bool = False, prec="f64") -> torch.Tensor:
+        out = self.new_field(prec)
+        _need(buf, out.numel(), "input")
+        W.check(self.lib.wl_batch_dslash(self.h, _ptr(out), _ptr(buf), out_parity, int(dagger), _prec(prec)))
+        return out
+
+    def apply_J(self, buf: torch.Tensor, kappa: Sequence[float], mu2: Optional[Sequence[float]] = None,
+                prec="f64") -> torch.Tensor:
+        n = len(self.lattices)
+        out = self.new_field(prec)
+        _need(buf, out.numel(), "input")
+        k = (C.c_double * n)(*[float(v) for v in kappa])
+        m = (C.c_double * n)(*[float(v) for v in mu2]) if mu2 is not None else None
+        W.check(self.lib.wl_batch_apply_J(self.h, _ptr(out), _ptr(buf), k, m, _prec(prec)))
+        return out
+
+    def cg_solve(self, b: torch.Tensor, kappa: Sequence[float], mu2: Optional[Sequence[float]] = None,
+                 params: Optional[CG] = None):
+        """x (batch field) with J_l x_l = b_l for every lattice; (x, [CgResult], rc)."""
+        params = params or CG()
+        n = len(self.lattices)
+        x = self.new_field("f64")
+        _need(b, x.numel(), "rhs")
+        k = (C.c_double * n)(*[float(v) for v in kappa])
+        m = (C.c_double * n)(*[float(v) for v in mu2]) if mu2 is not None else None
+        st = (W.CgStats * n)()
+        prm = params.c()
+        rc = W.check(self.lib.wl_batch_cg_solve(self.h, _ptr(x), _ptr(b), k, m, C.byref(prm), st))
+        return x, [CgResult(s.iters, s.reliable_updates, bool(s.converged), s.true_rel_res) for s in st], rc
+
+
 def integrator_schedule(nsteps: Sequence[int], integrator: str = "omelyan", omelyan_lambda: float = 0.0):
     """The library's overlaid integrator schedule (host only): list of
     ('S', scale, weight) and ('T', weight), weights in units of tau."""
