@@ -83,6 +83,7 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
 
   // ---- initial state: x = x0 (0 unless given), r = b - A x0, p = r
   norm2_host(L, b, nrhs, bb.data(), nh);
+  for (int i = 0; i < nrhs; ++i) WL_REQUIRE(std::isfinite(bb[i]), WL_EINVAL, "cg: non-finite right-hand side");
   if (prm.use_x0) {
     for (int i = 0; i < nrhs; ++i)  // a zero source has the zero solution
       if (bb[i] == 0.0) zero_dev(L, static_cast<char*>(x) + size_t(i) * nh * hb64, nh * hb64);
@@ -332,6 +333,7 @@ int cg_multishift_run(wl_lattice* L, void* x_out, const void* b, double kappa, c
 
   std::vector<double> bb(nrhs);
   norm2_host(L, b, nrhs, bb.data());
+  for (int i = 0; i < nrhs; ++i) WL_REQUIRE(std::isfinite(bb[i]), WL_EINVAL, "cg: non-finite right-hand side");
   zero_dev(L, x, fb * nsys);
   copy_dev(L, r, b, fb * nrhs);
   for (int s = 0; s < nshift; ++s) copy_dev(L, p + size_t(s) * nrhs * fb, b, fb * nrhs);

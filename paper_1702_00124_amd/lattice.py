@@ -12,6 +12,7 @@ fields are opaque uint8 device tensors of ``field_bytes`` bytes.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -353,15 +354,32 @@ class WilsonLattice:
         """0: thread per site; 1: direction-parallel; for every rhs class."""
         self.set_hop_config(prec, -1, variant=variant)
 
-    def autotune(self):
+    def autotune(self, cache: Optional[str] = None):
         """Time the hop configurations per precision and rhs class and keep the fastest.
 
         Returns {prec: [48 microsecond timings]} in the order the C API documents:
         class 0 (site, dp), then classes 1 and 2 (site 1, site 2, dp 1, dp 2, dp 4),
-        each per (stream, use_xcd) = (0, 1), (0, 0), (1, 1), (1, 0)."""
+        each per (stream, use_xcd) = (0, 1), (0, 0), (1, 1), (1, 0).
+
+        cache: a JSON file of earlier results keyed by lattice extents, device
+        name and library build; on a hit the stored configurations are set and
+        their timings returned without timing anything, else the tuning result
+        is added to the file."""
+        key = tune_cache_key(self.L, torch.cuda.get_device_name(self.device), W.LIB_PATH) if cache else None
+        if key:
+            hit = tune_cache_read(cache, key)
+            if hit is not None:
+                for prec, cfgs in hit["configs"].items():
+                    for k, c in enumerate(cfgs):
+                        W.check(self.lib.wl_set_hop_config(self.h, _prec(prec), k, *c))
+                return hit["us"]
         us = (C.c_double * 144)()
         W.check(self.lib.wl_autotune(self.h, us))
-        return {name: list(us[48 * i:48 * i + 48]) for name, i in PREC.items()}
+        res = {name: list(us[48 * i:48 * i + 48]) for name, i in PREC.items()}
+        if key:
+            tune_cache_write(cache, key, {"configs": {p: [list(self.hop_config(p, k)) for k in range(3)] for p in PREC},
+                                          "us": res})
+        return res
 
     def time_hop(self, prec="f64", nrhs: int = 1, nlaunch: int = 200) -> float:
         """Average microseconds per hop launch over a back-to-back burst."""
@@ -395,6 +413,38 @@ class WilsonLattice:
         a, b = C.c_longlong(), C.c_longlong()
         W.check(self.lib.wl_counters(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+
+def tune_cache_key(L: Sequence[int], device_name: str, lib_path: str) -> str:
+    """Autotuner cache key: lattice extents, device and the library build (its bytes' sha256)."""
+    import hashlib
+    with open(lib_path, "rb") as f:
+        build = hashlib.sha256(f.read()).hexdigest()[:16]
+    return f"{'x'.join(str(int(v)) for v in L)}|{device_name}|{build}"
+
+
+def tune_cache_read(path: str, key: str):
+    import json
+    try:
+        with open(path) as f:
+            return json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def tune_cache_write(path: str, key: str, entry) -> None:
+    """Add one entry (written to a temporary file, then renamed over the cache)."""
+    import json
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        data = {}
+    data[key] = entry
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1)
+    os.replace(tmp, path)
 
 
 class WilsonBatch:

@@ -242,3 +242,18 @@ def test_dslash_launch_config_invariance(variant):
     assert rel(ow.J(U, to_np(lat.export_spinor(x)), L, 0.155, 0.0), b) <= 1.01e-10
     with pytest.raises(Exception):
         lat.set_hop_config("f64", 0, npass=3)
+
+
+def test_autotune_cache_hit_sets_same_configurations(tmp_path):
+    """A second lattice of the same shape takes the cached configurations without timing."""
+    L = (8, 8, 8, 8)
+    path = str(tmp_path / "tune.json")
+    lat1, _ = make_lattice(L)
+    us1 = lat1.autotune(cache=path)
+    lat2, _ = make_lattice(L)
+    for prec in ("f64", "f32", "bf16"):
+        lat2.set_hop_config(prec, -1, variant=0 if lat1.hop_config(prec, 0)[0] else 1)
+    us2 = lat2.autotune(cache=path)
+    assert us2 == us1
+    for prec in ("f64", "f32", "bf16"):
+        assert [lat2.hop_config(prec, k) for k in range(3)] == [lat1.hop_config(prec, k) for k in range(3)]

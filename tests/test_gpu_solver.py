@@ -212,3 +212,16 @@ def test_multishift_rejects_initial_guess():
     b = lat.import_spinor(torch.from_numpy(half_noise(L, 2130)))
     with pytest.raises(W.WilsonError):
         lat.cg_multishift(b, 0.155, [0.0, 0.1], params=CG(use_x0=True))
+
+
+def test_cg_rejects_non_finite_source():
+    """A NaN or Inf in b is reported as WL_EINVAL before any iteration."""
+    from paper_1702_00124_amd import _lib as W
+    L = (4, 4, 4, 4)
+    lat, U = make_lattice(L)
+    for bad in (np.nan, np.inf):
+        b = half_noise(L, 2140)
+        b[7, 1, 2] = bad
+        with pytest.raises(W.WilsonError) as e:
+            lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), 0.155, "J", params=CG(inner="f32"))
+        assert e.value.code == W.WL_EINVAL and "non-finite" in str(e.value)

@@ -116,3 +116,22 @@ def test_binding_structs_match_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_autotune_cache_file_round_trip(tmp_path):
+    """The autotuner cache: key from extents, device and library build; entries
+    added one by one to one JSON file; a missing or corrupt file reads as empty."""
+    from paper_1702_00124_amd import _lib as W
+    from paper_1702_00124_amd.lattice import tune_cache_key, tune_cache_read, tune_cache_write
+    k1 = tune_cache_key((16, 16, 16, 32), "gpu", W.LIB_PATH)
+    k2 = tune_cache_key((8, 8, 8, 16), "gpu", W.LIB_PATH)
+    assert k1 != k2 and k1.startswith("16x16x16x32|gpu|")
+    path = str(tmp_path / "tune.json")
+    assert tune_cache_read(path, k1) is None
+    e1 = {"configs": {"f64": [[0, 1, 1, 0]] * 3}, "us": {"f64": [1.0] * 48}}
+    e2 = {"configs": {"f32": [[1, 4, 0, 1]] * 3}, "us": {"f32": [2.0] * 48}}
+    tune_cache_write(path, k1, e1)
+    tune_cache_write(path, k2, e2)
+    assert tune_cache_read(path, k1) == e1 and tune_cache_read(path, k2) == e2
+    (tmp_path / "bad.json").write_text("{not json")
+    assert tune_cache_read(str(tmp_path / "bad.json"), k1) is None
