@@ -483,6 +483,17 @@ def main():
         tseq, sseq = timed(seq64, reps=2)
         tbat, (_, sbat, _) = timed(lambda: lat.cg_solve(b8, KAPPA, "J", mu2=SHIFTS, nrhs=8,
                                                         params=CG(tol=1e-10, inner="f32")), reps=2)
+        # the same batch with other inner settings, each to the same FP64 true residual
+        variants = {}
+        for name, prm in (("f32_graph", CG(tol=1e-10, inner="f32", use_graph=True)),
+                          ("f32_delta0.01", CG(tol=1e-10, inner="f32", delta=0.01)),
+                          ("bf16", CG(tol=1e-10, inner="bf16")),
+                          ("bf16_graph", CG(tol=1e-10, inner="bf16", use_graph=True))):
+            tv, (_, sv, rcv) = timed(lambda: lat.cg_solve(b8, KAPPA, "J", mu2=SHIFTS, nrhs=8, params=prm), reps=2)
+            variants[name] = {"ms": round(tv * 1e3, 2), "iters_max": max(v.iters for v in sv),
+                              "reliable_updates": sv[0].reliable_updates,
+                              "true_res_max": max(v.true_rel_res for v in sv), "rc": rcv,
+                              "speedup_vs_sequential_f64": round(tseq / tv, 3)}
         # 8 sources x the 4 shifts = 32 systems: one multi-shift FP64 solve (one Krylov
         # space per source) vs two batched FP32-inner solves of 16 systems each
         SH4 = SHIFTS[:4]
@@ -506,6 +517,7 @@ def main():
             "eight_rhs_sequential_f64_ms": round(tseq * 1e3, 2),
             "eight_rhs_batched_mixed_ms": round(tbat * 1e3, 2),
             "multi_rhs_speedup": round(tseq / tbat, 3),
+            "eight_rhs_batched_variants": variants,
             "eight_rhs_iters_f64": [s.iters for s in sseq], "eight_rhs_iters_batched": [s.iters for s in sbat],
             "eight_rhs_true_res_max": max(s.true_rel_res for s in sbat),
             "multishift_32_systems_f64_ms": round(tms * 1e3, 2),

@@ -135,3 +135,18 @@ def test_autotune_cache_file_round_trip(tmp_path):
     assert tune_cache_read(path, k1) == e1 and tune_cache_read(path, k2) == e2
     (tmp_path / "bad.json").write_text("{not json")
     assert tune_cache_read(str(tmp_path / "bad.json"), k1) is None
+
+
+def test_cost_checkpoint_files_round_trip(tmp_path):
+    """Checkpoint state and arrays survive a write / read cycle exactly; no state reads as None."""
+    import numpy as np
+    from paper_1702_00124_amd.cost import Checkpoint
+    ck = Checkpoint(str(tmp_path / "ck"))
+    assert ck.load_state() is None
+    U = (np.arange(24, dtype=np.float64) * (1 + 0.5j)).reshape(2, 3, 4)
+    ck.save_array("links", U)
+    st = {"run": {"lattice": [4, 4, 4, 4]}, "phase": "MP", "k": 2, "rows": [[0.1, True, 5, 6, 0.5, 1.0]],
+          "done": {}}
+    ck.save_state(st)
+    assert np.array_equal(ck.load_array("links"), U) and ck.load_array("links").dtype == np.complex128
+    assert ck.load_state() == st
