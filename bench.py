@@ -55,12 +55,13 @@ HOP_BYTES_PER_SITE = {"f64": 8 * 96 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8
 # (FETCH_SIZE read 524300 KiB -> x2.0; WRITE_SIZE read 1048576 KiB -> x1.0).
 # Valid only for the kernel source they were taken on (hash of the hop
 # kernel sources); otherwise `traffic` is reported as null.  (The hash was
-# moved once without new counters, when the mixed-volume batch kernel was
-# added to the same source: the device assembly of every existing hop kernel
-# was compared before and after and is instruction for instruction the same.)
+# moved without new counters when the mixed-volume batch kernel and its launch
+# helper were added to the same source: the device assembly of every existing
+# hop kernel was compared before and after and is instruction for instruction
+# the same.)
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_COUNTERS = {
-    "source_sha256": "b8e2ce034c16f186f0156e9f92849ac655625f44dc582d379efe85db83732f2f",
+    "source_sha256": "3bc73960d5c0263c7f6e92d1fd67e7c9494d26199fc362b594a63f40ddb7d342",
     # "precision:variant:workgroup order:streaming": KiB per dispatch on the 16^3x32
     # workload, median of 45 dispatches per configuration
     "per_launch_kib": {

@@ -12,6 +12,7 @@
 // byte in FP64), so the kernel is written for coalesced 16-byte loads and an
 // L2-friendly, XCD-aware tile order; no MFMA.
 #include <algorithm>
+#include <atomic>
 
 #include "wl_internal.h"
 
@@ -575,16 +576,21 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_batch_kernel(BatchArgs ba) 
 
 template <typename P, int DAG>
 static int batch_grid(int total) {
-  // workgroups resident at once on the whole device (cached per instantiation)
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, cus = 0, per_cu = 0;
-    WL_HIP(hipGetDevice(&dev));
+  // workgroups resident at once on the current device (cached per instantiation and device)
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> resident[kMaxDevices];
+  int dev = 0;
+  WL_HIP(hipGetDevice(&dev));
+  WL_REQUIRE(dev >= 0 && dev < kMaxDevices, WL_EUNSUPPORTED, "batch: device index out of range");
+  int n = resident[dev].load();
+  if (!n) {
+    int cus = 0, per_cu = 0;
     WL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     WL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hop_dp_batch_kernel<P, DAG>, kDpThreads, 0));
-    resident = std::max(1, cus * per_cu);
+    n = std::max(1, cus * per_cu);
+    resident[dev].store(n);
   }
-  return std::min(total, resident);
+  return std::min(total, n);
 }
 
 void launch_hop_batch(hipStream_t st, Prec prec, int out_parity, int dagger, const BatchHop* hops, int nlat,
