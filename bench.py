@@ -341,6 +341,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--quick", action="store_true", help="skip the CG comparison legs")
+    ap.add_argument("--md-delta", type=float, default=0.01,
+                    help="reliable-update threshold of the trajectory's FP32-inner solves")
+    ap.add_argument("--md-poly-chunk", type=int, default=2,
+                    help="iterations between convergence checks of the polynomial terms' solves")
     ap.add_argument("--cg-graph", action="store_true",
                     help="the trajectory's solves replay each chunk of CG iterations as a captured HIP graph")
     ap.add_argument("--md-steps", default=",".join(map(str, NSTEPS)),
@@ -390,9 +394,11 @@ def main():
     log("hop configurations kept (variant, npass, use_xcd, stream) for 1, 2-4, 5-16 rhs:",
         {p: [lat.hop_config(p, k) for k in range(3)] for p in ("f64", "f32", "bf16")})
 
-    cg_md = CG(tol=1e-10, inner="f32", chunk=8, use_graph=args.cg_graph)
-    terms = [Term("POLY", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_md),
-             Term("POLYK_INV", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_md),
+    cg_md = CG(tol=1e-10, inner="f32", chunk=8, delta=args.md_delta, use_graph=args.cg_graph)
+    # the polynomial solve's operator is degree + 1 J applications: check convergence more often
+    cg_poly = CG(tol=1e-10, inner="f32", chunk=args.md_poly_chunk, delta=args.md_delta)
+    terms = [Term("POLY", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_poly),
+             Term("POLYK_INV", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_poly),
              Term("RATIO", KAPPA, mu2_num=MU2_HASENBUSCH, cg=cg_md)]
     ntraj = args.warmup + args.steps
     P, chi, u = [], [], li.uniforms(ntraj, li.seed_metropolis(0))
