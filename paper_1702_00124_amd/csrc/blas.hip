@@ -56,6 +56,120 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, double* x64, c
   if (threadIdx.x == 0) partials[rhs * pstride + (f % nh) * gridDim.x + site_block()] = s;
 }
 
+// ------------------------------------------------------------------ fused CG scalars
+// One CG iteration after the operator is two kernels instead of four: every
+// block sums the partial-sum row it needs itself (the same entries in the same
+// order, so every block gets the same value) and derives alpha or beta; one
+// block records the scalars.  Within a kernel the state is only written where
+// no other block reads it, or as flags that go from 0 to 1 under a condition
+// every block evaluates the same way.
+__device__ __forceinline__ double row_sum_all(const double* row, int nb, double* lds) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += row[b];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) lds[0] = s;
+  __syncthreads();
+  const double v = lds[0];
+  __syncthreads();
+  return v;
+}
+
+// alpha = |r|^2 / <p, A p> from the operator's partial sums (row rhs of pstride,
+// nb_dot entries), then x += alpha p, r -= alpha A p and the |r|^2 partial sums
+// into rr_partials (row rhs of pstride)
+template <typename P>
+__global__ __launch_bounds__(kBlock) void cg_update_fused_kernel(Geo g, double* x64, char* r, const char* p,
+                                                                const char* Ap, double* st, size_t stride,
+                                                                size_t stride64, const double* dot_partials,
+                                                                int nb_dot, double* rr_partials, int pstride,
+                                                                int nh) {
+  using R = typename P::real;
+  __shared__ double lds[kBlock / 64];
+  const int f = blockIdx.y;
+  const int rhs = f / nh;
+  const int blk = site_block();
+  const int h = blk * kBlock + threadIdx.x;
+  const int Vh = g.Vh;
+  const double pAp = row_sum_all(dot_partials + size_t(rhs) * pstride, nb_dot, lds);
+  const bool done = st[CG_DONE * kMaxRhs + rhs] != 0.0;
+  const bool ok = pAp > 0.0 && pAp < 1e300;  // A is HPD: <p, A p> positive and finite
+  const bool brk = st[CG_BREAK * kMaxRhs + rhs] != 0.0 || (!done && !ok);
+  const double rr = st[CG_RR * kMaxRhs + rhs];
+  const double alpha = (done || brk) ? 0.0 : rr / pAp;
+  if (blk == 0 && f % nh == 0 && threadIdx.x == 0) {
+    st[CG_PAP * kMaxRhs + rhs] = pAp;
+    st[CG_ALPHA * kMaxRhs + rhs] = alpha;
+    st[CG_RROLD * kMaxRhs + rhs] = rr;
+    if (brk) st[CG_BREAK * kMaxRhs + rhs] = 1.0;
+  }
+  double part = 0.0;
+  if (h < Vh && !done && !brk) {
+    const size_t off = f * stride;
+    Spinor<R> pv = SpinorIO<P>::load(p + off, h, Vh);
+    Spinor<R> av = SpinorIO<P>::load(Ap + off, h, Vh);
+    Spinor<R> rv = SpinorIO<P>::load(r + off, h, Vh);
+    char* xb = reinterpret_cast<char*>(x64) + f * stride64;
+    Spinor<double> xv = SpinorIO<PrecF64>::load(xb, h, Vh);
+    const R ar = R(alpha);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      xv.c[k].r += alpha * double(pv.c[k].r);
+      xv.c[k].i += alpha * double(pv.c[k].i);
+      rv.c[k] = rv.c[k] - ar * av.c[k];
+    }
+    SpinorIO<PrecF64>::store(xb, h, Vh, xv);
+    SpinorIO<P>::store(r + off, h, Vh, rv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part += double(rv.c[k].r) * double(rv.c[k].r) + double(rv.c[k].i) * double(rv.c[k].i);
+  } else if (h < Vh && !done) {
+    // broken down: r is left alone; its |r|^2 still goes to the partial sums
+    const Spinor<R> rv = SpinorIO<P>::load(r + f * stride, h, Vh);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part += double(rv.c[k].r) * double(rv.c[k].r) + double(rv.c[k].i) * double(rv.c[k].i);
+  }
+  const double s = block_sum(part, lds);
+  if (threadIdx.x == 0) rr_partials[rhs * pstride + (f % nh) * gridDim.x + blk] = s;
+}
+
+// beta = |r_new|^2 / |r_old|^2 from the update's partial sums (nb_rr entries),
+// the convergence and breakdown flags, then p = r + beta p
+template <typename P>
+__global__ __launch_bounds__(kBlock) void cg_xpay_fused_kernel(Geo g, char* p, const char* r, double* st,
+                                                              size_t stride, const double* rr_partials, int nb_rr,
+                                                              int pstride, int nh) {
+  using R = typename P::real;
+  __shared__ double lds[kBlock / 64];
+  const int f = blockIdx.y;
+  const int rhs = f / nh;
+  const int blk = site_block();
+  const int h = blk * kBlock + threadIdx.x;
+  const int Vh = g.Vh;
+  const double rr_new = row_sum_all(rr_partials + size_t(rhs) * pstride, nb_rr, lds);
+  const bool done_old = st[CG_DONE * kMaxRhs + rhs] != 0.0;
+  const bool brk = st[CG_BREAK * kMaxRhs + rhs] != 0.0 || !(rr_new < 1e300);  // also catches NaN
+  const bool conv = !brk && rr_new <= st[CG_TOL2 * kMaxRhs + rhs] * st[CG_BB * kMaxRhs + rhs];
+  const bool done = done_old || conv;
+  const double beta = (brk || done_old) ? 0.0 : rr_new / st[CG_RROLD * kMaxRhs + rhs];
+  if (blk == 0 && f % nh == 0 && threadIdx.x == 0) {
+    if (brk) st[CG_BREAK * kMaxRhs + rhs] = 1.0;
+    st[CG_BETA * kMaxRhs + rhs] = beta;  // frozen at 0 once broken down, until the host restarts it
+    if (!brk && !done_old) {
+      st[CG_RR * kMaxRhs + rhs] = rr_new;
+      st[CG_ITERS * kMaxRhs + rhs] += 1.0;
+      if (rr_new > st[CG_MAXRR * kMaxRhs + rhs]) st[CG_MAXRR * kMaxRhs + rhs] = rr_new;
+      if (conv) st[CG_DONE * kMaxRhs + rhs] = 1.0;
+    }
+  }
+  if (h >= Vh || done) return;
+  const R rb = R(beta);
+  const size_t off = f * stride;
+  Spinor<R> pv = SpinorIO<P>::load(p + off, h, Vh);
+  const Spinor<R> rv = SpinorIO<P>::load(r + off, h, Vh);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) pv.c[k] = rv.c[k] + rb * pv.c[k];
+  SpinorIO<P>::store(p + off, h, Vh, pv);
+}
+
 template <typename P>
 __global__ __launch_bounds__(kBlock) void cg_xpay_kernel(Geo g, char* p, const char* r, const double* st,
                                                         size_t stride, int nh) {
@@ -369,6 +483,30 @@ void launch_cg_update(wl_lattice* L, Prec prec, void* x64, void* r, const void* 
     hipLaunchKernelGGL((cg_update_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (double*)x64, (char*)r,
                        (const char*)p, (const char*)Ap, st, spinor_bytes(prec, L->Vh), spinor_bytes(F64, L->Vh), partials,
                        stride, nh);
+  });
+  WL_HIP(hipGetLastError());
+}
+
+void launch_cg_update_fused(wl_lattice* L, Prec prec, void* x64, void* r, const void* p, const void* Ap, double* st,
+                            int nrhs, int nh, const double* dot_partials, int nb_dot, double* rr_partials,
+                            int pstride) {
+  dim3 grid(blas_blocks(L), nrhs * nh);
+  by_prec(prec, [&](auto P) {
+    using PT = decltype(P);
+    hipLaunchKernelGGL((cg_update_fused_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (double*)x64,
+                       (char*)r, (const char*)p, (const char*)Ap, st, spinor_bytes(prec, L->Vh),
+                       spinor_bytes(F64, L->Vh), dot_partials, nb_dot, rr_partials, pstride, nh);
+  });
+  WL_HIP(hipGetLastError());
+}
+
+void launch_cg_xpay_fused(wl_lattice* L, Prec prec, void* p, const void* r, double* st, int nrhs, int nh,
+                          const double* rr_partials, int nb_rr, int pstride) {
+  dim3 grid(blas_blocks(L), nrhs * nh);
+  by_prec(prec, [&](auto P) {
+    using PT = decltype(P);
+    hipLaunchKernelGGL((cg_xpay_fused_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (char*)p,
+                       (const char*)r, st, spinor_bytes(prec, L->Vh), rr_partials, nb_rr, pstride, nh);
   });
   WL_HIP(hipGetLastError());
 }

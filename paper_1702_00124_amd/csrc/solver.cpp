@@ -62,7 +62,7 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   void* Ap = ws_get(L, "cg_Ap", fbi);
   void* r64 = ws_get(L, "cg_r64", fb64);
   void* Ax64 = ws_get(L, "cg_Ax64", fb64);
-  ensure_partials(L, size_t(nrhs) * nbrow * 2 + 64);
+  ensure_partials(L, size_t(nrhs) * nbrow * 3 + 64);
   double* st = L->dscal + kCgState;
   const long long kmat0 = L->n_kmat;
   long long kmat_extra = 0;
@@ -126,13 +126,26 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   // the update writes nh * blas_blocks of |r|^2 (never more than nbrow)
   const int nb_upd = nh * blas_blocks(L);
   WL_REQUIRE(nb_upd <= nbrow, WL_EINVAL, "cg: reduction row too narrow");
+  // Fused scalars (alpha in the update kernel, beta in the p update) save two
+  // launches per iteration but make every block re-read a partial-sum row:
+  // worth it while those re-reads (blocks x row entries) stay small, e.g. at
+  // 16^3 x 32 (256 x 1024); at 32^3 x 64 (4096 x 16384) the separate kernels win.
+  // The operator's <p, A p> partial sums (complex for the generic operators:
+  // two rows per rhs) come first; the fused update's |r|^2 partial sums follow.
+  const bool fuse = size_t(nbrow) * size_t(blas_blocks(L)) <= (size_t(1) << 20);
+  double* rr_part = L->partials + size_t(2) * nrhs * nbrow;
   auto issue_chunk = [&]() {
     for (int it = 0; it < chunk; ++it) {
       apply_lp(ip, Ap, p, DotOut{L->partials, nbrow});
-      launch_cg_alpha(L, L->partials, nbrow, nbrow, st, nrhs);
-      launch_cg_update(L, ip, x, r, p, Ap, st, nrhs, nh, L->partials, nbrow);
-      launch_cg_beta(L, L->partials, nbrow, nb_upd, st, nrhs);
-      launch_cg_xpay(L, ip, p, r, st, nrhs, nh);
+      if (fuse) {
+        launch_cg_update_fused(L, ip, x, r, p, Ap, st, nrhs, nh, L->partials, nbrow, rr_part, nbrow);
+        launch_cg_xpay_fused(L, ip, p, r, st, nrhs, nh, rr_part, nb_upd, nbrow);
+      } else {
+        launch_cg_alpha(L, L->partials, nbrow, nbrow, st, nrhs);
+        launch_cg_update(L, ip, x, r, p, Ap, st, nrhs, nh, L->partials, nbrow);
+        launch_cg_beta(L, L->partials, nbrow, nb_upd, st, nrhs);
+        launch_cg_xpay(L, ip, p, r, st, nrhs, nh);
+      }
     }
   };
 

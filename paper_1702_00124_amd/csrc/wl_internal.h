@@ -167,6 +167,14 @@ void launch_cg_update(wl_lattice* L, Prec prec, void* x64, void* r, const void* 
                       const double* st, int nrhs, int nh, double* partials, int stride);
 // p = r + beta[r] p
 void launch_cg_xpay(wl_lattice* L, Prec prec, void* p, const void* r, const double* st, int nrhs, int nh);
+// the CG iteration's two vector kernels with alpha and beta derived inside
+// (the operator's <p, A p> partial sums: rows of pstride, nb_dot entries; the
+// |r|^2 partial sums go to rr_partials, rows of pstride, nh * blas blocks entries)
+void launch_cg_update_fused(wl_lattice* L, Prec prec, void* x64, void* r, const void* p, const void* Ap, double* st,
+                            int nrhs, int nh, const double* dot_partials, int nb_dot, double* rr_partials,
+                            int pstride);
+void launch_cg_xpay_fused(wl_lattice* L, Prec prec, void* p, const void* r, double* st, int nrhs, int nh,
+                          const double* rr_partials, int nb_rr, int pstride);
 // dst = convert(src), both nrhs half fields
 void launch_convert(wl_lattice* L, Prec dprec, void* dst, Prec sprec, const void* src, int nrhs);
 // out = a[r] x + b[r] (g5 ? gamma5 y : y), complex coefficients; x or y may be null

@@ -14,8 +14,10 @@ enum CgStateRow {
   CG_TOL2 = 7,
   CG_MAXRR = 8,  // largest |r|^2 since the last reliable update
   CG_BREAK = 9,  // set when <p, A p> or |r|^2 is not a positive finite number
-  CG_NROWS = 10
+  CG_RROLD = 10, // |r|^2 at the start of the iteration (the fused update keeps it for beta)
+  CG_NROWS = 11
 };
+static_assert(CG_NROWS * 16 <= 256, "CG state rows overlap the multi-shift state");
 
 // Multi-shift CG state (after the CG rows): per shifted system q = s * nrhs + r
 // rows of kMaxSys doubles, then per-rhs rows of kMaxRhs.
