@@ -112,8 +112,10 @@ int apply_K(wl_lattice* lat, void* out, const void* in, double kappa, const doub
  * FP64 reliable updates r = b - A x whenever the iterated residual fell by
  * delta since the last update.  x and b: internal F64 fields.  stats: host
  * array of nrhs entries (may be NULL).  Returns WL_ENOCONV, with x the last
- * iterate and stats filled, if some rhs misses tol within maxiter; WL_EINVAL
- * for a non-finite |b|^2 (NaN or Inf in b). */
+ * iterate and stats filled, if some rhs misses tol within maxiter, or keeps
+ * breaking down (a non-positive <p, A p>: an operator that is not positive
+ * definite) through several restarts; WL_EINVAL for a non-finite |b|^2 (NaN or
+ * Inf in b). */
 typedef struct {
   double tol;      /* relative true-residual target, e.g. 1e-10 */
   int maxiter;     /* per rhs */

@@ -156,6 +156,11 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   bool all_verified = true;  // an initial guess can already be a solution
   for (int i = 0; i < nrhs; ++i) all_verified = all_verified && verified[i];
   bool out_of_iters = false;
+  // termination also without progress: a system that keeps breaking down
+  // never advances its iteration count, so stop after a few fruitless
+  // restarts in a row, and in any case once 4 maxiter iterations were issued
+  int stalled = 0, last_max_it = -1;
+  const long long issue_cap = 4LL * prm.maxiter + chunk;
   while (!all_verified) {
     if (prm.use_graph && chunks > 0) {
       if (!cg_graph.exec) {
@@ -242,6 +247,12 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
     for (int i = 0; i < nrhs; ++i) all_verified = all_verified && verified[i];
     if (all_verified) break;
     if (max_it >= prm.maxiter) {
+      out_of_iters = true;
+      break;
+    }
+    stalled = (broke && max_it == last_max_it) ? stalled + 1 : 0;
+    last_max_it = max_it;
+    if (stalled >= 4 || (long long)chunks * chunk >= issue_cap) {
       out_of_iters = true;
       break;
     }

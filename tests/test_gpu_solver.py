@@ -11,6 +11,7 @@ import torch
 
 from oracle import solver as osol, wilson as ow
 from paper_1702_00124_amd.lattice import CG
+from paper_1702_00124_amd import _lib as W
 from tests.gpu_common import full_noise, half_noise, make_lattice, need_gpu, rel, say, to_np
 
 pytestmark = pytest.mark.gpu
@@ -225,3 +226,18 @@ def test_cg_rejects_non_finite_source():
         with pytest.raises(W.WilsonError) as e:
             lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), 0.155, "J", params=CG(inner="f32"))
         assert e.value.code == W.WL_EINVAL and "non-finite" in str(e.value)
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_cg_breakdown_terminates(inner):
+    """J = K-hat - 10 is negative definite (spec K-hat lies in [0, (1 + 64 kappa^2)^2]):
+    <p, J p> < 0 breaks the iteration at once; the solver restarts, then gives
+    up with WL_ENOCONV instead of looping, leaving a finite x."""
+    L = (4, 4, 4, 4)
+    lat, U = make_lattice(L)
+    b = half_noise(L, 2150)
+    x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), 0.155, "J", mu2=[-10.0],
+                             params=CG(tol=1e-10, inner=inner, maxiter=1000, chunk=4))
+    say(f"  {inner}: rc {rc}, iters {st[0].iters}, reliable updates {st[0].reliable_updates}")
+    assert rc == W.WL_ENOCONV and not st[0].converged
+    assert np.isfinite(to_np(lat.export_spinor(x))).all()
