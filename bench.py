@@ -481,8 +481,26 @@ def main():
                 best = min(best, time.perf_counter() - t)
             return best, out
 
-        t64, (_, s64, _) = timed(lambda: lat.cg_solve(b1, KAPPA, "J", mu2=[0.0], params=CG(tol=1e-10, inner="f64")))
-        t32, (_, s32, _) = timed(lambda: lat.cg_solve(b1, KAPPA, "J", mu2=[0.0], params=CG(tol=1e-10, inner="f32")))
+        t64, (x64, s64, _) = timed(lambda: lat.cg_solve(b1, KAPPA, "J", mu2=[0.0], params=CG(tol=1e-10, inner="f64")))
+        t32, (x32, s32, _) = timed(lambda: lat.cg_solve(b1, KAPPA, "J", mu2=[0.0], params=CG(tol=1e-10, inner="f32")))
+        _, (x16, _, _) = timed(lambda: lat.cg_solve(b1, KAPPA, "J", mu2=[0.0], params=CG(tol=1e-10, inner="bf16")),
+                               reps=1)
+
+        def rel_err(a, b):
+            return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        # storage-precision errors against the FP64 path on the same input (relative l2)
+        src = torch.from_numpy(bs[0])
+        ref_hop = lat.export_spinor(lat.dslash(lat.import_spinor(src), 1))
+        ref_k = lat.export_spinor(lat.apply_K(lat.import_spinor(src), KAPPA, "J"))
+        prec_err = {"cg_solution_f32_inner_vs_f64": rel_err(lat.export_spinor(x32), lat.export_spinor(x64)),
+                    "cg_solution_bf16_inner_vs_f64": rel_err(lat.export_spinor(x16), lat.export_spinor(x64))}
+        for pr in ("f32", "bf16"):
+            hop = lat.export_spinor(lat.dslash(lat.import_spinor(src, pr), 1, prec=pr), pr)
+            kj = lat.export_spinor(lat.apply_K(lat.import_spinor(src, pr), KAPPA, "J", prec=pr), pr)
+            prec_err[f"hop_{pr}_vs_f64"] = rel_err(hop, ref_hop)
+            prec_err[f"khat_{pr}_vs_f64"] = rel_err(kj, ref_k)
+        extra["precision_errors"] = {k: float(f"{v:.3e}") for k, v in prec_err.items()}
+        log("precision errors", json.dumps(extra["precision_errors"]))
 
         def seq64():
             return [lat.cg_solve(bj[j], KAPPA, "J", mu2=[SHIFTS[j]], params=CG(tol=1e-10, inner="f64"))[1][0]
