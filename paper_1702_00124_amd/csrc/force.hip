@@ -129,21 +129,29 @@ __device__ __forceinline__ void bilinear_dir(const Geo& g, const Coord& c, int p
   for (int a = 0; a < 8; ++a) f[a * g.Vh + h] += coeff * gr[a];
 }
 
-__global__ __launch_bounds__(kBlock) void bilinear_kernel(Geo g, double* F, const char* Ae, const char* Ao,
-                                                         const char* Ce, const char* Co, const void* U,
-                                                         double coeff) {
-  const int h = blockIdx.x * kBlock + threadIdx.x;
+// one thread per link (x, mu): four times the threads of a thread per site,
+// which the latency of the neighbour gathers needs.  A workgroup holds 64
+// sites, one wavefront per direction, so the site's own spinors, read by all
+// four wavefronts, come from the CU's cache after the first.
+constexpr int kBilSites = 64;
+__global__ __launch_bounds__(4 * kBilSites) void bilinear_kernel(Geo g, double* F, const char* Ae, const char* Ao,
+                                                                const char* Ce, const char* Co, const void* U,
+                                                                double coeff) {
+  const int h = blockIdx.x * kBilSites + (threadIdx.x & (kBilSites - 1));
   const int p = blockIdx.y;
+  const int mu = threadIdx.x / kBilSites;  // uniform in the wavefront
   if (h >= g.Vh) return;
   const char* Ah[2] = {Ae, Ao};
   const char* Ch[2] = {Ce, Co};
   const Coord c = site_coords(g, h, p);
   const Spinor<double> Ax = SpinorIO<PrecF64>::load(Ah[p], h, g.Vh);
   const Spinor<double> Cx = SpinorIO<PrecF64>::load(Ch[p], h, g.Vh);
-  bilinear_dir<0>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff);
-  bilinear_dir<1>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff);
-  bilinear_dir<2>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff);
-  bilinear_dir<3>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff);
+  switch (mu) {
+    case 0: bilinear_dir<0>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff); break;
+    case 1: bilinear_dir<1>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff); break;
+    case 2: bilinear_dir<2>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff); break;
+    default: bilinear_dir<3>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff); break;
+  }
 }
 
 // ------------------------------------------------------------------ gauge force
@@ -318,8 +326,8 @@ __global__ __launch_bounds__(kBlock) void sumsq_kernel(const double* P, size_t n
 // ------------------------------------------------------------------ launchers
 void launch_bilinear(wl_lattice* L, double* F, const void* Ae, const void* Ao, const void* Ce, const void* Co,
                      double coeff) {
-  dim3 grid(site_blocks(L->Vh), 2);
-  hipLaunchKernelGGL(bilinear_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, F, (const char*)Ae,
+  dim3 grid((L->Vh + kBilSites - 1) / kBilSites, 2);  // (64-site tile, parity)
+  hipLaunchKernelGGL(bilinear_kernel, grid, dim3(4 * kBilSites), 0, L->stream, L->geo, F, (const char*)Ae,
                      (const char*)Ao, (const char*)Ce, (const char*)Co, L->Ufull, coeff);
   WL_HIP(hipGetLastError());
 }
