@@ -421,30 +421,38 @@ __global__ __launch_bounds__(kBlock) void ms_xpay_kernel(Geo g, char* p, const c
   SpinorIO<PrecF64>::store(p + off, h, Vh, pv);
 }
 
-// One step of the Chebyshev filter recurrence:
-//   tprev <- ct * t + cw * w - tprev        (t_{m+1} = 2 y(J) t_m - t_{m-1}, w = J t_m)
-//   eprev <- ce * e + 2 t - eprev           (e_{m+1} = 2 y0 e_m + 2 t_m - e_{m-1})
+// Start and end of the Chebyshev filter recurrence (the steps in between are
+// fused into the hop kernels' epilogue):
+//   start: t_0 = in, e_0 = 0, e_1 = in          (one read, three writes)
+//   end:   out = s e_{n+1} = s (ce e_n + 2 t_n - e_{n-1}),  ce = 2 y0
 template <typename P>
-__global__ __launch_bounds__(kBlock) void cheb_step_kernel(Geo g, const char* t, const char* w, char* tprev,
-                                                          const char* e, char* eprev, size_t stride, double ct,
-                                                          double cw, double ce) {
+__global__ __launch_bounds__(kBlock) void cheb_init_kernel(Geo g, const char* in, char* t0, char* e0, char* e1) {
   using R = typename P::real;
   const int h = site_block() * kBlock + threadIdx.x;
   if (h >= g.Vh) return;
-  const size_t off = blockIdx.y * stride;
-  const Spinor<R> tv = SpinorIO<P>::load(t + off, h, g.Vh);
-  const Spinor<R> wv = SpinorIO<P>::load(w + off, h, g.Vh);
-  const Spinor<R> ev = SpinorIO<P>::load(e + off, h, g.Vh);
-  Spinor<R> tp = SpinorIO<P>::load(tprev + off, h, g.Vh);
-  Spinor<R> ep = SpinorIO<P>::load(eprev + off, h, g.Vh);
-  const R rt = R(ct), rw = R(cw), re = R(ce), two = R(2);
+  const Spinor<R> v = SpinorIO<P>::load(in, h, g.Vh);
+  Spinor<R> z;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    tp.c[k] = rt * tv.c[k] + rw * wv.c[k] - tp.c[k];
-    ep.c[k] = re * ev.c[k] + two * tv.c[k] - ep.c[k];
-  }
-  SpinorIO<P>::store(tprev + off, h, g.Vh, tp);
-  SpinorIO<P>::store(eprev + off, h, g.Vh, ep);
+  for (int k = 0; k < 12; ++k) z.c[k] = zero<R>();
+  SpinorIO<P>::store(t0, h, g.Vh, v);
+  SpinorIO<P>::store(e0, h, g.Vh, z);
+  SpinorIO<P>::store(e1, h, g.Vh, v);
+}
+
+template <typename P>
+__global__ __launch_bounds__(kBlock) void cheb_last_kernel(Geo g, const char* t, const char* e, const char* eprev,
+                                                          char* out, double ce, double s) {
+  using R = typename P::real;
+  const int h = site_block() * kBlock + threadIdx.x;
+  if (h >= g.Vh) return;
+  const Spinor<R> tv = SpinorIO<P>::load(t, h, g.Vh);
+  const Spinor<R> ev = SpinorIO<P>::load(e, h, g.Vh);
+  const Spinor<R> pv = SpinorIO<P>::load(eprev, h, g.Vh);
+  const R re = R(ce), two = R(2), rs = R(s);
+  Spinor<R> o;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) o.c[k] = rs * (re * ev.c[k] + two * tv.c[k] - pv.c[k]);
+  SpinorIO<P>::store(out, h, g.Vh, o);
 }
 
 // STREAM-style copy (the practical bandwidth ceiling): every thread moves four
@@ -596,14 +604,21 @@ void launch_ms_xpay(wl_lattice* L, void* p, const void* r, const double* st, con
   WL_HIP(hipGetLastError());
 }
 
-void launch_cheb_step(wl_lattice* L, const void* t, const void* w, void* tprev, const void* e, void* eprev, double ct,
-                      double cw, double ce, int nrhs, Prec prec) {
-  dim3 grid(blas_blocks(L), nrhs);
+void launch_cheb_init(wl_lattice* L, const void* in, void* t0, void* e0, void* e1, Prec prec) {
   by_prec(prec, [&](auto P) {
     using PT = decltype(P);
-    hipLaunchKernelGGL((cheb_step_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (const char*)t,
-                       (const char*)w, (char*)tprev, (const char*)e, (char*)eprev, spinor_bytes(prec, L->Vh), ct, cw,
-                       ce);
+    hipLaunchKernelGGL((cheb_init_kernel<PT>), dim3(blas_blocks(L)), dim3(kBlock), 0, L->stream, L->geo,
+                       (const char*)in, (char*)t0, (char*)e0, (char*)e1);
+  });
+  WL_HIP(hipGetLastError());
+}
+
+void launch_cheb_last(wl_lattice* L, const void* t, const void* e, const void* eprev, void* out, double ce, double s,
+                      Prec prec) {
+  by_prec(prec, [&](auto P) {
+    using PT = decltype(P);
+    hipLaunchKernelGGL((cheb_last_kernel<PT>), dim3(blas_blocks(L)), dim3(kBlock), 0, L->stream, L->geo,
+                       (const char*)t, (const char*)e, (const char*)eprev, (char*)out, ce, s);
   });
   WL_HIP(hipGetLastError());
 }

@@ -7,8 +7,9 @@
 // P_n(J) psi runs the real three-term recurrence
 //   t_{m+1} = 2 y(J) t_m - t_{m-1}        (t_m = T_m(y(J)) psi)
 //   e_{m+1} = 2 y0 e_m + 2 t_m - e_{m-1}  (e_m = (T_m(y0) - T_m(y(J)))/(y0 - y(J)) psi)
-// so that P_n(J) psi = (2/(b-a)) e_{n+1} / T_{n+1}(y0): n J applications, each
-// step of the recurrence fused into the last hop of its J application.  Q(J), with P = Q^dag Q, is the product
+// so that P_n(J) psi = (2/(b-a)) e_{n+1} / T_{n+1}(y0): n J applications, t_1
+// and each later step of the recurrence fused into the last hop of its J
+// application, the start vectors and the scaled last step one kernel each.  Q(J), with P = Q^dag Q, is the product
 // over the n/2 roots z_k = ((b+a)/2)(1 - cos t_k) - i sqrt(ab) sin t_k,
 // t_k = 2 pi k/(n+1), times sqrt(c), c the leading coefficient of P_n.
 //
@@ -65,32 +66,22 @@ static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, doubl
   void* tB = ws_get(L, "pl_tB", fb);
   void* eA = ws_get(L, "pl_eA", fb);
   void* eB = ws_get(L, "pl_eB", fb);
-  void* w = ws_get(L, "pl_w", fb);
   const double a = pd.a, b = pd.b;
   const double y0 = (b + a) / (b - a);
   const double ct = 2.0 * (b + a) / (b - a), cw = -4.0 / (b - a);
-  // t0 = in, t1 = y(J) in, e0 = 0, e1 = in (copies by the site kernels, in
-  // their XCD order)
-  const double one[2] = {1.0, 0.0};
-  launch_caxpby(L, tA, one, in, nullptr, nullptr, 0, 1, pr);
-  op_j(L, pr, w, in, kappa, &mu2, 1);
-  const double c1[2] = {(b + a) / (b - a), 0.0}, c2[2] = {-2.0 / (b - a), 0.0};
-  launch_caxpby(L, tB, c1, in, c2, w, 0, 1, pr);
-  launch_caxpby(L, eA, nullptr, nullptr, nullptr, nullptr, 0, 1, pr);  // zero
-  launch_caxpby(L, eB, one, in, nullptr, nullptr, 0, 1, pr);
-  for (int m = 1; m <= pd.n; ++m) {
-    if (m < pd.n) {
-      // J t_m and the step in one pass: tA <- t_{m+1}, eA <- e_{m+1}
-      const ChebStep cs{tA, eB, eA, ct, cw, 2.0 * y0};
-      op_j(L, pr, nullptr, tB, kappa, &mu2, 1, DotOut(), &cs);
-    } else {
-      launch_cheb_step(L, tB, tB, tA, eB, eA, ct, 0.0, 2.0 * y0, 1, pr);  // e_{n+1} only
-    }
+  // t0 = in, e0 = 0, e1 = in; t1 = y(J) in = c1 in + c2 J in from J's epilogue
+  launch_cheb_init(L, in, tA, eA, eB, pr);
+  const double lin[2] = {-2.0 / (b - a), (b + a) / (b - a)};
+  op_j(L, pr, tB, in, kappa, &mu2, 1, DotOut(), nullptr, lin);
+  for (int m = 1; m < pd.n; ++m) {
+    // J t_m and the step in one pass: tA <- t_{m+1}, eA <- e_{m+1}
+    const ChebStep cs{tA, eB, eA, ct, cw, 2.0 * y0};
+    op_j(L, pr, nullptr, tB, kappa, &mu2, 1, DotOut(), &cs);
     std::swap(tA, tB);
     std::swap(eA, eB);
   }
-  const double s[2] = {(2.0 / (b - a)) / cheb_T_above_one(pd.n + 1, y0), 0.0};
-  launch_caxpby(L, out, s, eB, nullptr, nullptr, 0, 1, pr);
+  // out = s e_{n+1}, e_{n+1} = 2 y0 e_n + 2 t_n - e_{n-1}
+  launch_cheb_last(L, tB, eB, eA, out, 2.0 * y0, (2.0 / (b - a)) / cheb_T_above_one(pd.n + 1, y0), pr);
 }
 
 // out = sqrt(c) prod_k (J - z_k) in   (conjugate roots for Q^dag)

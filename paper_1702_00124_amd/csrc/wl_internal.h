@@ -188,9 +188,10 @@ void launch_finish_sum(wl_lattice* L, const double* partials, int stride, int nb
                        double* out_dev);
 // plain device copy of bytes (multiple of 16) from a to b
 void launch_stream_copy(wl_lattice* L, const void* a, void* b, size_t bytes);
-// Chebyshev recurrence step: tprev <- ct t + cw w - tprev ; eprev <- ce e + 2 t - eprev
-void launch_cheb_step(wl_lattice* L, const void* t, const void* w, void* tprev, const void* e, void* eprev,
-                      double ct, double cw, double ce, int nrhs, Prec prec = F64);
+// Chebyshev recurrence start (t0 = in, e0 = 0, e1 = in) and end (out = s (ce e + 2 t - eprev))
+void launch_cheb_init(wl_lattice* L, const void* in, void* t0, void* e0, void* e1, Prec prec);
+void launch_cheb_last(wl_lattice* L, const void* t, const void* e, const void* eprev, void* out, double ce, double s,
+                      Prec prec);
 // CG scalar steps on the device state (see solver.cpp for the layout)
 void launch_cg_alpha(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);
 void launch_cg_beta(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);

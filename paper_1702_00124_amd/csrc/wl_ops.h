@@ -24,9 +24,10 @@ struct ChebStep {
 };
 // even sites: out = K-hat in + mu2[r] in; optional partials of Re<in, out>
 // (one row per rhs, hop_tiles(L, prec) blocks); with cheb, out is not written
-// and the Chebyshev step consumes J in
+// and the Chebyshev step consumes J in; with lin (one rhs), out = lin[0] J in +
+// lin[1] in, from the same last-hop epilogue
 void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const double* mu2, int nrhs,
-          const DotOut& dot = DotOut(), const ChebStep* cheb = nullptr);
+          const DotOut& dot = DotOut(), const ChebStep* cheb = nullptr, const double* lin = nullptr);
 // full lattice (F64 halves back to back, nrhs = 1): M, M^dag, K = M^dag M
 void op_m_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger);
 void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const DotOut& dot = DotOut());
