@@ -36,6 +36,10 @@
  * Errors: every function returns WL_OK (0) or a negative code; nothing throws
  * or aborts across the ABI.  wl_last_error() gives the calling thread's
  * message for the last failure.  All lattice extents must be even.
+ *
+ * Threads: a context (and a batch, with the lattices it holds) is used by one
+ * host thread at a time: calls share its workspace and device-resident solver
+ * state.  Different contexts may be driven from different threads.
  */
 #ifndef WILSON_HMC_H
 #define WILSON_HMC_H
