@@ -150,3 +150,11 @@ def test_cost_checkpoint_files_round_trip(tmp_path):
     ck.save_state(st)
     assert np.array_equal(ck.load_array("links"), U) and ck.load_array("links").dtype == np.complex128
     assert ck.load_state() == st
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says so."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(os.path.dirname(HEADER), "..", "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
