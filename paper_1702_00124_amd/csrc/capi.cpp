@@ -66,6 +66,7 @@ void* ws_get(wl_lattice* L, const std::string& name, size_t bytes) {
     WL_HIP(hipStreamSynchronize(L->stream));
     WL_HIP(hipFree(it->second.first));
     L->ws.erase(it);
+    ++L->ws_gen;
   }
   void* p = nullptr;
   device_alloc(&p, bytes);
@@ -79,6 +80,7 @@ void ensure_partials(wl_lattice* L, size_t n) {
     WL_HIP(hipStreamSynchronize(L->stream));
     WL_HIP(hipFree(L->partials));
     L->partials = nullptr;
+    ++L->ws_gen;
   }
   device_alloc(reinterpret_cast<void**>(&L->partials), n * sizeof(double));
   L->partials_len = n;

@@ -32,10 +32,14 @@ namespace {
 struct CgGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  ~CgGraph() {
+  long long ws_gen = -1;  // the lattice's workspace generation the capture saw
+  void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
   }
+  ~CgGraph() { reset(); }
 };
 
 }  // namespace
@@ -133,8 +137,8 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   // The operator's <p, A p> partial sums (complex for the generic operators:
   // two rows per rhs) come first; the fused update's |r|^2 partial sums follow.
   const bool fuse = size_t(nbrow) * size_t(blas_blocks(L)) <= (size_t(1) << 20);
-  double* rr_part = L->partials + size_t(2) * nrhs * nbrow;
   auto issue_chunk = [&]() {
+    double* rr_part = L->partials + size_t(2) * nrhs * nbrow;  // read afresh: the partials may have grown
     for (int it = 0; it < chunk; ++it) {
       apply_lp(ip, Ap, p, DotOut{L->partials, nbrow});
       if (fuse) {
@@ -163,6 +167,9 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   const long long issue_cap = 4LL * prm.maxiter + chunk;
   while (!all_verified) {
     if (prm.use_graph && chunks > 0) {
+      // a workspace buffer freed since the capture (an FP64 true residual can
+      // grow the operator's buffers) leaves the graph with dead addresses
+      if (cg_graph.exec && cg_graph.ws_gen != L->ws_gen) cg_graph.reset();
       if (!cg_graph.exec) {
         if (!L->capture_stream) WL_HIP(hipStreamCreateWithFlags(&L->capture_stream, hipStreamNonBlocking));
         hipStream_t keep = L->stream;
@@ -190,6 +197,7 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
           L->n_hop_p[q] = hp0[q];
         }
         WL_HIP(hipGraphInstantiate(&cg_graph.exec, cg_graph.graph, nullptr, nullptr, 0));
+        cg_graph.ws_gen = L->ws_gen;
       }
       WL_HIP(hipGraphLaunch(cg_graph.exec, L->stream));
       L->n_hop += hops_per_chunk;

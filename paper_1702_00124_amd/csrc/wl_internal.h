@@ -91,6 +91,9 @@ struct wl_lattice {
   double* hscal = nullptr;                   // pinned host mirror
   hipStream_t capture_stream = nullptr;      // side stream for hipGraph capture
   std::map<std::string, std::pair<void*, size_t>> ws;
+  // bumped whenever a workspace buffer or the partials are freed (grown): a
+  // captured graph that holds their old addresses must be captured again
+  long long ws_gen = 0;
   long long n_hop = 0;                       // hop applications (single rhs units)
   long long n_hop_p[3] = {0, 0, 0};          // ... per storage precision
   long long n_kmat = 0;                      // K-hat / K applications (single rhs units)

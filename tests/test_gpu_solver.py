@@ -241,3 +241,18 @@ def test_cg_breakdown_terminates(inner):
     say(f"  {inner}: rc {rc}, iters {st[0].iters}, reliable updates {st[0].reliable_updates}")
     assert rc == W.WL_ENOCONV and not st[0].converged
     assert np.isfinite(to_np(lat.export_spinor(x))).all()
+
+
+def test_cg_graph_recaptured_after_workspace_grows():
+    """Regression: on a fresh lattice a graph-captured FP32-inner CG whose first
+    FP64 reliable update comes after the capture (threshold 0.001, chunks of 2)
+    grows the operator's workspace in that update; the chunk graph is captured
+    again instead of being replayed with the freed buffers."""
+    L, kappa = (8, 8, 8, 8), 0.155
+    lat, U = make_lattice(L)
+    b = half_noise(L, 2160)
+    x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), kappa, "J", mu2=[0.0],
+                             params=CG(tol=1e-10, inner="f32", delta=0.001, chunk=2, use_graph=True))
+    say(f"  iters {st[0].iters}, reliable updates {st[0].reliable_updates}")
+    assert rc == 0 and st[0].converged
+    assert rel(ow.J(U, to_np(lat.export_spinor(x)), L, kappa, 0.0), b) <= 1.01e-10
