@@ -362,7 +362,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU domain decomposition is a design, not part of this build.", file=sys.stderr)
+              "the multi-GPU domain decomposition is a design only; nothing here uses a second GPU.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
