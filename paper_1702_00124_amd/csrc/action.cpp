@@ -195,12 +195,47 @@ void grad_re_dmhat(wl_lattice* L, double* F, const void* A, const void* B, doubl
 }
 
 // F += coeff * grad Re(Lv^dag dJ Rv)
-void grad_re_dj(wl_lattice* L, double* F, const void* Lv, const void* Rv, double kappa, double coeff) {
-  void* MR = ws_get(L, "gj_M", hbytes(L));
-  op_mhat(L, F64, MR, Rv, kappa, 0, 1);
-  grad_re_dmhat(L, F, MR, Lv, kappa, coeff);
-  op_mhat(L, F64, MR, Lv, kappa, 0, 1);
-  grad_re_dmhat(L, F, MR, Rv, kappa, coeff);
+//   = grad Re((M-hat Rv)^dag dM-hat Lv) + grad Re((M-hat Lv)^dag dM-hat Rv):
+// D_oe Rv and D_oe Lv serve both the M-hat applications and the bilinears'
+// odd halves (six hops; three when Lv and Rv are one field, whose two terms
+// agree).  With jl set, also jl = J Lv = M-hat^dag (M-hat Lv) + mu2 Lv, from
+// the M-hat Lv and (D^dag)_oe M-hat Lv already at hand: one more hop.
+void grad_re_dj(wl_lattice* L, double* F, const void* Lv, const void* Rv, double kappa, double coeff,
+                void* jl = nullptr, double mu2 = 0.0) {
+  const size_t hb = hbytes(L);
+  void* M = ws_get(L, "gj_M", hb);
+  void* Ro = ws_get(L, "gj_Ro", hb);
+  void* Lo = ws_get(L, "gj_Lo", hb);
+  void* Ao = ws_get(L, "gm_Ao", hb);
+  const double k2 = kappa * kappa;
+  const HopEpi plain;
+  // F += cc grad Re((M-hat A)^dag D-part B), given Aodd = D_oe A and Bodd = D_oe B;
+  // leaves M = M-hat A and Ao = (D^dag)_oe M-hat A
+  auto half = [&](const void* A, const void* Aodd, const void* B, const void* Bodd, double cc) {
+    HopEpi mh;
+    mh.x = A;
+    mh.a = -k2;
+    launch_hop(L, F64, M, Aodd, 0, 0, 1, mh);
+    launch_hop(L, F64, Ao, M, 1, 1, 1, plain);
+    launch_bilinear(L, F, M, Ao, B, Bodd, -k2 * cc);
+  };
+  launch_hop(L, F64, Lo, Lv, 1, 0, 1, plain);  // D_oe Lv
+  if (Lv == Rv) {
+    half(Lv, Lo, Lv, Lo, 2.0 * coeff);
+  } else {
+    launch_hop(L, F64, Ro, Rv, 1, 0, 1, plain);  // D_oe Rv
+    half(Rv, Ro, Lv, Lo, coeff);
+    half(Lv, Lo, Rv, Ro, coeff);
+  }
+  if (jl) {
+    HopEpi e;
+    e.x = M;
+    e.a = -k2;
+    e.y = Lv;
+    e.by[0] = mu2;
+    launch_hop(L, F64, jl, Ao, 0, 1, 1, e);  // M-hat^dag M-hat Lv + mu2 Lv
+    L->n_kmat += 1;  // still one multiplication by J in the cost count
+  }
 }
 
 // F += coeff * sum_k grad Re(L_k^dag dJ R_k) over the factors (J - z_k) of Q:
@@ -224,9 +259,8 @@ void chain_grad(wl_lattice* L, double* F, const wl_term& t, const void* right, c
   }
   copy_dev(L, Lv, left_top, fb);
   for (int k = m - 1; k >= 0; --k) {
-    grad_re_dj(L, F, Lv, R[k], t.kappa, coeff);
+    grad_re_dj(L, F, Lv, R[k], t.kappa, coeff, k > 0 ? w : nullptr, t.mu2);  // w = J Lv
     if (k > 0) {
-      op_j(L, F64, w, Lv, t.kappa, &t.mu2, 1);
       const double mzc[2] = {-zr[k], zi[k]};
       launch_caxpby(L, Lv, one, w, mzc, Lv, 0, 1);
     }
