@@ -59,12 +59,13 @@ HOP_BYTES_PER_SITE = {"f64": 8 * 96 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8
 # Valid only for the kernel source they were taken on (hash of the hop
 # kernel sources); otherwise `traffic` is reported as null.  (The hash was
 # moved without new counters when the mixed-volume batch kernel and its launch
-# helper were added to the same source: the device assembly of every existing
+# helper were added to the same source, and again when that kernel's tiles were
+# given XCD-contiguous ranges: each time the device assembly of every other
 # hop kernel was compared before and after and is instruction for instruction
 # the same.)
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_COUNTERS = {
-    "source_sha256": "3bc73960d5c0263c7f6e92d1fd67e7c9494d26199fc362b594a63f40ddb7d342",
+    "source_sha256": "848e9887a18a03b02546138746e2ab9d67595a030a429fbfe6705b85d3b2af68",
     # "precision:variant:workgroup order:streaming": KiB per dispatch on the 16^3x32
     # workload, median of 45 dispatches per configuration
     "per_launch_kib": {
@@ -338,6 +339,47 @@ def kernels_only(lat, Vh, li, torch):
         KERNELS_ONLY_CONFIGS, "then 5 copies of 1 GiB")
 
 
+def solver_kernels(lat, Vh, li, torch, CG, WilsonLattice, WilsonBatch):
+    """Launches of the solver and force kernels for kernel-trace and counter
+    runs, at the trajectory's lattice: three FP32-inner CG solves of J x = b
+    (mu2 0.05, to 1e-10, threshold 0.01, eager launches: the fused CG update and
+    xpay kernels once per iteration), 50 FP32 batched hops over the 8^3x16 +
+    12^3x24 + 16^3x32 mixed-volume batch (one launch each), 50 force bilinears,
+    then 5 device copies of 1 GiB for the counter calibration."""
+    b = lat.import_spinor(torch.from_numpy(li.gaussian_spinor((Vh, 4, 3), li.seed_source(0))))
+    prm = CG(tol=1e-10, inner="f32", delta=MIXED_DELTA)
+    for _ in range(3):
+        _, st, rc = lat.cg_solve(b, KAPPA, "J", mu2=[MU2_HASENBUSCH], params=prm)
+        assert rc == 0
+    vols = [(8, 8, 8, 16), (12, 12, 12, 24), (16, 16, 16, 32)]
+    lats = []
+    for i, Lv in enumerate(vols):
+        lt = WilsonLattice(Lv, t_bc=-1)
+        lt.set_links(torch.from_numpy(li.random_links(Lv, LINK_SPREAD, li.seed_links(10 + i))))
+        lats.append(lt)
+    B = WilsonBatch(lats)
+    bb = B.pack([torch.from_numpy(li.gaussian_spinor((li.volume(Lv) // 2, 4, 3), li.seed_source(200 + i)))
+                 for i, Lv in enumerate(vols)], "f32")
+    for _ in range(50):
+        B.dslash(bb, 0, prec="f32")
+    A = lat.new_field("f64", 1, full=True)
+    A.zero_()
+    F = lat.new_su3()
+    for _ in range(50):
+        lat.force_bilinear(A, A, F)
+    torch.cuda.synchronize()
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"solver-kernels done: 3 FP32-inner CG solves ({st[0].iters} iterations each), 50 batched FP32 hops over",
+        vols, "50 force bilinears, 5 copies of 1 GiB")
+    B.close()
+    for lt in lats:
+        lt.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,6 +398,9 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch the hop kernels (50 per configuration and precision) and a 1 GiB copy, "
                          "for counter runs")
+    ap.add_argument("--solver-kernels", action="store_true",
+                    help="only launch the fused CG kernels (three FP32-inner solves), the mixed-volume batch hop "
+                         "and the force bilinear, and a 1 GiB copy, for counter runs")
     ap.add_argument("--kernels-volume", default=None,
                     help="Lx,Ly,Lz,Lt of the --kernels-only lattice (default the trajectory's 16,16,16,32; "
                          "32,32,32,64 is the large-volume lattice with plaquette ~0.60 links)")
@@ -392,6 +437,9 @@ def main():
     log(f"plaquette {plaq0:.4f}")
     if args.kernels_only:
         kernels_only(lat, Vh, li, torch)
+        return
+    if args.solver_kernels:
+        solver_kernels(lat, Vh, li, torch, CG, WilsonLattice, WilsonBatch)
         return
     tune = lat.autotune()
     log(f"hop autotune (us per launch, candidates in the C API order): {tune}")

@@ -512,8 +512,18 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_batch_kernel(BatchArgs ba) 
     if (ba.d[l].dot)
       for (int i = ba.tile0[l + 1] - ba.tile0[l] + int(threadIdx.x); i < ba.part_len; i += kDpThreads)
         ba.d[l].partials[i] = 0.0;
+  // XCD-aware: with the grid a multiple of 8, the workgroups the hardware puts
+  // on one XCD walk one contiguous eighth of the concatenated tiles, so a
+  // tile's neighbours are mostly read through that XCD's own L2
   const int total = ba.tile0[ba.nlat];
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+  int t0 = blockIdx.x, t1 = total, step = gridDim.x;
+  if ((gridDim.x & 7) == 0) {
+    const int per = (total + 7) >> 3;
+    step = gridDim.x >> 3;
+    t0 = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    t1 = min(total, ((blockIdx.x & 7) + 1) * per);
+  }
+  for (int t = t0; t < t1; t += step) {
     int l = 0;
     while (l + 1 < ba.nlat && t >= ba.tile0[l + 1]) ++l;
     const BatchDesc& d = ba.d[l];
@@ -590,7 +600,9 @@ static int batch_grid(int total) {
     n = std::max(1, cus * per_cu);
     resident[dev].store(n);
   }
-  return std::min(total, n);
+  // a multiple of 8 for the kernel's XCD-aware tile ranges (some workgroups
+  // may find no tile)
+  return (std::min(total, n) + 7) & ~7;
 }
 
 void launch_hop_batch(hipStream_t st, Prec prec, int out_parity, int dagger, const BatchHop* hops, int nlat,
