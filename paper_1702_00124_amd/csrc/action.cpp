@@ -194,49 +194,69 @@ void grad_re_dmhat(wl_lattice* L, double* F, const void* A, const void* B, doubl
   launch_bilinear(L, F, A, Ao, B, Bo, -kappa * kappa * coeff);
 }
 
-// F += coeff * grad Re(Lv^dag dJ Rv)
-//   = grad Re((M-hat Rv)^dag dM-hat Lv) + grad Re((M-hat Lv)^dag dM-hat Rv):
-// D_oe Rv and D_oe Lv serve both the M-hat applications and the bilinears'
-// odd halves (six hops; three when Lv and Rv are one field, whose two terms
-// agree).  With jl set, also jl = J Lv = M-hat^dag (M-hat Lv) + mu2 Lv, from
-// the M-hat Lv and (D^dag)_oe M-hat Lv already at hand: one more hop.
-void grad_re_dj(wl_lattice* L, double* F, const void* Lv, const void* Rv, double kappa, double coeff,
-                void* jl = nullptr, double mu2 = 0.0) {
+// The pieces of M-hat v that Re(L^dag dJ R) and J v share: D_oe v, M-hat v
+// = v - kappa^2 D_eo D_oe v and (D^dag)_oe M-hat v.
+struct HatParts {
+  void* odd;
+  void* m;
+  void* ao;
+};
+
+HatParts hat_ws(wl_lattice* L, const std::string& name) {
   const size_t hb = hbytes(L);
-  void* M = ws_get(L, "gj_M", hb);
-  void* Ro = ws_get(L, "gj_Ro", hb);
-  void* Lo = ws_get(L, "gj_Lo", hb);
-  void* Ao = ws_get(L, "gm_Ao", hb);
-  const double k2 = kappa * kappa;
-  const HopEpi plain;
-  // F += cc grad Re((M-hat A)^dag D-part B), given Aodd = D_oe A and Bodd = D_oe B;
-  // leaves M = M-hat A and Ao = (D^dag)_oe M-hat A
-  auto half = [&](const void* A, const void* Aodd, const void* B, const void* Bodd, double cc) {
-    HopEpi mh;
-    mh.x = A;
-    mh.a = -k2;
-    launch_hop(L, F64, M, Aodd, 0, 0, 1, mh);
-    launch_hop(L, F64, Ao, M, 1, 1, 1, plain);
-    launch_bilinear(L, F, M, Ao, B, Bodd, -k2 * cc);
-  };
-  launch_hop(L, F64, Lo, Lv, 1, 0, 1, plain);  // D_oe Lv
-  if (Lv == Rv) {
-    half(Lv, Lo, Lv, Lo, 2.0 * coeff);
-  } else {
-    launch_hop(L, F64, Ro, Rv, 1, 0, 1, plain);  // D_oe Rv
-    half(Rv, Ro, Lv, Lo, coeff);
-    half(Lv, Lo, Rv, Ro, coeff);
-  }
-  if (jl) {
-    HopEpi e;
-    e.x = M;
-    e.a = -k2;
-    e.y = Lv;
-    e.by[0] = mu2;
-    launch_hop(L, F64, jl, Ao, 0, 1, 1, e);  // M-hat^dag M-hat Lv + mu2 Lv
-    L->n_kmat += 1;  // still one multiplication by J in the cost count
-  }
+  return HatParts{ws_get(L, name + "_o", hb), ws_get(L, name + "_m", hb), ws_get(L, name + "_a", hb)};
 }
+
+// three hops
+void hat_parts(wl_lattice* L, const void* v, double kappa, const HatParts& p) {
+  const HopEpi plain;
+  HopEpi mh;
+  mh.x = v;
+  mh.a = -kappa * kappa;
+  launch_hop(L, F64, p.odd, v, 1, 0, 1, plain);  // D_oe v
+  launch_hop(L, F64, p.m, p.odd, 0, 0, 1, mh);   // M-hat v
+  launch_hop(L, F64, p.ao, p.m, 1, 1, 1, plain);  // (D^dag)_oe M-hat v
+}
+
+// jv = J v = M-hat^dag (M-hat v) + mu2 v from v's parts: one hop, counted as
+// one multiplication by J in the cost count
+void j_from_parts(wl_lattice* L, void* jv, const void* v, const HatParts& p, double kappa, double mu2) {
+  HopEpi e;
+  e.x = p.m;
+  e.a = -kappa * kappa;
+  e.y = v;
+  e.by[0] = mu2;
+  launch_hop(L, F64, jv, p.ao, 0, 1, 1, e);
+  L->n_kmat += 1;
+}
+
+// F += coeff * grad Re(Lv^dag dJ Rv)
+//   = grad Re((M-hat Rv)^dag dM-hat Lv) + grad Re((M-hat Lv)^dag dM-hat Rv),
+// two bilinears on the two fields' parts
+void grad_re_dj_parts(wl_lattice* L, double* F, const void* Lv, const HatParts& lp, const void* Rv,
+                      const HatParts& rp, double kappa, double coeff) {
+  const double c = -kappa * kappa * coeff;
+  launch_bilinear(L, F, rp.m, rp.ao, Lv, lp.odd, c);
+  launch_bilinear(L, F, lp.m, lp.ao, Rv, rp.odd, c);
+}
+
+// the same from the fields alone: six hops, three when Lv and Rv are one
+// field (whose two terms agree)
+void grad_re_dj(wl_lattice* L, double* F, const void* Lv, const void* Rv, double kappa, double coeff) {
+  const HatParts lp = hat_ws(L, "gj_l");
+  hat_parts(L, Lv, kappa, lp);
+  if (Lv == Rv) {
+    launch_bilinear(L, F, lp.m, lp.ao, Lv, lp.odd, -2.0 * kappa * kappa * coeff);
+    return;
+  }
+  const HatParts rp = hat_ws(L, "gj_r");
+  hat_parts(L, Rv, kappa, rp);
+  grad_re_dj_parts(L, F, Lv, lp, Rv, rp, kappa, coeff);
+}
+
+// the chain keeps every R_k's parts from building R_{k+1} while they fit in
+// this many bytes; past it they are recomputed per term (three more hops)
+constexpr size_t kChainKeepBytes = size_t(4) << 30;
 
 // F += coeff * sum_k grad Re(L_k^dag dJ R_k) over the factors (J - z_k) of Q:
 // R_k = prod_{j<k} (J - z_j) right,  L_k = prod_{j>k} (J - conj z_j) left_top
@@ -246,21 +266,30 @@ void chain_grad(wl_lattice* L, double* F, const wl_term& t, const void* right, c
   poly_q_roots(pd, zr, zi);
   const int m = int(zr.size());
   const size_t fb = hbytes(L);
+  const bool keep = size_t(3) * size_t(m) * fb <= kChainKeepBytes;
   std::vector<void*> R(m);
+  std::vector<HatParts> P(keep ? m : 1);
   for (int j = 0; j < m; ++j) R[j] = ws_get(L, "ch_R" + std::to_string(j), fb);
+  for (size_t j = 0; j < P.size(); ++j) P[j] = hat_ws(L, "ch_P" + std::to_string(j));
+  auto parts = [&](int j) -> const HatParts& { return P[keep ? j : 0]; };
+  const HatParts lp = hat_ws(L, "ch_PL");
   void* w = ws_get(L, "ch_w", fb);
   void* Lv = ws_get(L, "ch_L", fb);
   const double one[2] = {1.0, 0.0};
   copy_dev(L, R[0], right, fb);
   for (int j = 0; j + 1 < m; ++j) {
-    op_j(L, F64, w, R[j], t.kappa, &t.mu2, 1);
+    hat_parts(L, R[j], t.kappa, parts(j));
+    j_from_parts(L, w, R[j], parts(j), t.kappa, t.mu2);
     const double mz[2] = {-zr[j], -zi[j]};
     launch_caxpby(L, R[j + 1], one, w, mz, R[j], 0, 1);
   }
   copy_dev(L, Lv, left_top, fb);
   for (int k = m - 1; k >= 0; --k) {
-    grad_re_dj(L, F, Lv, R[k], t.kappa, coeff, k > 0 ? w : nullptr, t.mu2);  // w = J Lv
+    if (!keep || k == m - 1) hat_parts(L, R[k], t.kappa, parts(k));
+    hat_parts(L, Lv, t.kappa, lp);
+    grad_re_dj_parts(L, F, Lv, lp, R[k], parts(k), t.kappa, coeff);
     if (k > 0) {
+      j_from_parts(L, w, Lv, lp, t.kappa, t.mu2);  // w = J Lv
       const double mzc[2] = {-zr[k], zi[k]};
       launch_caxpby(L, Lv, one, w, mzc, Lv, 0, 1);
     }
