@@ -220,7 +220,11 @@ int wl_action(wl_lattice* lat, const wl_term* term, const void* phi, double* S);
 
 /* Fermion force (Sec. 2: dS_F/dU): F += coeff * grad^a S_term, the Lie
  * derivatives d/de S(exp(i e T^a) U_mu(x)) at e = 0.  F: internal su(3)
- * field, accumulated.  S_out: optional host action value (NULL to skip). */
+ * field, accumulated.  S_out: optional host action value (NULL to skip).
+ * The POLY and POLYK_INV forces run over the m root factors of Q and keep
+ * 3m device fields of workspace while those fit in 16 GiB (the environment
+ * variable WL_CHAIN_KEEP_BYTES, a byte count, replaces the bound), else they
+ * recompute them (three more hops per factor, the same result). */
 int fermion_force(wl_lattice* lat, double* F, const wl_term* term, const void* phi, double coeff,
                   double* S_out);
 /* The link-derivative primitive: F += coeff * grad^a Re(A^dag D C) for full

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <functional>
 #include <vector>
 
@@ -255,8 +256,17 @@ void grad_re_dj(wl_lattice* L, double* F, const void* Lv, const void* Rv, double
 }
 
 // the chain keeps every R_k's parts from building R_{k+1} while they fit in
-// this many bytes; past it they are recomputed per term (three more hops)
-constexpr size_t kChainKeepBytes = size_t(4) << 30;
+// 16 GiB (or the byte count in the environment variable WL_CHAIN_KEEP_BYTES);
+// past it they are recomputed per term (three more hops per root factor)
+size_t chain_keep_bytes() {
+  const char* v = std::getenv("WL_CHAIN_KEEP_BYTES");
+  if (v && *v) {
+    char* end = nullptr;
+    const unsigned long long n = std::strtoull(v, &end, 10);
+    if (end && *end == '\0') return size_t(n);
+  }
+  return size_t(16) << 30;
+}
 
 // F += coeff * sum_k grad Re(L_k^dag dJ R_k) over the factors (J - z_k) of Q:
 // R_k = prod_{j<k} (J - z_j) right,  L_k = prod_{j>k} (J - conj z_j) left_top
@@ -266,7 +276,7 @@ void chain_grad(wl_lattice* L, double* F, const wl_term& t, const void* right, c
   poly_q_roots(pd, zr, zi);
   const int m = int(zr.size());
   const size_t fb = hbytes(L);
-  const bool keep = size_t(3) * size_t(m) * fb <= kChainKeepBytes;
+  const bool keep = size_t(3) * size_t(m) * fb <= chain_keep_bytes();
   std::vector<void*> R(m);
   std::vector<HatParts> P(keep ? m : 1);
   for (int j = 0; j < m; ++j) R[j] = ws_get(L, "ch_R" + std::to_string(j), fb);

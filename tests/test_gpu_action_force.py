@@ -171,6 +171,27 @@ def test_poly_force_order16():
         assert rel(F, oact.force(ops, ot, phi)) <= 1e-9
 
 
+def test_poly_force_chain_recompute_path_is_identical(monkeypatch):
+    """The force chain keeps each root factor's M-hat parts while they fit a byte
+    budget (WL_CHAIN_KEEP_BYTES) and recomputes them per term past it: the same
+    hops on the same inputs, so both paths give the same force bit for bit, and
+    the oracle's."""
+    say("POLY / POLYK_INV force, kept vs recomputed chain parts")
+    lat, U = make_lattice(L4)
+    ops = oact.Ops(U, L4)
+    phi = half_noise(L4, 3005)
+    b = lat.import_spinor(torch.from_numpy(phi))
+    for kind in ("POLY", "POLYK_INV"):
+        gt, ot = _term(kind, n=16)
+        monkeypatch.delenv("WL_CHAIN_KEEP_BYTES", raising=False)
+        F_keep = to_np(lat.export_su3(lat.fermion_force(gt, b)))
+        monkeypatch.setenv("WL_CHAIN_KEEP_BYTES", "0")
+        F_re = to_np(lat.export_su3(lat.fermion_force(gt, b)))
+        monkeypatch.delenv("WL_CHAIN_KEEP_BYTES")
+        assert np.array_equal(F_keep, F_re), kind
+        assert rel(F_re, oact.force(ops, ot, phi)) <= 1e-9
+
+
 def _hmc_setup(scale=1):
     terms_g = [Term("POLY", KAPPA, mu2=MU2, degree=4, cg=CG(tol=1e-13)),
                Term("POLYK_INV", KAPPA, mu2=MU2, degree=4, cg=CG(tol=1e-13)),
