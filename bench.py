@@ -391,6 +391,8 @@ def main():
                     help="reliable-update threshold of the trajectory's FP32-inner solves")
     ap.add_argument("--md-poly-chunk", type=int, default=2,
                     help="iterations between convergence checks of the polynomial terms' solves")
+    ap.add_argument("--md-poly-inner", default="f32", choices=("f32", "bf16"),
+                    help="storage precision of the polynomial terms' inner iterations")
     ap.add_argument("--cg-graph", action="store_true",
                     help="the trajectory's solves replay each chunk of CG iterations as a captured HIP graph")
     ap.add_argument("--md-steps", default=",".join(map(str, NSTEPS)),
@@ -448,7 +450,7 @@ def main():
 
     cg_md = CG(tol=1e-10, inner="f32", chunk=8, delta=args.md_delta, use_graph=args.cg_graph)
     # the polynomial solve's operator is degree + 1 J applications: check convergence more often
-    cg_poly = CG(tol=1e-10, inner="f32", chunk=args.md_poly_chunk, delta=args.md_delta)
+    cg_poly = CG(tol=1e-10, inner=args.md_poly_inner, chunk=args.md_poly_chunk, delta=args.md_delta)
     terms = [Term("POLY", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_poly),
              Term("POLYK_INV", KAPPA, mu2=MU2_HASENBUSCH, degree=POLY_N, a=POLY_A, b=POLY_B, cg=cg_poly),
              Term("RATIO", KAPPA, mu2_num=MU2_HASENBUSCH, cg=cg_md)]
