@@ -93,6 +93,36 @@ def test_batch_cg_matches_oracle_residual_and_single_solves(batch, inner, graph)
         assert rel(xg, to_np(lats[i].export_spinor(xsingle))) <= 200 * 2e-10, L
 
 
+MAX8 = [(4, 4, 4, 4), (6, 4, 4, 10), (4, 4, 4, 6), (8, 4, 4, 4), (4, 6, 4, 4), (4, 4, 6, 8), (6, 6, 4, 4),
+        (8, 8, 8, 8)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_of_eight_lattices(prec):
+    """The largest batch: 8 lattices, 63 tiles of 64 sites, two with a ragged last
+    tile, so the eighths of the tile range that the XCDs walk straddle lattice
+    boundaries; each lattice's hop against the oracle.  A ninth lattice is refused."""
+    say("batch of 8", prec)
+    lats, links = [], []
+    for i, L in enumerate(MAX8):
+        lat, U = make_lattice(L, seed=1700 + i)
+        lats.append(lat)
+        links.append(U)
+    B = WilsonBatch(lats)
+    psi = [half_noise(L, 720 + i) for i, L in enumerate(MAX8)]
+    for parity, dagger in ((0, False), (1, True)):
+        out = B.unpack(B.dslash(B.pack([torch.from_numpy(p) for p in psi], prec), parity, dagger, prec), prec)
+        for i, L in enumerate(MAX8):
+            err = rel(to_np(out[i]), ow.hop_eo(links[i], psi[i], L, parity, t_bc=-1, dagger=dagger))
+            assert err <= TOL[prec], (prec, parity, dagger, L, err)
+    extra, _ = make_lattice((4, 4, 4, 4), seed=1799)
+    with pytest.raises(W.WilsonError):
+        WilsonBatch(lats + [extra])
+    B.close()
+    for lat in lats + [extra]:
+        lat.close()
+
+
 def test_batch_of_one_and_errors():
     L = (6, 4, 4, 10)
     lat, U = make_lattice(L)
