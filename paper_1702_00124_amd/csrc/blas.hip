@@ -20,10 +20,11 @@ __device__ __forceinline__ int site_block() { return xcd_block(blockIdx.x, gridD
 
 // ------------------------------------------------------------------ CG update
 // fields are indexed f = rhs * nh + half (nh = 2 for full-lattice fields)
-template <typename P>
-__global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, double* x64, char* r, const char* p,
+// (the iterate x is held in XP: FP64, or FP32 between a mixed CG's reliable updates)
+template <typename P, typename XP>
+__global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, char* xacc, char* r, const char* p,
                                                           const char* Ap, const double* st, size_t stride,
-                                                          size_t stride64, double* partials, int pstride, int nh) {
+                                                          size_t stridex, double* partials, int pstride, int nh) {
   using R = typename P::real;
   __shared__ double lds[kBlock / 64];
   const int f = blockIdx.y;
@@ -38,16 +39,17 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(Geo g, double* x64, c
     Spinor<R> pv = SpinorIO<P>::load(p + off, h, Vh);
     Spinor<R> av = SpinorIO<P>::load(Ap + off, h, Vh);
     Spinor<R> rv = SpinorIO<P>::load(r + off, h, Vh);
-    char* xb = reinterpret_cast<char*>(x64) + f * stride64;
-    Spinor<double> xv = SpinorIO<PrecF64>::load(xb, h, Vh);
+    using XR = typename XP::real;
+    char* xb = xacc + f * stridex;
+    Spinor<XR> xv = SpinorIO<XP>::load(xb, h, Vh);
     const R ar = R(alpha);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      xv.c[k].r += alpha * double(pv.c[k].r);
-      xv.c[k].i += alpha * double(pv.c[k].i);
+      xv.c[k].r = XR(double(xv.c[k].r) + alpha * double(pv.c[k].r));
+      xv.c[k].i = XR(double(xv.c[k].i) + alpha * double(pv.c[k].i));
       rv.c[k] = rv.c[k] - ar * av.c[k];
     }
-    SpinorIO<PrecF64>::store(xb, h, Vh, xv);
+    SpinorIO<XP>::store(xb, h, Vh, xv);
     SpinorIO<P>::store(r + off, h, Vh, rv);
 #pragma unroll
     for (int k = 0; k < 12; ++k) part += double(rv.c[k].r) * double(rv.c[k].r) + double(rv.c[k].i) * double(rv.c[k].i);
@@ -77,10 +79,10 @@ __device__ __forceinline__ double row_sum_all(const double* row, int nb, double*
 // alpha = |r|^2 / <p, A p> from the operator's partial sums (row rhs of pstride,
 // nb_dot entries), then x += alpha p, r -= alpha A p and the |r|^2 partial sums
 // into rr_partials (row rhs of pstride)
-template <typename P>
-__global__ __launch_bounds__(kBlock) void cg_update_fused_kernel(Geo g, double* x64, char* r, const char* p,
+template <typename P, typename XP>
+__global__ __launch_bounds__(kBlock) void cg_update_fused_kernel(Geo g, char* xacc, char* r, const char* p,
                                                                 const char* Ap, double* st, size_t stride,
-                                                                size_t stride64, const double* dot_partials,
+                                                                size_t stridex, const double* dot_partials,
                                                                 int nb_dot, double* rr_partials, int pstride,
                                                                 int nh) {
   using R = typename P::real;
@@ -108,16 +110,17 @@ __global__ __launch_bounds__(kBlock) void cg_update_fused_kernel(Geo g, double* 
     Spinor<R> pv = SpinorIO<P>::load(p + off, h, Vh);
     Spinor<R> av = SpinorIO<P>::load(Ap + off, h, Vh);
     Spinor<R> rv = SpinorIO<P>::load(r + off, h, Vh);
-    char* xb = reinterpret_cast<char*>(x64) + f * stride64;
-    Spinor<double> xv = SpinorIO<PrecF64>::load(xb, h, Vh);
+    using XR = typename XP::real;
+    char* xb = xacc + f * stridex;
+    Spinor<XR> xv = SpinorIO<XP>::load(xb, h, Vh);
     const R ar = R(alpha);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      xv.c[k].r += alpha * double(pv.c[k].r);
-      xv.c[k].i += alpha * double(pv.c[k].i);
+      xv.c[k].r = XR(double(xv.c[k].r) + alpha * double(pv.c[k].r));
+      xv.c[k].i = XR(double(xv.c[k].i) + alpha * double(pv.c[k].i));
       rv.c[k] = rv.c[k] - ar * av.c[k];
     }
-    SpinorIO<PrecF64>::store(xb, h, Vh, xv);
+    SpinorIO<XP>::store(xb, h, Vh, xv);
     SpinorIO<P>::store(r + off, h, Vh, rv);
 #pragma unroll
     for (int k = 0; k < 12; ++k) part += double(rv.c[k].r) * double(rv.c[k].r) + double(rv.c[k].i) * double(rv.c[k].i);
@@ -483,28 +486,75 @@ static void by_prec(Prec p, F&& f) {
   }
 }
 
-void launch_cg_update(wl_lattice* L, Prec prec, void* x64, void* r, const void* p, const void* Ap,
+static void check_xprec(Prec prec, Prec xprec) {
+  WL_REQUIRE(xprec == F64 || (xprec == F32 && prec != F64), WL_EINVAL,
+             "cg: the iterate is FP64, or FP32 under lower-precision storage");
+}
+
+void launch_cg_update(wl_lattice* L, Prec prec, Prec xprec, void* x, void* r, const void* p, const void* Ap,
                       const double* st, int nrhs, int nh, double* partials, int stride) {
+  check_xprec(prec, xprec);
   dim3 grid(blas_blocks(L), nrhs * nh);
   by_prec(prec, [&](auto P) {
     using PT = decltype(P);
-    hipLaunchKernelGGL((cg_update_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (double*)x64, (char*)r,
-                       (const char*)p, (const char*)Ap, st, spinor_bytes(prec, L->Vh), spinor_bytes(F64, L->Vh), partials,
-                       stride, nh);
+    auto go = [&](auto X) {
+      using XT = decltype(X);
+      hipLaunchKernelGGL((cg_update_kernel<PT, XT>), grid, dim3(kBlock), 0, L->stream, L->geo, (char*)x, (char*)r,
+                         (const char*)p, (const char*)Ap, st, spinor_bytes(prec, L->Vh), spinor_bytes(xprec, L->Vh),
+                         partials, stride, nh);
+    };
+    if (xprec == F64) go(PrecF64{});
+    else go(PrecF32{});
   });
   WL_HIP(hipGetLastError());
 }
 
-void launch_cg_update_fused(wl_lattice* L, Prec prec, void* x64, void* r, const void* p, const void* Ap, double* st,
-                            int nrhs, int nh, const double* dot_partials, int nb_dot, double* rr_partials,
-                            int pstride) {
+void launch_cg_update_fused(wl_lattice* L, Prec prec, Prec xprec, void* x, void* r, const void* p, const void* Ap,
+                            double* st, int nrhs, int nh, const double* dot_partials, int nb_dot,
+                            double* rr_partials, int pstride) {
+  check_xprec(prec, xprec);
   dim3 grid(blas_blocks(L), nrhs * nh);
   by_prec(prec, [&](auto P) {
     using PT = decltype(P);
-    hipLaunchKernelGGL((cg_update_fused_kernel<PT>), grid, dim3(kBlock), 0, L->stream, L->geo, (double*)x64,
-                       (char*)r, (const char*)p, (const char*)Ap, st, spinor_bytes(prec, L->Vh),
-                       spinor_bytes(F64, L->Vh), dot_partials, nb_dot, rr_partials, pstride, nh);
+    auto go = [&](auto X) {
+      using XT = decltype(X);
+      hipLaunchKernelGGL((cg_update_fused_kernel<PT, XT>), grid, dim3(kBlock), 0, L->stream, L->geo, (char*)x,
+                         (char*)r, (const char*)p, (const char*)Ap, st, spinor_bytes(prec, L->Vh),
+                         spinor_bytes(xprec, L->Vh), dot_partials, nb_dot, rr_partials, pstride, nh);
+    };
+    if (xprec == F64) go(PrecF64{});
+    else go(PrecF32{});
   });
+  WL_HIP(hipGetLastError());
+}
+
+// x64 += x32 and x32 = 0 over nf fields: a mixed CG's FP32 iterate folded into
+// the FP64 solution before each FP64 true residual
+__global__ __launch_bounds__(kBlock) void cg_fold_kernel(Geo g, char* x64, char* x32, size_t s64, size_t s32) {
+  const int f = blockIdx.y;
+  const int h = site_block() * kBlock + threadIdx.x;
+  const int Vh = g.Vh;
+  if (h >= Vh) return;
+  char* xb = x64 + f * s64;
+  char* yb = x32 + f * s32;
+  Spinor<double> xv = SpinorIO<PrecF64>::load(xb, h, Vh);
+  const Spinor<float> yv = SpinorIO<PrecF32>::load(yb, h, Vh);
+  Spinor<float> z;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    xv.c[k].r += double(yv.c[k].r);
+    xv.c[k].i += double(yv.c[k].i);
+    z.c[k].r = 0.0f;
+    z.c[k].i = 0.0f;
+  }
+  SpinorIO<PrecF64>::store(xb, h, Vh, xv);
+  SpinorIO<PrecF32>::store(yb, h, Vh, z);
+}
+
+void launch_cg_fold(wl_lattice* L, void* x64, void* x32, int nf) {
+  dim3 grid(blas_blocks(L), nf);
+  hipLaunchKernelGGL(cg_fold_kernel, grid, dim3(kBlock), 0, L->stream, L->geo, (char*)x64, (char*)x32,
+                     spinor_bytes(F64, L->Vh), spinor_bytes(F32, L->Vh));
   WL_HIP(hipGetLastError());
 }
 

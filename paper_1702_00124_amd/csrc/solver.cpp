@@ -66,6 +66,10 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   void* Ap = ws_get(L, "cg_Ap", fbi);
   void* r64 = ws_get(L, "cg_r64", fb64);
   void* Ax64 = ws_get(L, "cg_Ax64", fb64);
+  // a mixed CG accumulates its iterations' steps in FP32 and folds them into the
+  // FP64 x before each FP64 true residual (so the update moves half the bytes of x)
+  const Prec xp = mixed ? F32 : F64;
+  void* xa = mixed ? ws_get(L, "cg_x32", spinor_bytes(F32, L->Vh) * nh * nrhs) : x;
   ensure_partials(L, size_t(nrhs) * nbrow * 3 + 64);
   double* st = L->dscal + kCgState;
   const long long kmat0 = L->n_kmat;
@@ -74,6 +78,7 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   // true residual r64 = b - A x (FP64); rr_true[r] = |r64|^2
   std::vector<double> rr_true(nrhs), bb(nrhs);
   auto true_residual = [&]() {
+    if (mixed) launch_cg_fold(L, x, xa, nrhs * nh);
     apply64(Ax64, x);
     ++kmat_extra;
     double ca[2 * kMaxRhs] = {0}, cb[2 * kMaxRhs] = {0};
@@ -86,6 +91,7 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
   };
 
   // ---- initial state: x = x0 (0 unless given), r = b - A x0, p = r
+  if (mixed) zero_dev(L, xa, spinor_bytes(F32, L->Vh) * nh * nrhs);
   norm2_host(L, b, nrhs, bb.data(), nh);
   for (int i = 0; i < nrhs; ++i) WL_REQUIRE(std::isfinite(bb[i]), WL_EINVAL, "cg: non-finite right-hand side");
   if (prm.use_x0) {
@@ -142,11 +148,11 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
     for (int it = 0; it < chunk; ++it) {
       apply_lp(ip, Ap, p, DotOut{L->partials, nbrow});
       if (fuse) {
-        launch_cg_update_fused(L, ip, x, r, p, Ap, st, nrhs, nh, L->partials, nbrow, rr_part, nbrow);
+        launch_cg_update_fused(L, ip, xp, xa, r, p, Ap, st, nrhs, nh, L->partials, nbrow, rr_part, nbrow);
         launch_cg_xpay_fused(L, ip, p, r, st, nrhs, nh, rr_part, nb_upd, nbrow);
       } else {
         launch_cg_alpha(L, L->partials, nbrow, nbrow, st, nrhs);
-        launch_cg_update(L, ip, x, r, p, Ap, st, nrhs, nh, L->partials, nbrow);
+        launch_cg_update(L, ip, xp, xa, r, p, Ap, st, nrhs, nh, L->partials, nbrow);
         launch_cg_beta(L, L->partials, nbrow, nb_upd, st, nrhs);
         launch_cg_xpay(L, ip, p, r, st, nrhs, nh);
       }

@@ -163,19 +163,22 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
 
 // ------------------------------------------------------------------ BLAS-1 (blas.hip)
 int blas_blocks(const wl_lattice* L);
-// x (F64) += alpha[r] p ; r -= alpha[r] Ap ; partial |r|^2   (p, r, Ap in prec);
-// alpha and the done flags are read from the device CG state st
-// (nh = 2 when every rhs is a full-lattice field of two halves)
-void launch_cg_update(wl_lattice* L, Prec prec, void* x64, void* r, const void* p, const void* Ap,
+// x += alpha[r] p ; r -= alpha[r] Ap ; partial |r|^2   (p, r, Ap in prec; x in
+// xprec: F64, or F32 when prec is F32 or BF16); alpha and the done flags are
+// read from the device CG state st (nh = 2 when every rhs is a full-lattice
+// field of two halves)
+void launch_cg_update(wl_lattice* L, Prec prec, Prec xprec, void* x, void* r, const void* p, const void* Ap,
                       const double* st, int nrhs, int nh, double* partials, int stride);
+// x64 += x32, x32 = 0 (nf fields; x64 F64, x32 F32)
+void launch_cg_fold(wl_lattice* L, void* x64, void* x32, int nf);
 // p = r + beta[r] p
 void launch_cg_xpay(wl_lattice* L, Prec prec, void* p, const void* r, const double* st, int nrhs, int nh);
 // the CG iteration's two vector kernels with alpha and beta derived inside
 // (the operator's <p, A p> partial sums: rows of pstride, nb_dot entries; the
 // |r|^2 partial sums go to rr_partials, rows of pstride, nh * blas blocks entries)
-void launch_cg_update_fused(wl_lattice* L, Prec prec, void* x64, void* r, const void* p, const void* Ap, double* st,
-                            int nrhs, int nh, const double* dot_partials, int nb_dot, double* rr_partials,
-                            int pstride);
+void launch_cg_update_fused(wl_lattice* L, Prec prec, Prec xprec, void* x, void* r, const void* p, const void* Ap,
+                            double* st, int nrhs, int nh, const double* dot_partials, int nb_dot,
+                            double* rr_partials, int pstride);
 void launch_cg_xpay_fused(wl_lattice* L, Prec prec, void* p, const void* r, double* st, int nrhs, int nh,
                           const double* rr_partials, int nb_rr, int pstride);
 // dst = convert(src), both nrhs half fields
