@@ -387,7 +387,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--quick", action="store_true", help="skip the CG comparison legs")
-    ap.add_argument("--md-delta", type=float, default=0.01,
+    ap.add_argument("--md-delta", type=float, default=0.003,
                     help="reliable-update threshold of the trajectory's FP32-inner solves")
     ap.add_argument("--md-poly-chunk", type=int, default=2,
                     help="iterations between convergence checks of the polynomial terms' solves")
