@@ -395,6 +395,9 @@ def main():
                     help="storage precision of the polynomial terms' inner iterations")
     ap.add_argument("--cg-graph", action="store_true",
                     help="the trajectory's solves replay each chunk of CG iterations as a captured HIP graph")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of hop autotuning results for the trajectory's lattice: read on a hit, "
+                         "written otherwise (a profiled run takes the configurations an unprofiled run tuned)")
     ap.add_argument("--md-steps", default=",".join(map(str, NSTEPS)),
                     help="integrator steps per scale (poly, poly-K inverse, ratio, gauge); profiling runs shorten them")
     ap.add_argument("--kernels-only", action="store_true",
@@ -443,7 +446,13 @@ def main():
     if args.solver_kernels:
         solver_kernels(lat, Vh, li, torch, CG, WilsonLattice, WilsonBatch)
         return
-    tune = lat.autotune()
+    if args.tune_cache:
+        from paper_1702_00124_amd import _lib as W
+        from paper_1702_00124_amd.lattice import tune_cache_key, tune_cache_read, tune_device_id
+        key = tune_cache_key(L, tune_device_id(0), W.LIB_PATH)
+        hit = tune_cache_read(args.tune_cache, key) is not None
+        log(f"hop tuning cache {args.tune_cache}: key {key}, {'hit' if hit else 'miss (tuning now)'}")
+    tune = lat.autotune(cache=args.tune_cache)
     log(f"hop autotune (us per launch, candidates in the C API order): {tune}")
     log("hop configurations kept (variant, npass, use_xcd, stream) for 1, 2-4, 5-16 rhs:",
         {p: [lat.hop_config(p, k) for k in range(3)] for p in ("f64", "f32", "bf16")})

@@ -362,10 +362,10 @@ class WilsonLattice:
         each per (stream, use_xcd) = (0, 1), (0, 0), (1, 1), (1, 0).
 
         cache: a JSON file of earlier results keyed by lattice extents, device
-        name and library build; on a hit the stored configurations are set and
+        (ISA, compute units, memory) and library build; on a hit the stored configurations are set and
         their timings returned without timing anything, else the tuning result
         is added to the file."""
-        key = tune_cache_key(self.L, torch.cuda.get_device_name(self.device), W.LIB_PATH) if cache else None
+        key = tune_cache_key(self.L, tune_device_id(self.device), W.LIB_PATH) if cache else None
         if key:
             hit = tune_cache_read(cache, key)
             if hit is not None:
@@ -413,6 +413,14 @@ class WilsonLattice:
         a, b = C.c_longlong(), C.c_longlong()
         W.check(self.lib.wl_counters(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+
+def tune_device_id(device) -> str:
+    """The device as the tuning cache knows it: ISA, compute units and memory
+    size (the marketing name can read empty, e.g. under a profiler)."""
+    pr = torch.cuda.get_device_properties(device)
+    arch = getattr(pr, "gcnArchName", "") or pr.name
+    return f"{arch.split(':')[0]}/{pr.multi_processor_count}cu/{pr.total_memory >> 30}GiB"
 
 
 def tune_cache_key(L: Sequence[int], device_name: str, lib_path: str) -> str:
