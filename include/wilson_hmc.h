@@ -112,9 +112,10 @@ int apply_K(wl_lattice* lat, void* out, const void* in, double kappa, const doub
  * in FP64; a rhs whose x0 already meets tol takes 0 iterations; x of a zero
  * source is set to 0); stops when the FP64 true residual |b - A x| <= tol |b|
  * for every rhs.  inner = WL_F64 runs plain FP64 CG; WL_F32 / WL_BF16 run the
- * inner iteration with that storage (FP32 arithmetic, FP64 dot products) and
- * FP64 reliable updates r = b - A x whenever the iterated residual fell by
- * delta since the last update.  x and b: internal F64 fields.  stats: host
+ * inner iteration with that storage (FP32 arithmetic, FP64 dot products, the
+ * steps accumulated in an FP32 copy of x that is added to the FP64 x before
+ * each update) and FP64 reliable updates r = b - A x whenever the iterated
+ * residual fell by delta since the last update.  x and b: internal F64 fields.  stats: host
  * array of nrhs entries (may be NULL).  Returns WL_ENOCONV, with x the last
  * iterate and stats filled, if some rhs misses tol within maxiter, or keeps
  * breaking down (a non-positive <p, A p>: an operator that is not positive
