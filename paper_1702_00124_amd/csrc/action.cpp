@@ -172,7 +172,22 @@ void solve_poly(wl_lattice* L, void* x, const void* b, const wl_term& t, int mod
   const PolyDesc pd = pdesc(t);
   auto apply = [&](Prec pr, void* out, const void* in) { poly_apply(L, mode, out, in, t.kappa, t.mu2, pd, pr); };
   wl_cg_params cg = t.cg;
-  chrono_in(L, ch, x, b, [&](void* out, const void* in) { apply(F64, out, in); }, cg);
+  // the guess needs the operator on each stored solution: in FP32 when the
+  // solve iterates in lower precision (the guess is only a starting point;
+  // convergence is still judged on the FP64 residual)
+  const Prec gp = Prec(cg.inner) == F64 ? F64 : F32;
+  auto apply_guess = [&](void* out, const void* in) {
+    if (gp == F64) {
+      apply(F64, out, in);
+      return;
+    }
+    void* a = ws_get(L, "pg_in", spinor_bytes(gp, L->Vh));
+    void* o = ws_get(L, "pg_out", spinor_bytes(gp, L->Vh));
+    launch_convert(L, gp, a, F64, in, 1);
+    apply(gp, o, a);
+    launch_convert(L, F64, out, gp, o, 1);
+  };
+  chrono_in(L, ch, x, b, apply_guess, cg);
   const int rc = cg_run_generic(L, x, b, apply, cg, &st);
   chrono_out(L, ch, x);
   if (iters) *iters += st.iters;

@@ -312,15 +312,19 @@ def test_paper_action_trajectory_matches_oracle(action):
     assert r.accepted and rel(to_np(lat.get_links()), r.U) <= 1e-10
 
 
-@pytest.mark.parametrize("depth", [1, 4])
-def test_hmc_chronological_guess_matches_cold_start(depth):
+@pytest.mark.parametrize("depth,inner", [(1, "f64"), (4, "f64"), (4, "f32")])
+def test_hmc_chronological_guess_matches_cold_start(depth, inner):
     """WL_HMC_CHRONO: each force solve starts from the minimal-residual
     extrapolation over its term's last `depth` solutions.  Same end point as
-    x0 = 0 up to the solver tolerance (1e-13: the forces differ by <= cond *
-    2e-13), in fewer CG iterations."""
-    say("hmc chronological initial guess, depth", depth)
+    x0 = 0 up to the solver tolerance (1e-13 in FP64, 1e-12 with FP32 inner
+    iterations, where the polynomial terms build their guess with the FP32
+    operator: the forces differ by <= cond * 2 tol), in fewer CG iterations."""
+    import dataclasses
+    say("hmc chronological initial guess, depth", depth, "inner", inner)
     L = (6, 4, 4, 10)
     terms_g, _, nsteps = _hmc_setup(scale=2)
+    if inner != "f64":
+        terms_g = [dataclasses.replace(t, cg=CG(tol=1e-12, inner=inner)) for t in terms_g]
     Vh = li.volume(L) // 2
     P0 = li.gaussian_momenta(L, li.seed_md(3, 15))
     out = []
