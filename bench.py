@@ -341,9 +341,10 @@ def kernels_only(lat, Vh, li, torch):
 
 def solver_kernels(lat, Vh, li, torch, CG, WilsonLattice, WilsonBatch):
     """Launches of the solver and force kernels for kernel-trace and counter
-    runs, at the trajectory's lattice: three FP32-inner CG solves of J x = b
-    (mu2 0.05, to 1e-10, threshold 0.01, eager launches: the fused CG update and
-    xpay kernels once per iteration), 50 FP32 batched hops over the 8^3x16 +
+    runs, on the given lattice: three FP32-inner CG solves of J x = b (mu2
+    0.05, to 1e-10, threshold 0.01, eager launches: the CG update and xpay
+    kernels once per iteration, fused with the scalar steps where the
+    reduction rows are short), 50 FP32 batched hops over the 8^3x16 +
     12^3x24 + 16^3x32 mixed-volume batch (one launch each), 50 force bilinears,
     then 5 device copies of 1 GiB for the counter calibration."""
     b = lat.import_spinor(torch.from_numpy(li.gaussian_spinor((Vh, 4, 3), li.seed_source(0))))
@@ -407,7 +408,7 @@ def main():
                     help="only launch the fused CG kernels (three FP32-inner solves), the mixed-volume batch hop "
                          "and the force bilinear, and a 1 GiB copy, for counter runs")
     ap.add_argument("--kernels-volume", default=None,
-                    help="Lx,Ly,Lz,Lt of the --kernels-only lattice (default the trajectory's 16,16,16,32; "
+                    help="Lx,Ly,Lz,Lt of the --kernels-only or --solver-kernels lattice (default the trajectory's 16,16,16,32; "
                          "32,32,32,64 is the large-volume lattice with plaquette ~0.60 links)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -422,13 +423,17 @@ def main():
     from paper_1702_00124_amd.lattice import CG, Term, WilsonBatch, WilsonLattice
 
     torch.cuda.set_device(0)
-    if args.kernels_only and args.kernels_volume:
+    if (args.kernels_only or args.solver_kernels) and args.kernels_volume:
         Lk = tuple(int(v) for v in args.kernels_volume.split(","))
         assert len(Lk) == 4
         lat = WilsonLattice(Lk, t_bc=-1)
         lat.set_links(torch.from_numpy(li.random_links(Lk, 0.432, li.seed_links(4))))
-        log(f"kernels-only lattice {Lk}, plaquette {lat.plaquette():.4f}")
-        kernels_only(lat, li.volume(Lk) // 2, li, torch)
+        log(f"{'kernels-only' if args.kernels_only else 'solver-kernels'} lattice {Lk}, "
+            f"plaquette {lat.plaquette():.4f}")
+        if args.kernels_only:
+            kernels_only(lat, li.volume(Lk) // 2, li, torch)
+        else:
+            solver_kernels(lat, li.volume(Lk) // 2, li, torch, CG, WilsonLattice, WilsonBatch)
         return
     Vh = L[0] * L[1] * L[2] * L[3] // 2
     nsteps = [int(v) for v in args.md_steps.split(",")]

@@ -275,9 +275,26 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(Geo g, const char* x, const
 }
 
 // one workgroup per row
+// threads of the alpha kernel, whose row holds one partial sum per hop tile
+// (16384 at 32^3 x 64); the |r|^2 rows are four times shorter and keep kBlock
+constexpr int kRowThreads = 1024;
+
 __device__ __forceinline__ double row_sum(const double* partials, int stride, int nb, int row, double* lds) {
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partials[row * stride + b];
+  // eight accumulators per thread, so that its loads are in flight together
+  // rather than one after another (rows reach 16384 entries at 32^3 x 64);
+  // the order is fixed, so every call sums a row alike
+  const double* p = partials + size_t(row) * size_t(stride);
+  const int nt = blockDim.x;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int b = threadIdx.x;
+  for (; b + 7 * nt < nb; b += 8 * nt) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += p[b + k * nt];
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k)  // fewer than 8 left
+    if (b + k * nt < nb) a[k] += p[b + k * nt];
+  const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   return block_sum(s, lds);
 }
 
@@ -288,8 +305,8 @@ __global__ __launch_bounds__(kBlock) void finish_sum_kernel(const double* partia
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void cg_alpha_kernel(const double* partials, int stride, int nb, double* st) {
-  __shared__ double lds[kBlock / 64];
+__global__ __launch_bounds__(kRowThreads) void cg_alpha_kernel(const double* partials, int stride, int nb, double* st) {
+  __shared__ double lds[kRowThreads / 64];
   const int r = blockIdx.x;
   const double pAp = row_sum(partials, stride, nb, r, lds);
   if (threadIdx.x == 0) {
@@ -625,7 +642,7 @@ void launch_finish_sum(wl_lattice* L, const double* partials, int stride, int nb
 }
 
 void launch_cg_alpha(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs) {
-  hipLaunchKernelGGL(cg_alpha_kernel, dim3(nrhs), dim3(kBlock), 0, L->stream, partials, stride, nb, st);
+  hipLaunchKernelGGL(cg_alpha_kernel, dim3(nrhs), dim3(kRowThreads), 0, L->stream, partials, stride, nb, st);
   WL_HIP(hipGetLastError());
 }
 
