@@ -106,6 +106,20 @@ typedef enum {
 int apply_K(wl_lattice* lat, void* out, const void* in, double kappa, const double* mu2, int nrhs,
             wl_op op, wl_prec prec);
 
+/* apply_K without device allocation, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operators, kernels and results as apply_K, with the
+ * operator's intermediates in a fixed 256 MiB device scratch array that the
+ * library holds on every device it runs on until the process ends (set up
+ * when a context is created on that device).  Scratch needed: WL_OP_J two
+ * internal half fields of nrhs rhs, WL_OP_MHAT / WL_OP_MHAT_DAG one,
+ * WL_OP_K one full field, WL_OP_M / WL_OP_MDAG none.  WL_EINVAL (and
+ * nothing launched) when that exceeds 256 MiB.  Every call on one device
+ * shares that device's scratch: calls that overlap on one device (other
+ * streams or threads) race.  Hop timing samples (wl_profile) are not taken. */
+int apply_K_noalloc(wl_lattice* lat, void* out, const void* in, double kappa, const double* mu2, int nrhs,
+                    wl_op op, wl_prec prec);
+
 /* Conjugate gradient (Sec. 2: inversion of K by CG) on op = WL_OP_J (even
  * sites, nrhs right-hand sides, shifts mu2[r]) or WL_OP_K (full lattice,
  * nrhs = 1).  x0 = 0, or the contents of x when use_x0 = 1 (then r = b - A x0

@@ -68,6 +68,7 @@ SIGNATURES = {
     "wl_export_su3": (I, [P, P, P]),
     "wilson_dslash": (I, [P, P, P, I, I, I, I]),
     "apply_K": (I, [P, P, P, D, C.POINTER(D), I, I, I]),
+    "apply_K_noalloc": (I, [P, P, P, D, C.POINTER(D), I, I, I]),
     "cg_solve": (I, [P, P, P, D, C.POINTER(D), I, I, C.POINTER(CgParams), C.POINTER(CgStats)]),
     "cg_multishift": (I, [P, P, P, D, C.POINTER(D), I, I, C.POINTER(CgParams), C.POINTER(CgStats)]),
     "poly_filter_apply": (I, [P, P, P, D, D, C.POINTER(Poly), I]),

@@ -30,7 +30,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 SOURCES = ["capi.cpp", "ops.cpp", "solver.cpp", "poly.cpp", "action.cpp", "hmc.cpp",
-           "batch.cpp", "dslash.hip", "blas.hip", "pack.hip", "force.hip"]
+           "batch.cpp", "dslash.hip", "blas.hip", "pack.hip", "force.hip", "noalloc.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -9,6 +9,9 @@
 #include "wl_ops.h"
 
 namespace wl {
+void scratch_register(int device);
+void* scratch_ptr(int device);
+size_t scratch_limit();
 int hmc_run(wl_lattice* L, const wl_hmc_params& prm, double* P, const void* chi, double u, wl_hmc_result* res);
 double plaquette_host(wl_lattice* L);
 struct Event {
@@ -107,6 +110,7 @@ int wl_create(wl_lattice** out, const int32_t Ls[4], int32_t t_bc, void* hip_str
     wl_lattice* L = new wl_lattice();
     try {
       WL_HIP(hipGetDevice(&L->device));
+      scratch_register(L->device);
       for (int m = 0; m < 4; ++m) {
         L->L[m] = Ls[m];
         L->geo.L[m] = Ls[m];
@@ -282,6 +286,36 @@ int apply_K(wl_lattice* L, void* out, const void* in, double kappa, const double
     WL_REQUIRE(out && in && out != in, WL_EINVAL, "null or aliased field");
     set_device(L);
     op_apply(L, op, Prec(prec), out, in, kappa, mu2, nrhs);
+    return WL_OK;
+  });
+}
+
+int apply_K_noalloc(wl_lattice* L, void* out, const void* in, double kappa, const double* mu2, int nrhs, wl_op op,
+                    wl_prec prec) {
+  return guard([&]() {
+    check_lat(L);
+    check_prec_rhs(prec, nrhs);
+    WL_REQUIRE(out && in && out != in, WL_EINVAL, "null or aliased field");
+    WL_REQUIRE(op >= WL_OP_M && op <= WL_OP_J, WL_EINVAL, "unknown operator");
+    WL_REQUIRE(nrhs == 1 || op == WL_OP_J || op == WL_OP_MHAT || op == WL_OP_MHAT_DAG, WL_EUNSUPPORTED,
+               "full-lattice operators take one rhs");
+    const size_t need = op_scratch_bytes(L, op, Prec(prec), nrhs);
+    WL_REQUIRE(need <= scratch_limit(), WL_EINVAL,
+               "apply_K_noalloc: this operator needs " + std::to_string(need) + " bytes of scratch, above the "
+               "fixed " + std::to_string(scratch_limit()) + "-byte limit (use apply_K)");
+    set_device(L);
+    char* base = static_cast<char*>(scratch_ptr(L->device));
+    OpScratch scr;
+    scr.odd = base;
+    scr.even = base + op_scratch_bytes(L, WL_OP_MHAT, Prec(prec), nrhs);  // J: after the odd fields
+    L->prof_suspended = 1;  // no timing events from this call
+    try {
+      op_apply(L, op, Prec(prec), out, in, kappa, mu2, nrhs, DotOut(), &scr);
+    } catch (...) {
+      L->prof_suspended = 0;
+      throw;
+    }
+    L->prof_suspended = 0;
     return WL_OK;
   });
 }

@@ -686,7 +686,8 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
   const HopConfig& cfg = L->hop_cfg[prec][hop_kind(nrhs)];
   a.use_xcd = cfg.use_xcd;
   // sampled event timing (never inside a graph capture)
-  const bool timed = L->prof_on && !L->prof_capturing && nrhs == 1 && L->prof_ev[prec].size() < 2 * kProfPairs;
+  const bool timed = L->prof_on && !L->prof_capturing && !L->prof_suspended && nrhs == 1 &&
+                     L->prof_ev[prec].size() < 2 * kProfPairs;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     WL_HIP(hipEventCreate(&e0));

@@ -14,8 +14,19 @@ void copy_dev(wl_lattice* L, void* dst, const void* src, size_t bytes) {
 
 void zero_dev(wl_lattice* L, void* dst, size_t bytes) { WL_HIP(hipMemsetAsync(dst, 0, bytes, L->stream)); }
 
-void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger, int nrhs) {
-  void* odd = ws_get(L, "op_odd", spinor_bytes(prec, L->Vh) * nrhs);
+size_t op_scratch_bytes(const wl_lattice* L, int op, Prec prec, int nrhs) {
+  const size_t fb = spinor_bytes(prec, L->Vh) * size_t(nrhs);
+  switch (op) {
+    case WL_OP_J: return 2 * fb;                              // odd and even intermediates
+    case WL_OP_MHAT: case WL_OP_MHAT_DAG: return fb;          // odd intermediate
+    case WL_OP_K: return 2 * spinor_bytes(prec, L->Vh);       // full-lattice M in
+    default: return 0;
+  }
+}
+
+void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger, int nrhs,
+             const OpScratch* scr) {
+  void* odd = scr ? scr->odd : ws_get(L, "op_odd", spinor_bytes(prec, L->Vh) * nrhs);
   HopEpi e1;
   launch_hop(L, prec, odd, in, 1, dagger, nrhs, e1);
   HopEpi e2;
@@ -25,11 +36,11 @@ void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, 
 }
 
 void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const double* mu2, int nrhs,
-          const DotOut& dot, const ChebStep* cheb, const double* lin) {
+          const DotOut& dot, const ChebStep* cheb, const double* lin, const OpScratch* scr) {
   WL_REQUIRE(!lin || (nrhs == 1 && !cheb && !dot.partials), WL_EINVAL, "op_j: lin takes one rhs, no dot or step");
   const size_t fb = spinor_bytes(prec, L->Vh) * nrhs;
-  void* odd = ws_get(L, "op_odd", fb);
-  void* v = ws_get(L, "op_even", fb);
+  void* odd = scr ? scr->odd : ws_get(L, "op_odd", fb);
+  void* v = scr ? scr->even : ws_get(L, "op_even", fb);
   HopEpi e;
   launch_hop(L, prec, odd, in, 1, 0, nrhs, e);  // D_oe in
   e.x = in;
@@ -88,9 +99,10 @@ void op_m_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa
   launch_hop(L, prec, oo, ie, 1, dagger, 1, e);
 }
 
-void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const DotOut& dot) {
+void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const DotOut& dot,
+               const OpScratch* scr) {
   const size_t hb = spinor_bytes(prec, L->Vh);
-  char* t = static_cast<char*>(ws_get(L, "op_full", 2 * hb));
+  char* t = static_cast<char*>(scr ? scr->odd : ws_get(L, "op_full", 2 * hb));
   op_m_full(L, prec, t, in, kappa, 0);
   const char* ie = static_cast<const char*>(in);
   char* oe = static_cast<char*>(out);
@@ -113,15 +125,15 @@ void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa
 }
 
 void op_apply(wl_lattice* L, int op, Prec prec, void* out, const void* in, double kappa, const double* mu2,
-              int nrhs, const DotOut& dot) {
+              int nrhs, const DotOut& dot, const OpScratch* scr) {
   switch (op) {
-    case WL_OP_J: op_j(L, prec, out, in, kappa, mu2, nrhs, dot); break;
+    case WL_OP_J: op_j(L, prec, out, in, kappa, mu2, nrhs, dot, nullptr, nullptr, scr); break;
     case WL_OP_K:
       WL_REQUIRE(nrhs == 1, WL_EUNSUPPORTED, "full-lattice K takes one rhs");
-      op_k_full(L, prec, out, in, kappa, dot);
+      op_k_full(L, prec, out, in, kappa, dot, scr);
       break;
-    case WL_OP_MHAT: op_mhat(L, prec, out, in, kappa, 0, nrhs); break;
-    case WL_OP_MHAT_DAG: op_mhat(L, prec, out, in, kappa, 1, nrhs); break;
+    case WL_OP_MHAT: op_mhat(L, prec, out, in, kappa, 0, nrhs, scr); break;
+    case WL_OP_MHAT_DAG: op_mhat(L, prec, out, in, kappa, 1, nrhs, scr); break;
     case WL_OP_M:
       WL_REQUIRE(nrhs == 1, WL_EUNSUPPORTED, "full-lattice M takes one rhs");
       op_m_full(L, prec, out, in, kappa, 0);

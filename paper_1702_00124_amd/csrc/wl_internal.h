@@ -105,6 +105,7 @@ struct wl_lattice {
   // optional event timing of sampled hop launches, per storage precision
   int prof_on = 0;
   int prof_capturing = 0;
+  int prof_suspended = 0;               // set by entry points that must not create events
   std::vector<hipEvent_t> prof_ev[3];   // start/stop pairs
   double prof_ms[3] = {0, 0, 0};
   long long prof_n[3] = {0, 0, 0};

@@ -12,8 +12,19 @@ struct DotOut {
   int stride = 0;
 };
 
+// intermediates of the operators supplied by the caller instead of the
+// workspace: odd = the D_oe result (J, M-hat; nrhs fields) or, for the
+// full-lattice K, the full M in (two halves); even = J's g5 M-hat in
+struct OpScratch {
+  void* odd = nullptr;
+  void* even = nullptr;
+};
+// bytes of caller-supplied intermediates op needs (odd followed by even)
+size_t op_scratch_bytes(const wl_lattice* L, int op, Prec prec, int nrhs);
+
 // even sites: out = M-hat in (dagger: M-hat^dag), nrhs fields of precision prec
-void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger, int nrhs);
+void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger, int nrhs,
+             const OpScratch* scr = nullptr);
 // one step of the Chebyshev recurrence fused into J's last hop (one rhs):
 // tprev <- ct in + cw J in - tprev, eprev <- ce e + 2 in - eprev
 struct ChebStep {
@@ -27,13 +38,15 @@ struct ChebStep {
 // and the Chebyshev step consumes J in; with lin (one rhs), out = lin[0] J in +
 // lin[1] in, from the same last-hop epilogue
 void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const double* mu2, int nrhs,
-          const DotOut& dot = DotOut(), const ChebStep* cheb = nullptr, const double* lin = nullptr);
+          const DotOut& dot = DotOut(), const ChebStep* cheb = nullptr, const double* lin = nullptr,
+          const OpScratch* scr = nullptr);
 // full lattice (F64 halves back to back, nrhs = 1): M, M^dag, K = M^dag M
 void op_m_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, int dagger);
-void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const DotOut& dot = DotOut());
+void op_k_full(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const DotOut& dot = DotOut(),
+               const OpScratch* scr = nullptr);
 // generic dispatch used by the solver; dot rows hold 2 * blocks for the full lattice
 void op_apply(wl_lattice* L, int op, Prec prec, void* out, const void* in, double kappa, const double* mu2,
-              int nrhs, const DotOut& dot = DotOut());
+              int nrhs, const DotOut& dot = DotOut(), const OpScratch* scr = nullptr);
 inline int op_dot_blocks(const wl_lattice* L, int op, Prec prec) {
   return (op == WL_OP_K ? 2 : 1) * hop_tiles(L, prec);
 }

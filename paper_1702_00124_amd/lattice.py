@@ -220,6 +220,19 @@ class WilsonLattice:
         W.check(self.lib.apply_K(self.h, _ptr(out), _ptr(buf), kappa, m, nrhs, OPS[op], _prec(prec)))
         return out
 
+    def apply_K_noalloc(self, buf: torch.Tensor, out: torch.Tensor, kappa: float, op: str = "J",
+                        mu2: Sequence[float] = (0.0,), prec="f64", nrhs: int = 1) -> torch.Tensor:
+        """apply_K with the operator's intermediates in the library's fixed device
+        scratch: no device allocation in the call (the caller passes out)."""
+        full = op in ("M", "MDAG", "K")
+        if 1 <= nrhs <= 16:
+            need = self.field_bytes(prec, nrhs) * (2 if full else 1)
+            _need(buf, need, "input")
+            _need(out, need, "output")
+        m = (C.c_double * max(nrhs, 1))(*list(mu2)[:nrhs]) if mu2 is not None else None
+        W.check(self.lib.apply_K_noalloc(self.h, _ptr(out), _ptr(buf), kappa, m, nrhs, OPS[op], _prec(prec)))
+        return out
+
     def cg_solve(self, b: torch.Tensor, kappa: float, op: str = "J", mu2: Sequence[float] = (0.0,), nrhs: int = 1,
                  params: Optional[CG] = None, x: Optional[torch.Tensor] = None):
         params = params or CG()
