@@ -42,3 +42,29 @@ def bilinear_grad(U, A, C, L, t_bc=-1) -> np.ndarray:
         Wm = np.einsum("xab,xbc->xac", Ub, Xi) - np.einsum("xab,xbc->xac", Theta, su3.dagger(Ub))
         out[mu] = su3.grad_from_matrix(Wm)
     return out
+
+
+def bilinear_grad_at(U, A, C, L, links, t_bc=-1) -> np.ndarray:
+    """bilinear_grad evaluated only at the listed links, written link by link from the
+    same definition (the two terms of Re(A^dag D C) that hold U_mu(x)): for large
+    lattices, where sampled links check a full-size force.
+
+    links: sequence of (mu, x), x a flat full-lattice site index.  Returns [n, 8]."""
+    g = lat.gammas()
+    one = np.eye(4)
+    out = np.zeros((len(links), 8))
+    for i, (mu, x) in enumerate(links):
+        c = [x % L[0], (x // L[0]) % L[1], (x // (L[0] * L[1])) % L[2], x // (L[0] * L[1] * L[2])]
+        c[mu] += 1
+        wrapped = c[mu] == L[mu]
+        c[mu] %= L[mu]
+        y = c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]))
+        ph = float(t_bc) if (wrapped and mu == 3) else 1.0
+        Ub = ph * U[mu][x]                                   # U_mu(x) with its fermion phase
+        PAx = (one - g[mu]) @ A[x]                           # [(1 - g_mu) A(x)], 4 x 3
+        PAy = (one + g[mu]) @ A[y]                           # [(1 + g_mu) A(y)]
+        Xi = sum(np.outer(C[y][s], np.conj(PAx[s])) for s in range(4))
+        Theta = sum(np.outer(C[x][s], np.conj(PAy[s])) for s in range(4))
+        Wm = Ub @ Xi - Theta @ np.conj(Ub.T)
+        out[i] = su3.grad_from_matrix(Wm)
+    return out

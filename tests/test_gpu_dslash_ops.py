@@ -13,7 +13,7 @@ import torch
 import lattice_inputs as li
 from oracle import wilson as ow
 from paper_1702_00124_amd.lattice import CG
-from tests.gpu_common import full_noise, half_noise, make_lattice, need_gpu, rel, say, to_np
+from tests.gpu_common import LOWP_MAX, full_noise, half_noise, make_lattice, need_gpu, rel, rel_max, say, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -87,8 +87,10 @@ def test_dslash_low_precision_error(prec, tol, variant):
     for r in range(4):
         ref = ow.hop_eo(U, psi[r], L, 0)
         e = rel(got[r], ref)
-        say(f"  rhs {r}: relative error vs FP64 oracle {e:.3e}")
+        em = rel_max(got[r], ref)
+        say(f"  rhs {r}: relative error vs FP64 oracle {e:.3e}, max element {em:.3e}")
         assert e <= tol
+        assert em <= LOWP_MAX[prec]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)

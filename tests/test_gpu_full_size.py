@@ -9,7 +9,7 @@ import torch
 import lattice_inputs as li
 from oracle import wilson as ow
 from paper_1702_00124_amd.lattice import CG
-from tests.gpu_common import need_gpu, rel, say, to_np
+from tests.gpu_common import check_prec, need_gpu, rel, say, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,8 @@ def test_hop_sampled_sites_full_size(big, prec):
         got = to_np(lat.export_spinor(out, prec, nrhs)).reshape(nrhs, Vh, 4, 3)
         for r in range(nrhs):
             ref = ow.hop_eo_at(U, psi[r], L, 0, sites, t_bc=-1)
-            e = rel(got[r][sites], ref)
-            say(f"  rhs {r}: sampled relative error {e:.2e}")
+            e, em = check_prec(got[r][sites], ref, prec, ("rhs", r))
+            say(f"  rhs {r}: sampled relative error {e:.2e} (max element {em:.2e})")
             assert e <= TOL[prec]
         del psi, out, got
     if prec == "f64":   # the other parity and the dagger, one rhs
@@ -69,3 +69,79 @@ def test_batched_cg_full_size_true_residual(big, inner):
     for r in range(4):
         assert st[r].converged
         assert rel(Jx[r], b[r]) <= 1.01e-10
+
+
+def _sample_links(V, n_per_dir, seed):
+    """n_per_dir random links per direction plus 16 time links crossing the antiperiodic edge."""
+    rng = np.random.default_rng(seed)
+    links = [(mu, int(x)) for mu in range(4) for x in rng.choice(V, n_per_dir, replace=False)]
+    edge0 = (L[3] - 1) * L[0] * L[1] * L[2]
+    links += [(3, int(edge0 + x)) for x in rng.choice(L[0] * L[1] * L[2], 16, replace=False)]
+    return links
+
+
+def test_force_bilinear_sampled_links_full_size(big):
+    """The link-derivative primitive Re(A^dag D C) at 32^3 x 64 on random full fields,
+    at 272 sampled links against the oracle's link-by-link evaluation (pinned against
+    the whole-lattice derivative and finite differences on small lattices): FP64 bar."""
+    from oracle import force as ofo
+    from tests.gpu_common import rel_max
+    lat, U = big
+    V = lat.V
+    say("full size force bilinear")
+    A = li.gaussian_spinor((V, 4, 3), 5400)
+    C = li.gaussian_spinor((V, 4, 3), 5401)
+    F = lat.force_bilinear(lat.import_full(torch.from_numpy(A)), lat.import_full(torch.from_numpy(C)))
+    got = to_np(lat.export_su3(F))
+    links = _sample_links(V, 64, 12)
+    ref = ofo.bilinear_grad_at(U, A, C, L, links)
+    g = np.array([got[mu, x] for mu, x in links])
+    e, em = rel(g, ref), rel_max(g, ref)
+    say(f"  sampled links: relative error {e:.2e}, max element {em:.2e}")
+    assert e <= 1e-12 and em <= 1e-12
+    del A, C, F, got
+
+
+@pytest.mark.timeout(600)
+def test_term_force_sampled_links_full_size(big):
+    """The KINV term's force phi^dag J^-1 phi at 32^3 x 64 (kappa 0.156, mu2 0.05,
+    FP64 solve to 1e-13 on the GPU), with phi = J X built by the oracle from a seeded
+    X, so that the oracle knows the solution without solving: at sampled links the
+    force 2 kappa^2 grad Re(A^dag D C), A = M-hat X (+ (D^dag)_oe A on odd sites),
+    C = X (+ D_oe X), against the GPU force.  Bound: the solve's relative error
+    <= cond(J) 1e-13 (cond ~ 100), doubled by the bilinear form: asserted at 1e-9."""
+    from oracle import force as ofo, lattice as olat
+    from paper_1702_00124_amd.lattice import Term
+    from tests.gpu_common import rel_max
+    lat, U = big
+    kappa, mu2 = 0.156, 0.05
+    V, Vh = lat.V, lat.Vh
+    say("full size term force: oracle J X (four whole-lattice hops)")
+    X = li.gaussian_spinor((Vh, 4, 3), 5500)
+    Y = ow.Mhat(U, X, L, kappa)
+    phi = ow.Mhat(U, Y, L, kappa, dagger=True) + mu2 * X
+    say("  GPU solve and force")
+    term = Term("KINV", kappa, mu2=mu2, cg=CG(tol=1e-13, inner="f64", maxiter=20000))
+    got = to_np(lat.export_su3(lat.fermion_force(term, lat.import_spinor(torch.from_numpy(phi)))))
+    links = _sample_links(V, 64, 13)
+    # the fields of the bilinear at the sites the sampled links touch
+    ev, od = olat.parity_sites(L, 0), olat.parity_sites(L, 1)
+    A = np.zeros((V, 4, 3), dtype=np.complex128)
+    Cf = np.zeros((V, 4, 3), dtype=np.complex128)
+    A[ev], Cf[ev] = Y, X
+    touched = set()
+    for mu, x in links:
+        c = [x % L[0], (x // L[0]) % L[1], (x // (L[0] * L[1])) % L[2], x // (L[0] * L[1] * L[2])]
+        c[mu] = (c[mu] + 1) % L[mu]
+        touched.update((x, c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]))))
+    def parity(s):
+        return (s % L[0] + (s // L[0]) % L[1] + (s // (L[0] * L[1])) % L[2] + s // (L[0] * L[1] * L[2])) % 2
+    odd_full = np.array(sorted(s for s in touched if parity(s) == 1), dtype=np.int64)
+    pos = np.searchsorted(od, odd_full)
+    A[odd_full] = ow.hop_eo_at(U, Y, L, 1, pos, t_bc=-1, dagger=True)
+    Cf[odd_full] = ow.hop_eo_at(U, X, L, 1, pos, t_bc=-1)
+    ref = 2 * kappa ** 2 * ofo.bilinear_grad_at(U, A, Cf, L, links)
+    g = np.array([got[mu, x] for mu, x in links])
+    e, em = rel(g, ref), rel_max(g, ref)
+    say(f"  sampled links: relative error {e:.2e}, max element {em:.2e}")
+    assert e <= 1e-9 and em <= 1e-9

@@ -16,7 +16,7 @@ import torch
 
 from oracle import wilson as ow
 from paper_1702_00124_amd.lattice import CG
-from tests.gpu_common import half_noise, make_lattice, rel, say, to_np
+from tests.gpu_common import check_prec, half_noise, make_lattice, rel, say, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,7 @@ def test_hop_matches_oracle(tuned, prec, nrhs):
         got = to_np(lat.export_spinor(out, prec, nrhs)).reshape(psi.shape)
         for r in range(nrhs):
             ref = ow.hop_eo(U, psi[r], L, parity, t_bc=-1)
-            assert rel(got[r], ref) <= TOL[prec], (prec, nrhs, parity, r)
+            check_prec(got[r], ref, prec, (nrhs, parity, r))
 
 
 @pytest.mark.parametrize("inner", ["f32", "bf16"])

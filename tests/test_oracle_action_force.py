@@ -219,3 +219,44 @@ def test_quotient_polynomial_closed_form_and_roots():
     assert np.abs(np.abs(q) ** 2 / ref - 1).max() < 1e-10
     with pytest.raises(ValueError):
         poly.roots_of(24, a, b, 6)       # 7 does not divide 25
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 4, 10)])
+def test_bilinear_at_sampled_links_matches_whole_lattice(L):
+    """The link-by-link evaluation (used on large lattices at sampled links) equals the
+    whole-lattice bilinear derivative at every link, time wrap included."""
+    from oracle import force as ofo
+    U = _links(L)
+    V = li.volume(L)
+    A = li.gaussian_spinor((V, 4, 3), 71)
+    C = li.gaussian_spinor((V, 4, 3), 72)
+    whole = ofo.bilinear_grad(U, A, C, L)
+    links = [(mu, x) for mu in range(4) for x in range(V)]
+    at = ofo.bilinear_grad_at(U, A, C, L, links).reshape(4, V, 8)
+    assert np.max(np.abs(at - whole)) <= 1e-13 * np.max(np.abs(whole))
+
+
+def test_bilinear_at_matches_finite_differences_of_the_hop():
+    """d/de Re(A^dag D(U') C), U'_mu(x) = exp(i e T^a) U_mu(x) at single links (one of
+    them crossing the antiperiodic time edge), by central differences of the oracle's
+    hop: pins the per-link evaluation on its own."""
+    from oracle import force as ofo
+    L = L4
+    U = _links(L)
+    V = li.volume(L)
+    A = li.gaussian_spinor((V, 4, 3), 73)
+    C = li.gaussian_spinor((V, 4, 3), 74)
+    T = lat.generators()
+    x_edge = 1 + L[0] * (2 + L[1] * (3 + L[2] * (L[3] - 1)))   # t = Lt - 1: its t link wraps
+    links = [(0, 5), (1, 77), (2, 130), (3, 200), (3, x_edge)]
+    got = ofo.bilinear_grad_at(U, A, C, L, links)
+    eps = 1e-6
+    for i, (mu, x) in enumerate(links):
+        for a in (0, 3, 7):
+            vals = []
+            for s in (+1, -1):
+                Up = U.copy()
+                Up[mu][x] = su3.expi(s * eps, T[a]) @ U[mu][x]
+                vals.append(np.vdot(A, wl.hop(Up, C, L)).real)
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            assert abs(fd - got[i, a]) <= 1e-6 * max(1.0, abs(got[i, a])), (mu, x, a, fd, got[i, a])
