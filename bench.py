@@ -417,18 +417,19 @@ def large_volume(lat, li, torch, np, CG):
     return out
 
 
-KERNELS_ONLY_CONFIGS = [(v, x, st) for v in (0, 1) for x in (1, 0) for st in (0, 1)]   # (variant, use_xcd, stream)
+KERNELS_ONLY_CONFIGS = [(v, x, st) for v in (0, 1) for x in (1, 0, 2) for st in (0, 1)]   # (variant, order, stream)
 
 
 def kernels_only_configs(prec: str, nrhs: int):
-    """(variant, npass, use_xcd, stream) launched per precision by --kernels-only: one rhs
-    takes the 8 of KERNELS_ONLY_CONFIGS; several rhs take every candidate the autotuner
-    times for their class (site npass 1 and, for FP32 / BF16, 2; direction-parallel npass 1,
-    2, 4), each per (use_xcd, stream)."""
+    """(variant, npass, order, stream) tried per precision by --kernels-only: one rhs
+    takes KERNELS_ONLY_CONFIGS; several rhs take every candidate the autotuner times
+    for their class (site npass 1 and, for FP32 / BF16, 2; direction-parallel npass 1,
+    2, 4), each per (order, stream).  Configurations the lattice does not allow (the
+    z-blocked order 2) are skipped at launch time and left out of the logged list."""
     if nrhs == 1:
         return [(v, 1, x, st) for v, x, st in KERNELS_ONLY_CONFIGS]
     cands = [(0, 1)] + ([(0, 2)] if prec != "f64" else []) + [(1, 1), (1, 2), (1, 4)]
-    return [(v, n, x, st) for v, n in cands for x in (1, 0) for st in (0, 1)]
+    return [(v, n, x, st) for v, n in cands for x in (1, 0, 2) for st in (0, 1)]
 
 
 def kernels_only(lat, Vh, li, torch, nrhs: int = 1):
@@ -438,12 +439,18 @@ def kernels_only(lat, Vh, li, torch, nrhs: int = 1):
     / WRITE_SIZE calibrate the counters."""
     import numpy as np
     psi = li.gaussian_spinor((Vh, 4, 3) if nrhs == 1 else (nrhs, Vh, 4, 3), li.seed_source(0))
+    from paper_1702_00124_amd import WilsonError
     kind = {1: 0}.get(nrhs, 1 if nrhs <= 4 else 2)
+    launched = []
     for prec in ("f64", "f32", "bf16"):
         b = lat.import_spinor(torch.from_numpy(np.ascontiguousarray(psi)), prec)
         out = lat.new_field(prec, nrhs)
         for variant, npass, xcd, stream in kernels_only_configs(prec, nrhs):
-            lat.set_hop_config(prec, kind, variant=variant, npass=npass, use_xcd=xcd, stream=stream)
+            try:
+                lat.set_hop_config(prec, kind, variant=variant, npass=npass, use_xcd=xcd, stream=stream)
+            except WilsonError:
+                continue
+            launched.append([prec, variant, npass, xcd, stream])
             for _ in range(50):
                 lat.dslash(b, 0, prec=prec, nrhs=nrhs, out=out)
         del b, out
@@ -453,9 +460,8 @@ def kernels_only(lat, Vh, li, torch, nrhs: int = 1):
     for _ in range(5):
         dst.copy_(src)
     torch.cuda.synchronize()
-    log(f"kernels-only done: per precision (f64, f32, bf16) 50 hop launches of {nrhs} rhs for each "
-        "(variant, npass, use_xcd, stream) in", {p: kernels_only_configs(p, nrhs) for p in ("f64", "f32", "bf16")},
-        "then 5 copies of 1 GiB")
+    log(f"kernels-only done: 50 hop launches of {nrhs} rhs for each [precision, variant, npass, order, stream] "
+        "in KERNELS_LAUNCHED " + json.dumps(launched) + " then 5 copies of 1 GiB")
 
 
 def solver_kernels(lat, Vh, li, torch, CG, WilsonLattice, WilsonBatch):

@@ -60,16 +60,22 @@ typedef struct wl_lattice wl_lattice;
 /* Thread-local message of the last failing call ("" if none). */
 const char* wl_last_error(void);
 
-/* Create a context for an Lx x Ly x Lz x Lt lattice (all even, Lx >= 2) with
+/* Create a context for an Lx x Ly x Lz x Lt lattice (all even, 2 .. 32768,
+ * volume at most 2^30) with
  * fermion time boundary phase t_bc (+1 periodic, -1 antiperiodic, Sec. 3.1
  * workload).  hip_stream: a hipStream_t (NULL = default stream). */
 int wl_create(wl_lattice** out, const int32_t L[4], int32_t t_bc, void* hip_stream);
 int wl_destroy(wl_lattice* lat);
 int wl_set_stream(wl_lattice* lat, void* hip_stream);
 
-/* Gauge links U (Sec. 2): copy canonical complex128 [4][V][3][3] in / out. */
-int wl_set_links(wl_lattice* lat, const void* U_canon);
-int wl_get_links(wl_lattice* lat, void* U_canon);
+/* Gauge links U (Sec. 2): copy canonical complex128 [4][V][3][3] in / out.
+ * on_device = 1: U_canon is a device array on the context's device (stream
+ * ordered); on_device = 0: a host array, staged through a workspace buffer of
+ * the context (64 V bytes, kept), and the call synchronises the stream before
+ * it returns, so the host array may be reused at once.  The caller keeps
+ * ownership of U_canon.  WL_EINVAL for a null array or another flag value. */
+int wl_set_links(wl_lattice* lat, const void* U_canon, int on_device);
+int wl_get_links(wl_lattice* lat, void* U_canon, int on_device);
 
 /* Bytes of one internal half-lattice spinor field of nrhs right-hand sides. */
 int wl_field_bytes(const wl_lattice* lat, wl_prec prec, int nrhs, size_t* bytes);
@@ -175,11 +181,16 @@ int cg_multishift(wl_lattice* lat, void* x, const void* b, double kappa, const d
 /* Chebyshev filter polynomial (Sec. 2, polynomial filtering): order degree on
  * [a, b] approximating 1/x, 1 - x P(x) = T_{degree+1}(y(x)) / T_{degree+1}(y(0)),
  * y(x) = (b + a - 2x)/(b - a), or its quotient by a lower order (degree_div);
- * applied to J = K-hat(kappa) + mu2 on even sites.  P = Q^dag Q with Q built
- * from P's roots of negative imaginary part (degree and degree_div even for
- * the Q modes).  F64 internal fields, nrhs = 1.  WL_EINVAL for a degree
- * outside 1..512, an interval without 0 < a < b, or a divisor order that
- * does not divide. */
+ * applied to J = K-hat(kappa) + mu2 (one shift for every rhs) on even sites.
+ * P = Q^dag Q with Q built from P's roots of negative imaginary part (degree
+ * and degree_div even for the Q modes).  in / out: internal half fields of
+ * nrhs rhs in storage precision prec (F64 computes in FP64, F32 / BF16 in
+ * FP32 with that storage between the steps), distinct buffers.  P runs the
+ * real three-term recurrence (degree J applications, each step fused into the
+ * epilogue of its J's last hop); P J one more J; Q and Q^dag the root factors.
+ * WL_EINVAL for a degree outside 1..512, an interval without 0 < a < b, a
+ * divisor order that does not divide, nrhs outside 1..16 or an unknown
+ * precision. */
 typedef struct {
   int degree;
   double a, b;
@@ -192,7 +203,7 @@ typedef struct {
 typedef enum { WL_POLY_P = 0, WL_POLY_PJ = 1, WL_POLY_Q = 2, WL_POLY_QDAG = 3 } wl_poly_mode;
 
 int poly_filter_apply(wl_lattice* lat, void* out, const void* in, double kappa, double mu2,
-                      const wl_poly* poly, wl_poly_mode mode);
+                      const wl_poly* poly, wl_poly_mode mode, int nrhs, wl_prec prec);
 
 /* Pseudofermion action terms (Sec. 2, 3.3, 4.1, 4.2).  Every term has its
  * operator J = K-hat(kappa) + mu2 on the even sites: the paper's Hasenbusch
@@ -290,7 +301,7 @@ typedef struct {
   double S0[9], S1[9];   /* per term, then gauge */
   double plaquette;      /* of the links the call leaves */
   int accepted;
-  long long n_kmat;      /* K-hat (or K) applications, the cost numerator of Sec. 3.1 */
+  long long n_kmat;      /* K multiplications (the cost numerator N_mat of Sec. 3.1; rule at wl_counters) */
   long long cg_iters;
 } wl_hmc_result;
 
@@ -331,8 +342,37 @@ int wl_batch_cg_solve(wl_batch* batch, void* x, const void* b, const double* kap
 int wl_integrator_schedule(const int* nsteps, int nscales, int scheme, double lambda, int* kinds, int* terms,
                            double* weights, int max_events, int* n_events);
 
-/* Counters: hop applications and K applications since create (single rhs units). */
+/* Counters since create.  n_hop: hop launches in single-rhs units (graph
+ * replays included).  n_kmat: the cost count of Sec. 3.1, fermion-matrix K
+ * multiplications, one per rhs for each application of a term's K-type
+ * operator J = K-hat(kappa) + mu2 or the full-lattice K:
+ *   * apply_K with WL_OP_J / WL_OP_K: 1;  WL_OP_M, MDAG, MHAT, MHAT_DAG and
+ *     wilson_dslash: 0 (parts of a multiplication);
+ *   * a CG on J or K: 1 per iteration of each rhs until that rhs converges,
+ *     plus 1 per rhs for each FP64 residual b - A x (reliable updates, the
+ *     final check, the start from a given x0); iterations a chunk issues
+ *     past a rhs's convergence are not counted;
+ *   * a polynomial: P_n(J) n, a quotient P_n / P_m 2q (q = its root factors
+ *     of Q), P(J) J one more, Q(J) and Q(J)^dag q; a CG on P(J) or P(J) J
+ *     counts its operator applications as above times these;
+ *   * a J assembled inside a force chain from fields already multiplied by
+ *     M-hat: 1.
+ * The multi-shift CG counts one per base iteration (the shifted systems
+ * share its J) and one per rhs for each residual; mixed-volume batch J: 1 per
+ * lattice per launch. */
 int wl_counters(const wl_lattice* lat, long long* n_hop, long long* n_kmat);
+/* Tracing of the cost count: wl_solve_log(lat, 1) clears and starts a log of
+ * every CG the context runs (cg_solve, the solves inside heatbaths, actions,
+ * forces and trajectories; not the multi-shift or batch solvers);
+ * wl_solve_log(lat, 0) stops and clears.  wl_solve_log_read copies, per
+ * solve in order, the iterations summed over its rhs, its FP64 residual
+ * applications (summed over rhs) and the K multiplications per operator
+ * application (1 for J / K, the polynomial's count for P(J) and P(J) J)
+ * into host arrays of max entries (any may be NULL); *n = the number of
+ * solves (WL_EINVAL if above max). */
+int wl_solve_log(wl_lattice* lat, int enable);
+int wl_solve_log_read(const wl_lattice* lat, int max, int* n, long long* iters, long long* residuals,
+                      long long* jpa);
 /* Hop launch configuration, kept per storage precision and per rhs-count
  * class (kind 0: one rhs; 1: 2-4 rhs; 2: 5-16 rhs):
  *   variant  0 = one thread per output site (all 8 directions);
@@ -342,8 +382,13 @@ int wl_counters(const wl_lattice* lat, long long* n_hop, long long* n_kmat);
  *            2 (FP32, BF16, even rhs counts) rhs reuse each link held in
  *            registers; site: 2 = two rhs per thread (FP32, BF16, even rhs
  *            counts), else one;
- *   use_xcd  1 = workgroups renumbered so that each of the 8 XCDs walks a
- *            contiguous range of sites; 0 = the hardware's round-robin order;
+ *   use_xcd  the workgroup order: 1 = renumbered so that each of the 8 XCDs
+ *            walks a contiguous range of sites; 0 = the hardware's round-robin
+ *            order; 2 = z-blocked round-robin: 8 z planes at a time through
+ *            every t, so that a site's t neighbours are read within a few
+ *            hundred workgroups of each other (valid where a z plane holds a
+ *            multiple of 8 workgroup tiles, 64 sites for direction-parallel,
+ *            256 for thread-per-site, and Lz is a multiple of 8 above 8);
  *   stream   1 = non-temporal loads of links and epilogue operands and
  *            non-temporal output stores (pays on volumes beyond the caches),
  *            0 = ordinary cached access.
@@ -356,14 +401,15 @@ int wl_counters(const wl_lattice* lat, long long* n_hop, long long* n_kmat);
  * wl_autotune times on this lattice, for every precision, class 0 at 1 rhs
  * over {site, direction-parallel}, classes 1 and 2 at 4 and 8 rhs over
  * {site npass 1, 2; direction-parallel npass 1, 2, 4}, each candidate with
- * (stream, use_xcd) = (0, 1), (0, 0), (1, 1), (1, 0), as bursts in which each
- * launch reads the previous launch's output (best of 3 bursts of 20), and
- * keeps the fastest of every class.  stream = 1 is a candidate only where the
- * hop's working set (links and two fields of that class) exceeds the 256 MiB
- * last-level cache.  us_out: optional host array of 3 x 48 microseconds per
- * launch (0 for candidates not timed), per precision (F64, F32, BF16): 8 for
- * class 0 (site, dp per (stream, use_xcd) in that order), then 20 for class 1
- * and 20 for class 2 (site 1, site 2, dp 1, dp 2, dp 4 per (stream, use_xcd)). */
+ * (stream, use_xcd) = (0, 1), (0, 0), (0, 2), (1, 1), (1, 0), (1, 2), as
+ * bursts in which each launch reads the previous launch's output (best of 3
+ * bursts of 20), and keeps the fastest of every class.  stream = 1 is a
+ * candidate only where the hop's working set (links and two fields of that
+ * class) exceeds the 256 MiB last-level cache, use_xcd = 2 only where valid.
+ * us_out: optional host array of 3 x 72 microseconds per launch (0 for
+ * candidates not timed), per precision (F64, F32, BF16): 12 for class 0 (site,
+ * dp per (stream, use_xcd) in that order), then 30 for class 1 and 30 for
+ * class 2 (site 1, site 2, dp 1, dp 2, dp 4 per (stream, use_xcd)). */
 int wl_set_hop_config(wl_lattice* lat, wl_prec prec, int kind, int variant, int npass, int use_xcd, int stream);
 int wl_get_hop_config(const wl_lattice* lat, wl_prec prec, int kind, int* variant, int* npass, int* use_xcd,
                       int* stream);

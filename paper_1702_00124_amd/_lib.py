@@ -51,14 +51,14 @@ class HmcResult(C.Structure):
 
 
 # name -> (restype, argtypes)
-P, D, I, SZ = C.c_void_p, C.c_double, C.c_int, C.c_size_t
+P, D, I, SZ, LL = C.c_void_p, C.c_double, C.c_int, C.c_size_t, C.c_longlong
 SIGNATURES = {
     "wl_last_error": (C.c_char_p, []),
     "wl_create": (I, [C.POINTER(P), C.POINTER(C.c_int32), C.c_int32, P]),
     "wl_destroy": (I, [P]),
     "wl_set_stream": (I, [P, P]),
-    "wl_set_links": (I, [P, P]),
-    "wl_get_links": (I, [P, P]),
+    "wl_set_links": (I, [P, P, I]),
+    "wl_get_links": (I, [P, P, I]),
     "wl_field_bytes": (I, [P, I, I, C.POINTER(SZ)]),
     "wl_import_spinor": (I, [P, P, P, I, I]),
     "wl_export_spinor": (I, [P, P, P, I, I]),
@@ -71,7 +71,7 @@ SIGNATURES = {
     "apply_K_noalloc": (I, [P, P, P, D, C.POINTER(D), I, I, I]),
     "cg_solve": (I, [P, P, P, D, C.POINTER(D), I, I, C.POINTER(CgParams), C.POINTER(CgStats)]),
     "cg_multishift": (I, [P, P, P, D, C.POINTER(D), I, I, C.POINTER(CgParams), C.POINTER(CgStats)]),
-    "poly_filter_apply": (I, [P, P, P, D, D, C.POINTER(Poly), I]),
+    "poly_filter_apply": (I, [P, P, P, D, D, C.POINTER(Poly), I, I, I]),
     "wl_heatbath": (I, [P, P, C.POINTER(Term), P]),
     "wl_action": (I, [P, C.POINTER(Term), P, C.POINTER(D)]),
     "fermion_force": (I, [P, P, C.POINTER(Term), P, D, C.POINTER(D)]),
@@ -81,6 +81,8 @@ SIGNATURES = {
     "wl_link_update": (I, [P, P, D]),
     "hmc_trajectory": (I, [P, C.POINTER(HmcParams), P, P, D, C.POINTER(HmcResult)]),
     "wl_counters": (I, [P, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+    "wl_solve_log": (I, [P, I]),
+    "wl_solve_log_read": (I, [P, I, C.POINTER(I), C.POINTER(LL), C.POINTER(LL), C.POINTER(LL)]),
     "wl_batch_create": (I, [C.POINTER(P), C.POINTER(P), I]),
     "wl_batch_destroy": (I, [P]),
     "wl_batch_slot_bytes": (I, [P, I, C.POINTER(SZ)]),

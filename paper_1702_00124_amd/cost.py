@@ -127,6 +127,8 @@ def run(L=(8, 8, 8, 16), kappa=0.155, beta=5.6, ntherm=60, ntraj=40, actions=Non
             torch.cuda.synchronize()
             rows.append((r.dH, bool(r.accepted), int(r.n_kmat), int(r.cg_iters), r.plaquette,
                          time.perf_counter() - t0))
+            log(f"{name} {k}: dH {r.dH:.4f} accepted {int(r.accepted)} n_mat {r.n_kmat} cg {r.cg_iters} "
+                f"plaquette {r.plaquette:.5f} ({rows[-1][5]:.2f} s)")
             if ck:
                 ck.save_array("links", lat.get_links().cpu().numpy())
                 state["k"], state["rows"] = k + 1, rows

@@ -188,7 +188,7 @@ void solve_poly(wl_lattice* L, void* x, const void* b, const wl_term& t, int mod
     launch_convert(L, F64, out, gp, o, 1);
   };
   chrono_in(L, ch, x, b, apply_guess, cg);
-  const int rc = cg_run_generic(L, x, b, apply, cg, &st);
+  const int rc = cg_run_generic(L, x, b, apply, cg, &st, poly_j_count(mode, pd));
   chrono_out(L, ch, x);
   if (iters) *iters += st.iters;
   WL_REQUIRE(rc == WL_OK, rc, "polynomial CG did not converge");

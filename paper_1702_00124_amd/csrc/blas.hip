@@ -445,11 +445,18 @@ __global__ __launch_bounds__(kBlock) void ms_xpay_kernel(Geo g, char* p, const c
 // fused into the hop kernels' epilogue):
 //   start: t_0 = in, e_0 = 0, e_1 = in          (one read, three writes)
 //   end:   out = s e_{n+1} = s (ce e_n + 2 t_n - e_{n-1}),  ce = 2 y0
+// (nrhs fields, rhs = blockIdx.y, stride bytes apart)
 template <typename P>
-__global__ __launch_bounds__(kBlock) void cheb_init_kernel(Geo g, const char* in, char* t0, char* e0, char* e1) {
+__global__ __launch_bounds__(kBlock) void cheb_init_kernel(Geo g, const char* in, char* t0, char* e0, char* e1,
+                                                          size_t stride) {
   using R = typename P::real;
   const int h = site_block() * kBlock + threadIdx.x;
   if (h >= g.Vh) return;
+  const size_t off = blockIdx.y * stride;
+  in += off;
+  t0 += off;
+  e0 += off;
+  e1 += off;
   const Spinor<R> v = SpinorIO<P>::load(in, h, g.Vh);
   Spinor<R> z;
 #pragma unroll
@@ -461,10 +468,15 @@ __global__ __launch_bounds__(kBlock) void cheb_init_kernel(Geo g, const char* in
 
 template <typename P>
 __global__ __launch_bounds__(kBlock) void cheb_last_kernel(Geo g, const char* t, const char* e, const char* eprev,
-                                                          char* out, double ce, double s) {
+                                                          char* out, double ce, double s, size_t stride) {
   using R = typename P::real;
   const int h = site_block() * kBlock + threadIdx.x;
   if (h >= g.Vh) return;
+  const size_t off = blockIdx.y * stride;
+  t += off;
+  e += off;
+  eprev += off;
+  out += off;
   const Spinor<R> tv = SpinorIO<P>::load(t, h, g.Vh);
   const Spinor<R> ev = SpinorIO<P>::load(e, h, g.Vh);
   const Spinor<R> pv = SpinorIO<P>::load(eprev, h, g.Vh);
@@ -671,21 +683,22 @@ void launch_ms_xpay(wl_lattice* L, void* p, const void* r, const double* st, con
   WL_HIP(hipGetLastError());
 }
 
-void launch_cheb_init(wl_lattice* L, const void* in, void* t0, void* e0, void* e1, Prec prec) {
+void launch_cheb_init(wl_lattice* L, const void* in, void* t0, void* e0, void* e1, Prec prec, int nrhs) {
   by_prec(prec, [&](auto P) {
     using PT = decltype(P);
-    hipLaunchKernelGGL((cheb_init_kernel<PT>), dim3(blas_blocks(L)), dim3(kBlock), 0, L->stream, L->geo,
-                       (const char*)in, (char*)t0, (char*)e0, (char*)e1);
+    hipLaunchKernelGGL((cheb_init_kernel<PT>), dim3(blas_blocks(L), nrhs), dim3(kBlock), 0, L->stream, L->geo,
+                       (const char*)in, (char*)t0, (char*)e0, (char*)e1, spinor_bytes(prec, L->Vh));
   });
   WL_HIP(hipGetLastError());
 }
 
 void launch_cheb_last(wl_lattice* L, const void* t, const void* e, const void* eprev, void* out, double ce, double s,
-                      Prec prec) {
+                      Prec prec, int nrhs) {
   by_prec(prec, [&](auto P) {
     using PT = decltype(P);
-    hipLaunchKernelGGL((cheb_last_kernel<PT>), dim3(blas_blocks(L)), dim3(kBlock), 0, L->stream, L->geo,
-                       (const char*)t, (const char*)e, (const char*)eprev, (char*)out, ce, s);
+    hipLaunchKernelGGL((cheb_last_kernel<PT>), dim3(blas_blocks(L), nrhs), dim3(kBlock), 0, L->stream, L->geo,
+                       (const char*)t, (const char*)e, (const char*)eprev, (char*)out, ce, s,
+                       spinor_bytes(prec, L->Vh));
   });
   WL_HIP(hipGetLastError());
 }

@@ -103,7 +103,9 @@ int wl_create(wl_lattice** out, const int32_t Ls[4], int32_t t_bc, void* hip_str
   return guard([&]() {
     WL_REQUIRE(out && Ls, WL_EINVAL, "null argument");
     *out = nullptr;
-    for (int m = 0; m < 4; ++m) WL_REQUIRE(Ls[m] >= 2 && Ls[m] % 2 == 0, WL_EINVAL, "lattice extents must be even and >= 2");
+    for (int m = 0; m < 4; ++m)
+      WL_REQUIRE(Ls[m] >= 2 && Ls[m] <= 32768 && Ls[m] % 2 == 0, WL_EINVAL,
+                 "lattice extents must be even, >= 2 and <= 32768");
     WL_REQUIRE(t_bc == 1 || t_bc == -1, WL_EINVAL, "t_bc must be +1 or -1");
     const long long V = (long long)Ls[0] * Ls[1] * Ls[2] * Ls[3];
     WL_REQUIRE(V <= (1LL << 30), WL_EUNSUPPORTED, "volume too large");
@@ -121,6 +123,7 @@ int wl_create(wl_lattice** out, const int32_t Ls[4], int32_t t_bc, void* hip_str
       L->geo.Vh = L->Vh;
       L->geo.Vhp = padded_sites(L->Vh);
       L->geo.tbc = t_bc;
+      geo_init(L->geo);
       L->stream = static_cast<hipStream_t>(hip_stream);
       device_alloc(&L->Ufull, full_links_bytes(L->Vh));
       for (int p = 0; p < 3; ++p) device_alloc(&L->U[p], links_bytes(Prec(p), L->Vh));
@@ -166,21 +169,39 @@ int wl_set_stream(wl_lattice* L, void* s) {
   });
 }
 
-int wl_set_links(wl_lattice* L, const void* U) {
+int wl_set_links(wl_lattice* L, const void* U, int on_device) {
   return guard([&]() {
     check_lat(L);
     WL_REQUIRE(U, WL_EINVAL, "null links");
+    WL_REQUIRE(on_device == 0 || on_device == 1, WL_EINVAL, "on_device must be 0 or 1");
     set_device(L);
+    if (!on_device) {  // stage the host array in the workspace, then pack on the device
+      const size_t bytes = size_t(4) * L->V * 9 * 16;
+      void* stage = ws_get(L, "links_stage", bytes);
+      WL_HIP(hipMemcpyAsync(stage, U, bytes, hipMemcpyHostToDevice, L->stream));
+      launch_pack_links(L, stage);
+      WL_HIP(hipStreamSynchronize(L->stream));  // the host array may be reused on return
+      return WL_OK;
+    }
     launch_pack_links(L, U);
     return WL_OK;
   });
 }
 
-int wl_get_links(wl_lattice* L, void* U) {
+int wl_get_links(wl_lattice* L, void* U, int on_device) {
   return guard([&]() {
     check_lat(L);
     WL_REQUIRE(U, WL_EINVAL, "null links");
+    WL_REQUIRE(on_device == 0 || on_device == 1, WL_EINVAL, "on_device must be 0 or 1");
     set_device(L);
+    if (!on_device) {
+      const size_t bytes = size_t(4) * L->V * 9 * 16;
+      void* stage = ws_get(L, "links_stage", bytes);
+      launch_unpack_links(L, stage);
+      WL_HIP(hipMemcpyAsync(U, stage, bytes, hipMemcpyDeviceToHost, L->stream));
+      WL_HIP(hipStreamSynchronize(L->stream));
+      return WL_OK;
+    }
     launch_unpack_links(L, U);
     return WL_OK;
   });
@@ -341,12 +362,14 @@ int cg_multishift(wl_lattice* L, void* x, const void* b, double kappa, const dou
 }
 
 int poly_filter_apply(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const wl_poly* poly,
-                      wl_poly_mode mode) {
+                      wl_poly_mode mode, int nrhs, wl_prec prec) {
   return guard([&]() {
     check_lat(L);
-    WL_REQUIRE(out && in && poly, WL_EINVAL, "null argument");
+    check_prec_rhs(prec, nrhs);
+    WL_REQUIRE(out && in && poly && out != in, WL_EINVAL, "null or aliased argument");
     set_device(L);
-    poly_apply(L, mode, out, in, kappa, mu2, PolyDesc{poly->degree, poly->a, poly->b, poly->degree_div});
+    poly_apply(L, mode, out, in, kappa, mu2, PolyDesc{poly->degree, poly->a, poly->b, poly->degree_div}, Prec(prec),
+               nrhs);
     return WL_OK;
   });
 }
@@ -489,7 +512,9 @@ int wl_set_hop_config(wl_lattice* L, wl_prec prec, int kind, int variant, int np
     WL_REQUIRE(kind >= -1 && kind < kHopKinds, WL_EINVAL, "hop class must be -1, 0, 1 or 2");
     WL_REQUIRE(variant == kHopSite || variant == kHopDirParallel, WL_EINVAL, "unknown hop variant");
     WL_REQUIRE(npass == 1 || npass == 2 || npass == 4, WL_EINVAL, "npass must be 1, 2 or 4");
-    WL_REQUIRE(use_xcd == 0 || use_xcd == 1, WL_EINVAL, "use_xcd must be 0 or 1");
+    WL_REQUIRE(use_xcd == 0 || use_xcd == 1 ||
+                   (use_xcd == 2 && zblock_ok(L->geo, variant == kHopDirParallel ? 64 : kBlock)),
+               WL_EINVAL, "use_xcd must be 0, 1, or 2 where the lattice allows the z-blocked order");
     WL_REQUIRE(stream == 0 || stream == 1, WL_EINVAL, "stream must be 0 or 1");
     WL_HIP(hipStreamSynchronize(L->stream));
     for (int k = 0; k < kHopKinds; ++k)
@@ -635,7 +660,7 @@ int wl_autotune(wl_lattice* L, double* us_out) {
         const int max_stream = wset > kLastLevelCache ? 1 : 0;
         std::vector<HopConfig> cand;
         for (int stm = 0; stm <= 1; ++stm)
-          for (int xcd = 1; xcd >= 0; --xcd) {
+          for (int xcd : {1, 0, 2}) {
             if (k == 0) {
               cand.push_back({kHopSite, 1, xcd, stm});
               cand.push_back({kHopDirParallel, 1, xcd, stm});
@@ -647,7 +672,8 @@ int wl_autotune(wl_lattice* L, double* us_out) {
         double best = 1e30;
         HopConfig keep = L->hop_cfg[p][k];
         for (const HopConfig& c : cand) {
-          if (c.stream > max_stream) {  // not a candidate on this volume
+          if (c.stream > max_stream ||
+              (c.use_xcd == 2 && !zblock_ok(L->geo, c.variant == kHopDirParallel ? 64 : kBlock))) {  // not here
             if (us_out) us_out[slot] = 0.0;
             ++slot;
             continue;
@@ -741,6 +767,31 @@ int wl_batch_cg_solve(wl_batch* B, void* x, const void* b, const double* kappa, 
     WL_REQUIRE(!params->use_x0, WL_EUNSUPPORTED, "batch CG starts from x = 0");
     set_device(batch_big(B));
     return batch_cg(B, x, b, kappa, mu2, *params, stats);
+  });
+}
+
+int wl_solve_log(wl_lattice* L, int enable) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(enable == 0 || enable == 1, WL_EINVAL, "enable must be 0 or 1");
+    L->solve_log.clear();
+    L->solve_log_on = enable;
+    return WL_OK;
+  });
+}
+
+int wl_solve_log_read(const wl_lattice* L, int max, int* n, long long* iters, long long* residuals, long long* jpa) {
+  return guard([&]() {
+    check_lat(L);
+    WL_REQUIRE(n && max >= 0, WL_EINVAL, "bad arguments");
+    *n = int(L->solve_log.size());
+    WL_REQUIRE(*n <= max, WL_EINVAL, "solve log longer than the buffers");
+    for (int i = 0; i < *n; ++i) {
+      if (iters) iters[i] = L->solve_log[i][0];
+      if (residuals) residuals[i] = L->solve_log[i][1];
+      if (jpa) jpa[i] = L->solve_log[i][2];
+    }
+    return WL_OK;
   });
 }
 

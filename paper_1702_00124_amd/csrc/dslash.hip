@@ -13,6 +13,7 @@
 // L2-friendly, XCD-aware tile order; no MFMA.
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "wl_internal.h"
 
@@ -38,7 +39,7 @@ struct HopArgs {
   int part_off;
   int use_xcd;
   int rows;  // rhs groups per tile
-  // fused Chebyshev step (one rhs): with w the epilogue's result,
+  // fused Chebyshev step (every rhs): with w the epilogue's result,
   //   tprev <- ct t + cw w - tprev,  eprev <- ce e + 2 t - eprev,  w not stored
   const char* ch_t;
   char* ch_tprev;
@@ -50,11 +51,28 @@ struct HopArgs {
 // Flattened grid: block b -> (tile, rhs group).  The XCD-aware renumbering
 // gives each XCD a contiguous block range, and the rhs groups of one tile are
 // adjacent inside it, so a tile's links are fetched once into that XCD's L2
-// and reused by every group.
+// and reused by every group.  The z-blocked order walks kZBlock z planes
+// through every t before the next planes: a tile's t neighbours are then
+// kZBlock planes of tiles away instead of a whole time slice (what the L2 has
+// to hold between the two reads), and with a multiple of 8 tiles per plane
+// its z and t neighbours are dealt to its own XCD.
+template <int SITES>  // sites per workgroup
 __device__ __forceinline__ void hop_block_coords(const HopArgs& a, int* tile, int* row) {
-  const int b = a.use_xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-  *tile = b / a.rows;
-  *row = b - *tile * a.rows;
+  const int b = a.use_xcd == 1 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int seq = b / a.rows;
+  *row = b - seq * a.rows;
+  if (a.use_xcd != 2) {
+    *tile = seq;
+    return;
+  }
+  const int tz = a.g.Lxh * a.g.L[1] / SITES;  // workgroup tiles per z plane
+  const int j = seq % tz;
+  int r = seq / tz;
+  const int zi = r % kZBlock;
+  r /= kZBlock;
+  const int t = r % a.g.L[3];
+  const int zb = r / a.g.L[3];
+  *tile = (t * a.g.L[2] + zb * kZBlock + zi) * tz + j;
 }
 
 template <typename P, int MU, int DAG, int NR, bool ST>
@@ -124,31 +142,33 @@ __device__ __forceinline__ void epi_store_unit(char* base, int u, int h, int Vh,
   else UnitIO<P>::store(base, u, h, Vh, c);
 }
 
-// the fused Chebyshev step on one 16-byte unit u of site h, w = the unit's result
+// the fused Chebyshev step on one 16-byte unit u of site h of the rhs at byte
+// offset off, w = the unit's result
 template <typename P, bool ST>
-__device__ __forceinline__ void cheb_unit(const HopArgs& a, int u, int h, int Vh, const cplx<typename P::real>* w) {
+__device__ __forceinline__ void cheb_unit(const HopArgs& a, size_t off, int u, int h, int Vh,
+                                          const cplx<typename P::real>* w) {
   using R = typename P::real;
   using UIO = UnitIO<P>;
   cplx<R> t[UIO::CPU], tp[UIO::CPU], e[UIO::CPU], ep[UIO::CPU];
-  epi_load_unit<P, ST>(a.ch_t, u, h, Vh, t);
-  epi_load_unit<P, ST>(a.ch_tprev, u, h, Vh, tp);
-  epi_load_unit<P, ST>(a.ch_e, u, h, Vh, e);
-  epi_load_unit<P, ST>(a.ch_eprev, u, h, Vh, ep);
+  epi_load_unit<P, ST>(a.ch_t + off, u, h, Vh, t);
+  epi_load_unit<P, ST>(a.ch_tprev + off, u, h, Vh, tp);
+  epi_load_unit<P, ST>(a.ch_e + off, u, h, Vh, e);
+  epi_load_unit<P, ST>(a.ch_eprev + off, u, h, Vh, ep);
   const R rt = R(a.ch_ct), rw = R(a.ch_cw), re = R(a.ch_ce), two = R(2);
 #pragma unroll
   for (int q = 0; q < UIO::CPU; ++q) {
     tp[q] = rt * t[q] + rw * w[q] - tp[q];
     ep[q] = re * e[q] + two * t[q] - ep[q];
   }
-  epi_store_unit<P, ST>(a.ch_tprev, u, h, Vh, tp);
-  epi_store_unit<P, ST>(a.ch_eprev, u, h, Vh, ep);
+  epi_store_unit<P, ST>(a.ch_tprev + off, u, h, Vh, tp);
+  epi_store_unit<P, ST>(a.ch_eprev + off, u, h, Vh, ep);
 }
 
 template <typename P, int DAG, int NR, bool ST, bool CHEB = false>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
   using R = typename P::real;
   int b, row;
-  hop_block_coords(a, &b, &row);
+  hop_block_coords<kBlock>(a, &b, &row);
   const int h = b * kBlock + threadIdx.x;
   const int Vh = a.g.Vh;
   const int r0 = row * NR;
@@ -194,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
       if constexpr (CHEB) {
         using UIO = UnitIO<P>;
 #pragma unroll
-        for (int u = 0; u < UIO::NU; ++u) cheb_unit<P, ST>(a, u, h, Vh, o.c + u * UIO::CPU);
+        for (int u = 0; u < UIO::NU; ++u) cheb_unit<P, ST>(a, off, u, h, Vh, o.c + u * UIO::CPU);
         continue;
       }
       epi_store<P, ST>(a.out + off, h, Vh, o);
@@ -234,41 +254,201 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 constexpr int kDpSites = 64;
 constexpr int kDpThreads = 8 * kDpSites;
 
+// ------------------------------------------------------------------ BF16 products from packed storage
+// A stored BF16 complex number is a pair (re in the low half, im in the high
+// half): the operand format of the bf16 dot product with FP32 accumulation,
+// d = a.lo b.lo + a.hi b.hi + c, whose products are exact in FP32.  With a
+// spinor component p = (pr, pi) as stored, Re(u p) = (ur, -ui).p and
+// Im(u p) = (ui, ur).p; for the adjoint product conj(u) p the pairs are
+// (ur, ui) and (-ui, ur).  The spin projection (1 + S g_mu) p = p_top + c p_bot,
+// c one of +1, -1, +i, -i, is folded into the choice of pairs for p_bot
+// (u (-p) takes (-A, -B), u (i p) takes (-B, A), u (-i p) takes (B, -A)), so
+// the projected half spinor is never formed: no unpacking of the input and no
+// rounding of the projection.  The link's third row, rebuilt in FP32 from the
+// two stored rows, is rounded to BF16 like the stored ones.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c,
+                                         false);
+}
+// a.b with a zero accumulator: the three-operand form takes the constant 0
+// directly (the two-operand form the compiler picks would first clear a register)
+__device__ __forceinline__ float dot2_first(uint32_t a, uint32_t b) {
+  float d;
+  asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
+  return d;
+}
+__device__ __forceinline__ uint32_t swap16(uint32_t u) { return __builtin_amdgcn_alignbit(u, u, 16); }
+
+// the product matrix's entries (a, b) as the four pairs A (real part), B
+// (imaginary part) and their negatives
+struct Bf16Link {
+  uint32_t A[9], B[9], nA[9], nB[9];
+};
+
+// links of one direction; the forward product takes U, the backward one U^dag
+template <int FWD>
+__device__ __forceinline__ void bf16_link(const char* base, int h, Bf16Link* L, bool stream) {
+  const uint2* b = reinterpret_cast<const uint2*>(base);
+  uint32_t m[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const uint2 v = stream ? ld_stream(b + fidx(j, h, 3)) : b[fidx(j, h, 3)];
+    m[2 * j] = v.x;
+    m[2 * j + 1] = v.y;
+  }
+  SU3<float> u;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) u.m[k] = {bf16_to_f32(m[k] & 0xFFFFu), bf16_to_f32(m[k] >> 16)};
+  third_row(u);
+#pragma unroll
+  for (int k = 6; k < 9; ++k) m[k] = pack_bf16x2(u.m[k].r, u.m[k].i);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      const int e = 3 * a + bb;
+      const uint32_t w = FWD ? m[3 * a + bb] : m[3 * bb + a];  // U_ab, or conj(U_ba) for U^dag
+      const uint32_t sw = swap16(w);
+      if (FWD) {
+        L->A[e] = w ^ 0x80000000u;   // (ur, -ui)
+        L->B[e] = sw;                // (ui, ur)
+        L->nA[e] = w ^ 0x00008000u;  // (-ur, ui)
+        L->nB[e] = sw ^ 0x80008000u; // (-ui, -ur)
+      } else {
+        L->A[e] = w;                 // (ur, ui)
+        L->B[e] = sw ^ 0x00008000u;  // (-ui, ur)
+        L->nA[e] = w ^ 0x80008000u;  // (-ur, -ui)
+        L->nB[e] = sw ^ 0x80000000u; // (ui, -ur)
+      }
+    }
+}
+
+// (product matrix) (p_top + c p_bot) for one half spinor: 3 complex results,
+// 36 dot products; CC: 0 -> c = +1, 1 -> -1, 2 -> +i, 3 -> -i
+template <int CC>
+__device__ __forceinline__ void bf16_half(const Bf16Link& L, const uint32_t* pt, const uint32_t* pb, cplx<float>* w) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float re = dot2_first(L.A[3 * a], pt[0]), im = dot2_first(L.B[3 * a], pt[0]);
+#pragma unroll
+    for (int bb = 1; bb < 3; ++bb) {
+      const int e = 3 * a + bb;
+      re = dot2(L.A[e], pt[bb], re);
+      im = dot2(L.B[e], pt[bb], im);
+    }
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      const int e = 3 * a + bb;
+      if (CC == 0) {
+        re = dot2(L.A[e], pb[bb], re);
+        im = dot2(L.B[e], pb[bb], im);
+      } else if (CC == 1) {
+        re = dot2(L.nA[e], pb[bb], re);
+        im = dot2(L.nB[e], pb[bb], im);
+      } else if (CC == 2) {
+        re = dot2(L.nB[e], pb[bb], re);
+        im = dot2(L.A[e], pb[bb], im);
+      } else {
+        re = dot2(L.B[e], pb[bb], re);
+        im = dot2(L.nA[e], pb[bb], im);
+      }
+    }
+    w[a] = {re, im};
+  }
+}
+
+// the two projected halves of (1 + S g_MU) p, multiplied: p as 12 stored pairs
+// (component 3 spin + colour); h0 = p0 + c0 p_b0, h1 = p1 + c1 p_b1 as in project()
+template <int MU, int S>
+__device__ __forceinline__ void bf16_project_mul(const Bf16Link& L, const uint32_t* p, cplx<float>* w) {
+  constexpr int mi = S > 0 ? 3 : 2, pi = S > 0 ? 2 : 3;  // c = -S i, c = +S i
+  constexpr int m1 = S > 0 ? 1 : 0, p1 = S > 0 ? 0 : 1;  // c = -S,   c = +S
+  if (MU == 0) {         // h0 = p0 - S i p3, h1 = p1 - S i p2
+    bf16_half<mi>(L, p + 0, p + 9, w);
+    bf16_half<mi>(L, p + 3, p + 6, w + 3);
+  } else if (MU == 1) {  // h0 = p0 - S p3, h1 = p1 + S p2
+    bf16_half<m1>(L, p + 0, p + 9, w);
+    bf16_half<p1>(L, p + 3, p + 6, w + 3);
+  } else if (MU == 2) {  // h0 = p0 - S i p2, h1 = p1 + S i p3
+    bf16_half<mi>(L, p + 0, p + 6, w);
+    bf16_half<pi>(L, p + 3, p + 9, w + 3);
+  } else {               // h0 = p0 + S p2, h1 = p1 + S p3
+    bf16_half<p1>(L, p + 0, p + 6, w);
+    bf16_half<p1>(L, p + 3, p + 9, w + 3);
+  }
+}
+
+// the link a direction-parallel wavefront holds: unpacked SU(3) in FP32 / FP64,
+// the dot-product pairs for BF16
+template <typename P>
+struct DpLink {
+  using type = SU3<typename P::real>;
+};
+template <>
+struct DpLink<PrecBF16> {
+  using type = Bf16Link;
+};
+
 // the wavefront's direction: its neighbour, time-boundary phase and link
 template <typename P, int MU, int FWD, bool ST>
-__device__ __forceinline__ void dp_link(const HopArgs& a, const Coord& c, int h, SU3<typename P::real>* U, int* hn,
-                                        typename P::real* ph) {
+__device__ __forceinline__ void dp_link(const HopArgs& a, const Coord& c, int h, typename DpLink<P>::type* U,
+                                        int* hn, typename P::real* ph) {
   using R = typename P::real;
   const int Vh = a.g.Vh;
   const size_t lb = LinkIO<P>::bytes * size_t(a.g.Vhp);
   bool wrap;
   *hn = neighbour<MU>(a.g, c, FWD ? +1 : -1, &wrap);
-  *U = FWD ? LinkIO<P>::template load<ST>(a.links + (a.parity * 4 + MU) * lb, h, Vh)
-           : LinkIO<P>::template load<ST>(a.links + ((1 - a.parity) * 4 + MU) * lb, *hn, Vh);
+  const char* base = FWD ? a.links + (a.parity * 4 + MU) * lb : a.links + ((1 - a.parity) * 4 + MU) * lb;
+  if constexpr (std::is_same<P, PrecBF16>::value) {
+    bf16_link<FWD>(base, FWD ? h : *hn, U, ST);
+  } else {
+    *U = LinkIO<P>::template load<ST>(base, FWD ? h : *hn, Vh);
+  }
   *ph = wrap ? R(a.g.tbc) : R(1);
 }
 
 // project, multiply and store to LDS the half-spinor results of NRP rhs
 template <typename P, int MU, int FWD, int DAG, int NRP>
-__device__ __forceinline__ void dp_spin(const HopArgs& a, const SU3<typename P::real>& U, int hn,
+__device__ __forceinline__ void dp_spin(const HopArgs& a, const typename DpLink<P>::type& U, int hn,
                                         typename P::real ph, int r0, cplx<typename P::real>* W, int lane) {
   using R = typename P::real;
   constexpr int S = FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1);  // projector sign (1 + S g_mu)
   constexpr int D = 2 * MU + (FWD ? 0 : 1);
+  if constexpr (std::is_same<P, PrecBF16>::value) {
 #pragma unroll
-  for (int r = 0; r < NRP; ++r) {
-    const Spinor<R> s = SpinorIO<P>::load(a.in + (r0 + r) * a.rhs_stride, hn, a.g.Vh);
-    const Half<R> hp = project<MU, S>(s);
-    Half<R> w;
-    if (FWD) {
-      su3_mul(U, hp.c, w.c);
-      su3_mul(U, hp.c + 3, w.c + 3);
-    } else {
-      su3_dag_mul(U, hp.c, w.c);
-      su3_dag_mul(U, hp.c + 3, w.c + 3);
+    for (int r = 0; r < NRP; ++r) {
+      const uint4* b = reinterpret_cast<const uint4*>(a.in + (r0 + r) * a.rhs_stride);
+      uint32_t p[12];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const uint4 v = b[fidx(j, hn, 3)];
+        p[4 * j] = v.x;
+        p[4 * j + 1] = v.y;
+        p[4 * j + 2] = v.z;
+        p[4 * j + 3] = v.w;
+      }
+      cplx<float> w[6];
+      bf16_project_mul<MU, S>(U, p, w);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) W[((r * 8 + D) * 6 + k) * kDpSites + lane] = MU == 3 ? ph * w[k] : w[k];
     }
+  } else {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) W[((r * 8 + D) * 6 + k) * kDpSites + lane] = ph * w.c[k];
+    for (int r = 0; r < NRP; ++r) {
+      const Spinor<R> s = SpinorIO<P>::load(a.in + (r0 + r) * a.rhs_stride, hn, a.g.Vh);
+      const Half<R> hp = project<MU, S>(s);
+      Half<R> w;
+      if (FWD) {
+        su3_mul(U, hp.c, w.c);
+        su3_mul(U, hp.c + 3, w.c + 3);
+      } else {
+        su3_dag_mul(U, hp.c, w.c);
+        su3_dag_mul(U, hp.c + 3, w.c + 3);
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) W[((r * 8 + D) * 6 + k) * kDpSites + lane] = MU == 3 ? ph * w.c[k] : w.c[k];
+    }
   }
 }
 
@@ -304,14 +484,14 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
   __shared__ cplx<R> W[NRP * 8 * 6 * kDpSites];
   __shared__ double red[kDpThreads / 64];
   int tile, row;
-  hop_block_coords(a, &tile, &row);
+  hop_block_coords<kDpSites>(a, &tile, &row);
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int Vh = a.g.Vh;
   const int h = tile * kDpSites + lane;
   const bool active = h < Vh;
   const int r0 = row * NR;
-  SU3<R> U;
+  typename DpLink<P>::type U;
   int hn = 0;
   R ph = R(1);
   if (active) {
@@ -366,7 +546,7 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
             if (a.y) o[q] = o[q] + cy * yv[q];
           }
           if constexpr (CHEB) {
-            cheb_unit<P, ST>(a, u, h, Vh, o);
+            cheb_unit<P, ST>(a, off, u, h, Vh, o);
             continue;
           }
           epi_store_unit<P, ST>(a.out + off, u, h, Vh, o);
@@ -414,13 +594,14 @@ static void dispatch_dp(HopArgs a, int nrhs, hipStream_t st, int max_pass) {
 template <typename P, int DAG, bool ST>
 static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, const HopConfig& c) {
   if constexpr (DAG == 0) {
-    if (a.ch_t) {  // fused Chebyshev step: one rhs, forward hop
-      a.rows = 1;
+    if (a.ch_t) {  // fused Chebyshev step: forward hop, one rhs per pass / thread
+      a.rows = nrhs;
       if (c.variant == kHopDirParallel)
-        hipLaunchKernelGGL((hop_dp_kernel<P, 0, 1, 1, ST, true>), dim3((a.g.Vh + kDpSites - 1) / kDpSites),
+        hipLaunchKernelGGL((hop_dp_kernel<P, 0, 1, 1, ST, true>), dim3((a.g.Vh + kDpSites - 1) / kDpSites * nrhs),
                            dim3(kDpThreads), 0, st, a);
       else
-        hipLaunchKernelGGL((hop_kernel<P, 0, 1, ST, true>), dim3(site_blocks(a.g.Vh)), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((hop_kernel<P, 0, 1, ST, true>), dim3(site_blocks(a.g.Vh) * nrhs), dim3(kBlock), 0, st,
+                           a);
       return;
     }
   }
@@ -492,7 +673,7 @@ struct BatchArgs {
 // one wavefront's direction of a batch tile: link, neighbour, projected product into LDS
 template <typename P, int MU, int FWD, int DAG>
 __device__ __forceinline__ void dp_dir(const HopArgs& a, const Coord& c, int h, cplx<typename P::real>* W, int lane) {
-  SU3<typename P::real> U;
+  typename DpLink<P>::type U;
   int hn = 0;
   typename P::real ph;
   dp_link<P, MU, FWD, false>(a, c, h, &U, &hn, &ph);
@@ -656,7 +837,7 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
                 int nrhs, const HopEpi& e) {
   WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs, WL_EINVAL, "nrhs out of range");
   WL_REQUIRE(out != in, WL_EINVAL, "hop output must not alias its input");
-  WL_REQUIRE(!e.cheb_t || (nrhs == 1 && !dagger && !e.dot), WL_EINVAL, "fused Chebyshev step: one rhs, forward");
+  WL_REQUIRE(!e.cheb_t || (!dagger && !e.dot), WL_EINVAL, "fused Chebyshev step: forward hop, no dot");
   ensure_lowp_links(L);
   HopArgs a;
   a.g = L->geo;

@@ -91,39 +91,62 @@ __device__ __forceinline__ void load_link_at(const void* U, const Geo& g, Coord 
 //   Xi    = sum_k hC_k (x) hA_k^dag,  h = upper rows of (1 - g_mu) C(y), (1 - g_mu) A(x)
 //   Theta = sum_k gC_k (x) gA_k^dag,  g = upper rows of (1 + g_mu) C(x), (1 + g_mu) A(y)
 // (the lower spin rows of a projected spinor are unit phases times the upper
-// rows, so the four-spin sums reduce to the two upper rows).
+// rows, so the four-spin sums reduce to the two upper rows).  Xi and Theta
+// have rank two, so W is formed without them and without any 3x3 product:
+//   W_ij = sum_k (U hC_k)_i conj(hA_k)_j - gC_k,i conj(U gA_k)_j,
+// four SU(3) x vector products and, of W, only the entries the su(3)
+// coefficients read (imaginary diagonal, the six off-diagonal entries).  The
+// link comes from the two-row FP64 copy, its third row rebuilt.
 template <int MU>
 __device__ __forceinline__ void bilinear_dir(const Geo& g, const Coord& c, int p, int h, const char* Ah[2],
-                                             const char* Ch[2], const Spinor<double>& Ax,
-                                             const Spinor<double>& Cx, const void* U, double* F, double coeff) {
+                                             const char* Ch[2], const char* U2, double* F, double coeff) {
   bool wrap;
   const int hy = neighbour<MU>(g, c, +1, &wrap);
-  const Spinor<double> Ay = SpinorIO<PrecF64>::load(Ah[1 - p], hy, g.Vh);
-  const Spinor<double> Cy = SpinorIO<PrecF64>::load(Ch[1 - p], hy, g.Vh);
-  const Half<double> hA = project<MU, -1>(Ax);
-  const Half<double> hC = project<MU, -1>(Cy);
-  const Half<double> gA = project<MU, +1>(Ay);
-  const Half<double> gC = project<MU, +1>(Cx);
-  cd Xi[9], Th[9], Um[9];
+  const char* Ub = U2 + size_t(p * 4 + MU) * LinkIO<PrecF64>::bytes * g.Vhp;
+  const double ph = wrap ? double(g.tbc) : 1.0;
+  // W accumulated in two stages (U hC (x) hA^dag, then - gC (x) (U gA)^dag), the
+  // scheduler kept from hoisting the second stage's loads into the first: four
+  // spinors in flight at once held every wavefront to two per SIMD
+  cd w01, w10, w02, w20, w12, w21;
+  double d0, d1, d2;
+  {
+    const Half<double> hC = project<MU, -1>(SpinorIO<PrecF64>::load(Ch[1 - p], hy, g.Vh));
+    const Half<double> hA = project<MU, -1>(SpinorIO<PrecF64>::load(Ah[p], h, g.Vh));
+    const SU3<double> U = LinkIO<PrecF64>::load(Ub, h, g.Vh);
+    cd u[6];  // ph U hC_k
+    su3_mul(U, hC.c, u);
+    su3_mul(U, hC.c + 3, u + 3);
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      Xi[3 * a + b] = hC.c[a] * conj(hA.c[b]) + hC.c[3 + a] * conj(hA.c[3 + b]);
-      Th[3 * a + b] = gC.c[a] * conj(gA.c[b]) + gC.c[3 + a] * conj(gA.c[3 + b]);
-    }
-  load_link(U, p, MU, h, g.Vhp, Um);
-  if (wrap) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Um[k] = double(g.tbc) * Um[k];
+    for (int k = 0; k < 6; ++k) u[k] = ph * u[k];
+    auto P = [&](int i, int j) { return u[i] * conj(hA.c[j]) + u[3 + i] * conj(hA.c[3 + j]); };
+    w01 = P(0, 1), w10 = P(1, 0), w02 = P(0, 2), w20 = P(2, 0), w12 = P(1, 2), w21 = P(2, 1);
+    d0 = P(0, 0).i, d1 = P(1, 1).i, d2 = P(2, 2).i;
   }
-  cd W1[9], W2[9];
-  mat_mul(Um, Xi, W1);
-  mat_mul_dag(Th, Um, W2);
+  __builtin_amdgcn_sched_barrier(0);
+  {
+    const Half<double> gA = project<MU, +1>(SpinorIO<PrecF64>::load(Ah[1 - p], hy, g.Vh));
+    const Half<double> gC = project<MU, +1>(SpinorIO<PrecF64>::load(Ch[p], h, g.Vh));
+    const SU3<double> U = LinkIO<PrecF64>::load(Ub, h, g.Vh);  // again, from the cache
+    cd v[6];  // ph U gA_k
+    su3_mul(U, gA.c, v);
+    su3_mul(U, gA.c + 3, v + 3);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) W1[k] = W1[k] - W2[k];
+    for (int k = 0; k < 6; ++k) v[k] = ph * v[k];
+    auto Q = [&](int i, int j) { return gC.c[i] * conj(v[j]) + gC.c[3 + i] * conj(v[3 + j]); };
+    w01 = w01 - Q(0, 1), w10 = w10 - Q(1, 0), w02 = w02 - Q(0, 2), w20 = w20 - Q(2, 0);
+    w12 = w12 - Q(1, 2), w21 = w21 - Q(2, 1);
+    d0 -= Q(0, 0).i, d1 -= Q(1, 1).i, d2 -= Q(2, 2).i;
+  }
+  // g^a = Re(i tr(T^a W)) = -Im tr(T^a W), T^a = lambda^a / 2
   double gr[8];
-  su3_grad(W1, gr);
+  gr[0] = -0.5 * (w01.i + w10.i);
+  gr[1] = -0.5 * (w01.r - w10.r);
+  gr[2] = -0.5 * (d0 - d1);
+  gr[3] = -0.5 * (w02.i + w20.i);
+  gr[4] = -0.5 * (w02.r - w20.r);
+  gr[5] = -0.5 * (w12.i + w21.i);
+  gr[6] = -0.5 * (w12.r - w21.r);
+  gr[7] = -(d0 + d1 - 2.0 * d2) * 0.28867513459481288225;  // 1 / (2 sqrt 3)
   double* f = F + size_t(p * 4 + MU) * 8 * g.Vh;
 #pragma unroll
   for (int a = 0; a < 8; ++a) f[a * g.Vh + h] += coeff * gr[a];
@@ -135,7 +158,7 @@ __device__ __forceinline__ void bilinear_dir(const Geo& g, const Coord& c, int p
 // four wavefronts, come from the CU's cache after the first.
 constexpr int kBilSites = 64;
 __global__ __launch_bounds__(4 * kBilSites) void bilinear_kernel(Geo g, double* F, const char* Ae, const char* Ao,
-                                                                const char* Ce, const char* Co, const void* U,
+                                                                const char* Ce, const char* Co, const char* U2,
                                                                 double coeff) {
   const int h = blockIdx.x * kBilSites + (threadIdx.x & (kBilSites - 1));
   const int p = blockIdx.y;
@@ -144,13 +167,11 @@ __global__ __launch_bounds__(4 * kBilSites) void bilinear_kernel(Geo g, double* 
   const char* Ah[2] = {Ae, Ao};
   const char* Ch[2] = {Ce, Co};
   const Coord c = site_coords(g, h, p);
-  const Spinor<double> Ax = SpinorIO<PrecF64>::load(Ah[p], h, g.Vh);
-  const Spinor<double> Cx = SpinorIO<PrecF64>::load(Ch[p], h, g.Vh);
   switch (mu) {
-    case 0: bilinear_dir<0>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff); break;
-    case 1: bilinear_dir<1>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff); break;
-    case 2: bilinear_dir<2>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff); break;
-    default: bilinear_dir<3>(g, c, p, h, Ah, Ch, Ax, Cx, U, F, coeff); break;
+    case 0: bilinear_dir<0>(g, c, p, h, Ah, Ch, U2, F, coeff); break;
+    case 1: bilinear_dir<1>(g, c, p, h, Ah, Ch, U2, F, coeff); break;
+    case 2: bilinear_dir<2>(g, c, p, h, Ah, Ch, U2, F, coeff); break;
+    default: bilinear_dir<3>(g, c, p, h, Ah, Ch, U2, F, coeff); break;
   }
 }
 
@@ -326,9 +347,10 @@ __global__ __launch_bounds__(kBlock) void sumsq_kernel(const double* P, size_t n
 // ------------------------------------------------------------------ launchers
 void launch_bilinear(wl_lattice* L, double* F, const void* Ae, const void* Ao, const void* Ce, const void* Co,
                      double coeff) {
+  ensure_lowp_links(L);  // the two-row FP64 link copy
   dim3 grid((L->Vh + kBilSites - 1) / kBilSites, 2);  // (64-site tile, parity)
   hipLaunchKernelGGL(bilinear_kernel, grid, dim3(4 * kBilSites), 0, L->stream, L->geo, F, (const char*)Ae,
-                     (const char*)Ao, (const char*)Ce, (const char*)Co, L->Ufull, coeff);
+                     (const char*)Ao, (const char*)Ce, (const char*)Co, (const char*)L->U[F64], coeff);
   WL_HIP(hipGetLastError());
 }
 

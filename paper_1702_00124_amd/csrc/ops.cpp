@@ -37,7 +37,7 @@ void op_mhat(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, 
 
 void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const double* mu2, int nrhs,
           const DotOut& dot, const ChebStep* cheb, const double* lin, const OpScratch* scr) {
-  WL_REQUIRE(!lin || (nrhs == 1 && !cheb && !dot.partials), WL_EINVAL, "op_j: lin takes one rhs, no dot or step");
+  WL_REQUIRE(!lin || (!cheb && !dot.partials), WL_EINVAL, "op_j: lin takes no dot or step");
   const size_t fb = spinor_bytes(prec, L->Vh) * nrhs;
   void* odd = scr ? scr->odd : ws_get(L, "op_odd", fb);
   void* v = scr ? scr->even : ws_get(L, "op_even", fb);
@@ -62,7 +62,7 @@ void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, con
   if (lin) {  // lin0 (g5 M-hat v + mu2 in) + lin1 in
     e4.cx = lin[0];
     e4.a = -kappa * kappa * lin[0];
-    e4.by[0] = lin[0] * e4.by[0] + lin[1];
+    for (int r = 0; r < nrhs; ++r) e4.by[r] = lin[0] * e4.by[r] + lin[1];
     e4.y = in;
   }
   if (dot.partials) {

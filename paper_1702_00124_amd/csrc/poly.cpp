@@ -48,6 +48,18 @@ void poly_q_roots(const PolyDesc& pd, std::vector<double>& re, std::vector<doubl
   }
 }
 
+long long poly_j_count(int mode, const PolyDesc& pd) {
+  std::vector<double> zr, zi;
+  poly_q_roots(pd, zr, zi);
+  const long long q = (long long)zr.size();
+  const long long p = pd.ndiv > 0 ? 2 * q : pd.n;
+  switch (mode) {
+    case WL_POLY_P: return p;
+    case WL_POLY_PJ: return p + 1;
+    default: return q;
+  }
+}
+
 void check_poly(const PolyDesc& pd) {
   WL_REQUIRE(pd.n >= 1 && pd.n <= 512, WL_EINVAL, "polynomial degree out of range");
   WL_REQUIRE(pd.a > 0.0 && pd.b > pd.a, WL_EINVAL, "polynomial interval needs 0 < a < b");
@@ -59,9 +71,11 @@ void check_poly(const PolyDesc& pd) {
   }
 }
 
-// out = P_n(J) in by the recurrence, fields and arithmetic in storage precision pr
-static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd, Prec pr) {
-  const size_t fb = spinor_bytes(pr, L->Vh);
+// out = P_n(J) in by the recurrence, nrhs fields, storage precision pr
+static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd, Prec pr,
+                   int nrhs) {
+  const size_t fb = spinor_bytes(pr, L->Vh) * nrhs;
+  std::vector<double> shifts(nrhs, mu2);
   void* tA = ws_get(L, "pl_tA", fb);
   void* tB = ws_get(L, "pl_tB", fb);
   void* eA = ws_get(L, "pl_eA", fb);
@@ -70,65 +84,73 @@ static void poly_P(wl_lattice* L, void* out, const void* in, double kappa, doubl
   const double y0 = (b + a) / (b - a);
   const double ct = 2.0 * (b + a) / (b - a), cw = -4.0 / (b - a);
   // t0 = in, e0 = 0, e1 = in; t1 = y(J) in = c1 in + c2 J in from J's epilogue
-  launch_cheb_init(L, in, tA, eA, eB, pr);
+  launch_cheb_init(L, in, tA, eA, eB, pr, nrhs);
   const double lin[2] = {-2.0 / (b - a), (b + a) / (b - a)};
-  op_j(L, pr, tB, in, kappa, &mu2, 1, DotOut(), nullptr, lin);
+  op_j(L, pr, tB, in, kappa, shifts.data(), nrhs, DotOut(), nullptr, lin);
   for (int m = 1; m < pd.n; ++m) {
     // J t_m and the step in one pass: tA <- t_{m+1}, eA <- e_{m+1}
     const ChebStep cs{tA, eB, eA, ct, cw, 2.0 * y0};
-    op_j(L, pr, nullptr, tB, kappa, &mu2, 1, DotOut(), &cs);
+    op_j(L, pr, nullptr, tB, kappa, shifts.data(), nrhs, DotOut(), &cs);
     std::swap(tA, tB);
     std::swap(eA, eB);
   }
   // out = s e_{n+1}, e_{n+1} = 2 y0 e_n + 2 t_n - e_{n-1}
-  launch_cheb_last(L, tB, eB, eA, out, 2.0 * y0, (2.0 / (b - a)) / cheb_T_above_one(pd.n + 1, y0), pr);
+  launch_cheb_last(L, tB, eB, eA, out, 2.0 * y0, (2.0 / (b - a)) / cheb_T_above_one(pd.n + 1, y0), pr, nrhs);
 }
 
 // out = sqrt(c) prod_k (J - z_k) in   (conjugate roots for Q^dag)
 static void poly_Q(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
-                   int dagger, Prec pr) {
+                   int dagger, Prec pr, int nrhs) {
   WL_REQUIRE(pd.n % 2 == 0, WL_EINVAL, "P = Q^dag Q needs an even degree");
-  const size_t fb = spinor_bytes(pr, L->Vh);
+  const size_t fb = spinor_bytes(pr, L->Vh) * nrhs;
   void* v = ws_get(L, "pl_qv", fb);
   void* w = ws_get(L, "pl_w", fb);
-  std::vector<double> zr, zi;
+  std::vector<double> zr, zi, shifts(nrhs, mu2);
   poly_q_roots(pd, zr, zi);
   copy_dev(L, v, in, fb);
   for (size_t k = 0; k < zr.size(); ++k) {
-    op_j(L, pr, w, v, kappa, &mu2, 1);
-    const double one[2] = {1.0, 0.0};
-    const double mz[2] = {-zr[k], dagger ? zi[k] : -zi[k]};
-    launch_caxpby(L, v, one, w, mz, v, 0, 1, pr);
+    op_j(L, pr, w, v, kappa, shifts.data(), nrhs);
+    std::vector<double> one(2 * nrhs), mz(2 * nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+      one[2 * r] = 1.0;
+      one[2 * r + 1] = 0.0;
+      mz[2 * r] = -zr[k];
+      mz[2 * r + 1] = dagger ? zi[k] : -zi[k];
+    }
+    launch_caxpby(L, v, one.data(), w, mz.data(), v, 0, nrhs, pr);
   }
-  const double sc[2] = {std::sqrt(poly_lead(pd)), 0.0};
-  launch_caxpby(L, out, sc, v, nullptr, nullptr, 0, 1, pr);
+  std::vector<double> sc(2 * nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r) sc[2 * r] = std::sqrt(poly_lead(pd));
+  launch_caxpby(L, out, sc.data(), v, nullptr, nullptr, 0, nrhs, pr);
 }
 
 // P(J) in: the recurrence for P_n, Q^dag Q for a quotient
 static void poly_full(wl_lattice* L, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
-                      Prec pr) {
+                      Prec pr, int nrhs) {
   if (pd.ndiv == 0) {
-    poly_P(L, out, in, kappa, mu2, pd, pr);
+    poly_P(L, out, in, kappa, mu2, pd, pr, nrhs);
     return;
   }
-  void* q = ws_get(L, "pl_qq", spinor_bytes(pr, L->Vh));
-  poly_Q(L, q, in, kappa, mu2, pd, 0, pr);
-  poly_Q(L, out, q, kappa, mu2, pd, 1, pr);
+  void* q = ws_get(L, "pl_qq", spinor_bytes(pr, L->Vh) * nrhs);
+  poly_Q(L, q, in, kappa, mu2, pd, 0, pr, nrhs);
+  poly_Q(L, out, q, kappa, mu2, pd, 1, pr, nrhs);
 }
 
 void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
-                Prec pr) {
+                Prec pr, int nrhs) {
   check_poly(pd);
+  WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs, WL_EINVAL, "nrhs must be 1..16");
   switch (mode) {
-    case WL_POLY_P: poly_full(L, out, in, kappa, mu2, pd, pr); break;
+    case WL_POLY_P: poly_full(L, out, in, kappa, mu2, pd, pr, nrhs); break;
     case WL_POLY_PJ: {
-      void* jin = ws_get(L, "pl_jin", spinor_bytes(pr, L->Vh));
-      op_j(L, pr, jin, in, kappa, &mu2, 1);
-      poly_full(L, out, jin, kappa, mu2, pd, pr);
+      void* jin = ws_get(L, "pl_jin", spinor_bytes(pr, L->Vh) * nrhs);
+      std::vector<double> shifts(nrhs, mu2);
+      op_j(L, pr, jin, in, kappa, shifts.data(), nrhs);
+      poly_full(L, out, jin, kappa, mu2, pd, pr, nrhs);
       break;
     }
-    case WL_POLY_Q: poly_Q(L, out, in, kappa, mu2, pd, 0, pr); break;
-    case WL_POLY_QDAG: poly_Q(L, out, in, kappa, mu2, pd, 1, pr); break;
+    case WL_POLY_Q: poly_Q(L, out, in, kappa, mu2, pd, 0, pr, nrhs); break;
+    case WL_POLY_QDAG: poly_Q(L, out, in, kappa, mu2, pd, 1, pr, nrhs); break;
     default: throw Error(WL_EINVAL, "unknown polynomial mode");
   }
 }

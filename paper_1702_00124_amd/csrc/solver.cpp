@@ -47,10 +47,15 @@ struct CgGraph {
 
 // CG core.  apply_lp: inner-precision operator with fused Re<in, out>
 // partials (rows of nbrow); apply64: FP64 operator for true residuals.
-// Fields hold nrhs right-hand sides of nh halves each.
+// Fields hold nrhs right-hand sides of nh halves each.  With jpa > 0 the
+// cost counter is set to what the solve needed: jpa K multiplications per
+// operator application, one application per iteration of each rhs up to its
+// convergence and one per rhs for each FP64 residual b - A x (applications a
+// chunk issues past a rhs's convergence are not counted); jpa = 0 leaves the
+// counter to the operator's own launches.
 static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int nbrow, size_t hb64, size_t hbi,
                    const ApplyLowp& apply_lp, const Apply64& apply64, const wl_cg_params& prm,
-                   wl_cg_stats* stats, bool count_kmat) {
+                   wl_cg_stats* stats, long long jpa) {
   WL_REQUIRE(nrhs >= 1 && nrhs <= kMaxRhs && nrhs * nh <= kMaxRhs, WL_EINVAL, "nrhs out of range");
   WL_REQUIRE(prm.tol > 0.0 && prm.maxiter > 0, WL_EINVAL, "cg: tol and maxiter must be positive");
   const Prec ip = Prec(prm.inner);
@@ -275,8 +280,10 @@ static int cg_core(wl_lattice* L, void* x, const void* b, int nrhs, int nh, int 
 
   long long iters_total = 0;
   for (int i = 0; i < nrhs; ++i) iters_total += (long long)S(CG_ITERS, i);
-  // K applications actually made (graph replays are not seen by the launch counters)
-  if (count_kmat) L->n_kmat = kmat0 + iters_total + kmat_extra * nrhs;
+  // K multiplications the solve needed (graph replays are not seen by the launch counters)
+  if (jpa > 0) L->n_kmat = kmat0 + (iters_total + kmat_extra * nrhs) * jpa;
+  if (L->solve_log_on)
+    L->solve_log.push_back({iters_total, kmat_extra * nrhs, jpa > 0 ? jpa : 0});
   if (stats) {
     for (int i = 0; i < nrhs; ++i) {
       stats[i].iters = int(S(CG_ITERS, i));
@@ -300,7 +307,7 @@ int cg_run(wl_lattice* L, void* x, const void* b, double kappa, const double* mu
   Apply64 a64 = [&](void* out, const void* in) { op_apply(L, op, F64, out, in, kappa, mu2, nrhs); };
   const Prec ipr = (ip == F32 || ip == BF16) ? ip : F64;
   return cg_core(L, x, b, nrhs, nh, op_dot_blocks(L, op, ipr), spinor_bytes(F64, L->Vh),
-                 spinor_bytes((ip == F32 || ip == BF16) ? ip : F64, L->Vh), lp, a64, prm, stats, true);
+                 spinor_bytes((ip == F32 || ip == BF16) ? ip : F64, L->Vh), lp, a64, prm, stats, 1);
 }
 
 int cg_run_batch(wl_lattice* L, void* x, const void* b, int nrhs, int nbrow, const ApplyLowp& lp, const Apply64& a64,
@@ -312,12 +319,12 @@ int cg_run_batch(wl_lattice* L, void* x, const void* b, int nrhs, int nbrow, con
   // the operator outputs are written at the lattices' sites only: clear the rest
   zero_dev(L, ws_get(L, "cg_Ap", hbi * nrhs), hbi * nrhs);
   zero_dev(L, ws_get(L, "cg_Ax64", hb64 * nrhs), hb64 * nrhs);
-  return cg_core(L, x, b, nrhs, 1, nbrow, hb64, hbi, lp, a64, prm, stats, false);
+  return cg_core(L, x, b, nrhs, 1, nbrow, hb64, hbi, lp, a64, prm, stats, 0);
 }
 
 int cg_run_generic(wl_lattice* L, void* x, const void* b,
                    const std::function<void(Prec, void*, const void*)>& apply, const wl_cg_params& prm_in,
-                   wl_cg_stats* stats) {
+                   wl_cg_stats* stats, long long jpa) {
   wl_cg_params prm = prm_in;
   prm.use_graph = 0;  // the polynomial operators synchronise nothing but are host-sequenced; no capture
   const Prec ip = Prec(prm.inner);
@@ -329,7 +336,7 @@ int cg_run_generic(wl_lattice* L, void* x, const void* b,
   };
   Apply64 a64 = [&](void* out, const void* in) { apply(F64, out, in); };
   return cg_core(L, x, b, 1, 1, nb, spinor_bytes(F64, L->Vh),
-                 spinor_bytes((ip == F32 || ip == BF16) ? ip : F64, L->Vh), lp, a64, prm, stats, false);
+                 spinor_bytes((ip == F32 || ip == BF16) ? ip : F64, L->Vh), lp, a64, prm, stats, jpa);
 }
 
 // ------------------------------------------------------------------ multi-shift CG

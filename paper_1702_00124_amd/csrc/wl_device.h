@@ -474,7 +474,24 @@ struct Geo {
   int Vh;    // V / 2
   int Vhp;   // Vh rounded up to whole 64-site tiles (field extent)
   int tbc;   // +1 periodic, -1 antiperiodic in time (fermions only)
+  // reciprocals of Lxh, Ly, Lz for the site-coordinate divisions (geo_init)
+  double rcp[3];
 };
+
+// fill the derived fields of a geometry whose L, Lxh, Vh, Vhp, tbc are set
+inline void geo_init(Geo& g) {
+  g.rcp[0] = 1.0 / g.Lxh;
+  g.rcp[1] = 1.0 / g.L[1];
+  g.rcp[2] = 1.0 / g.L[2];
+}
+
+// floor(n / d) for 0 <= n < 2^30 and 1 <= d <= 2^15, r = 1 / d rounded to
+// nearest: (n + 1/2) r in FP64 is within 2^-22 of (n + 1/2) / d, whose
+// distance to the nearest integer is at least 1 / (2 d) >= 2^-16, so the
+// truncation is exact (three instructions instead of an integer division)
+__device__ __forceinline__ int div_rcp(int n, double r) {
+  return int(__builtin_fma(double(n), r, 0.5 * r));
+}
 
 struct Coord {
   int x, y, z, t;
@@ -482,12 +499,12 @@ struct Coord {
 
 __device__ __forceinline__ Coord site_coords(const Geo& g, int h, int parity) {
   Coord c;
-  int xh = h % g.Lxh;
-  int r = h / g.Lxh;
-  c.y = r % g.L[1];
-  r /= g.L[1];
-  c.z = r % g.L[2];
-  c.t = r / g.L[2];
+  int r = div_rcp(h, g.rcp[0]);
+  const int xh = h - r * g.Lxh;
+  int q = div_rcp(r, g.rcp[1]);
+  c.y = r - q * g.L[1];
+  c.t = div_rcp(q, g.rcp[2]);
+  c.z = q - c.t * g.L[2];
   c.x = 2 * xh + ((c.y + c.z + c.t + parity) & 1);
   return c;
 }

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <map>
 #include <stdexcept>
@@ -24,11 +25,23 @@ constexpr int kProfPairs = 4096;  // sampled hop launches timed per precision
 enum HopVariant { kHopSite = 0, kHopDirParallel = 1 };
 // how a hop is launched: kernel variant; npass = direction-parallel: most rhs
 // passes per link held in registers (1, 2, 4), site: rhs per thread (1, 2);
-// use_xcd = XCD-contiguous workgroup numbering (else hardware round-robin);
+// use_xcd = workgroup order: 1 XCD-contiguous ranges, 0 the hardware's
+// round-robin, 2 z-blocked round-robin (kZBlock z planes at a time through
+// every t, so a tile's t neighbours follow it within a few hundred
+// workgroups; valid where zblock_ok);
 // stream = non-temporal link and epilogue loads and output stores
 struct HopConfig {
   int variant, npass, use_xcd, stream;
 };
+constexpr int kZBlock = 8;
+// the z-blocked order needs whole 64-site tiles per z plane, a multiple of 8
+// of them (so a tile's z and t neighbours share its XCD) and Lz a multiple of
+// kZBlock above it
+inline bool zblock_ok(const Geo& g, int sites_per_block) {
+  const long long plane = (long long)g.Lxh * g.L[1];
+  return plane % sites_per_block == 0 && (plane / sites_per_block) % 8 == 0 && g.L[2] % kZBlock == 0 &&
+         g.L[2] > kZBlock;
+}
 // rhs-count classes with their own configuration: 1, 2-4, 5-16
 constexpr int kHopKinds = 3;
 inline int hop_kind(int nrhs) { return nrhs <= 1 ? 0 : (nrhs <= 4 ? 1 : 2); }
@@ -106,6 +119,10 @@ struct wl_lattice {
   int prof_on = 0;
   int prof_capturing = 0;
   int prof_suspended = 0;               // set by entry points that must not create events
+  // optional log of the solves (wl_solve_log): iterations summed over rhs,
+  // FP64 residual applications, K multiplications per operator application
+  int solve_log_on = 0;
+  std::vector<std::array<long long, 3>> solve_log;
   std::vector<hipEvent_t> prof_ev[3];   // start/stop pairs
   double prof_ms[3] = {0, 0, 0};
   long long prof_n[3] = {0, 0, 0};
@@ -133,9 +150,10 @@ struct HopEpi {
   double* partials = nullptr;
   int part_stride = 0;      // per-rhs stride of partials
   int part_off = 0;         // block offset inside a rhs row
-  // fused Chebyshev step (one rhs, forward hop; out is not written):
-  // with w the result above, cheb_tprev <- ct t + cw w - cheb_tprev and
-  // cheb_eprev <- ce e + 2 t - cheb_eprev (t = cheb_t, e = cheb_e)
+  // fused Chebyshev step (forward hop, no dot; out is not written): for
+  // every rhs, with w the result above, cheb_tprev <- ct t + cw w - cheb_tprev
+  // and cheb_eprev <- ce e + 2 t - cheb_eprev (t = cheb_t, e = cheb_e; fields
+  // of nrhs rhs laid out as the hop's)
   const void* cheb_t = nullptr;
   void* cheb_tprev = nullptr;
   const void* cheb_e = nullptr;
@@ -195,10 +213,10 @@ void launch_finish_sum(wl_lattice* L, const double* partials, int stride, int nb
                        double* out_dev);
 // plain device copy of bytes (multiple of 16) from a to b
 void launch_stream_copy(wl_lattice* L, const void* a, void* b, size_t bytes);
-// Chebyshev recurrence start (t0 = in, e0 = 0, e1 = in) and end (out = s (ce e + 2 t - eprev))
-void launch_cheb_init(wl_lattice* L, const void* in, void* t0, void* e0, void* e1, Prec prec);
+// Chebyshev recurrence start (t0 = in, e0 = 0, e1 = in) and end (out = s (ce e + 2 t - eprev)), nrhs fields
+void launch_cheb_init(wl_lattice* L, const void* in, void* t0, void* e0, void* e1, Prec prec, int nrhs = 1);
 void launch_cheb_last(wl_lattice* L, const void* t, const void* e, const void* eprev, void* out, double ce, double s,
-                      Prec prec);
+                      Prec prec, int nrhs = 1);
 // CG scalar steps on the device state (see solver.cpp for the layout)
 void launch_cg_alpha(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);
 void launch_cg_beta(wl_lattice* L, const double* partials, int stride, int nb, double* st, int nrhs);

@@ -35,8 +35,8 @@ struct ChebStep {
 };
 // even sites: out = K-hat in + mu2[r] in; optional partials of Re<in, out>
 // (one row per rhs, hop_tiles(L, prec) blocks); with cheb, out is not written
-// and the Chebyshev step consumes J in; with lin (one rhs), out = lin[0] J in +
-// lin[1] in, from the same last-hop epilogue
+// and the Chebyshev step consumes J in (every rhs); with lin, out = lin[0] J in
+// + lin[1] in, from the same last-hop epilogue
 void op_j(wl_lattice* L, Prec prec, void* out, const void* in, double kappa, const double* mu2, int nrhs,
           const DotOut& dot = DotOut(), const ChebStep* cheb = nullptr, const double* lin = nullptr,
           const OpScratch* scr = nullptr);
@@ -68,10 +68,10 @@ int cg_multishift_run(wl_lattice* L, void* x, const void* b, double kappa, const
 // CG on a general HPD operator on even-site fields (one rhs, x and b F64):
 // apply(prec, out, in) must leave out = A in with fields of storage precision
 // prec (prm.inner for the iteration, F64 for true residuals).  Used for P(J)
-// and P(J) J.
+// and P(J) J; jpa = the K multiplications of one application (cost count).
 int cg_run_generic(wl_lattice* L, void* x, const void* b,
                    const std::function<void(Prec, void*, const void*)>& apply, const wl_cg_params& prm,
-                   wl_cg_stats* stats);
+                   wl_cg_stats* stats, long long jpa);
 // the solver core's operators: the inner-precision one with fused Re<in, out>
 // partial sums (a row of DotOut.stride entries per rhs), and the FP64 one
 using ApplyLowp = std::function<void(Prec, void*, const void*, const DotOut&)>;
@@ -96,15 +96,18 @@ void batch_j(wl_batch* B, Prec prec, void* out, const void* in, const double* ka
 int batch_cg(wl_batch* B, void* x, const void* b, const double* kappa, const double* mu2, const wl_cg_params& prm,
              wl_cg_stats* stats);
 
-// polynomial filter (poly.cpp), F64, one rhs
+// polynomial filter (poly.cpp): nrhs fields of storage precision pr, one shift mu2
 struct PolyDesc {
   int n;
   double a, b;
   int ndiv = 0;  // > 0: the quotient P_n / P_ndiv
 };
 void poly_apply(wl_lattice* L, int mode, void* out, const void* in, double kappa, double mu2, const PolyDesc& pd,
-                Prec pr = F64);
+                Prec pr = F64, int nrhs = 1);
 double poly_lead(const PolyDesc& pd);
+// K multiplications (J applications) of one poly_apply per rhs: P_n n; a
+// quotient P_n / P_m 2 q (Q^dag Q, q root factors); P J one more; Q, Q^dag q
+long long poly_j_count(int mode, const PolyDesc& pd);
 void check_poly(const PolyDesc& pd);
 void poly_q_roots(const PolyDesc& pd, std::vector<double>& re, std::vector<double>& im);
 

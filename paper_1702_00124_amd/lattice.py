@@ -36,6 +36,12 @@ def _ptr(t: torch.Tensor) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _host_ptr(t: torch.Tensor) -> C.c_void_p:
+    if t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous host tensor")
+    return C.c_void_p(t.data_ptr())
+
+
 def _prec(p) -> int:
     return PREC[p] if isinstance(p, str) else int(p)
 
@@ -149,13 +155,17 @@ class WilsonLattice:
 
     # ---------------------------------------------------------------- links / fields
     def set_links(self, U: torch.Tensor):
-        U = U.to(device=self.device, dtype=torch.complex128).contiguous()
+        """Canonical complex128 [4, V, 3, 3] links; a CPU tensor is handed over as a host
+        array (the library stages it), a device tensor as a device array."""
+        on_device = U.device.type != "cpu"
+        U = (U.to(device=self.device) if on_device else U).to(dtype=torch.complex128).contiguous()
         assert U.shape == (4, self.V, 3, 3)
-        W.check(self.lib.wl_set_links(self.h, _ptr(U)))
+        W.check(self.lib.wl_set_links(self.h, _ptr(U) if on_device else _host_ptr(U), int(on_device)))
 
-    def get_links(self) -> torch.Tensor:
-        U = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device=self.device)
-        W.check(self.lib.wl_get_links(self.h, _ptr(U)))
+    def get_links(self, host: bool = False) -> torch.Tensor:
+        """The links as canonical complex128 [4, V, 3, 3] (host=True: into a CPU tensor)."""
+        U = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device="cpu" if host else self.device)
+        W.check(self.lib.wl_get_links(self.h, _host_ptr(U) if host else _ptr(U), int(not host)))
         return U
 
     def import_spinor(self, psi: torch.Tensor, prec="f64") -> torch.Tensor:
@@ -271,12 +281,15 @@ class WilsonLattice:
         return x[s * nrhs * fb:(s + 1) * nrhs * fb]
 
     def poly_filter_apply(self, buf: torch.Tensor, kappa: float, mu2: float, degree: int, a: float, b: float,
-                          mode: str = "P", out: Optional[torch.Tensor] = None, degree_div: int = 0) -> torch.Tensor:
-        out = self.new_field("f64") if out is None else out
-        _need(buf, self.field_bytes("f64"), "input")
-        _need(out, self.field_bytes("f64"), "output")
+                          mode: str = "P", out: Optional[torch.Tensor] = None, degree_div: int = 0,
+                          nrhs: int = 1, prec="f64") -> torch.Tensor:
+        out = self.new_field(prec, nrhs) if out is None else out
+        if 1 <= nrhs <= 16:
+            _need(buf, self.field_bytes(prec, nrhs), "input")
+            _need(out, self.field_bytes(prec, nrhs), "output")
         p = W.Poly(degree, a, b, degree_div)
-        W.check(self.lib.poly_filter_apply(self.h, _ptr(out), _ptr(buf), kappa, mu2, C.byref(p), POLY_MODE[mode]))
+        W.check(self.lib.poly_filter_apply(self.h, _ptr(out), _ptr(buf), kappa, mu2, C.byref(p), POLY_MODE[mode],
+                                           nrhs, _prec(prec)))
         return out
 
     # ---------------------------------------------------------------- action terms / forces
@@ -370,9 +383,10 @@ class WilsonLattice:
     def autotune(self, cache: Optional[str] = None):
         """Time the hop configurations per precision and rhs class and keep the fastest.
 
-        Returns {prec: [48 microsecond timings]} in the order the C API documents:
+        Returns {prec: [72 microsecond timings]} in the order the C API documents:
         class 0 (site, dp), then classes 1 and 2 (site 1, site 2, dp 1, dp 2, dp 4),
-        each per (stream, use_xcd) = (0, 1), (0, 0), (1, 1), (1, 0).
+        each per (stream, order) = (0, 1), (0, 0), (0, 2), (1, 1), (1, 0), (1, 2)
+        (0 where not a candidate).
 
         cache: a JSON file of earlier results keyed by lattice extents, device
         (ISA, compute units, memory) and library build; on a hit the stored configurations are set and
@@ -386,9 +400,9 @@ class WilsonLattice:
                     for k, c in enumerate(cfgs):
                         W.check(self.lib.wl_set_hop_config(self.h, _prec(prec), k, *c))
                 return hit["us"]
-        us = (C.c_double * 144)()
+        us = (C.c_double * 216)()
         W.check(self.lib.wl_autotune(self.h, us))
-        res = {name: list(us[48 * i:48 * i + 48]) for name, i in PREC.items()}
+        res = {name: list(us[72 * i:72 * i + 72]) for name, i in PREC.items()}
         if key:
             tune_cache_write(cache, key, {"configs": {p: [list(self.hop_config(p, k)) for k in range(3)] for p in PREC},
                                           "us": res})
@@ -421,6 +435,20 @@ class WilsonLattice:
         n = (C.c_longlong * 3)()
         W.check(self.lib.wl_hop_counts(self.h, n))
         return {name: n[i] for name, i in PREC.items()}
+
+    def solve_log(self, enable: bool = True):
+        """Start (clearing) or stop the log of every CG this context runs."""
+        W.check(self.lib.wl_solve_log(self.h, int(enable)))
+
+    def solve_log_read(self, max_solves: int = 100000):
+        """[(iterations summed over rhs, FP64 residual applications, K multiplications
+        per operator application)] of the logged solves, in order."""
+        n = C.c_int()
+        it = (C.c_longlong * max_solves)()
+        rs = (C.c_longlong * max_solves)()
+        jp = (C.c_longlong * max_solves)()
+        W.check(self.lib.wl_solve_log_read(self.h, max_solves, C.byref(n), it, rs, jp))
+        return [(it[i], rs[i], jp[i]) for i in range(n.value)]
 
     def counters(self):
         a, b = C.c_longlong(), C.c_longlong()

@@ -14,7 +14,7 @@ import lattice_inputs as li
 from oracle import action as oact, force as oforce, gauge as ogauge, hmc as ohmc
 from oracle import lattice as olat, poly as opoly, su3 as osu3, wilson as ow
 from paper_1702_00124_amd.lattice import CG, Term
-from tests.gpu_common import full_noise, half_noise, make_lattice, need_gpu, rel, say, to_np
+from tests.gpu_common import full_noise, half_noise, make_lattice, need_gpu, rel, rel_max, say, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +38,54 @@ def test_poly_filter_matches_oracle(mode, n, variant):
            "Q": lambda: opoly.apply_Q(J, psi, n, 0.001, 8.0),
            "QDAG": lambda: opoly.apply_Q(J, psi, n, 0.001, 8.0, dagger=True)}[mode]()
     assert rel(got, ref) <= 1e-12
+
+
+# FP32 storage between the recurrence's steps: each J application and step rounds at
+# 2^-24 relative, and the recurrence for e_m (whose terms grow like m^2 near the
+# interval's end) carries a rounding of step m to the end with a factor up to ~n^2:
+# n^2 2^-24 = 1.5e-5 at n = 16 (observed 1.1e-5); bounds 1e-4 (l2) and 2e-4 (max element).
+POLY_TOL = {"f64": (1e-12, 1e-12), "f32": (1e-4, 2e-4)}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("mode", ["P", "PJ", "Q", "QDAG"])
+def test_poly_filter_multi_rhs_matches_oracle(mode, prec):
+    """poly_filter_apply on 4 rhs at once (the recurrence's fused steps run per rhs in one
+    launch) on 6x4x4x10 (two hop tiles, ragged tail), order 16 on [0.001, 8], against the
+    oracle rhs by rhs."""
+    L = (6, 4, 4, 10)
+    say("poly multi-rhs", mode, prec)
+    lat, U = make_lattice(L)
+    psi = half_noise(L, 62, nrhs=4)
+    out = lat.poly_filter_apply(lat.import_spinor(torch.from_numpy(psi), prec), KAPPA, MU2, 16, 0.001, 8.0, mode,
+                                nrhs=4, prec=prec)
+    got = to_np(lat.export_spinor(out, prec, 4))
+    J = lambda v: ow.J(U, v, L, KAPPA, MU2)
+    l2, mx = POLY_TOL[prec]
+    for r in range(4):
+        ref = {"P": lambda: opoly.apply_P(J, psi[r], 16, 0.001, 8.0),
+               "PJ": lambda: opoly.apply_PJ(J, psi[r], 16, 0.001, 8.0),
+               "Q": lambda: opoly.apply_Q(J, psi[r], 16, 0.001, 8.0),
+               "QDAG": lambda: opoly.apply_Q(J, psi[r], 16, 0.001, 8.0, dagger=True)}[mode]()
+        e, em = rel(got[r], ref), rel_max(got[r], ref)
+        say(f"  rhs {r}: relative error {e:.2e}, max element {em:.2e}")
+        assert e <= l2 and em <= mx
+
+
+def test_links_host_and_device_arrays():
+    """wl_set_links / wl_get_links with host arrays (staged by the library) and with
+    device arrays give the same links, bit for bit."""
+    L = (6, 4, 4, 10)
+    say("links from host and device arrays")
+    lat, U = make_lattice(L)          # set from a host array
+    assert np.array_equal(lat.get_links(host=True).numpy(), U)
+    assert np.array_equal(to_np(lat.get_links()), U)
+    U2 = li.random_links(L, 0.3, 77)
+    lat.set_links(torch.from_numpy(U2).to(lat.device))   # device array
+    assert np.array_equal(lat.get_links(host=True).numpy(), U2)
+    psi = half_noise(L, 63)
+    got = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi)), 0)))
+    assert rel(got, ow.hop_eo(U2, psi, L, 0)) <= 1e-12
 
 
 def test_bilinear_primitive_matches_oracle():
@@ -158,6 +206,27 @@ def test_poly_solve_low_precision_inner(inner, variant):
     S_g = lat.action(gt, lat.import_spinor(torch.from_numpy(phi)))
     S_r = oact.action(oact.Ops(U, L4), ot, phi)
     assert abs(S_g - S_r) <= 1e-9 * abs(S_r)
+
+
+@pytest.mark.parametrize("kind", ["KINV", "RATIO", "POLYK_INV", "POLYK_INV_16"])
+def test_term_force_fp32_inner_matches_oracle(kind):
+    """The force under the trajectory's own solver settings (FP32 inner iterations,
+    FP64 reliable updates at threshold 0.003, FP64 true residual 1e-10) against the
+    oracle's force with FP64 solves at 1e-13.  A solution x with relative residual
+    r has relative error <= cond(A) r (cond < 30 for J and < 40 for P(J) J at 4^4),
+    and the force is bilinear in it, so the force's relative error is bounded by
+    about 2 cond r: asserted at 1e-8, the observed error reported."""
+    say("FP32-inner term force vs oracle", kind)
+    lat, U = make_lattice(L4)
+    ops = oact.Ops(U, L4)
+    phi = half_noise(L4, 3005)
+    name, n = (kind, None) if kind != "POLYK_INV_16" else ("POLYK_INV", 16)
+    gt, ot = _term(name, n=n)
+    gt.cg = CG(tol=1e-10, inner="f32", chunk=2, delta=0.003)
+    F = to_np(lat.export_su3(lat.fermion_force(gt, lat.import_spinor(torch.from_numpy(phi)))))
+    e = rel(F, oact.force(ops, ot, phi))
+    say(f"  force relative error {e:.2e}")
+    assert e <= 1e-8
 
 
 def test_poly_force_order16():
