@@ -302,6 +302,9 @@ def mixed_volume(li, torch, CG, WilsonLattice, WilsonBatch):
 
 
 LARGE_L, LARGE_KAPPA, LARGE_SPREAD = (32, 32, 32, 64), 0.156, 0.432
+# 2 spinors x 24 + 4 links x 12 (two rows) + 32 coefficients read and written, FP64
+BILINEAR_BYTES_PER_SITE = 8 * (2 * 24 + 4 * 12 + 2 * 32)
+VARIANT_NAMES = ["thread-per-site", "direction-parallel"]
 SPINOR_BYTES = {"f64": 192, "f32": 96, "bf16": 48}
 LINK_BYTES = {"f64": 96, "f32": 48, "bf16": 24}
 
@@ -352,7 +355,7 @@ def hbm_roofline(lat):
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": _traffic(prec, nrhs, cfg),
             "kernel": f"hop {prec} x{nrhs} rhs on {'x'.join(map(str, LARGE_L))} "
-                      f"({['thread-per-site', 'direction-parallel'][variant]}, npass {npass}, "
+                      f"({VARIANT_NAMES[variant]}, npass {npass}, "
                       f"{'XCD-contiguous' if use_xcd else 'round-robin'} workgroup order, "
                       f"{'streaming' if stream else 'cached'} access)",
             "config": list(cfg), "avg_launch_us": round(us, 2), "algorithmic_bytes_per_launch": byt,
@@ -397,20 +400,23 @@ def large_volume(lat, li, torch, np, CG):
     res["bf16_x4_speedup_per_rhs"] = round(res["f64_x1"]["ms"] / res["bf16_x4"]["ms_per_rhs"], 3)
     res["f32_x4_speedup_per_rhs"] = round(res["f64_x1"]["ms"] / res["f32_x4"]["ms_per_rhs"], 3)
     out["cg"] = res
-    # force bilinear: 2 full spinors + 4 links + read/write of 32 coefficients per site
+    # force bilinear: 2 full FP64 spinors, 4 two-row FP64 links, read and write of 32
+    # force coefficients per site; two distinct spinor fields
     A = lat.new_field("f64", 1, full=True)
-    A.zero_()
+    A.fill_(0.5)
+    Cf = lat.new_field("f64", 1, full=True)
+    Cf.fill_(0.25)
     F = lat.new_su3()
     for _ in range(2):
-        lat.force_bilinear(A, A, F)
+        lat.force_bilinear(A, Cf, F)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(10):
-        lat.force_bilinear(A, A, F)
+        lat.force_bilinear(A, Cf, F)
     e1.record()
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) / 10 * 1e3
-    fb = 1472 * 2 * Vh
+    fb = BILINEAR_BYTES_PER_SITE * 2 * Vh
     out["force_bilinear"] = {"us": round(us, 1), "GBs": round(fb / (us * 1e-6) / 1e9, 1),
                              "frac": round(fb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": fb}
     out["hop_config"] = {p: [lat.hop_config(p, k) for k in range(3)] for p in ("f64", "f32", "bf16")}
@@ -489,10 +495,12 @@ def solver_kernels(lat, Vh, li, torch, CG, WilsonLattice, WilsonBatch):
     for _ in range(50):
         B.dslash(bb, 0, prec="f32")
     A = lat.new_field("f64", 1, full=True)
-    A.zero_()
+    A.fill_(0.5)
+    Cf = lat.new_field("f64", 1, full=True)
+    Cf.fill_(0.25)
     F = lat.new_su3()
     for _ in range(50):
-        lat.force_bilinear(A, A, F)
+        lat.force_bilinear(A, Cf, F)
     torch.cuda.synchronize()
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
     dst = torch.empty_like(src)
@@ -701,7 +709,7 @@ def main():
     trajectory_hop = {
         "bound": "llc", "achieved": round(bytes_per_hop[dom] / (avg_us * 1e-6) / 1e9, 1), "unit": "GB/s",
         "frac_of_hbm_peak": round(bytes_per_hop[dom] / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernel": f"hop {dom} on 16x16x16x32 ({['thread-per-site', 'direction-parallel'][variant]}, "
+        "kernel": f"hop {dom} on 16x16x16x32 ({VARIANT_NAMES[variant]}, "
                   f"{'XCD-contiguous' if use_xcd else 'round-robin'} workgroup order, "
                   f"{'streaming' if stream else 'cached'} access)",
         "avg_launch_us": round(avg_us, 2), "in_situ_avg_us": round(prof[dom][0], 2),

@@ -384,11 +384,12 @@ int wl_solve_log_read(const wl_lattice* lat, int max, int* n, long long* iters, 
  *            counts), else one;
  *   use_xcd  the workgroup order: 1 = renumbered so that each of the 8 XCDs
  *            walks a contiguous range of sites; 0 = the hardware's round-robin
- *            order; 2 = z-blocked round-robin: 8 z planes at a time through
- *            every t, so that a site's t neighbours are read within a few
- *            hundred workgroups of each other (valid where a z plane holds a
- *            multiple of 8 workgroup tiles, 64 sites for direction-parallel,
- *            256 for thread-per-site, and Lz is a multiple of 8 above 8);
+ *            order (several rhs groups of one tile on one XCD); 2 = z-blocked
+ *            round-robin: 8 z planes at a time through every t, so that a
+ *            site's t neighbours are read within a few hundred workgroups of
+ *            each other, each XCD keeping its own 64-site columns of the z
+ *            planes (valid where a z plane holds a multiple of 8 tiles of 64
+ *            sites and Lz is a multiple of 8 above 8);
  *   stream   1 = non-temporal loads of links and epilogue operands and
  *            non-temporal output stores (pays on volumes beyond the caches),
  *            0 = ordinary cached access.

@@ -513,7 +513,7 @@ int wl_set_hop_config(wl_lattice* L, wl_prec prec, int kind, int variant, int np
     WL_REQUIRE(variant == kHopSite || variant == kHopDirParallel, WL_EINVAL, "unknown hop variant");
     WL_REQUIRE(npass == 1 || npass == 2 || npass == 4, WL_EINVAL, "npass must be 1, 2 or 4");
     WL_REQUIRE(use_xcd == 0 || use_xcd == 1 ||
-                   (use_xcd == 2 && zblock_ok(L->geo, variant == kHopDirParallel ? 64 : kBlock)),
+                   (use_xcd == 2 && zblock_ok(L->geo)),
                WL_EINVAL, "use_xcd must be 0, 1, or 2 where the lattice allows the z-blocked order");
     WL_REQUIRE(stream == 0 || stream == 1, WL_EINVAL, "stream must be 0 or 1");
     WL_HIP(hipStreamSynchronize(L->stream));
@@ -673,7 +673,7 @@ int wl_autotune(wl_lattice* L, double* us_out) {
         HopConfig keep = L->hop_cfg[p][k];
         for (const HopConfig& c : cand) {
           if (c.stream > max_stream ||
-              (c.use_xcd == 2 && !zblock_ok(L->geo, c.variant == kHopDirParallel ? 64 : kBlock))) {  // not here
+              (c.use_xcd == 2 && !zblock_ok(L->geo))) {  // not here
             if (us_out) us_out[slot] = 0.0;
             ++slot;
             continue;

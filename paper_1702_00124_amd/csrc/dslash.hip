@@ -51,19 +51,39 @@ struct HopArgs {
 // Flattened grid: block b -> (tile, rhs group).  The XCD-aware renumbering
 // gives each XCD a contiguous block range, and the rhs groups of one tile are
 // adjacent inside it, so a tile's links are fetched once into that XCD's L2
-// and reused by every group.  The z-blocked order walks kZBlock z planes
-// through every t before the next planes: a tile's t neighbours are then
-// kZBlock planes of tiles away instead of a whole time slice (what the L2 has
-// to hold between the two reads), and with a multiple of 8 tiles per plane
-// its z and t neighbours are dealt to its own XCD.
+// and reused by every group.  In the hardware's round-robin deal (orders 0
+// and 2) the groups of a tile are kept on one XCD instead: blocks b, b + 8,
+// b + 16, ... take the groups of the tile that b alone would take with one
+// group (the grid is padded to whole groups of 8 tiles, hop_grid).  The
+// z-blocked order walks kZBlock z planes through every t before the next
+// planes: a tile's t neighbours are then kZBlock planes of tiles away instead
+// of a whole time slice (what the L2 has to hold between the two reads), and
+// with a multiple of 8 tiles per plane its z and t neighbours are dealt to its
+// own XCD.  False for the padding blocks.
 template <int SITES>  // sites per workgroup
-__device__ __forceinline__ void hop_block_coords(const HopArgs& a, int* tile, int* row) {
-  const int b = a.use_xcd == 1 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-  const int seq = b / a.rows;
-  *row = b - seq * a.rows;
+__device__ __forceinline__ bool hop_block_seq(const HopArgs& a, int* seq, int* row) {
+  if (a.use_xcd == 1) {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    *seq = b / a.rows;
+    *row = b - *seq * a.rows;
+    return true;
+  }
+  const int b = blockIdx.x;
+  const int g8 = b / (8 * a.rows);
+  const int rem = b - g8 * 8 * a.rows;
+  *row = rem >> 3;
+  *seq = g8 * 8 + (rem & 7);
+  return *seq < (a.g.Vh + SITES - 1) / SITES;
+}
+
+// direction-parallel kernel: the workgroup's 64-site tile
+template <int SITES>
+__device__ __forceinline__ bool hop_block_coords(const HopArgs& a, int* tile, int* row) {
+  int seq;
+  if (!hop_block_seq<SITES>(a, &seq, row)) return false;
   if (a.use_xcd != 2) {
     *tile = seq;
-    return;
+    return true;
   }
   const int tz = a.g.Lxh * a.g.L[1] / SITES;  // workgroup tiles per z plane
   const int j = seq % tz;
@@ -73,6 +93,161 @@ __device__ __forceinline__ void hop_block_coords(const HopArgs& a, int* tile, in
   const int t = r % a.g.L[3];
   const int zb = r / a.g.L[3];
   *tile = (t * a.g.L[2] + zb * kZBlock + zi) * tz + j;
+  return true;
+}
+
+// thread-per-site kernel: the 64-site tile of the calling wavefront.  Its
+// workgroup's 4 wavefronts take 4 consecutive tiles, or in the z-blocked order
+// one 64-site column of 4 consecutive z planes, workgroups walking the columns
+// of a plane fastest: with a multiple of 8 columns per plane every XCD keeps
+// its own columns through all z and t, so a site's z and t neighbours come from
+// its own L2 as the direction-parallel kernel's do.
+__device__ __forceinline__ bool site_tile(const HopArgs& a, int* tile64, int* row) {
+  constexpr int W = kBlock / 64;  // wavefronts per workgroup
+  int seq;
+  if (!hop_block_seq<kBlock>(a, &seq, row)) return false;
+  const int w = threadIdx.x >> 6;
+  if (a.use_xcd != 2) {
+    *tile64 = seq * W + w;
+    return true;
+  }
+  const int tz = a.g.Lxh * a.g.L[1] / 64;  // columns per z plane
+  const int j = seq % tz;
+  int r = seq / tz;
+  const int zq = r % (kZBlock / W);
+  r /= kZBlock / W;
+  const int t = r % a.g.L[3];
+  const int zb = r / a.g.L[3];
+  *tile64 = (t * a.g.L[2] + zb * kZBlock + zq * W + w) * tz + j;
+  return true;
+}
+
+// blocks of a hop launch over tiles of SITES sites and a.rows rhs groups
+template <int SITES>
+static int hop_grid(const HopArgs& a) {
+  const int nt = (a.g.Vh + SITES - 1) / SITES;
+  return a.use_xcd == 1 ? nt * a.rows : (nt + 7) / 8 * 8 * a.rows;
+}
+
+// ------------------------------------------------------------------ BF16 products from packed storage
+// A stored BF16 complex number is a pair (re in the low half, im in the high
+// half): the operand format of the bf16 dot product with FP32 accumulation,
+// d = a.lo b.lo + a.hi b.hi + c, whose products are exact in FP32.  With a
+// spinor component p = (pr, pi) as stored, Re(u p) = (ur, -ui).p and
+// Im(u p) = (ui, ur).p; for the adjoint product conj(u) p the pairs are
+// (ur, ui) and (-ui, ur).  The spin projection (1 + S g_mu) p = p_top + c p_bot,
+// c one of +1, -1, +i, -i, is folded into the products: u (-p) is (A, B) on
+// -p, u (i p) is (B, A) on (-p, p) and u (-i p) (B, A) on (p, -p), with -p the
+// stored pairs with both sign bits flipped, so the projected half spinor is
+// never formed: no unpacking of the input and no rounding of the projection.
+// The link's third row is rebuilt from the two stored rows by the same dot
+// products (FP32 sums of exact products) and rounded to BF16 like them.
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c,
+                                         false);
+}
+// a.b with a zero accumulator (the compiler's own choice of encoding: a
+// dot product written as inline assembly is invisible to its hazard checks)
+__device__ __forceinline__ float dot2_first(uint32_t a, uint32_t b) { return dot2(a, b, 0.0f); }
+__device__ __forceinline__ uint32_t swap16(uint32_t u) { return __builtin_amdgcn_alignbit(u, u, 16); }
+
+// the product matrix's entries (a, b) as the pairs A (real part) and B
+// (imaginary part of the product)
+struct Bf16Link {
+  uint32_t A[9], B[9];
+};
+
+// links of one direction; the forward product takes U, the backward one U^dag
+template <int FWD>
+__device__ __forceinline__ void bf16_link(const char* base, int h, Bf16Link* L, bool stream) {
+  const uint2* b = reinterpret_cast<const uint2*>(base);
+  uint32_t m[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const uint2 v = stream ? ld_stream(b + fidx(j, h, 3)) : b[fidx(j, h, 3)];
+    m[2 * j] = v.x;
+    m[2 * j + 1] = v.y;
+  }
+  // third row m[6 + j] = conj(m[k] m[3 + l] - m[l] m[3 + k]), (j, k, l) cyclic,
+  // from the pairs: Re(a b) = a.conj(b), Im(a b) = a.swap(b)
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int k = (j + 1) % 3, l = (j + 2) % 3;
+    const uint32_t a = m[k], b = m[3 + l], c = m[l], d = m[3 + k];
+    const float re = dot2(c, d ^ 0x00008000u, dot2_first(a, b ^ 0x80000000u));  // Re(a b) - Re(c d)
+    const float im = dot2(c, swap16(d), dot2_first(a, swap16(b) ^ 0x80008000u));  // -(Im(a b) - Im(c d))
+    m[6 + j] = pack_bf16x2(re, im);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      const int e = 3 * a + bb;
+      const uint32_t w = FWD ? m[3 * a + bb] : m[3 * bb + a];  // U_ab, or conj(U_ba) for U^dag
+      const uint32_t sw = swap16(w);
+      if (FWD) {
+        L->A[e] = w ^ 0x80000000u;   // (ur, -ui)
+        L->B[e] = sw;                // (ui, ur)
+      } else {
+        L->A[e] = w;                 // (ur, ui)
+        L->B[e] = sw ^ 0x00008000u;  // (-ui, ur)
+      }
+    }
+}
+
+// (product matrix) (p_top + c p_bot) for one half spinor: 3 complex results,
+// 36 dot products; CC: 0 -> c = +1, 1 -> -1, 2 -> +i, 3 -> -i
+template <int CC>
+__device__ __forceinline__ void bf16_half(const Bf16Link& L, const uint32_t* pt, const uint32_t* pb, cplx<float>* w) {
+  uint32_t nb[3];  // -p_bot
+#pragma unroll
+  for (int bb = 0; bb < 3; ++bb) nb[bb] = pb[bb] ^ 0x80008000u;
+  // the operands of p_bot's products for the real and the imaginary part
+  const uint32_t* pr = (CC == 0 || CC == 3) ? pb : nb;
+  const uint32_t* pi = (CC == 0 || CC == 2) ? pb : nb;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float re = dot2_first(L.A[3 * a], pt[0]), im = dot2_first(L.B[3 * a], pt[0]);
+#pragma unroll
+    for (int bb = 1; bb < 3; ++bb) {
+      const int e = 3 * a + bb;
+      re = dot2(L.A[e], pt[bb], re);
+      im = dot2(L.B[e], pt[bb], im);
+    }
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      const int e = 3 * a + bb;
+      if (CC <= 1) {  // c = +-1: Re = A.(c p), Im = B.(c p)
+        re = dot2(L.A[e], pr[bb], re);
+        im = dot2(L.B[e], pi[bb], im);
+      } else {        // c = +-i: Re = B.(-+p), Im = A.(+-p)
+        re = dot2(L.B[e], pr[bb], re);
+        im = dot2(L.A[e], pi[bb], im);
+      }
+    }
+    w[a] = {re, im};
+  }
+}
+
+// the two projected halves of (1 + S g_MU) p, multiplied: p as 12 stored pairs
+// (component 3 spin + colour); h0 = p0 + c0 p_b0, h1 = p1 + c1 p_b1 as in project()
+template <int MU, int S>
+__device__ __forceinline__ void bf16_project_mul(const Bf16Link& L, const uint32_t* p, cplx<float>* w) {
+  constexpr int mi = S > 0 ? 3 : 2, pi = S > 0 ? 2 : 3;  // c = -S i, c = +S i
+  constexpr int m1 = S > 0 ? 1 : 0, p1 = S > 0 ? 0 : 1;  // c = -S,   c = +S
+  if (MU == 0) {         // h0 = p0 - S i p3, h1 = p1 - S i p2
+    bf16_half<mi>(L, p + 0, p + 9, w);
+    bf16_half<mi>(L, p + 3, p + 6, w + 3);
+  } else if (MU == 1) {  // h0 = p0 - S p3, h1 = p1 + S p2
+    bf16_half<m1>(L, p + 0, p + 9, w);
+    bf16_half<p1>(L, p + 3, p + 6, w + 3);
+  } else if (MU == 2) {  // h0 = p0 - S i p2, h1 = p1 + S i p3
+    bf16_half<mi>(L, p + 0, p + 6, w);
+    bf16_half<pi>(L, p + 3, p + 9, w + 3);
+  } else {               // h0 = p0 + S p2, h1 = p1 + S p3
+    bf16_half<p1>(L, p + 0, p + 6, w);
+    bf16_half<p1>(L, p + 3, p + 9, w + 3);
+  }
 }
 
 template <typename P, int MU, int DAG, int NR, bool ST>
@@ -84,6 +259,39 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h,
   const int Vh = a.g.Vh;
   const size_t lb = LinkIO<P>::bytes * size_t(a.g.Vhp);
   bool wrap;
+  if constexpr (std::is_same<P, PrecBF16>::value) {  // products from the stored pairs
+#pragma unroll
+    for (int fwd = 1; fwd >= 0; --fwd) {
+      const int hn = neighbour<MU>(a.g, c, fwd ? +1 : -1, &wrap);
+      Bf16Link U;
+      if (fwd) bf16_link<1>(a.links + (a.parity * 4 + MU) * lb, h, &U, ST);
+      else bf16_link<0>(a.links + ((1 - a.parity) * 4 + MU) * lb, hn, &U, ST);
+      const R ph = wrap ? R(a.g.tbc) : R(1);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint4* b = reinterpret_cast<const uint4*>(a.in + (r0 + r) * a.rhs_stride);
+        uint32_t p[12];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const uint4 v = b[fidx(j, hn, 3)];
+          p[4 * j] = v.x;
+          p[4 * j + 1] = v.y;
+          p[4 * j + 2] = v.z;
+          p[4 * j + 3] = v.w;
+        }
+        Half<R> w;
+        if (fwd) bf16_project_mul<MU, SF>(U, p, w.c);
+        else bf16_project_mul<MU, SB>(U, p, w.c);
+        if (MU == 3) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) w.c[k] = ph * w.c[k];
+        }
+        if (fwd) reconstruct_add<MU, SF>(acc[r], w);
+        else reconstruct_add<MU, SB>(acc[r], w);
+      }
+    }
+    return;
+  }
   // forward: U_mu(x) in(x + mu)
   {
     const int hf = neighbour<MU>(a.g, c, +1, &wrap);
@@ -167,9 +375,9 @@ __device__ __forceinline__ void cheb_unit(const HopArgs& a, size_t off, int u, i
 template <typename P, int DAG, int NR, bool ST, bool CHEB = false>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
   using R = typename P::real;
-  int b, row;
-  hop_block_coords<kBlock>(a, &b, &row);
-  const int h = b * kBlock + threadIdx.x;
+  int tile, row;
+  if (!site_tile(a, &tile, &row)) return;
+  const int h = tile * 64 + (threadIdx.x & 63);
   const int Vh = a.g.Vh;
   const int r0 = row * NR;
   double part[NR];
@@ -233,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
     }
   }
   // one partial per wavefront of 64 sites, as in the direction-parallel variant
-  const int slot = b * (kBlock / 64) + (threadIdx.x >> 6);
+  const int slot = tile;
   if (a.dot && slot * 64 < Vh) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -253,131 +461,6 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
 // sites), which hides memory latency on small lattices.
 constexpr int kDpSites = 64;
 constexpr int kDpThreads = 8 * kDpSites;
-
-// ------------------------------------------------------------------ BF16 products from packed storage
-// A stored BF16 complex number is a pair (re in the low half, im in the high
-// half): the operand format of the bf16 dot product with FP32 accumulation,
-// d = a.lo b.lo + a.hi b.hi + c, whose products are exact in FP32.  With a
-// spinor component p = (pr, pi) as stored, Re(u p) = (ur, -ui).p and
-// Im(u p) = (ui, ur).p; for the adjoint product conj(u) p the pairs are
-// (ur, ui) and (-ui, ur).  The spin projection (1 + S g_mu) p = p_top + c p_bot,
-// c one of +1, -1, +i, -i, is folded into the choice of pairs for p_bot
-// (u (-p) takes (-A, -B), u (i p) takes (-B, A), u (-i p) takes (B, -A)), so
-// the projected half spinor is never formed: no unpacking of the input and no
-// rounding of the projection.  The link's third row, rebuilt in FP32 from the
-// two stored rows, is rounded to BF16 like the stored ones.
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
-  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c,
-                                         false);
-}
-// a.b with a zero accumulator: the three-operand form takes the constant 0
-// directly (the two-operand form the compiler picks would first clear a register)
-__device__ __forceinline__ float dot2_first(uint32_t a, uint32_t b) {
-  float d;
-  asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
-  return d;
-}
-__device__ __forceinline__ uint32_t swap16(uint32_t u) { return __builtin_amdgcn_alignbit(u, u, 16); }
-
-// the product matrix's entries (a, b) as the four pairs A (real part), B
-// (imaginary part) and their negatives
-struct Bf16Link {
-  uint32_t A[9], B[9], nA[9], nB[9];
-};
-
-// links of one direction; the forward product takes U, the backward one U^dag
-template <int FWD>
-__device__ __forceinline__ void bf16_link(const char* base, int h, Bf16Link* L, bool stream) {
-  const uint2* b = reinterpret_cast<const uint2*>(base);
-  uint32_t m[9];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const uint2 v = stream ? ld_stream(b + fidx(j, h, 3)) : b[fidx(j, h, 3)];
-    m[2 * j] = v.x;
-    m[2 * j + 1] = v.y;
-  }
-  SU3<float> u;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) u.m[k] = {bf16_to_f32(m[k] & 0xFFFFu), bf16_to_f32(m[k] >> 16)};
-  third_row(u);
-#pragma unroll
-  for (int k = 6; k < 9; ++k) m[k] = pack_bf16x2(u.m[k].r, u.m[k].i);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb) {
-      const int e = 3 * a + bb;
-      const uint32_t w = FWD ? m[3 * a + bb] : m[3 * bb + a];  // U_ab, or conj(U_ba) for U^dag
-      const uint32_t sw = swap16(w);
-      if (FWD) {
-        L->A[e] = w ^ 0x80000000u;   // (ur, -ui)
-        L->B[e] = sw;                // (ui, ur)
-        L->nA[e] = w ^ 0x00008000u;  // (-ur, ui)
-        L->nB[e] = sw ^ 0x80008000u; // (-ui, -ur)
-      } else {
-        L->A[e] = w;                 // (ur, ui)
-        L->B[e] = sw ^ 0x00008000u;  // (-ui, ur)
-        L->nA[e] = w ^ 0x80008000u;  // (-ur, -ui)
-        L->nB[e] = sw ^ 0x80000000u; // (ui, -ur)
-      }
-    }
-}
-
-// (product matrix) (p_top + c p_bot) for one half spinor: 3 complex results,
-// 36 dot products; CC: 0 -> c = +1, 1 -> -1, 2 -> +i, 3 -> -i
-template <int CC>
-__device__ __forceinline__ void bf16_half(const Bf16Link& L, const uint32_t* pt, const uint32_t* pb, cplx<float>* w) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float re = dot2_first(L.A[3 * a], pt[0]), im = dot2_first(L.B[3 * a], pt[0]);
-#pragma unroll
-    for (int bb = 1; bb < 3; ++bb) {
-      const int e = 3 * a + bb;
-      re = dot2(L.A[e], pt[bb], re);
-      im = dot2(L.B[e], pt[bb], im);
-    }
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb) {
-      const int e = 3 * a + bb;
-      if (CC == 0) {
-        re = dot2(L.A[e], pb[bb], re);
-        im = dot2(L.B[e], pb[bb], im);
-      } else if (CC == 1) {
-        re = dot2(L.nA[e], pb[bb], re);
-        im = dot2(L.nB[e], pb[bb], im);
-      } else if (CC == 2) {
-        re = dot2(L.nB[e], pb[bb], re);
-        im = dot2(L.A[e], pb[bb], im);
-      } else {
-        re = dot2(L.B[e], pb[bb], re);
-        im = dot2(L.nA[e], pb[bb], im);
-      }
-    }
-    w[a] = {re, im};
-  }
-}
-
-// the two projected halves of (1 + S g_MU) p, multiplied: p as 12 stored pairs
-// (component 3 spin + colour); h0 = p0 + c0 p_b0, h1 = p1 + c1 p_b1 as in project()
-template <int MU, int S>
-__device__ __forceinline__ void bf16_project_mul(const Bf16Link& L, const uint32_t* p, cplx<float>* w) {
-  constexpr int mi = S > 0 ? 3 : 2, pi = S > 0 ? 2 : 3;  // c = -S i, c = +S i
-  constexpr int m1 = S > 0 ? 1 : 0, p1 = S > 0 ? 0 : 1;  // c = -S,   c = +S
-  if (MU == 0) {         // h0 = p0 - S i p3, h1 = p1 - S i p2
-    bf16_half<mi>(L, p + 0, p + 9, w);
-    bf16_half<mi>(L, p + 3, p + 6, w + 3);
-  } else if (MU == 1) {  // h0 = p0 - S p3, h1 = p1 + S p2
-    bf16_half<m1>(L, p + 0, p + 9, w);
-    bf16_half<p1>(L, p + 3, p + 6, w + 3);
-  } else if (MU == 2) {  // h0 = p0 - S i p2, h1 = p1 + S i p3
-    bf16_half<mi>(L, p + 0, p + 6, w);
-    bf16_half<pi>(L, p + 3, p + 9, w + 3);
-  } else {               // h0 = p0 + S p2, h1 = p1 + S p3
-    bf16_half<p1>(L, p + 0, p + 6, w);
-    bf16_half<p1>(L, p + 3, p + 9, w + 3);
-  }
-}
 
 // the link a direction-parallel wavefront holds: unpacked SU(3) in FP32 / FP64,
 // the dot-product pairs for BF16
@@ -484,7 +567,7 @@ __global__ __launch_bounds__(kDpThreads) void hop_dp_kernel(HopArgs a) {
   __shared__ cplx<R> W[NRP * 8 * 6 * kDpSites];
   __shared__ double red[kDpThreads / 64];
   int tile, row;
-  hop_block_coords<kDpSites>(a, &tile, &row);
+  if (!hop_block_coords<kDpSites>(a, &tile, &row)) return;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int Vh = a.g.Vh;
@@ -583,7 +666,7 @@ static void dispatch_dp(HopArgs a, int nrhs, hipStream_t st, int max_pass) {
   const int groups = nrhs / NRP;
   const int npass = (max_pass >= 4 && groups % 4 == 0) ? 4 : ((max_pass >= 2 && groups % 2 == 0) ? 2 : 1);
   a.rows = groups / npass;
-  dim3 grid(((a.g.Vh + kDpSites - 1) / kDpSites) * a.rows);
+  const dim3 grid(hop_grid<kDpSites>(a));
   switch (npass) {
     case 4: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 4, ST>), grid, dim3(kDpThreads), 0, st, a); break;
     case 2: hipLaunchKernelGGL((hop_dp_kernel<P, DAG, NRP, 2, ST>), grid, dim3(kDpThreads), 0, st, a); break;
@@ -597,11 +680,10 @@ static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, const HopConfig& c)
     if (a.ch_t) {  // fused Chebyshev step: forward hop, one rhs per pass / thread
       a.rows = nrhs;
       if (c.variant == kHopDirParallel)
-        hipLaunchKernelGGL((hop_dp_kernel<P, 0, 1, 1, ST, true>), dim3((a.g.Vh + kDpSites - 1) / kDpSites * nrhs),
-                           dim3(kDpThreads), 0, st, a);
+        hipLaunchKernelGGL((hop_dp_kernel<P, 0, 1, 1, ST, true>), dim3(hop_grid<kDpSites>(a)), dim3(kDpThreads), 0,
+                           st, a);
       else
-        hipLaunchKernelGGL((hop_kernel<P, 0, 1, ST, true>), dim3(site_blocks(a.g.Vh) * nrhs), dim3(kBlock), 0, st,
-                           a);
+        hipLaunchKernelGGL((hop_kernel<P, 0, 1, ST, true>), dim3(hop_grid<kBlock>(a)), dim3(kBlock), 0, st, a);
       return;
     }
   }
@@ -622,12 +704,12 @@ static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, const HopConfig& c)
   if constexpr (narrow) {
     if (two) {
       a.rows = nrhs / 2;
-      hipLaunchKernelGGL((hop_kernel<P, DAG, 2, ST>), dim3(site_blocks(a.g.Vh) * a.rows), dim3(kBlock), 0, st, a);
+      hipLaunchKernelGGL((hop_kernel<P, DAG, 2, ST>), dim3(hop_grid<kBlock>(a)), dim3(kBlock), 0, st, a);
       return;
     }
   }
   a.rows = nrhs;
-  hipLaunchKernelGGL((hop_kernel<P, DAG, 1, ST>), dim3(site_blocks(a.g.Vh) * a.rows), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((hop_kernel<P, DAG, 1, ST>), dim3(hop_grid<kBlock>(a)), dim3(kBlock), 0, st, a);
 }
 
 template <typename P>

@@ -91,87 +91,132 @@ __device__ __forceinline__ void load_link_at(const void* U, const Geo& g, Coord 
 //   Xi    = sum_k hC_k (x) hA_k^dag,  h = upper rows of (1 - g_mu) C(y), (1 - g_mu) A(x)
 //   Theta = sum_k gC_k (x) gA_k^dag,  g = upper rows of (1 + g_mu) C(x), (1 + g_mu) A(y)
 // (the lower spin rows of a projected spinor are unit phases times the upper
-// rows, so the four-spin sums reduce to the two upper rows).  Xi and Theta
-// have rank two, so W is formed without them and without any 3x3 product:
-//   W_ij = sum_k (U hC_k)_i conj(hA_k)_j - gC_k,i conj(U gA_k)_j,
-// four SU(3) x vector products and, of W, only the entries the su(3)
-// coefficients read (imaginary diagonal, the six off-diagonal entries).  The
-// link comes from the two-row FP64 copy, its third row rebuilt.
+// rows, so the four-spin sums reduce to the two upper rows).  Both halves have
+// one form, X_s = sum_k (U v_k) (x) w_k^dag with v from site y, w from site x:
+//   s = 0:  v = (1 - g_mu) C(y), w = (1 - g_mu) A(x),   W = X_0 - X_1^dag,
+//   s = 1:  v = (1 + g_mu) A(y), w = (1 + g_mu) C(x),
+// and since Re(i tr(T^a M^dag)) = -Re(i tr(T^a M)) for Hermitian T^a, the link's
+// eight su(3) coefficients are g(X_0) + g(X_1).  A lane computes one X_s (of X
+// only the entries the coefficients read), the two lanes of a link swap halves
+// of their eight coefficients, and each updates four of the link's F entries.
+constexpr int kBilSites = 32;
+
 template <int MU>
-__device__ __forceinline__ void bilinear_dir(const Geo& g, const Coord& c, int p, int h, const char* Ah[2],
-                                             const char* Ch[2], const char* U2, double* F, double coeff) {
-  bool wrap;
-  const int hy = neighbour<MU>(g, c, +1, &wrap);
-  const char* Ub = U2 + size_t(p * 4 + MU) * LinkIO<PrecF64>::bytes * g.Vhp;
-  const double ph = wrap ? double(g.tbc) : 1.0;
-  // W accumulated in two stages (U hC (x) hA^dag, then - gC (x) (U gA)^dag), the
-  // scheduler kept from hoisting the second stage's loads into the first: four
-  // spinors in flight at once held every wavefront to two per SIMD
-  cd w01, w10, w02, w20, w12, w21;
-  double d0, d1, d2;
-  {
-    const Half<double> hC = project<MU, -1>(SpinorIO<PrecF64>::load(Ch[1 - p], hy, g.Vh));
-    const Half<double> hA = project<MU, -1>(SpinorIO<PrecF64>::load(Ah[p], h, g.Vh));
-    const SU3<double> U = LinkIO<PrecF64>::load(Ub, h, g.Vh);
-    cd u[6];  // ph U hC_k
-    su3_mul(U, hC.c, u);
-    su3_mul(U, hC.c + 3, u + 3);
+__device__ __forceinline__ void bilinear_finish(int s, const Spinor<double>& vs, const double2* own,
+                                                const double2* lrow, double* f, const double* fo, double cf,
+                                                int vh) {
+  const double sg = s ? 1.0 : -1.0;
+  const Half<double> v = project_s<MU>(vs, sg);
+  Spinor<double> ws;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) u[k] = ph * u[k];
-    auto P = [&](int i, int j) { return u[i] * conj(hA.c[j]) + u[3 + i] * conj(hA.c[3 + j]); };
-    w01 = P(0, 1), w10 = P(1, 0), w02 = P(0, 2), w20 = P(2, 0), w12 = P(1, 2), w21 = P(2, 1);
-    d0 = P(0, 0).i, d1 = P(1, 1).i, d2 = P(2, 2).i;
+  for (int k = 0; k < 12; ++k) {
+    const double2 e = own[k * kBilSites];
+    ws.c[k] = {e.x, e.y};
   }
-  __builtin_amdgcn_sched_barrier(0);
-  {
-    const Half<double> gA = project<MU, +1>(SpinorIO<PrecF64>::load(Ah[1 - p], hy, g.Vh));
-    const Half<double> gC = project<MU, +1>(SpinorIO<PrecF64>::load(Ch[p], h, g.Vh));
-    const SU3<double> U = LinkIO<PrecF64>::load(Ub, h, g.Vh);  // again, from the cache
-    cd v[6];  // ph U gA_k
-    su3_mul(U, gA.c, v);
-    su3_mul(U, gA.c + 3, v + 3);
+  const Half<double> w = project_s<MU>(ws, sg);
+  SU3<double> U;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = ph * v[k];
-    auto Q = [&](int i, int j) { return gC.c[i] * conj(v[j]) + gC.c[3 + i] * conj(v[3 + j]); };
-    w01 = w01 - Q(0, 1), w10 = w10 - Q(1, 0), w02 = w02 - Q(0, 2), w20 = w20 - Q(2, 0);
-    w12 = w12 - Q(1, 2), w21 = w21 - Q(2, 1);
-    d0 -= Q(0, 0).i, d1 -= Q(1, 1).i, d2 -= Q(2, 2).i;
+  for (int k = 0; k < 6; ++k) {
+    const double2 e = lrow[k * kBilSites];
+    U.m[k] = {e.x, e.y};
   }
-  // g^a = Re(i tr(T^a W)) = -Im tr(T^a W), T^a = lambda^a / 2
+  third_row(U);
+  cd u[6];  // U v_k
+  su3_mul(U, v.c, u);
+  su3_mul(U, v.c + 3, u + 3);
+  auto X = [&](int i, int j) { return u[i] * conj(w.c[j]) + u[3 + i] * conj(w.c[3 + j]); };
+  const cd x01 = X(0, 1), x10 = X(1, 0), x02 = X(0, 2), x20 = X(2, 0), x12 = X(1, 2), x21 = X(2, 1);
+  const double d0 = X(0, 0).i, d1 = X(1, 1).i, d2 = X(2, 2).i;
+  // g^a = Re(i tr(T^a X)) = -Im tr(T^a X), T^a = lambda^a / 2
   double gr[8];
-  gr[0] = -0.5 * (w01.i + w10.i);
-  gr[1] = -0.5 * (w01.r - w10.r);
+  gr[0] = -0.5 * (x01.i + x10.i);
+  gr[1] = -0.5 * (x01.r - x10.r);
   gr[2] = -0.5 * (d0 - d1);
-  gr[3] = -0.5 * (w02.i + w20.i);
-  gr[4] = -0.5 * (w02.r - w20.r);
-  gr[5] = -0.5 * (w12.i + w21.i);
-  gr[6] = -0.5 * (w12.r - w21.r);
+  gr[3] = -0.5 * (x02.i + x20.i);
+  gr[4] = -0.5 * (x02.r - x20.r);
+  gr[5] = -0.5 * (x12.i + x21.i);
+  gr[6] = -0.5 * (x12.r - x21.r);
   gr[7] = -(d0 + d1 - 2.0 * d2) * 0.28867513459481288225;  // 1 / (2 sqrt 3)
-  double* f = F + size_t(p * 4 + MU) * 8 * g.Vh;
+  // lane s keeps coefficients 4s .. 4s+3 and sends the other four to its partner
+  // (lane ^ 32, the same link)
 #pragma unroll
-  for (int a = 0; a < 8; ++a) f[a * g.Vh + h] += coeff * gr[a];
+  for (int a = 0; a < 4; ++a) {
+    const double mine = s ? gr[4 + a] : gr[a];
+    const double other = __shfl_xor(s ? gr[a] : gr[4 + a], 32, 64);
+    f[size_t(a) * vh] = fo[a] + cf * (mine + other);
+  }
 }
 
-// one thread per link (x, mu): four times the threads of a thread per site,
-// which the latency of the neighbour gathers needs.  A workgroup holds 64
-// sites, one wavefront per direction, so the site's own spinors, read by all
-// four wavefronts, come from the CU's cache after the first.
-constexpr int kBilSites = 64;
-__global__ __launch_bounds__(4 * kBilSites) void bilinear_kernel(Geo g, double* F, const char* Ae, const char* Ao,
-                                                                const char* Ce, const char* Co, const char* U2,
-                                                                double coeff) {
-  const int h = blockIdx.x * kBilSites + (threadIdx.x & (kBilSites - 1));
-  const int p = blockIdx.y;
-  const int mu = threadIdx.x / kBilSites;  // uniform in the wavefront
-  if (h >= g.Vh) return;
-  const char* Ah[2] = {Ae, Ao};
-  const char* Ch[2] = {Ce, Co};
-  const Coord c = site_coords(g, h, p);
-  switch (mu) {
-    case 0: bilinear_dir<0>(g, c, p, h, Ah, Ch, U2, F, coeff); break;
-    case 1: bilinear_dir<1>(g, c, p, h, Ah, Ch, U2, F, coeff); break;
-    case 2: bilinear_dir<2>(g, c, p, h, Ah, Ch, U2, F, coeff); break;
-    default: bilinear_dir<3>(g, c, p, h, Ah, Ch, U2, F, coeff); break;
+// A workgroup holds 32 sites of one parity, one wavefront per direction, the
+// two halves of a wavefront the two terms of the same 32 links.  The sites' own
+// spinors (A and C, used by all four directions) and the links' two stored rows
+// (one loaded by each half) pass through LDS, so each is read from memory once
+// per workgroup; the neighbour spinors are read by the lanes that use them.
+// Work items alternate parity (32 sites of parity 0, the same 32 of parity 1,
+// ...), so the neighbour spinors one parity gathers are the other parity's
+// own.  On large lattices the hardware's round-robin deal of workgroups over
+// the 8 XCDs is regrouped into runs of kBilChunk consecutive work items per
+// XCD: the x, y, z neighbours of a run are mostly in it and come from that
+// XCD's L2, while the chip as a whole still sweeps the lattice in order, so the
+// t neighbours, read again one t slice later, come from the Infinity Cache
+// (at 32^3 x 64: 572 us per bilinear, against 592 us in round-robin order and
+// 707 us with each XCD sweeping its own contiguous eighth of the lattice).
+constexpr int kBilChunk = 64;
+__global__ __launch_bounds__(256) void bilinear_kernel(Geo g, int nwork, int chunked, double* F, const char* Ae,
+                                                       const char* Ao, const char* Ce, const char* Co,
+                                                       const char* U2, double coeff) {
+  __shared__ double2 own[2 * 12 * kBilSites];  // [A, C][unit][site]
+  __shared__ double2 lrow[4 * 6 * kBilSites];  // [mu][unit of the two rows][site]
+  const int b = blockIdx.x;
+  const int wk = chunked ? (b & ~(8 * kBilChunk - 1)) | ((b & 7) * kBilChunk) | ((b >> 3) & (kBilChunk - 1)) : b;
+  if (wk >= nwork) return;  // whole workgroups
+  const int p = wk & 1;
+  const int h0 = (wk >> 1) * kBilSites;
+  const int t = threadIdx.x, lane = t & 63, s = lane >> 5, j = lane & 31, mu = t >> 6;
+  const int h = h0 + j;
+  const bool act = h < g.Vh;
+  const char* Ap = p ? Ao : Ae;  // own parity
+  const char* Cp = p ? Co : Ce;
+  const char* An = p ? Ae : Ao;  // the neighbours' parity
+  const char* Cn = p ? Ce : Co;
+  double fo[4] = {0.0, 0.0, 0.0, 0.0};
+  double* f = F + size_t(p * 4 + mu) * 8 * g.Vh + size_t(4 * s) * g.Vh + h;
+  Spinor<double> vs;
+  double cf = coeff;
+  if (act) {
+    const Coord c = site_coords(g, h, p);
+    bool wrap = false;
+    int hy;
+    switch (mu) {
+      case 0: hy = neighbour<0>(g, c, +1, &wrap); break;
+      case 1: hy = neighbour<1>(g, c, +1, &wrap); break;
+      case 2: hy = neighbour<2>(g, c, +1, &wrap); break;
+      default: hy = neighbour<3>(g, c, +1, &wrap); break;
+    }
+    if (wrap) cf *= double(g.tbc);  // the link's fermion phase, common to both terms
+    vs = SpinorIO<PrecF64>::load(s ? An : Cn, hy, g.Vh);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) fo[a] = f[size_t(a) * g.Vh];
+    const double2* ub = reinterpret_cast<const double2*>(U2 + size_t(p * 4 + mu) * LinkIO<PrecF64>::bytes * g.Vhp);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lrow[(mu * 6 + 3 * s + k) * kBilSites + j] = ub[fidx(3 * s + k, h, 6)];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {  // 2 fields x 12 units x 32 sites, three per thread
+    const int idx = t + 256 * i, fld = idx / (12 * kBilSites), rem = idx - fld * 12 * kBilSites;
+    const int hs = h0 + (rem & (kBilSites - 1));
+    if (hs < g.Vh)
+      own[idx] = reinterpret_cast<const double2*>(fld ? Cp : Ap)[fidx(rem / kBilSites, hs, 12)];
+  }
+  __syncthreads();
+  if (!act) return;  // both lanes of a link leave together
+  const double2* ow = own + (s ? 12 * kBilSites : 0) + j;
+  const double2* lr = lrow + mu * 6 * kBilSites + j;
+  switch (mu) {  // uniform in the wavefront
+    case 0: bilinear_finish<0>(s, vs, ow, lr, f, fo, cf, g.Vh); break;
+    case 1: bilinear_finish<1>(s, vs, ow, lr, f, fo, cf, g.Vh); break;
+    case 2: bilinear_finish<2>(s, vs, ow, lr, f, fo, cf, g.Vh); break;
+    default: bilinear_finish<3>(s, vs, ow, lr, f, fo, cf, g.Vh); break;
   }
 }
 
@@ -348,8 +393,11 @@ __global__ __launch_bounds__(kBlock) void sumsq_kernel(const double* P, size_t n
 void launch_bilinear(wl_lattice* L, double* F, const void* Ae, const void* Ao, const void* Ce, const void* Co,
                      double coeff) {
   ensure_lowp_links(L);  // the two-row FP64 link copy
-  dim3 grid((L->Vh + kBilSites - 1) / kBilSites, 2);  // (64-site tile, parity)
-  hipLaunchKernelGGL(bilinear_kernel, grid, dim3(4 * kBilSites), 0, L->stream, L->geo, F, (const char*)Ae,
+  const int nwork = 2 * ((L->Vh + kBilSites - 1) / kBilSites);  // (32 sites, parity)
+  const int run = 8 * kBilChunk;                                 // one run per XCD
+  const int chunked = nwork >= 8 * run;
+  dim3 grid(chunked ? (nwork + run - 1) / run * run : nwork);
+  hipLaunchKernelGGL(bilinear_kernel, grid, dim3(256), 0, L->stream, L->geo, nwork, chunked, F, (const char*)Ae,
                      (const char*)Ao, (const char*)Ce, (const char*)Co, (const char*)L->U[F64], coeff);
   WL_HIP(hipGetLastError());
 }

@@ -58,15 +58,13 @@ template <typename T>
 __device__ __forceinline__ cplx<T> zero() { return {T(0), T(0)}; }
 
 // ------------------------------------------------------------------ bf16
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
-// round to nearest even (inputs here are finite)
-__device__ __forceinline__ uint32_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u >> 16;
-}
+// two FP32 values rounded to nearest even into one word (lo, hi): one
+// v_cvt_pk_bf16_f32 on gfx950
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
-  return f32_to_bf16(lo) | (f32_to_bf16(hi) << 16);
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
 }
 
 // ------------------------------------------------------------------ storage precisions
@@ -416,12 +414,11 @@ __device__ __forceinline__ void su3_dag_mul(const SU3<T>& u, const cplx<T>* v, c
 }
 
 // ------------------------------------------------------------------ spin projection
-// (1 + S gamma_MU) psi has two independent spin rows h0, h1 (chiral basis);
-// the lower rows are phases times h0 / h1.  MU = 0..3 is x, y, z, t.
-template <int MU, int S, typename T>
-__device__ __forceinline__ Half<T> project(const Spinor<T>& p) {
+// (1 + s gamma_MU) psi, s = +-1, has two independent spin rows h0, h1 (chiral
+// basis); the lower rows are phases times h0 / h1.  MU = 0..3 is x, y, z, t.
+template <int MU, typename T>
+__device__ __forceinline__ Half<T> project_s(const Spinor<T>& p, T s) {
   Half<T> h;
-  const T s = T(S);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     cplx<T> p0 = p.c[a], p1 = p.c[3 + a], p2 = p.c[6 + a], p3 = p.c[9 + a];
@@ -440,6 +437,10 @@ __device__ __forceinline__ Half<T> project(const Spinor<T>& p) {
     }
   }
   return h;
+}
+template <int MU, int S, typename T>
+__device__ __forceinline__ Half<T> project(const Spinor<T>& p) {
+  return project_s<MU>(p, T(S));
 }
 
 // acc += (1 + S gamma_MU)-reconstruction of the half spinor w

@@ -37,10 +37,9 @@ constexpr int kZBlock = 8;
 // the z-blocked order needs whole 64-site tiles per z plane, a multiple of 8
 // of them (so a tile's z and t neighbours share its XCD) and Lz a multiple of
 // kZBlock above it
-inline bool zblock_ok(const Geo& g, int sites_per_block) {
+inline bool zblock_ok(const Geo& g) {
   const long long plane = (long long)g.Lxh * g.L[1];
-  return plane % sites_per_block == 0 && (plane / sites_per_block) % 8 == 0 && g.L[2] % kZBlock == 0 &&
-         g.L[2] > kZBlock;
+  return plane % 64 == 0 && (plane / 64) % 8 == 0 && g.L[2] % kZBlock == 0 && g.L[2] > kZBlock;
 }
 // rhs-count classes with their own configuration: 1, 2-4, 5-16
 constexpr int kHopKinds = 3;

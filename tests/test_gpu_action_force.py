@@ -88,13 +88,20 @@ def test_links_host_and_device_arrays():
     assert rel(got, ow.hop_eo(U2, psi, L, 0)) <= 1e-12
 
 
-def test_bilinear_primitive_matches_oracle():
-    L = (6, 4, 4, 10)
+@pytest.mark.parametrize("L", [(6, 4, 4, 10), (4, 2, 6, 6)])
+def test_bilinear_primitive_matches_oracle(L):
+    """Whole 32-site work items (6x4x4x10: 480 sites per parity) and a ragged last
+    one (4x2x6x6: 144); the force accumulates into what F holds."""
     say("bilinear", L)
     lat, U = make_lattice(L)
     A, Cf = full_noise(L, 71), full_noise(L, 72)
     F = lat.force_bilinear(lat.import_full(torch.from_numpy(A)), lat.import_full(torch.from_numpy(Cf)))
-    assert rel(to_np(lat.export_su3(F)), oforce.bilinear_grad(U, A, Cf, L, -1)) <= 1e-12
+    ref = oforce.bilinear_grad(U, A, Cf, L, -1)
+    assert rel(to_np(lat.export_su3(F)), ref) <= 1e-12
+    F0 = li.gaussian_momenta(L, 73)
+    F = lat.force_bilinear(lat.import_full(torch.from_numpy(A)), lat.import_full(torch.from_numpy(Cf)),
+                           F=lat.import_su3(torch.from_numpy(F0)), coeff=-0.75)
+    assert rel(to_np(lat.export_su3(F)), F0 - 0.75 * ref) <= 1e-12
 
 
 def test_gauge_kernels_match_oracle():

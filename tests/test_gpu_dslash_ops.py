@@ -210,12 +210,42 @@ def test_dslash_link_reuse_passes_equal_single(nrhs, prec, passes):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_dslash_launch_config_invariance(variant):
+def test_dslash_zblocked_order_invariance(variant):
+    """The z-blocked workgroup order (32x32 z planes of 8 columns of 64 half
+    sites, Lz = 16: two blocks of 8 planes) changes no output bit against the
+    other two orders, with one rhs and with four (the rhs groups of a tile on
+    one XCD), in every storage precision; a CG whose J hops take it (with the
+    fused <p, Jp> partials per 64-site tile) converges to the oracle's J."""
+    L = (32, 32, 16, 4)
+    say("dslash z-blocked order", "variant", variant)
+    lat, U = make_lattice(L, variant=variant)
+    psi = half_noise(L, 38, nrhs=4)
+    for prec in ("f64", "f32", "bf16"):
+        for nrhs in (1, 4):
+            src = psi[0] if nrhs == 1 else psi
+            outs = {}
+            for xcd in (1, 0, 2):
+                lat.set_hop_config(prec, -1, use_xcd=xcd)
+                outs[xcd] = to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(src), prec), 0,
+                                                               prec=prec, nrhs=nrhs), prec, nrhs))
+            assert np.array_equal(outs[0], outs[1]), (prec, nrhs)
+            assert np.array_equal(outs[2], outs[1]), (prec, nrhs)
+            if prec == "f64" and nrhs == 4:
+                assert rel(outs[2][3], ow.hop_eo(U, psi[3], L, 0)) <= 1e-12
+    b = half_noise(L, 39)
+    x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), 0.155, "J", params=CG(tol=1e-10, inner="f32"))
+    assert rc == 0 and st[0].true_rel_res <= 1e-10
+    assert rel(ow.J(U, to_np(lat.export_spinor(x)), L, 0.155, 0.0), b) <= 1.01e-10
+
+
+@pytest.mark.parametrize("L", [(8, 8, 8, 8), (6, 4, 4, 10)])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_dslash_launch_config_invariance(variant, L):
     """Rhs per pass or thread, passes per link load and workgroup order change
     no output bit of a variant, streaming access at most one rounding; 8^4
-    spans eight 64-site tiles per parity."""
-    L = (8, 8, 8, 8)
-    say("dslash launch configurations", "variant", variant)
+    spans 32 64-site tiles per parity, 6x4x4x10 a ragged 7.5 (and 1.9 blocks of
+    the thread-per-site kernel, whose round-robin grid is padded to 8)."""
+    say("dslash launch configurations", "variant", variant, L)
     lat, U = make_lattice(L, variant=variant)
     psi = half_noise(L, 36, nrhs=4)
     outs = {}
