@@ -67,8 +67,129 @@ HOP_BYTES_PER_SITE = {"f64": 8 * 96 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8
 # sources); otherwise `traffic` is reported as null.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_COUNTERS = {
-    "source_sha256": None,
-    "per_launch_kib": {},
+    "source_sha256": "d70948aaebcf45d85eaf29f7fb0463c2cb22b1e5e263d6d8dba2b425ea484b77",
+    "per_launch_kib": {
+        "f64:1:0:1:1:0": {"fetch": 913394.2, "write": 196608.0},
+        "f64:1:0:1:1:1": {"fetch": 743429.2, "write": 196608.0},
+        "f64:1:0:1:0:0": {"fetch": 1014707.2, "write": 196608.0},
+        "f64:1:0:1:0:1": {"fetch": 884053.4, "write": 196608.0},
+        "f64:1:0:1:2:0": {"fetch": 866270.4, "write": 196608.0},
+        "f64:1:0:1:2:1": {"fetch": 671045.9, "write": 196608.1},
+        "f64:1:1:1:1:0": {"fetch": 689188.1, "write": 196608.0},
+        "f64:1:1:1:1:1": {"fetch": 689032.5, "write": 196608.0},
+        "f64:1:1:1:0:0": {"fetch": 556771.0, "write": 196608.0},
+        "f64:1:1:1:0:1": {"fetch": 543894.0, "write": 196608.0},
+        "f64:1:1:1:2:0": {"fetch": 568277.1, "write": 196608.0},
+        "f64:1:1:1:2:1": {"fetch": 568168.1, "write": 196608.0},
+        "f32:1:0:1:1:0": {"fetch": 370596.4, "write": 98304.0},
+        "f32:1:0:1:1:1": {"fetch": 302612.8, "write": 98308.8},
+        "f32:1:0:1:0:0": {"fetch": 488155.1, "write": 98304.0},
+        "f32:1:0:1:0:1": {"fetch": 420634.6, "write": 98306.2},
+        "f32:1:0:1:2:0": {"fetch": 397258.4, "write": 98304.0},
+        "f32:1:0:1:2:1": {"fetch": 308413.4, "write": 98304.5},
+        "f32:1:1:1:1:0": {"fetch": 344624.6, "write": 98304.0},
+        "f32:1:1:1:1:1": {"fetch": 343260.6, "write": 98304.0},
+        "f32:1:1:1:0:0": {"fetch": 272788.9, "write": 98304.0},
+        "f32:1:1:1:0:1": {"fetch": 271970.0, "write": 98304.0},
+        "f32:1:1:1:2:0": {"fetch": 284162.0, "write": 98304.0},
+        "f32:1:1:1:2:1": {"fetch": 283824.9, "write": 98304.0},
+        "bf16:1:0:1:1:0": {"fetch": 155539.8, "write": 49152.0},
+        "bf16:1:0:1:1:1": {"fetch": 131081.4, "write": 49152.0},
+        "bf16:1:0:1:0:0": {"fetch": 213345.2, "write": 49152.0},
+        "bf16:1:0:1:0:1": {"fetch": 185288.9, "write": 49152.0},
+        "bf16:1:0:1:2:0": {"fetch": 159753.9, "write": 49152.0},
+        "bf16:1:0:1:2:1": {"fetch": 139389.2, "write": 49152.0},
+        "bf16:1:1:1:1:0": {"fetch": 172059.6, "write": 49152.0},
+        "bf16:1:1:1:1:1": {"fetch": 129134.5, "write": 49152.0},
+        "bf16:1:1:1:0:0": {"fetch": 136048.8, "write": 49152.0},
+        "bf16:1:1:1:0:1": {"fetch": 136045.8, "write": 49152.0},
+        "bf16:1:1:1:2:0": {"fetch": 142120.5, "write": 49152.0},
+        "bf16:1:1:1:2:1": {"fetch": 137878.9, "write": 49152.0},
+        "f64:4:0:1:1:0": {"fetch": 2265737.1, "write": 786432.0},
+        "f64:4:0:1:1:1": {"fetch": 2591977.7, "write": 786432.2},
+        "f64:4:0:1:0:0": {"fetch": 2391897.6, "write": 786432.0},
+        "f64:4:0:1:0:1": {"fetch": 2797366.6, "write": 786433.1},
+        "f64:4:0:1:2:0": {"fetch": 1976976.1, "write": 786432.0},
+        "f64:4:0:1:2:1": {"fetch": 2113931.1, "write": 786432.1},
+        "f64:4:1:1:1:0": {"fetch": 1614850.2, "write": 786432.0},
+        "f64:4:1:1:1:1": {"fetch": 1673004.9, "write": 786432.0},
+        "f64:4:1:1:0:0": {"fetch": 1769895.7, "write": 786432.0},
+        "f64:4:1:1:0:1": {"fetch": 1795550.1, "write": 786432.0},
+        "f64:4:1:1:2:0": {"fetch": 1097199.8, "write": 786432.0},
+        "f64:4:1:1:2:1": {"fetch": 1127236.1, "write": 786432.0},
+        "f64:4:1:2:1:0": {"fetch": 1658172.0, "write": 786432.0},
+        "f64:4:1:2:1:1": {"fetch": 1714164.3, "write": 786432.0},
+        "f64:4:1:2:0:0": {"fetch": 1770484.1, "write": 786432.0},
+        "f64:4:1:2:0:1": {"fetch": 1823610.4, "write": 786432.0},
+        "f64:4:1:2:2:0": {"fetch": 1107465.7, "write": 786432.0},
+        "f64:4:1:2:2:1": {"fetch": 1201724.2, "write": 786432.0},
+        "f64:4:1:4:1:0": {"fetch": 1726463.4, "write": 786432.0},
+        "f64:4:1:4:1:1": {"fetch": 1641647.8, "write": 786432.0},
+        "f64:4:1:4:0:0": {"fetch": 1749168.0, "write": 786432.0},
+        "f64:4:1:4:0:1": {"fetch": 1639984.2, "write": 786432.0},
+        "f64:4:1:4:2:0": {"fetch": 1122142.0, "write": 786432.0},
+        "f64:4:1:4:2:1": {"fetch": 1096896.6, "write": 786432.0},
+        "f32:4:0:1:1:0": {"fetch": 1053165.2, "write": 393216.0},
+        "f32:4:0:1:1:1": {"fetch": 1202617.8, "write": 393225.2},
+        "f32:4:0:1:0:0": {"fetch": 1191908.6, "write": 393216.0},
+        "f32:4:0:1:0:1": {"fetch": 1385724.9, "write": 393231.4},
+        "f32:4:0:1:2:0": {"fetch": 861094.2, "write": 393216.0},
+        "f32:4:0:1:2:1": {"fetch": 926359.9, "write": 393217.4},
+        "f32:4:0:2:1:0": {"fetch": 822146.4, "write": 393216.0},
+        "f32:4:0:2:1:1": {"fetch": 817805.5, "write": 393216.0},
+        "f32:4:0:2:0:0": {"fetch": 1020546.3, "write": 393216.0},
+        "f32:4:0:2:0:1": {"fetch": 1019883.9, "write": 393216.2},
+        "f32:4:0:2:2:0": {"fetch": 575242.6, "write": 393216.0},
+        "f32:4:0:2:2:1": {"fetch": 559737.8, "write": 393216.0},
+        "f32:4:1:1:1:0": {"fetch": 788373.6, "write": 393216.0},
+        "f32:4:1:1:1:1": {"fetch": 796318.9, "write": 393216.0},
+        "f32:4:1:1:0:0": {"fetch": 701211.7, "write": 393216.0},
+        "f32:4:1:1:0:1": {"fetch": 529441.6, "write": 393216.0},
+        "f32:4:1:1:2:0": {"fetch": 546441.9, "write": 393216.0},
+        "f32:4:1:1:2:1": {"fetch": 551999.2, "write": 393216.0},
+        "f32:4:1:2:1:0": {"fetch": 794783.1, "write": 393216.0},
+        "f32:4:1:2:1:1": {"fetch": 790137.7, "write": 393216.0},
+        "f32:4:1:2:0:0": {"fetch": 662018.4, "write": 393216.0},
+        "f32:4:1:2:0:1": {"fetch": 519877.2, "write": 393216.0},
+        "f32:4:1:2:2:0": {"fetch": 548524.6, "write": 393216.0},
+        "f32:4:1:2:2:1": {"fetch": 546733.7, "write": 393216.0},
+        "f32:4:1:4:1:0": {"fetch": 794685.2, "write": 393216.0},
+        "f32:4:1:4:1:1": {"fetch": 790156.8, "write": 393216.0},
+        "f32:4:1:4:0:0": {"fetch": 661916.3, "write": 393216.0},
+        "f32:4:1:4:0:1": {"fetch": 519882.2, "write": 393216.0},
+        "f32:4:1:4:2:0": {"fetch": 548526.4, "write": 393216.0},
+        "f32:4:1:4:2:1": {"fetch": 546732.1, "write": 393216.0},
+        "bf16:4:0:1:1:0": {"fetch": 418178.1, "write": 196608.0},
+        "bf16:4:0:1:1:1": {"fetch": 476542.8, "write": 196608.0},
+        "bf16:4:0:1:0:0": {"fetch": 522971.2, "write": 196608.0},
+        "bf16:4:0:1:0:1": {"fetch": 563887.2, "write": 196608.0},
+        "bf16:4:0:1:2:0": {"fetch": 294347.1, "write": 196608.0},
+        "bf16:4:0:1:2:1": {"fetch": 346231.2, "write": 196608.0},
+        "bf16:4:0:2:1:0": {"fetch": 395519.4, "write": 196608.0},
+        "bf16:4:0:2:1:1": {"fetch": 395335.4, "write": 196608.0},
+        "bf16:4:0:2:0:0": {"fetch": 448932.5, "write": 196608.0},
+        "bf16:4:0:2:0:1": {"fetch": 419044.1, "write": 196608.0},
+        "bf16:4:0:2:2:0": {"fetch": 273550.0, "write": 196608.0},
+        "bf16:4:0:2:2:1": {"fetch": 273863.6, "write": 196608.0},
+        "bf16:4:1:1:1:0": {"fetch": 394155.9, "write": 196608.0},
+        "bf16:4:1:1:1:1": {"fetch": 401064.8, "write": 196608.0},
+        "bf16:4:1:1:0:0": {"fetch": 249374.5, "write": 196608.0},
+        "bf16:4:1:1:0:1": {"fetch": 253804.1, "write": 196608.0},
+        "bf16:4:1:1:2:0": {"fetch": 273292.2, "write": 196608.0},
+        "bf16:4:1:1:2:1": {"fetch": 280876.1, "write": 196608.0},
+        "bf16:4:1:2:1:0": {"fetch": 394310.9, "write": 196608.0},
+        "bf16:4:1:2:1:1": {"fetch": 394267.1, "write": 196608.0},
+        "bf16:4:1:2:0:0": {"fetch": 251090.4, "write": 196608.0},
+        "bf16:4:1:2:0:1": {"fetch": 249122.1, "write": 196608.0},
+        "bf16:4:1:2:2:0": {"fetch": 273430.8, "write": 196608.0},
+        "bf16:4:1:2:2:1": {"fetch": 273402.5, "write": 196608.0},
+        "bf16:4:1:4:1:0": {"fetch": 394313.3, "write": 196608.0},
+        "bf16:4:1:4:1:1": {"fetch": 394267.1, "write": 196608.0},
+        "bf16:4:1:4:0:0": {"fetch": 251085.8, "write": 196608.0},
+        "bf16:4:1:4:0:1": {"fetch": 249121.9, "write": 196608.0},
+        "bf16:4:1:4:2:0": {"fetch": 273430.4, "write": 196608.0},
+        "bf16:4:1:4:2:1": {"fetch": 273402.5, "write": 196608.0},
+    },
 }
 
 
