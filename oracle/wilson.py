@@ -81,6 +81,39 @@ def W(U, psi_e, L, kappa, mu, t_bc=-1, dagger=False):
     return Mhat(U, psi_e, L, kappa, t_bc, dagger) + s * 1j * mu * lat.apply_spin(g5, psi_e)
 
 
+def neighbours_h(L, p_from, sites_h) -> np.ndarray:
+    """Half-lattice indices (parity 1 - p_from) of the 8 nearest neighbours of the
+    listed parity-p_from sites (half-lattice indices), sorted, without repeats."""
+    full = lat.parity_sites(L, p_from)[np.asarray(sites_h)]
+    other = lat.parity_sites(L, 1 - p_from)
+    c = np.stack(np.unravel_index(full, tuple(reversed(L)))[::-1], axis=1)
+    out = []
+    for mu in range(4):
+        for d in (1, -1):
+            y = c.copy()
+            y[:, mu] = (y[:, mu] + d) % L[mu]
+            out.append(np.searchsorted(other, y[:, 0] + L[0] * (y[:, 1] + L[1] * (y[:, 2] + L[2] * y[:, 3]))))
+    return np.unique(np.concatenate(out))
+
+
+def J_at(U, psi_e, L, kappa, mu2, sites_h, t_bc=-1) -> np.ndarray:
+    """(J psi)(s) at the listed even sites only: M-hat and its adjoint written out
+    as in Mhat, each hop evaluated by hop_eo_at on just the sites the four nested
+    hops reach from the listed ones (for large lattices).  Returns [n, 4, 3]."""
+    Vh = psi_e.shape[0]
+    s0 = np.asarray(sites_h)
+    n1 = neighbours_h(L, 0, s0)                    # odd sites of D_oe^dag y read at s0
+    s2 = np.union1d(neighbours_h(L, 1, n1), s0)    # even sites of y = M-hat psi read there
+    n3 = neighbours_h(L, 0, s2)                    # odd sites of D_oe psi read at s2
+    o = np.zeros((Vh,) + psi_e.shape[1:], dtype=np.complex128)
+    o[n3] = hop_eo_at(U, psi_e, L, 1, n3, t_bc)
+    y = np.zeros_like(o)
+    y[s2] = psi_e[s2] - kappa ** 2 * hop_eo_at(U, o, L, 0, s2, t_bc)
+    o = np.zeros_like(o)
+    o[n1] = hop_eo_at(U, y, L, 1, n1, t_bc, dagger=True)
+    return y[s0] - kappa ** 2 * hop_eo_at(U, o, L, 0, s0, t_bc, dagger=True) + mu2 * psi_e[s0]
+
+
 def dense(op, n_sites, dtype=np.complex128):
     """Dense matrix of a linear map on [n_sites, 4, 3] fields (brute force, tiny lattices)."""
     n = n_sites * 12

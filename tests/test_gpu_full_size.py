@@ -57,7 +57,9 @@ def test_hop_sampled_sites_full_size(big, prec):
 @pytest.mark.parametrize("inner", ["bf16", "f32"])
 def test_batched_cg_full_size_true_residual(big, inner):
     """4 sources, kappa 0.156: every solution meets |b - J x| <= 1e-10 |b| with the
-    library's FP64 J (parity-checked against the oracle at small sizes)."""
+    library's FP64 J; that J itself against the oracle's at 24 sampled even sites
+    (evaluated from the sites its four nested hops reach), to 1e-12, and the
+    oracle's residual at those sites within the same 1e-10 |b|."""
     lat, U = big
     say("full size CG, inner", inner)
     b = li.gaussian_spinor((4, lat.Vh, 4, 3), 5300)
@@ -66,9 +68,17 @@ def test_batched_cg_full_size_true_residual(big, inner):
     say(f"  iterations {[s.iters for s in st]}, reliable updates {st[0].reliable_updates}")
     assert rc == 0
     Jx = to_np(lat.export_spinor(lat.apply_K(x, 0.156, "J", mu2=[0.0] * 4, nrhs=4), "f64", 4))
+    xs = to_np(lat.export_spinor(x, "f64", 4))
+    S0 = np.sort(np.random.default_rng(5301).choice(lat.Vh, 24, replace=False))
     for r in range(4):
         assert st[r].converged
         assert rel(Jx[r], b[r]) <= 1.01e-10
+        ref = ow.J_at(U, xs[r], L, 0.156, 0.0, S0)
+        e = rel(Jx[r][S0], ref)
+        res = np.linalg.norm(b[r][S0] - ref) / np.linalg.norm(b[r])
+        say(f"  rhs {r}: library J vs oracle at sampled sites {e:.2e}, oracle residual there {res:.2e}")
+        assert e <= 1e-12
+        assert res <= 1.01e-10
 
 
 def _sample_links(V, n_per_dir, seed):

@@ -154,3 +154,16 @@ def test_hop_at_sampled_sites_equals_full_hop(L):
             full = wl.hop_eo(U, psi, L, p, t_bc=-1, dagger=dagger)
             at = wl.hop_eo_at(U, psi, L, p, sites, t_bc=-1, dagger=dagger)
             assert np.abs(at - full[sites]).max() < 1e-13
+
+
+def test_J_at_matches_whole_lattice_J():
+    """The sampled-site J (used at full sizes) agrees with the whole-lattice J, at
+    sites including ones whose neighbourhoods wrap in every direction."""
+    L = (4, 4, 6, 8)
+    U = li.random_links(L, 0.447, 6)
+    Vh = li.volume(L) // 2
+    psi = li.gaussian_spinor((Vh, 4, 3), 41)
+    sites = np.sort(np.random.default_rng(4).choice(Vh, 11, replace=False))
+    full = wl.J(U, psi, L, 0.156, 0.05)
+    at = wl.J_at(U, psi, L, 0.156, 0.05, sites)
+    assert np.abs(at - full[sites]).max() < 1e-12 * np.abs(full).max()
