@@ -55,6 +55,13 @@ MIXED_DELTA = 0.01
 # algorithmic bytes of one hop application per output site: 8 two-row links + input
 # spinor read once + output spinor written once (perfect on-chip reuse)
 HOP_BYTES_PER_SITE = {"f64": 8 * 96 + 2 * 192, "f32": 8 * 48 + 2 * 96, "bf16": 8 * 24 + 2 * 48}
+# conventional flop count of one Wilson hop per output site and rhs (8 projections,
+# 8 SU(3) x half-spinor products, 7 accumulations), the third-row rebuild not counted
+HOP_FLOPS_PER_SITE = 1320
+
+
+def hop_gflops(nrhs: int, sites: int, us: float) -> float:
+    return round(HOP_FLOPS_PER_SITE * nrhs * sites / (us * 1e-6) / 1e9, 1)
 
 
 # HBM traffic of one hop launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
@@ -426,6 +433,7 @@ LARGE_L, LARGE_KAPPA, LARGE_SPREAD = (32, 32, 32, 64), 0.156, 0.432
 # 2 spinors x 24 + 4 links x 12 (two rows) + 32 coefficients read and written, FP64
 BILINEAR_BYTES_PER_SITE = 8 * (2 * 24 + 4 * 12 + 2 * 32)
 VARIANT_NAMES = ["thread-per-site", "direction-parallel"]
+ORDER_NAMES = ["round-robin", "XCD-contiguous", "z-blocked round-robin"]
 SPINOR_BYTES = {"f64": 192, "f32": 96, "bf16": 48}
 LINK_BYTES = {"f64": 96, "f32": 48, "bf16": 24}
 
@@ -477,10 +485,10 @@ def hbm_roofline(lat):
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": _traffic(prec, nrhs, cfg),
             "kernel": f"hop {prec} x{nrhs} rhs on {'x'.join(map(str, LARGE_L))} "
                       f"({VARIANT_NAMES[variant]}, npass {npass}, "
-                      f"{'XCD-contiguous' if use_xcd else 'round-robin'} workgroup order, "
+                      f"{ORDER_NAMES[use_xcd]} workgroup order, "
                       f"{'streaming' if stream else 'cached'} access)",
             "config": list(cfg), "avg_launch_us": round(us, 2), "algorithmic_bytes_per_launch": byt,
-            "launches": 500}
+            "launches": 500, "gflops": hop_gflops(nrhs, Vh, us)}
         log(f"hbm roofline {prec} x{nrhs}:", json.dumps(out[f"{prec}_x{nrhs}"]))
     return out
 
@@ -499,7 +507,8 @@ def large_volume(lat, li, torch, np, CG):
             us = lat.time_hop(p, nrhs, 200)
             byt = hop_bytes(p, nrhs, Vh)
             out["hop"][f"{p}_x{nrhs}"] = {"us": round(us, 1), "us_per_rhs": round(us / nrhs, 1),
-                                          "GBs": round(byt / (us * 1e-6) / 1e9, 1)}
+                                          "GBs": round(byt / (us * 1e-6) / 1e9, 1),
+                                          "GFLOPs": hop_gflops(nrhs, Vh, us)}
     out["copy_f64_hop_bytes_gbs"] = round(lat.stream_copy(HOP_BYTES_PER_SITE["f64"] * Vh // 2 // 16 * 16, 50), 1)
     log("large volume hop", json.dumps(out["hop"]), "copy of the FP64 hop's bytes:", out["copy_f64_hop_bytes_gbs"])
     bs = [li.gaussian_spinor((Vh, 4, 3), li.seed_source(100 + j)) for j in range(4)]
@@ -538,8 +547,11 @@ def large_volume(lat, li, torch, np, CG):
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) / 10 * 1e3
     fb = BILINEAR_BYTES_PER_SITE * 2 * Vh
+    # the same with every link counted as a full 3x3 matrix (18 reals, 1472 B per site)
+    fb_full = (BILINEAR_BYTES_PER_SITE + 8 * 4 * 6) * 2 * Vh
     out["force_bilinear"] = {"us": round(us, 1), "GBs": round(fb / (us * 1e-6) / 1e9, 1),
-                             "frac": round(fb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": fb}
+                             "frac": round(fb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": fb,
+                             "frac_full_links": round(fb_full / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
     out["hop_config"] = {p: [lat.hop_config(p, k) for k in range(3)] for p in ("f64", "f32", "bf16")}
     return out
 
@@ -831,13 +843,15 @@ def main():
         "bound": "llc", "achieved": round(bytes_per_hop[dom] / (avg_us * 1e-6) / 1e9, 1), "unit": "GB/s",
         "frac_of_hbm_peak": round(bytes_per_hop[dom] / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
         "kernel": f"hop {dom} on 16x16x16x32 ({VARIANT_NAMES[variant]}, "
-                  f"{'XCD-contiguous' if use_xcd else 'round-robin'} workgroup order, "
+                  f"{ORDER_NAMES[use_xcd]} workgroup order, "
                   f"{'streaming' if stream else 'cached'} access)",
         "avg_launch_us": round(avg_us, 2), "in_situ_avg_us": round(prof[dom][0], 2),
         "in_situ_samples": prof[dom][1], "algorithmic_bytes_per_launch": bytes_per_hop[dom],
+        "gflops": hop_gflops(1, Vh, avg_us),
         "note": "working set (links and two fields) inside the 256 MB last-level cache: not an HBM figure"}
     ex = np.exp(-np.array([r.dH for r in chain]))
-    extra = {"hop_avg_us": {p: round(v[0], 2) for p, v in prof.items()},
+    extra = {"hop_gflops_sustained": round(sum(n_hop.values()) * HOP_FLOPS_PER_SITE * Vh / wall / 1e9, 1),
+             "hop_avg_us": {p: round(v[0], 2) for p, v in prof.items()},
              "hop_gbs": {p: round(bytes_per_hop[p] / (v[0] * 1e-6) / 1e9, 1) if v[0] > 0 else None
                          for p, v in prof.items()},
              "trajectory_hop": trajectory_hop,
