@@ -4,7 +4,7 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--therm N] [--no-cpu] [--qu
 
 Workload: 16^3 x 32 lattice, kappa = 0.155, antiperiodic in time, synthetic
 links exp(i a H) with a = 0.447 (plaquette ~0.58), seeded, first thermalised
-by N (default 10) untimed HMC trajectories of the MP action.  One step is one
+by N (default 30) untimed HMC trajectories of the MP action.  One step is one
 HMC trajectory, with Metropolis, of the PF-MP action (polynomial filter on
 top of a Hasenbusch mass preconditioner) with the Wilson plaquette gauge
 action beta = 5.6: POLY(J) + POLYK_INV(J) + RATIO, J = K-hat + 0.05,
@@ -686,7 +686,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--therm", type=int, default=10,
+    ap.add_argument("--therm", type=int, default=30,
                     help="untimed MP trajectories that thermalise the synthetic links before the warmup")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--cpu-full", action="store_true",
