@@ -213,16 +213,16 @@ def test_dslash_link_reuse_passes_equal_single(nrhs, prec, passes):
 def test_dslash_zblocked_order_invariance(variant):
     """The z-blocked workgroup order (32x32 z planes of 8 columns of 64 half
     sites, Lz = 16: two blocks of 8 planes) changes no output bit against the
-    other two orders, with one rhs and with four (the rhs groups of a tile on
+    other two orders, with one rhs, four and eight (the rhs groups of a tile on
     one XCD), in every storage precision; a CG whose J hops take it (with the
     fused <p, Jp> partials per 64-site tile) converges to the oracle's J."""
     L = (32, 32, 16, 4)
     say("dslash z-blocked order", "variant", variant)
     lat, U = make_lattice(L, variant=variant)
-    psi = half_noise(L, 38, nrhs=4)
+    psi = half_noise(L, 38, nrhs=8)
     for prec in ("f64", "f32", "bf16"):
-        for nrhs in (1, 4):
-            src = psi[0] if nrhs == 1 else psi
+        for nrhs in (1, 4, 8):
+            src = psi[0] if nrhs == 1 else psi[:nrhs]
             outs = {}
             for xcd in (1, 0, 2):
                 lat.set_hop_config(prec, -1, use_xcd=xcd)
@@ -230,8 +230,8 @@ def test_dslash_zblocked_order_invariance(variant):
                                                                prec=prec, nrhs=nrhs), prec, nrhs))
             assert np.array_equal(outs[0], outs[1]), (prec, nrhs)
             assert np.array_equal(outs[2], outs[1]), (prec, nrhs)
-            if prec == "f64" and nrhs == 4:
-                assert rel(outs[2][3], ow.hop_eo(U, psi[3], L, 0)) <= 1e-12
+            if prec == "f64" and nrhs > 1:
+                assert rel(outs[2][nrhs - 1], ow.hop_eo(U, psi[nrhs - 1], L, 0)) <= 1e-12
     b = half_noise(L, 39)
     x, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), 0.155, "J", params=CG(tol=1e-10, inner="f32"))
     assert rc == 0 and st[0].true_rel_res <= 1e-10
