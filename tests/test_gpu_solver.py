@@ -256,3 +256,40 @@ def test_cg_graph_recaptured_after_workspace_grows():
     say(f"  iters {st[0].iters}, reliable updates {st[0].reliable_updates}")
     assert rc == 0 and st[0].converged
     assert rel(ow.J(U, to_np(lat.export_spinor(x)), L, kappa, 0.0), b) <= 1.01e-10
+
+
+def test_kappa_zero_degenerate():
+    """kappa = 0, where the hopping term drops out of M = 1 - kappa D and
+    M-hat = 1 - kappa^2 D_eo D_oe (Sec. 2): M, M^dag, K, M-hat and M-hat^dag are
+    the identity bit for bit in FP64 and J = (1 + mu2) times it; CG on J stops
+    after one iteration at b / (1 + mu2); the filter's four forms are the oracle's
+    polynomials of the number 1 + mu2 (n = 16 on [0.001, 8]); an action term with
+    kappa = 0 is refused."""
+    from oracle import poly as opoly
+    from paper_1702_00124_amd.lattice import Term
+    L = (6, 4, 4, 10)
+    mu2 = 0.05
+    lat, _ = make_lattice(L)
+    psi = half_noise(L, 81)
+    full = full_noise(L, 82)
+    x = lat.import_spinor(torch.from_numpy(psi))
+    xf = lat.import_full(torch.from_numpy(full))
+    for op in ("MHAT", "MHAT_DAG"):
+        assert np.array_equal(to_np(lat.export_spinor(lat.apply_K(x, 0.0, op=op))), psi), op
+    for op in ("M", "MDAG", "K"):
+        assert np.array_equal(to_np(lat.export_full(lat.apply_K(xf, 0.0, op=op))), full), op
+    assert rel(to_np(lat.export_spinor(lat.apply_K(x, 0.0, op="J", mu2=(mu2,)))), (1 + mu2) * psi) <= 1e-15
+    sol, st, rc = lat.cg_solve(x, 0.0, "J", mu2=(mu2,))
+    assert rc == 0 and st[0].iters == 1 and st[0].true_rel_res <= 1e-14
+    assert rel(to_np(lat.export_spinor(sol)), psi / (1 + mu2)) <= 1e-14
+    scale = lambda v: (1 + mu2) * v
+    for mode, ref in (("P", opoly.apply_P(scale, psi, 16, 0.001, 8.0)),
+                      ("PJ", opoly.apply_PJ(scale, psi, 16, 0.001, 8.0)),
+                      ("Q", opoly.apply_Q(scale, psi, 16, 0.001, 8.0)),
+                      ("QDAG", opoly.apply_Q(scale, psi, 16, 0.001, 8.0, dagger=True))):
+        got = to_np(lat.export_spinor(lat.poly_filter_apply(x, 0.0, mu2, 16, 0.001, 8.0, mode)))
+        say(f"kappa = 0, filter {mode}: relative difference {rel(got, ref):.2e}")
+        assert rel(got, ref) <= 1e-12, mode
+    with pytest.raises(W.WilsonError):
+        lat.heatbath(Term("KINV", 0.0, mu2), lat.import_spinor(torch.from_numpy(psi)))
+    lat.close()
