@@ -1,7 +1,7 @@
 """The paper's cost metric C = N_mat / P_acc (Sec. 3.1) for each of its actions.
 
     python -m paper_1702_00124_amd.cost [--lattice 8,8,8,16] [--kappa 0.155] [--beta 5.6]
-        [--therm 60] [--traj 40] [--actions MP,PF-MP,...] [--steps 20,10,40]
+        [--therm 60] [--traj 40] [--actions MP,PF-MP,...] [--steps 20,10,40] [--therm-steps 60,30,120]
 
 N_mat is the number of fermion-matrix multiplications (K-hat and J applications,
 including heatbath and action solves) per trajectory and P_acc the Metropolis
@@ -10,7 +10,8 @@ thermalised by HMC with the MP action: every exact action samples the same
 distribution det K-hat exp(-S_G), so one thermalised configuration serves all.
 Each action then runs its own Markov chain of --traj trajectories from it, with
 Omelyan steps (--steps: the cheapest term, every other term, the gauge action)
-on tau = 1, MD solves FP32 inner / FP64 reliable updates to 1e-10.  Reported per
+on tau = 1 (--therm-steps: the thermalisation's own rule, by default the same),
+MD solves FP32 inner / FP64 reliable updates to 1e-10.  Reported per
 action: C, P_acc, mean N_mat and CG iterations, <exp(-dH)> (1 in equilibrium, a
 check of the integrator and the chain), plaquette, seconds per trajectory.
 
@@ -70,10 +71,11 @@ class Checkpoint:
 
 
 def run(L=(8, 8, 8, 16), kappa=0.155, beta=5.6, ntherm=60, ntraj=40, actions=None, steps=(20, 10, 40),
-        log=print, checkpoint=None, max_traj=None, tune_cache=None):
+        log=print, checkpoint=None, max_traj=None, tune_cache=None, therm_steps=None):
     """checkpoint: directory for checkpoint / resume; max_traj: stop (returning
     None) after that many trajectories in this call, the state saved;
-    tune_cache: autotuner cache file."""
+    tune_cache: autotuner cache file; therm_steps: the step rule of the
+    thermalisation (default: steps)."""
     import numpy as np
     import torch
 
@@ -92,7 +94,7 @@ def run(L=(8, 8, 8, 16), kappa=0.155, beta=5.6, ntherm=60, ntraj=40, actions=Non
     cg = CG(tol=1e-10, inner="f32", chunk=8)
     ck = Checkpoint(checkpoint) if checkpoint else None
     run_key = {"lattice": list(L), "kappa": kappa, "beta": beta, "therm": ntherm, "traj": ntraj,
-               "steps": list(steps), "actions": names}
+               "steps": list(steps), "therm_steps": list(therm_steps or steps), "actions": names}
     state = ck.load_state() if ck else None
     if state is not None:
         if state["run"] != run_key:
@@ -104,13 +106,13 @@ def run(L=(8, 8, 8, 16), kappa=0.155, beta=5.6, ntherm=60, ntraj=40, actions=Non
         state = {"run": run_key, "phase": "therm", "k": 0, "rows": [], "done": {}}
     budget = [max_traj if max_traj is not None else -1]
 
-    def nsteps_for(n):
-        return [steps[0]] + [steps[1]] * (n - 1) + [steps[2]]
+    def nsteps_for(n, st):
+        return [st[0]] + [st[1]] * (n - 1) + [st[2]]
 
-    def chain(name, count, traj0):
+    def chain(name, count, traj0, st=steps):
         """Trajectories state['k']..count-1 of one chain; None if the budget ran out."""
         terms = build_terms(name, kappas, cg)
-        ns = nsteps_for(len(terms))
+        ns = nsteps_for(len(terms), st)
         u = li.uniforms(count, li.seed_metropolis(traj0))
         rows = [tuple(r) for r in state["rows"]]
         for k in range(state["k"], count):
@@ -142,7 +144,7 @@ def run(L=(8, 8, 8, 16), kappa=0.155, beta=5.6, ntherm=60, ntraj=40, actions=Non
 
     t_start = time.time()
     if state["phase"] == "therm":
-        rows, ns = chain("MP", ntherm, 100000)
+        rows, ns = chain("MP", ntherm, 100000, tuple(therm_steps or steps))
         if rows is None:
             lat.close()
             return None
@@ -155,7 +157,8 @@ def run(L=(8, 8, 8, 16), kappa=0.155, beta=5.6, ntherm=60, ntraj=40, actions=Non
         next_phase(names[0] if names else "end")
     U0 = (torch.from_numpy(ck.load_array("links_therm")) if ck else lat.get_links().clone())
     out = {"lattice": list(L), "kappa": kappa, "kappas": kappas, "beta": beta, "therm": ntherm, "traj": ntraj,
-           "steps_rule": list(steps), "thermalised_plaquette": state["thermalised_plaquette"], "actions": {}}
+           "steps_rule": list(steps), "therm_steps_rule": list(therm_steps or steps),
+           "thermalised_plaquette": state["thermalised_plaquette"], "actions": {}}
     for ai, name in enumerate(names):
         if name in state["done"]:
             out["actions"][name] = state["done"][name]
@@ -198,16 +201,19 @@ def main(argv=None):
     ap.add_argument("--traj", type=int, default=40)
     ap.add_argument("--actions", default=None, help="comma-separated subset of the paper's actions")
     ap.add_argument("--steps", default="20,10,40", help="steps: cheapest term, other terms, gauge")
+    ap.add_argument("--therm-steps", default=None, help="the same rule for the thermalisation (default: --steps)")
     ap.add_argument("--checkpoint", default=None, help="directory for checkpoint / resume")
     ap.add_argument("--max-traj", type=int, default=None, help="stop after this many trajectories (state saved)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (same launch configurations on resume)")
     args = ap.parse_args(argv)
     L = tuple(int(v) for v in args.lattice.split(","))
     steps = tuple(int(v) for v in args.steps.split(","))
+    therm_steps = tuple(int(v) for v in args.therm_steps.split(",")) if args.therm_steps else None
     out = run(L, args.kappa, args.beta, args.therm, args.traj,
               args.actions.split(",") if args.actions else None, steps,
               log=lambda *a: print("[cost]", *a, file=sys.stderr, flush=True),
-              checkpoint=args.checkpoint, max_traj=args.max_traj, tune_cache=args.tune_cache)
+              checkpoint=args.checkpoint, max_traj=args.max_traj, tune_cache=args.tune_cache,
+              therm_steps=therm_steps)
     if out is None:
         print(json.dumps({"stopped": True, "checkpoint": args.checkpoint}), flush=True)
     else:

@@ -12,8 +12,10 @@ def test_cost_driver_bookkeeping():
     from paper_1702_00124_amd import cost
     say("cost driver 4^4")
     out = cost.run((4, 4, 4, 4), 0.155, 5.6, ntherm=2, ntraj=3, actions=["MP", "2PF-1MP"], steps=(4, 2, 8),
-                   log=lambda *a: say(*a))
+                   therm_steps=(6, 3, 10), log=lambda *a: say(*a))
     assert set(out["actions"]) == {"MP", "2PF-1MP"}
+    assert out["steps_rule"] == [4, 2, 8] and out["therm_steps_rule"] == [6, 3, 10]
+    assert out["actions"]["2PF-1MP"]["nsteps"] == [4, 2, 2, 2, 8]
     for name, r in out["actions"].items():
         assert r["N_mat"] > 0 and 0.0 <= r["P_acc"] <= 1.0
         if r["P_acc"] > 0:
