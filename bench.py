@@ -432,7 +432,7 @@ def mixed_volume(li, torch, CG, WilsonLattice, WilsonBatch):
 LARGE_L, LARGE_KAPPA, LARGE_SPREAD = (32, 32, 32, 64), 0.156, 0.432
 # 2 spinors x 24 + 4 links x 12 (two rows) + 32 coefficients read and written, FP64
 BILINEAR_BYTES_PER_SITE = 8 * (2 * 24 + 4 * 12 + 2 * 32)
-VARIANT_NAMES = ["thread-per-site", "direction-parallel"]
+VARIANT_NAMES = ["thread-per-site", "direction-parallel", "thread-per-site, links shared in LDS"]
 ORDER_NAMES = ["round-robin", "XCD-contiguous", "z-blocked round-robin"]
 SPINOR_BYTES = {"f64": 192, "f32": 96, "bf16": 48}
 LINK_BYTES = {"f64": 96, "f32": 48, "bf16": 24}

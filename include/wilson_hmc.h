@@ -378,6 +378,11 @@ int wl_solve_log_read(const wl_lattice* lat, int max, int* n, long long* iters, 
  *   variant  0 = one thread per output site (all 8 directions);
  *            1 = direction-parallel (8 wavefronts, one per direction, over 64
  *                sites, combined through LDS);
+ *            2 = one thread per output site with the links shared: a
+ *                workgroup takes one 64-site tile for four rhs (one
+ *                wavefront each), reads the tile's 8 x 64 links once into
+ *                LDS and gives variant 0's results bit for bit (FP32 and BF16
+ *                from 4 rhs on; otherwise variant 0 runs);
  *   npass    direction-parallel: up to npass (1, 2, 4) passes of 1 (FP64) or
  *            2 (FP32, BF16, even rhs counts) rhs reuse each link held in
  *            registers; site: 2 = two rhs per thread (FP32, BF16, even rhs
@@ -393,24 +398,26 @@ int wl_solve_log_read(const wl_lattice* lat, int max, int* n, long long* iters, 
  *   stream   1 = non-temporal loads of links and epilogue operands and
  *            non-temporal output stores (pays on volumes beyond the caches),
  *            0 = ordinary cached access.
- * Results are identical for every npass and use_xcd; stream and the variant
- * change them by rounding only (stream: the compiler's contraction of products
- * into FMAs may differ; variant: the summation order of the 8 directions).
+ * Results are identical for every npass and use_xcd, and for variants 0 and
+ * 2; stream and variant 1 against the others change them by rounding only
+ * (stream: the compiler's contraction of products into FMAs may differ;
+ * variant 1: the summation order of the 8 directions).
  * wl_set_hop_config sets one class (kind = -1: all three); WL_EINVAL for
  * values outside these sets.  wl_get_hop_config reads one class (outputs may
  * be NULL).
  * wl_autotune times on this lattice, for every precision, class 0 at 1 rhs
  * over {site, direction-parallel}, classes 1 and 2 at 4 and 8 rhs over
- * {site npass 1, 2; direction-parallel npass 1, 2, 4}, each candidate with
+ * {site npass 1, 2; site with shared links (FP32, BF16); direction-parallel
+ * npass 1, 2, 4}, each candidate with
  * (stream, use_xcd) = (0, 1), (0, 0), (0, 2), (1, 1), (1, 0), (1, 2), as
  * bursts in which each launch reads the previous launch's output (best of 3
  * bursts of 20), and keeps the fastest of every class.  stream = 1 is a
  * candidate only where the hop's working set (links and two fields of that
  * class) exceeds the 256 MiB last-level cache, use_xcd = 2 only where valid.
- * us_out: optional host array of 3 x 72 microseconds per launch (0 for
+ * us_out: optional host array of 3 x 84 microseconds per launch (0 for
  * candidates not timed), per precision (F64, F32, BF16): 12 for class 0 (site,
- * dp per (stream, use_xcd) in that order), then 30 for class 1 and 30 for
- * class 2 (site 1, site 2, dp 1, dp 2, dp 4 per (stream, use_xcd)). */
+ * dp per (stream, use_xcd) in that order), then 36 for class 1 and 36 for
+ * class 2 (site 1, site 2, shared, dp 1, dp 2, dp 4 per (stream, use_xcd)). */
 int wl_set_hop_config(wl_lattice* lat, wl_prec prec, int kind, int variant, int npass, int use_xcd, int stream);
 int wl_get_hop_config(const wl_lattice* lat, wl_prec prec, int kind, int* variant, int* npass, int* use_xcd,
                       int* stream);

@@ -510,7 +510,8 @@ int wl_set_hop_config(wl_lattice* L, wl_prec prec, int kind, int variant, int np
     check_lat(L);
     check_prec_rhs(prec, 1);
     WL_REQUIRE(kind >= -1 && kind < kHopKinds, WL_EINVAL, "hop class must be -1, 0, 1 or 2");
-    WL_REQUIRE(variant == kHopSite || variant == kHopDirParallel, WL_EINVAL, "unknown hop variant");
+    WL_REQUIRE(variant == kHopSite || variant == kHopDirParallel || variant == kHopSiteShared, WL_EINVAL,
+               "unknown hop variant");
     WL_REQUIRE(npass == 1 || npass == 2 || npass == 4, WL_EINVAL, "npass must be 1, 2 or 4");
     WL_REQUIRE(use_xcd == 0 || use_xcd == 1 ||
                    (use_xcd == 2 && zblock_ok(L->geo)),
@@ -650,9 +651,10 @@ int wl_autotune(wl_lattice* L, double* us_out) {
     int slot = 0;
     for (int p = 0; p < 3; ++p) {
       for (int k = 0; k < kHopKinds; ++k) {
-        // one rhs: both variants; several: site with 1 or 2 rhs per thread and
-        // direction-parallel with 1, 2 or 4 passes; each in both workgroup
-        // orders, cached then streaming
+        // one rhs: site and direction-parallel; several: site with 1 or 2 rhs
+        // per thread, site with the links shared in LDS (FP32, BF16) and
+        // direction-parallel with 1, 2 or 4 passes; each in every workgroup
+        // order, cached then streaming
         // streaming access only where the hop's working set (links and two
         // fields) exceeds the last-level cache: below it the next kernel reads
         // this hop's output from the cache, which a burst of hops cannot show
@@ -666,14 +668,15 @@ int wl_autotune(wl_lattice* L, double* us_out) {
               cand.push_back({kHopDirParallel, 1, xcd, stm});
             } else {
               for (int np : {1, 2}) cand.push_back({kHopSite, np, xcd, stm});
+              cand.push_back({kHopSiteShared, 1, xcd, stm});
               for (int np : {1, 2, 4}) cand.push_back({kHopDirParallel, np, xcd, stm});
             }
           }
         double best = 1e30;
         HopConfig keep = L->hop_cfg[p][k];
         for (const HopConfig& c : cand) {
-          if (c.stream > max_stream ||
-              (c.use_xcd == 2 && !zblock_ok(L->geo))) {  // not here
+          if (c.stream > max_stream || (c.use_xcd == 2 && !zblock_ok(L->geo)) ||
+              (c.variant == kHopSiteShared && p == F64)) {  // not here
             if (us_out) us_out[slot] = 0.0;
             ++slot;
             continue;

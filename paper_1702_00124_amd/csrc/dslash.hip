@@ -39,6 +39,7 @@ struct HopArgs {
   int part_off;
   int use_xcd;
   int rows;  // rhs groups per tile
+  int nrhs;  // rhs of the launch
   // fused Chebyshev step (every rhs): with w the epilogue's result,
   //   tprev <- ct t + cw w - tprev,  eprev <- ce e + 2 t - eprev,  w not stored
   const char* ch_t;
@@ -250,9 +251,72 @@ __device__ __forceinline__ void bf16_project_mul(const Bf16Link& L, const uint32
   }
 }
 
-template <typename P, int MU, int DAG, int NR, bool ST>
+// ------------------------------------------------------------------ links shared through LDS
+// The shared-link variant of the thread-per-site kernel gives a workgroup one
+// 64-site tile and four rhs, one per wavefront.  Wavefront w reads the tile's
+// two links of direction w (forward at the site, backward at its neighbour)
+// once, in the form the products take (BF16: the product pairs with the
+// rebuilt third row; FP32: the SU(3) matrix with its third row), and puts them
+// in LDS; after one barrier every wavefront takes all 8 from there.  BF16
+// keeps the product pairs (18 words per link: the pair forms and the third
+// row are built once per tile instead of once per rhs); FP32 keeps the two
+// stored rows (12 words) and rebuilds the third row per rhs in the same
+// expression as the thread-per-site kernel.  The arithmetic is that kernel's,
+// bit for bit.
+template <typename P>
+constexpr int shl_words() { return std::is_same<P, PrecBF16>::value ? 18 : 12; }
+__device__ __forceinline__ void shl_put(uint32_t* S, int d, const Bf16Link& U, int lane) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    S[(d * 18 + e) * 64 + lane] = U.A[e];
+    S[(d * 18 + 9 + e) * 64 + lane] = U.B[e];
+  }
+}
+__device__ __forceinline__ void shl_get(const uint32_t* S, int d, Bf16Link* U, int lane) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    U->A[e] = S[(d * 18 + e) * 64 + lane];
+    U->B[e] = S[(d * 18 + 9 + e) * 64 + lane];
+  }
+}
+__device__ __forceinline__ void shl_put(uint32_t* S, int d, const SU3<float>& U, int lane) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    S[(d * 12 + 2 * k) * 64 + lane] = __builtin_bit_cast(uint32_t, U.m[k].r);
+    S[(d * 12 + 2 * k + 1) * 64 + lane] = __builtin_bit_cast(uint32_t, U.m[k].i);
+  }
+}
+__device__ __forceinline__ void shl_get(const uint32_t* S, int d, SU3<float>* U, int lane) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    U->m[k] = {__builtin_bit_cast(float, S[(d * 12 + 2 * k) * 64 + lane]),
+               __builtin_bit_cast(float, S[(d * 12 + 2 * k + 1) * 64 + lane])};
+  third_row(*U);
+}
+// the two links of direction MU into LDS (directions 2 MU forward, 2 MU + 1 backward)
+template <typename P, int MU, bool ST>
+__device__ __forceinline__ void shl_build(const HopArgs& a, const Coord& c, int h, uint32_t* S, int lane) {
+  const size_t lb = LinkIO<P>::bytes * size_t(a.g.Vhp);
+  const char* fwd = a.links + (a.parity * 4 + MU) * lb;
+  const char* bwd = a.links + ((1 - a.parity) * 4 + MU) * lb;
+  bool wrap;
+  const int hb = neighbour<MU>(a.g, c, -1, &wrap);
+  if constexpr (std::is_same<P, PrecBF16>::value) {
+    Bf16Link U;
+    bf16_link<1>(fwd, h, &U, ST);
+    shl_put(S, 2 * MU, U, lane);
+    bf16_link<0>(bwd, hb, &U, ST);
+    shl_put(S, 2 * MU + 1, U, lane);
+  } else {
+    shl_put(S, 2 * MU, LinkIO<P>::template load<ST>(fwd, h, a.g.Vh), lane);
+    shl_put(S, 2 * MU + 1, LinkIO<P>::template load<ST>(bwd, hb, a.g.Vh), lane);
+  }
+}
+
+// SHL: the links from the tile's copy S in LDS (the shared-link variant)
+template <typename P, int MU, int DAG, int NR, bool ST, bool SHL = false>
 __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h, int r0,
-                                        Spinor<typename P::real>* acc) {
+                                        Spinor<typename P::real>* acc, const uint32_t* S = nullptr) {
   using R = typename P::real;
   constexpr int SF = DAG ? +1 : -1;  // projector sign of the forward term
   constexpr int SB = -SF;
@@ -264,7 +328,8 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h,
     for (int fwd = 1; fwd >= 0; --fwd) {
       const int hn = neighbour<MU>(a.g, c, fwd ? +1 : -1, &wrap);
       Bf16Link U;
-      if (fwd) bf16_link<1>(a.links + (a.parity * 4 + MU) * lb, h, &U, ST);
+      if constexpr (SHL) shl_get(S, 2 * MU + (fwd ? 0 : 1), &U, (threadIdx.x & 63));
+      else if (fwd) bf16_link<1>(a.links + (a.parity * 4 + MU) * lb, h, &U, ST);
       else bf16_link<0>(a.links + ((1 - a.parity) * 4 + MU) * lb, hn, &U, ST);
       const R ph = wrap ? R(a.g.tbc) : R(1);
 #pragma unroll
@@ -295,7 +360,9 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h,
   // forward: U_mu(x) in(x + mu)
   {
     const int hf = neighbour<MU>(a.g, c, +1, &wrap);
-    const SU3<R> U = LinkIO<P>::template load<ST>(a.links + (a.parity * 4 + MU) * lb, h, Vh);
+    SU3<R> U;
+    if constexpr (SHL) shl_get(S, 2 * MU, &U, (threadIdx.x & 63));
+    else U = LinkIO<P>::template load<ST>(a.links + (a.parity * 4 + MU) * lb, h, Vh);
     const R ph = wrap ? R(a.g.tbc) : R(1);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -312,7 +379,9 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, const Coord& c, int h,
   // backward: U_mu(x - mu)^dag in(x - mu)
   {
     const int hb = neighbour<MU>(a.g, c, -1, &wrap);
-    const SU3<R> U = LinkIO<P>::template load<ST>(a.links + ((1 - a.parity) * 4 + MU) * lb, hb, Vh);
+    SU3<R> U;
+    if constexpr (SHL) shl_get(S, 2 * MU + 1, &U, (threadIdx.x & 63));
+    else U = LinkIO<P>::template load<ST>(a.links + ((1 - a.parity) * 4 + MU) * lb, hb, Vh);
     const R ph = wrap ? R(a.g.tbc) : R(1);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -372,17 +441,47 @@ __device__ __forceinline__ void cheb_unit(const HopArgs& a, size_t off, int u, i
   epi_store_unit<P, ST>(a.ch_eprev + off, u, h, Vh, ep);
 }
 
-template <typename P, int DAG, int NR, bool ST, bool CHEB = false>
+template <int WORDS>
+__device__ __forceinline__ uint32_t* shl_lds() {
+  __shared__ uint32_t S[8 * WORDS * 64];
+  return S;
+}
+
+// SHL: the shared-link variant (one 64-site tile for four rhs per workgroup,
+// NR = 1, FP32 or BF16)
+template <typename P, int DAG, int NR, bool ST, bool CHEB = false, bool SHL = false>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
   using R = typename P::real;
+  static_assert(!SHL || (NR == 1 && !CHEB && sizeof(R) == 4 && kBlock == 4 * 64), "shared links: 4 x 1 rhs");
   int tile, row;
-  if (!site_tile(a, &tile, &row)) return;
+  if constexpr (SHL) {
+    if (!hop_block_coords<kSiteTile>(a, &tile, &row)) return;
+  } else {
+    if (!site_tile(a, &tile, &row)) return;
+  }
   const int h = tile * 64 + (threadIdx.x & 63);
   const int Vh = a.g.Vh;
-  const int r0 = row * NR;
+  const int r0 = SHL ? row * 4 + (threadIdx.x >> 6) : row * NR;
   double part[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) part[r] = 0.0;
+  const uint32_t* S = nullptr;
+  if constexpr (SHL) {
+    uint32_t* St = shl_lds<shl_words<P>()>();
+    if (h < Vh) {
+      const Coord c = site_coords(a.g, h, a.parity);
+      const int lane = threadIdx.x & 63;
+      switch (threadIdx.x >> 6) {
+        case 0: shl_build<P, 0, ST>(a, c, h, St, lane); break;
+        case 1: shl_build<P, 1, ST>(a, c, h, St, lane); break;
+        case 2: shl_build<P, 2, ST>(a, c, h, St, lane); break;
+        default: shl_build<P, 3, ST>(a, c, h, St, lane); break;
+      }
+    }
+    __syncthreads();
+    if (r0 >= a.nrhs) return;  // the whole wavefront: no rhs left for it
+    S = St;
+  }
 
   if (h < Vh) {
     const Coord c = site_coords(a.g, h, a.parity);
@@ -391,10 +490,10 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
     for (int r = 0; r < NR; ++r)
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[r].c[k] = zero<R>();
-    hop_dir<P, 0, DAG, NR, ST>(a, c, h, r0, acc);
-    hop_dir<P, 1, DAG, NR, ST>(a, c, h, r0, acc);
-    hop_dir<P, 2, DAG, NR, ST>(a, c, h, r0, acc);
-    hop_dir<P, 3, DAG, NR, ST>(a, c, h, r0, acc);
+    hop_dir<P, 0, DAG, NR, ST, SHL>(a, c, h, r0, acc, S);
+    hop_dir<P, 1, DAG, NR, ST, SHL>(a, c, h, r0, acc, S);
+    hop_dir<P, 2, DAG, NR, ST, SHL>(a, c, h, r0, acc, S);
+    hop_dir<P, 3, DAG, NR, ST, SHL>(a, c, h, r0, acc, S);
 
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -690,6 +789,15 @@ static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, const HopConfig& c)
   // rhs per LDS pass (direction-parallel) or per thread (site): two for FP32
   // and BF16 with an even rhs count when the configuration allows, else one
   constexpr bool narrow = sizeof(typename P::real) == 4;
+  if constexpr (narrow) {
+    // shared links from four rhs on; below that the plain thread-per-site kernel
+    if (c.variant == kHopSiteShared && nrhs >= 4) {
+      a.rows = (nrhs + 3) / 4;
+      hipLaunchKernelGGL((hop_kernel<P, DAG, 1, ST, false, true>), dim3(hop_grid<kSiteTile>(a)), dim3(kBlock), 0, st,
+                         a);
+      return;
+    }
+  }
   const bool two = narrow && nrhs % 2 == 0 && (c.variant == kHopDirParallel || c.npass >= 2);
   if (c.variant == kHopDirParallel) {
     if constexpr (narrow) {
@@ -928,6 +1036,7 @@ void launch_hop(wl_lattice* L, Prec prec, void* out, const void* in, int out_par
   a.out = static_cast<char*>(out);
   a.links = static_cast<const char*>(L->U[prec]);
   a.rhs_stride = spinor_bytes(prec, L->Vh);
+  a.nrhs = nrhs;
   a.x = static_cast<const char*>(e.x);
   a.cx = e.cx;
   a.a = e.a;

@@ -22,7 +22,7 @@ constexpr int kBlock = 256;  // threads per workgroup of the site kernels
 constexpr int kScal = 2048;  // device scalar slots; the CG state starts at kCgState
 constexpr int kCgState = 1024;
 constexpr int kProfPairs = 4096;  // sampled hop launches timed per precision
-enum HopVariant { kHopSite = 0, kHopDirParallel = 1 };
+enum HopVariant { kHopSite = 0, kHopDirParallel = 1, kHopSiteShared = 2 };
 // how a hop is launched: kernel variant; npass = direction-parallel: most rhs
 // passes per link held in registers (1, 2, 4), site: rhs per thread (1, 2);
 // use_xcd = workgroup order: 1 XCD-contiguous ranges, 0 the hardware's

@@ -383,10 +383,10 @@ class WilsonLattice:
     def autotune(self, cache: Optional[str] = None):
         """Time the hop configurations per precision and rhs class and keep the fastest.
 
-        Returns {prec: [72 microsecond timings]} in the order the C API documents:
-        class 0 (site, dp), then classes 1 and 2 (site 1, site 2, dp 1, dp 2, dp 4),
-        each per (stream, order) = (0, 1), (0, 0), (0, 2), (1, 1), (1, 0), (1, 2)
-        (0 where not a candidate).
+        Returns {prec: [84 microsecond timings]} in the order the C API documents:
+        class 0 (site, dp), then classes 1 and 2 (site 1, site 2, site with shared
+        links, dp 1, dp 2, dp 4), each per (stream, order) = (0, 1), (0, 0), (0, 2),
+        (1, 1), (1, 0), (1, 2) (0 where not a candidate).
 
         cache: a JSON file of earlier results keyed by lattice extents, device
         (ISA, compute units, memory) and library build; on a hit the stored configurations are set and
@@ -400,9 +400,9 @@ class WilsonLattice:
                     for k, c in enumerate(cfgs):
                         W.check(self.lib.wl_set_hop_config(self.h, _prec(prec), k, *c))
                 return hit["us"]
-        us = (C.c_double * 216)()
+        us = (C.c_double * 252)()
         W.check(self.lib.wl_autotune(self.h, us))
-        res = {name: list(us[72 * i:72 * i + 72]) for name, i in PREC.items()}
+        res = {name: list(us[84 * i:84 * i + 84]) for name, i in PREC.items()}
         if key:
             tune_cache_write(cache, key, {"configs": {p: [list(self.hop_config(p, k)) for k in range(3)] for p in PREC},
                                           "us": res})

@@ -38,7 +38,7 @@ def test_layout_roundtrips(L):
     assert np.array_equal(to_np(lat.export_su3(lat.import_su3(torch.from_numpy(p)))), p)
 
 
-VARIANTS = [0, 1]   # thread per site, direction-parallel
+VARIANTS = [0, 1, 2]   # thread per site, direction-parallel, thread per site with the links shared in LDS
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -119,16 +119,22 @@ def test_variants_agree_and_autotune():
     for v in VARIANTS:
         lat.set_hop_variant("f64", v)
         outs.append(to_np(lat.export_spinor(lat.dslash(lat.import_spinor(torch.from_numpy(psi)), 0))))
-    assert rel(outs[0], outs[1]) <= 1e-14
+    assert rel(outs[0], outs[1]) <= 1e-14 and np.array_equal(outs[0], outs[2])
     res = lat.autotune()
     say(f"  autotune us per launch: {res}")
     # 8^4 fits the last-level cache: streaming candidates are not timed; a z plane of
     # 32 half sites holds no whole tile, so the z-blocked order is not a candidate either
-    for v in res.values():
-        assert len(v) == 72
+    # classes 1 and 2: site 1, site 2, shared (not FP64), dp 1, dp 2, dp 4 per (stream, order)
+    for name, v in res.items():
+        assert len(v) == 84
         assert min(v[0:4]) > 0 and v[4:12] == [0.0] * 8                # class 0
-        assert min(v[12:22]) > 0 and v[22:42] == [0.0] * 20            # class 1
-        assert min(v[42:52]) > 0 and v[52:72] == [0.0] * 20            # class 2
+        for c0 in (12, 48):                                             # classes 1 and 2
+            timed = v[c0:c0 + 12]
+            if name == "f64":
+                assert timed[2] == timed[8] == 0.0 and min(timed[:2] + timed[3:8] + timed[9:]) > 0
+            else:
+                assert min(timed) > 0
+            assert v[c0 + 12:c0 + 36] == [0.0] * 24
     for prec in ("f64", "f32", "bf16"):
         assert all(lat.hop_config(prec, k)[3] == 0 for k in range(3))
     for prec in ("f64", "f32", "bf16"):
@@ -275,6 +281,44 @@ def test_dslash_launch_config_invariance(variant, L):
     assert rel(ow.J(U, to_np(lat.export_spinor(x)), L, 0.155, 0.0), b) <= 1.01e-10
     with pytest.raises(Exception):
         lat.set_hop_config("f64", 0, npass=3)
+
+
+@pytest.mark.parametrize("L", [(8, 8, 8, 8), (6, 4, 4, 10)])
+def test_shared_link_variant_matches_site_kernel(L):
+    """The shared-link variant (a workgroup takes one 64-site tile for four rhs
+    and reads the tile's links into LDS once) gives the thread-per-site
+    kernel's output bit for bit: FP32 and BF16, 4, 5 and 8 rhs (a partly idle
+    last group of four), both output parities and the dagger, every workgroup
+    order, and with the fused epilogue (J with per-rhs shifts); a batched CG
+    whose J hops take it (with the fused <p, Jp> partials) converges to the
+    oracle's J."""
+    say("shared-link variant", L)
+    lat, U = make_lattice(L)
+    psi = half_noise(L, 91, nrhs=8)
+    shifts = [0.0, 0.005, 0.05, 0.5, 0.0, 0.005, 0.05, 0.5]
+    for prec in ("f32", "bf16"):
+        for nrhs in (4, 5, 8):
+            x = lat.import_spinor(torch.from_numpy(psi[:nrhs]), prec)
+            outs = {}
+            for variant, xcd in ((0, 1), (2, 1), (2, 0)):
+                lat.set_hop_config(prec, -1, variant=variant, npass=1, use_xcd=xcd, stream=0)
+                for parity in (0, 1):
+                    for dag in (False, True):
+                        outs[(variant, xcd, parity, dag)] = to_np(lat.export_spinor(
+                            lat.dslash(x, parity, dagger=dag, prec=prec, nrhs=nrhs), prec, nrhs))
+                outs[(variant, xcd, "J")] = to_np(lat.export_spinor(
+                    lat.apply_K(x, 0.155, op="J", mu2=shifts[:nrhs], prec=prec, nrhs=nrhs), prec, nrhs))
+            for k, v in outs.items():
+                assert np.array_equal(v, outs[(0, 1) + k[2:]]), (prec, nrhs, k)
+    lat.set_hop_config("f32", -1, variant=2, npass=1, use_xcd=0, stream=0)
+    b = half_noise(L, 92, nrhs=4)
+    xs, st, rc = lat.cg_solve(lat.import_spinor(torch.from_numpy(b)), 0.155, "J", mu2=shifts[:4], nrhs=4,
+                              params=CG(tol=1e-10, inner="f32"))
+    assert rc == 0 and all(s.true_rel_res <= 1e-10 for s in st)
+    xr = to_np(lat.export_spinor(xs, "f64", 4))
+    for r in range(4):
+        assert rel(ow.J(U, xr[r], L, 0.155, shifts[r]), b[r]) <= 1.01e-10
+    lat.close()
 
 
 def test_autotune_cache_hit_sets_same_configurations(tmp_path):
