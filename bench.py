@@ -74,128 +74,140 @@ def hop_gflops(nrhs: int, sites: int, us: float) -> float:
 # sources); otherwise `traffic` is reported as null.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_COUNTERS = {
-    "source_sha256": "d70948aaebcf45d85eaf29f7fb0463c2cb22b1e5e263d6d8dba2b425ea484b77",
+    "source_sha256": "9d8cd59c7750761353bd238eaaba6e4b1405de5f8c88e4e804750b0de0999c49",
     "per_launch_kib": {
-        "f64:1:0:1:1:0": {"fetch": 913394.2, "write": 196608.0},
-        "f64:1:0:1:1:1": {"fetch": 743429.2, "write": 196608.0},
-        "f64:1:0:1:0:0": {"fetch": 1014707.2, "write": 196608.0},
-        "f64:1:0:1:0:1": {"fetch": 884053.4, "write": 196608.0},
-        "f64:1:0:1:2:0": {"fetch": 866270.4, "write": 196608.0},
-        "f64:1:0:1:2:1": {"fetch": 671045.9, "write": 196608.1},
-        "f64:1:1:1:1:0": {"fetch": 689188.1, "write": 196608.0},
+        "f64:1:0:1:1:0": {"fetch": 913496.9, "write": 196608.0},
+        "f64:1:0:1:1:1": {"fetch": 743393.4, "write": 196608.0},
+        "f64:1:0:1:0:0": {"fetch": 1014398.6, "write": 196608.0},
+        "f64:1:0:1:0:1": {"fetch": 884247.0, "write": 196608.0},
+        "f64:1:0:1:2:0": {"fetch": 865780.2, "write": 196608.0},
+        "f64:1:0:1:2:1": {"fetch": 670386.8, "write": 196608.0},
+        "f64:1:1:1:1:0": {"fetch": 689175.4, "write": 196608.0},
         "f64:1:1:1:1:1": {"fetch": 689032.5, "write": 196608.0},
-        "f64:1:1:1:0:0": {"fetch": 556771.0, "write": 196608.0},
-        "f64:1:1:1:0:1": {"fetch": 543894.0, "write": 196608.0},
-        "f64:1:1:1:2:0": {"fetch": 568277.1, "write": 196608.0},
+        "f64:1:1:1:0:0": {"fetch": 556634.2, "write": 196608.0},
+        "f64:1:1:1:0:1": {"fetch": 543893.7, "write": 196608.0},
+        "f64:1:1:1:2:0": {"fetch": 568275.3, "write": 196608.0},
         "f64:1:1:1:2:1": {"fetch": 568168.1, "write": 196608.0},
-        "f32:1:0:1:1:0": {"fetch": 370596.4, "write": 98304.0},
-        "f32:1:0:1:1:1": {"fetch": 302612.8, "write": 98308.8},
-        "f32:1:0:1:0:0": {"fetch": 488155.1, "write": 98304.0},
-        "f32:1:0:1:0:1": {"fetch": 420634.6, "write": 98306.2},
-        "f32:1:0:1:2:0": {"fetch": 397258.4, "write": 98304.0},
-        "f32:1:0:1:2:1": {"fetch": 308413.4, "write": 98304.5},
-        "f32:1:1:1:1:0": {"fetch": 344624.6, "write": 98304.0},
-        "f32:1:1:1:1:1": {"fetch": 343260.6, "write": 98304.0},
-        "f32:1:1:1:0:0": {"fetch": 272788.9, "write": 98304.0},
-        "f32:1:1:1:0:1": {"fetch": 271970.0, "write": 98304.0},
-        "f32:1:1:1:2:0": {"fetch": 284162.0, "write": 98304.0},
-        "f32:1:1:1:2:1": {"fetch": 283824.9, "write": 98304.0},
-        "bf16:1:0:1:1:0": {"fetch": 155539.8, "write": 49152.0},
-        "bf16:1:0:1:1:1": {"fetch": 131081.4, "write": 49152.0},
-        "bf16:1:0:1:0:0": {"fetch": 213345.2, "write": 49152.0},
-        "bf16:1:0:1:0:1": {"fetch": 185288.9, "write": 49152.0},
-        "bf16:1:0:1:2:0": {"fetch": 159753.9, "write": 49152.0},
-        "bf16:1:0:1:2:1": {"fetch": 139389.2, "write": 49152.0},
-        "bf16:1:1:1:1:0": {"fetch": 172059.6, "write": 49152.0},
-        "bf16:1:1:1:1:1": {"fetch": 129134.5, "write": 49152.0},
-        "bf16:1:1:1:0:0": {"fetch": 136048.8, "write": 49152.0},
-        "bf16:1:1:1:0:1": {"fetch": 136045.8, "write": 49152.0},
-        "bf16:1:1:1:2:0": {"fetch": 142120.5, "write": 49152.0},
-        "bf16:1:1:1:2:1": {"fetch": 137878.9, "write": 49152.0},
-        "f64:4:0:1:1:0": {"fetch": 2265737.1, "write": 786432.0},
-        "f64:4:0:1:1:1": {"fetch": 2591977.7, "write": 786432.2},
-        "f64:4:0:1:0:0": {"fetch": 2391897.6, "write": 786432.0},
-        "f64:4:0:1:0:1": {"fetch": 2797366.6, "write": 786433.1},
-        "f64:4:0:1:2:0": {"fetch": 1976976.1, "write": 786432.0},
-        "f64:4:0:1:2:1": {"fetch": 2113931.1, "write": 786432.1},
-        "f64:4:1:1:1:0": {"fetch": 1614850.2, "write": 786432.0},
-        "f64:4:1:1:1:1": {"fetch": 1673004.9, "write": 786432.0},
-        "f64:4:1:1:0:0": {"fetch": 1769895.7, "write": 786432.0},
-        "f64:4:1:1:0:1": {"fetch": 1795550.1, "write": 786432.0},
-        "f64:4:1:1:2:0": {"fetch": 1097199.8, "write": 786432.0},
-        "f64:4:1:1:2:1": {"fetch": 1127236.1, "write": 786432.0},
-        "f64:4:1:2:1:0": {"fetch": 1658172.0, "write": 786432.0},
-        "f64:4:1:2:1:1": {"fetch": 1714164.3, "write": 786432.0},
-        "f64:4:1:2:0:0": {"fetch": 1770484.1, "write": 786432.0},
-        "f64:4:1:2:0:1": {"fetch": 1823610.4, "write": 786432.0},
-        "f64:4:1:2:2:0": {"fetch": 1107465.7, "write": 786432.0},
-        "f64:4:1:2:2:1": {"fetch": 1201724.2, "write": 786432.0},
-        "f64:4:1:4:1:0": {"fetch": 1726463.4, "write": 786432.0},
-        "f64:4:1:4:1:1": {"fetch": 1641647.8, "write": 786432.0},
-        "f64:4:1:4:0:0": {"fetch": 1749168.0, "write": 786432.0},
-        "f64:4:1:4:0:1": {"fetch": 1639984.2, "write": 786432.0},
-        "f64:4:1:4:2:0": {"fetch": 1122142.0, "write": 786432.0},
-        "f64:4:1:4:2:1": {"fetch": 1096896.6, "write": 786432.0},
-        "f32:4:0:1:1:0": {"fetch": 1053165.2, "write": 393216.0},
-        "f32:4:0:1:1:1": {"fetch": 1202617.8, "write": 393225.2},
-        "f32:4:0:1:0:0": {"fetch": 1191908.6, "write": 393216.0},
-        "f32:4:0:1:0:1": {"fetch": 1385724.9, "write": 393231.4},
-        "f32:4:0:1:2:0": {"fetch": 861094.2, "write": 393216.0},
-        "f32:4:0:1:2:1": {"fetch": 926359.9, "write": 393217.4},
-        "f32:4:0:2:1:0": {"fetch": 822146.4, "write": 393216.0},
-        "f32:4:0:2:1:1": {"fetch": 817805.5, "write": 393216.0},
-        "f32:4:0:2:0:0": {"fetch": 1020546.3, "write": 393216.0},
-        "f32:4:0:2:0:1": {"fetch": 1019883.9, "write": 393216.2},
-        "f32:4:0:2:2:0": {"fetch": 575242.6, "write": 393216.0},
-        "f32:4:0:2:2:1": {"fetch": 559737.8, "write": 393216.0},
-        "f32:4:1:1:1:0": {"fetch": 788373.6, "write": 393216.0},
-        "f32:4:1:1:1:1": {"fetch": 796318.9, "write": 393216.0},
-        "f32:4:1:1:0:0": {"fetch": 701211.7, "write": 393216.0},
-        "f32:4:1:1:0:1": {"fetch": 529441.6, "write": 393216.0},
-        "f32:4:1:1:2:0": {"fetch": 546441.9, "write": 393216.0},
-        "f32:4:1:1:2:1": {"fetch": 551999.2, "write": 393216.0},
-        "f32:4:1:2:1:0": {"fetch": 794783.1, "write": 393216.0},
-        "f32:4:1:2:1:1": {"fetch": 790137.7, "write": 393216.0},
-        "f32:4:1:2:0:0": {"fetch": 662018.4, "write": 393216.0},
-        "f32:4:1:2:0:1": {"fetch": 519877.2, "write": 393216.0},
-        "f32:4:1:2:2:0": {"fetch": 548524.6, "write": 393216.0},
-        "f32:4:1:2:2:1": {"fetch": 546733.7, "write": 393216.0},
-        "f32:4:1:4:1:0": {"fetch": 794685.2, "write": 393216.0},
-        "f32:4:1:4:1:1": {"fetch": 790156.8, "write": 393216.0},
-        "f32:4:1:4:0:0": {"fetch": 661916.3, "write": 393216.0},
-        "f32:4:1:4:0:1": {"fetch": 519882.2, "write": 393216.0},
-        "f32:4:1:4:2:0": {"fetch": 548526.4, "write": 393216.0},
-        "f32:4:1:4:2:1": {"fetch": 546732.1, "write": 393216.0},
-        "bf16:4:0:1:1:0": {"fetch": 418178.1, "write": 196608.0},
-        "bf16:4:0:1:1:1": {"fetch": 476542.8, "write": 196608.0},
-        "bf16:4:0:1:0:0": {"fetch": 522971.2, "write": 196608.0},
-        "bf16:4:0:1:0:1": {"fetch": 563887.2, "write": 196608.0},
-        "bf16:4:0:1:2:0": {"fetch": 294347.1, "write": 196608.0},
-        "bf16:4:0:1:2:1": {"fetch": 346231.2, "write": 196608.0},
-        "bf16:4:0:2:1:0": {"fetch": 395519.4, "write": 196608.0},
-        "bf16:4:0:2:1:1": {"fetch": 395335.4, "write": 196608.0},
-        "bf16:4:0:2:0:0": {"fetch": 448932.5, "write": 196608.0},
-        "bf16:4:0:2:0:1": {"fetch": 419044.1, "write": 196608.0},
-        "bf16:4:0:2:2:0": {"fetch": 273550.0, "write": 196608.0},
-        "bf16:4:0:2:2:1": {"fetch": 273863.6, "write": 196608.0},
-        "bf16:4:1:1:1:0": {"fetch": 394155.9, "write": 196608.0},
-        "bf16:4:1:1:1:1": {"fetch": 401064.8, "write": 196608.0},
-        "bf16:4:1:1:0:0": {"fetch": 249374.5, "write": 196608.0},
-        "bf16:4:1:1:0:1": {"fetch": 253804.1, "write": 196608.0},
-        "bf16:4:1:1:2:0": {"fetch": 273292.2, "write": 196608.0},
-        "bf16:4:1:1:2:1": {"fetch": 280876.1, "write": 196608.0},
-        "bf16:4:1:2:1:0": {"fetch": 394310.9, "write": 196608.0},
-        "bf16:4:1:2:1:1": {"fetch": 394267.1, "write": 196608.0},
-        "bf16:4:1:2:0:0": {"fetch": 251090.4, "write": 196608.0},
-        "bf16:4:1:2:0:1": {"fetch": 249122.1, "write": 196608.0},
-        "bf16:4:1:2:2:0": {"fetch": 273430.8, "write": 196608.0},
-        "bf16:4:1:2:2:1": {"fetch": 273402.5, "write": 196608.0},
-        "bf16:4:1:4:1:0": {"fetch": 394313.3, "write": 196608.0},
-        "bf16:4:1:4:1:1": {"fetch": 394267.1, "write": 196608.0},
-        "bf16:4:1:4:0:0": {"fetch": 251085.8, "write": 196608.0},
-        "bf16:4:1:4:0:1": {"fetch": 249121.9, "write": 196608.0},
-        "bf16:4:1:4:2:0": {"fetch": 273430.4, "write": 196608.0},
-        "bf16:4:1:4:2:1": {"fetch": 273402.5, "write": 196608.0},
+        "f32:1:0:1:1:0": {"fetch": 370495.7, "write": 98304.0},
+        "f32:1:0:1:1:1": {"fetch": 302546.1, "write": 98304.0},
+        "f32:1:0:1:0:0": {"fetch": 487680.3, "write": 98304.0},
+        "f32:1:0:1:0:1": {"fetch": 420724.8, "write": 98304.0},
+        "f32:1:0:1:2:0": {"fetch": 396506.2, "write": 98304.0},
+        "f32:1:0:1:2:1": {"fetch": 308374.1, "write": 98304.0},
+        "f32:1:1:1:1:0": {"fetch": 344623.6, "write": 98304.0},
+        "f32:1:1:1:1:1": {"fetch": 343206.9, "write": 98304.0},
+        "f32:1:1:1:0:0": {"fetch": 272701.0, "write": 98304.0},
+        "f32:1:1:1:0:1": {"fetch": 271975.6, "write": 98304.0},
+        "f32:1:1:1:2:0": {"fetch": 284163.3, "write": 98304.0},
+        "f32:1:1:1:2:1": {"fetch": 283829.4, "write": 98304.0},
+        "bf16:1:0:1:1:0": {"fetch": 155509.3, "write": 49152.0},
+        "bf16:1:0:1:1:1": {"fetch": 131144.8, "write": 49152.0},
+        "bf16:1:0:1:0:0": {"fetch": 213253.1, "write": 49152.0},
+        "bf16:1:0:1:0:1": {"fetch": 185417.7, "write": 49152.0},
+        "bf16:1:0:1:2:0": {"fetch": 159557.2, "write": 49152.0},
+        "bf16:1:0:1:2:1": {"fetch": 139436.8, "write": 49152.0},
+        "bf16:1:1:1:1:0": {"fetch": 172064.8, "write": 49152.0},
+        "bf16:1:1:1:1:1": {"fetch": 129137.6, "write": 49152.0},
+        "bf16:1:1:1:0:0": {"fetch": 136051.7, "write": 49152.0},
+        "bf16:1:1:1:0:1": {"fetch": 136049.1, "write": 49152.0},
+        "bf16:1:1:1:2:0": {"fetch": 142125.3, "write": 49152.0},
+        "bf16:1:1:1:2:1": {"fetch": 137884.6, "write": 49152.0},
+        "f64:4:0:1:1:0": {"fetch": 2264326.8, "write": 786432.0},
+        "f64:4:0:1:1:1": {"fetch": 2592094.2, "write": 786432.1},
+        "f64:4:0:1:0:0": {"fetch": 2391678.1, "write": 786432.0},
+        "f64:4:0:1:0:1": {"fetch": 2794149.2, "write": 786433.2},
+        "f64:4:0:1:2:0": {"fetch": 1977590.2, "write": 786432.0},
+        "f64:4:0:1:2:1": {"fetch": 2115297.0, "write": 786432.1},
+        "f64:4:1:1:1:0": {"fetch": 1614727.5, "write": 786432.0},
+        "f64:4:1:1:1:1": {"fetch": 1674605.8, "write": 786432.0},
+        "f64:4:1:1:0:0": {"fetch": 1769885.2, "write": 786432.0},
+        "f64:4:1:1:0:1": {"fetch": 1796038.8, "write": 786432.0},
+        "f64:4:1:1:2:0": {"fetch": 1097212.1, "write": 786432.0},
+        "f64:4:1:1:2:1": {"fetch": 1127403.1, "write": 786432.0},
+        "f64:4:1:2:1:0": {"fetch": 1658395.8, "write": 786432.0},
+        "f64:4:1:2:1:1": {"fetch": 1713753.6, "write": 786432.0},
+        "f64:4:1:2:0:0": {"fetch": 1770475.2, "write": 786432.0},
+        "f64:4:1:2:0:1": {"fetch": 1824037.6, "write": 786432.0},
+        "f64:4:1:2:2:0": {"fetch": 1107475.6, "write": 786432.0},
+        "f64:4:1:2:2:1": {"fetch": 1201687.3, "write": 786432.0},
+        "f64:4:1:4:1:0": {"fetch": 1726279.4, "write": 786432.0},
+        "f64:4:1:4:1:1": {"fetch": 1642047.4, "write": 786432.0},
+        "f64:4:1:4:0:0": {"fetch": 1749222.6, "write": 786432.0},
+        "f64:4:1:4:0:1": {"fetch": 1640163.7, "write": 786432.0},
+        "f64:4:1:4:2:0": {"fetch": 1122227.5, "write": 786432.0},
+        "f64:4:1:4:2:1": {"fetch": 1096886.0, "write": 786432.0},
+        "f32:4:0:1:1:0": {"fetch": 1052272.4, "write": 393216.0},
+        "f32:4:0:1:1:1": {"fetch": 1200200.9, "write": 393216.1},
+        "f32:4:0:1:0:0": {"fetch": 1191458.8, "write": 393216.0},
+        "f32:4:0:1:0:1": {"fetch": 1384565.8, "write": 393216.8},
+        "f32:4:0:1:2:0": {"fetch": 860496.8, "write": 393216.0},
+        "f32:4:0:1:2:1": {"fetch": 928192.6, "write": 393216.2},
+        "f32:4:0:2:1:0": {"fetch": 822773.2, "write": 393216.0},
+        "f32:4:0:2:1:1": {"fetch": 818040.4, "write": 393220.2},
+        "f32:4:0:2:0:0": {"fetch": 1019663.6, "write": 393216.0},
+        "f32:4:0:2:0:1": {"fetch": 1021525.4, "write": 393221.1},
+        "f32:4:0:2:2:0": {"fetch": 575283.3, "write": 393216.0},
+        "f32:4:0:2:2:1": {"fetch": 559357.0, "write": 393218.9},
+        "f32:4:2:1:1:0": {"fetch": 892088.2, "write": 393216.0},
+        "f32:4:2:1:1:1": {"fetch": 824568.2, "write": 393226.4},
+        "f32:4:2:1:0:0": {"fetch": 721293.1, "write": 393216.0},
+        "f32:4:2:1:0:1": {"fetch": 618994.3, "write": 393232.8},
+        "f32:4:2:1:2:0": {"fetch": 672780.1, "write": 393216.0},
+        "f32:4:2:1:2:1": {"fetch": 578189.1, "write": 393219.1},
+        "f32:4:1:1:1:0": {"fetch": 788358.6, "write": 393216.0},
+        "f32:4:1:1:1:1": {"fetch": 796189.1, "write": 393216.0},
+        "f32:4:1:1:0:0": {"fetch": 701364.0, "write": 393216.0},
+        "f32:4:1:1:0:1": {"fetch": 529556.8, "write": 393216.0},
+        "f32:4:1:1:2:0": {"fetch": 546443.1, "write": 393216.0},
+        "f32:4:1:1:2:1": {"fetch": 552052.4, "write": 393216.0},
+        "f32:4:1:2:1:0": {"fetch": 794966.3, "write": 393216.0},
+        "f32:4:1:2:1:1": {"fetch": 790269.2, "write": 393216.0},
+        "f32:4:1:2:0:0": {"fetch": 662014.4, "write": 393216.0},
+        "f32:4:1:2:0:1": {"fetch": 519934.1, "write": 393216.0},
+        "f32:4:1:2:2:0": {"fetch": 548581.2, "write": 393216.0},
+        "f32:4:1:2:2:1": {"fetch": 546702.1, "write": 393216.0},
+        "f32:4:1:4:1:0": {"fetch": 794875.2, "write": 393216.0},
+        "f32:4:1:4:1:1": {"fetch": 790255.2, "write": 393216.0},
+        "f32:4:1:4:0:0": {"fetch": 661927.4, "write": 393216.0},
+        "f32:4:1:4:0:1": {"fetch": 519827.0, "write": 393216.0},
+        "f32:4:1:4:2:0": {"fetch": 548584.8, "write": 393216.0},
+        "f32:4:1:4:2:1": {"fetch": 546705.5, "write": 393216.0},
+        "bf16:4:0:1:1:0": {"fetch": 418194.2, "write": 196608.0},
+        "bf16:4:0:1:1:1": {"fetch": 477033.3, "write": 196608.0},
+        "bf16:4:0:1:0:0": {"fetch": 522985.8, "write": 196608.0},
+        "bf16:4:0:1:0:1": {"fetch": 564065.8, "write": 196608.0},
+        "bf16:4:0:1:2:0": {"fetch": 294265.6, "write": 196608.0},
+        "bf16:4:0:1:2:1": {"fetch": 346296.0, "write": 196608.0},
+        "bf16:4:0:2:1:0": {"fetch": 395524.1, "write": 196608.0},
+        "bf16:4:0:2:1:1": {"fetch": 395290.2, "write": 196608.0},
+        "bf16:4:0:2:0:0": {"fetch": 448955.8, "write": 196608.0},
+        "bf16:4:0:2:0:1": {"fetch": 419162.8, "write": 196608.0},
+        "bf16:4:0:2:2:0": {"fetch": 273563.6, "write": 196608.0},
+        "bf16:4:0:2:2:1": {"fetch": 273851.1, "write": 196608.0},
+        "bf16:4:2:1:1:0": {"fetch": 395515.6, "write": 196608.0},
+        "bf16:4:2:1:1:1": {"fetch": 394244.3, "write": 196608.0},
+        "bf16:4:2:1:0:0": {"fetch": 257979.8, "write": 196608.0},
+        "bf16:4:2:1:0:1": {"fetch": 249157.0, "write": 196608.0},
+        "bf16:4:2:1:2:0": {"fetch": 274074.0, "write": 196608.0},
+        "bf16:4:2:1:2:1": {"fetch": 273260.1, "write": 196608.0},
+        "bf16:4:1:1:1:0": {"fetch": 394149.1, "write": 196608.0},
+        "bf16:4:1:1:1:1": {"fetch": 401083.7, "write": 196608.0},
+        "bf16:4:1:1:0:0": {"fetch": 249367.7, "write": 196608.0},
+        "bf16:4:1:1:0:1": {"fetch": 253801.4, "write": 196608.0},
+        "bf16:4:1:1:2:0": {"fetch": 273285.2, "write": 196608.0},
+        "bf16:4:1:1:2:1": {"fetch": 280872.8, "write": 196608.0},
+        "bf16:4:1:2:1:0": {"fetch": 394307.6, "write": 196608.0},
+        "bf16:4:1:2:1:1": {"fetch": 394270.8, "write": 196608.0},
+        "bf16:4:1:2:0:0": {"fetch": 251114.1, "write": 196608.0},
+        "bf16:4:1:2:0:1": {"fetch": 249124.9, "write": 196608.0},
+        "bf16:4:1:2:2:0": {"fetch": 273429.6, "write": 196608.0},
+        "bf16:4:1:2:2:1": {"fetch": 273405.7, "write": 196608.0},
+        "bf16:4:1:4:1:0": {"fetch": 394310.6, "write": 196608.0},
+        "bf16:4:1:4:1:1": {"fetch": 394270.8, "write": 196608.0},
+        "bf16:4:1:4:0:0": {"fetch": 251092.2, "write": 196608.0},
+        "bf16:4:1:4:0:1": {"fetch": 249125.2, "write": 196608.0},
+        "bf16:4:1:4:2:0": {"fetch": 273430.5, "write": 196608.0},
+        "bf16:4:1:4:2:1": {"fetch": 273405.8, "write": 196608.0},
     },
 }
 
@@ -562,12 +574,13 @@ KERNELS_ONLY_CONFIGS = [(v, x, st) for v in (0, 1) for x in (1, 0, 2) for st in 
 def kernels_only_configs(prec: str, nrhs: int):
     """(variant, npass, order, stream) tried per precision by --kernels-only: one rhs
     takes KERNELS_ONLY_CONFIGS; several rhs take every candidate the autotuner times
-    for their class (site npass 1 and, for FP32 / BF16, 2; direction-parallel npass 1,
-    2, 4), each per (order, stream).  Configurations the lattice does not allow (the
-    z-blocked order 2) are skipped at launch time and left out of the logged list."""
+    for their class (site npass 1 and, for FP32 / BF16, 2 and the shared-link variant;
+    direction-parallel npass 1, 2, 4), each per (order, stream).  Configurations the
+    lattice does not allow (the z-blocked order 2) are skipped at launch time and left
+    out of the logged list."""
     if nrhs == 1:
         return [(v, 1, x, st) for v, x, st in KERNELS_ONLY_CONFIGS]
-    cands = [(0, 1)] + ([(0, 2)] if prec != "f64" else []) + [(1, 1), (1, 2), (1, 4)]
+    cands = [(0, 1)] + ([(0, 2), (2, 1)] if prec != "f64" else []) + [(1, 1), (1, 2), (1, 4)]
     return [(v, n, x, st) for v, n in cands for x in (1, 0, 2) for st in (0, 1)]
 
 
