@@ -574,13 +574,13 @@ KERNELS_ONLY_CONFIGS = [(v, x, st) for v in (0, 1) for x in (1, 0, 2) for st in 
 def kernels_only_configs(prec: str, nrhs: int):
     """(variant, npass, order, stream) tried per precision by --kernels-only: one rhs
     takes KERNELS_ONLY_CONFIGS; several rhs take every candidate the autotuner times
-    for their class (site npass 1 and, for FP32 / BF16, 2 and the shared-link variant;
+    for their class (site npass 1 and, for FP32 / BF16, 2; the shared-link variant;
     direction-parallel npass 1, 2, 4), each per (order, stream).  Configurations the
     lattice does not allow (the z-blocked order 2) are skipped at launch time and left
     out of the logged list."""
     if nrhs == 1:
         return [(v, 1, x, st) for v, x, st in KERNELS_ONLY_CONFIGS]
-    cands = [(0, 1)] + ([(0, 2), (2, 1)] if prec != "f64" else []) + [(1, 1), (1, 2), (1, 4)]
+    cands = [(0, 1)] + ([(0, 2)] if prec != "f64" else []) + [(2, 1), (1, 1), (1, 2), (1, 4)]
     return [(v, n, x, st) for v, n in cands for x in (1, 0, 2) for st in (0, 1)]
 
 

@@ -381,8 +381,8 @@ int wl_solve_log_read(const wl_lattice* lat, int max, int* n, long long* iters, 
  *            2 = one thread per output site with the links shared: a
  *                workgroup takes one 64-site tile for four rhs (one
  *                wavefront each), reads the tile's 8 x 64 links once into
- *                LDS and gives variant 0's results bit for bit (FP32 and BF16
- *                from 4 rhs on; otherwise variant 0 runs);
+ *                LDS and gives variant 0's results bit for bit (from 4 rhs
+ *                on; with fewer, variant 0 runs);
  *   npass    direction-parallel: up to npass (1, 2, 4) passes of 1 (FP64) or
  *            2 (FP32, BF16, even rhs counts) rhs reuse each link held in
  *            registers; site: 2 = two rhs per thread (FP32, BF16, even rhs
@@ -407,8 +407,8 @@ int wl_solve_log_read(const wl_lattice* lat, int max, int* n, long long* iters, 
  * be NULL).
  * wl_autotune times on this lattice, for every precision, class 0 at 1 rhs
  * over {site, direction-parallel}, classes 1 and 2 at 4 and 8 rhs over
- * {site npass 1, 2; site with shared links (FP32, BF16); direction-parallel
- * npass 1, 2, 4}, each candidate with
+ * {site npass 1, 2; site with shared links; direction-parallel npass 1, 2,
+ * 4}, each candidate with
  * (stream, use_xcd) = (0, 1), (0, 0), (0, 2), (1, 1), (1, 0), (1, 2), as
  * bursts in which each launch reads the previous launch's output (best of 3
  * bursts of 20), and keeps the fastest of every class.  stream = 1 is a

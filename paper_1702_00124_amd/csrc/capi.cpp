@@ -652,7 +652,7 @@ int wl_autotune(wl_lattice* L, double* us_out) {
     for (int p = 0; p < 3; ++p) {
       for (int k = 0; k < kHopKinds; ++k) {
         // one rhs: site and direction-parallel; several: site with 1 or 2 rhs
-        // per thread, site with the links shared in LDS (FP32, BF16) and
+        // per thread, site with the links shared in LDS and
         // direction-parallel with 1, 2 or 4 passes; each in every workgroup
         // order, cached then streaming
         // streaming access only where the hop's working set (links and two
@@ -675,8 +675,7 @@ int wl_autotune(wl_lattice* L, double* us_out) {
         double best = 1e30;
         HopConfig keep = L->hop_cfg[p][k];
         for (const HopConfig& c : cand) {
-          if (c.stream > max_stream || (c.use_xcd == 2 && !zblock_ok(L->geo)) ||
-              (c.variant == kHopSiteShared && p == F64)) {  // not here
+          if (c.stream > max_stream || (c.use_xcd == 2 && !zblock_ok(L->geo))) {  // not here
             if (us_out) us_out[slot] = 0.0;
             ++slot;
             continue;

@@ -255,16 +255,16 @@ __device__ __forceinline__ void bf16_project_mul(const Bf16Link& L, const uint32
 // The shared-link variant of the thread-per-site kernel gives a workgroup one
 // 64-site tile and four rhs, one per wavefront.  Wavefront w reads the tile's
 // two links of direction w (forward at the site, backward at its neighbour)
-// once, in the form the products take (BF16: the product pairs with the
-// rebuilt third row; FP32: the SU(3) matrix with its third row), and puts them
-// in LDS; after one barrier every wavefront takes all 8 from there.  BF16
-// keeps the product pairs (18 words per link: the pair forms and the third
-// row are built once per tile instead of once per rhs); FP32 keeps the two
-// stored rows (12 words) and rebuilds the third row per rhs in the same
-// expression as the thread-per-site kernel.  The arithmetic is that kernel's,
-// bit for bit.
+// once and puts them in LDS; after one barrier every wavefront takes all 8
+// from there.  BF16 keeps the product pairs (18 words per link: the pair forms
+// and the third row are built once per tile instead of once per rhs); FP32 and
+// FP64 keep the two stored rows (12 and 24 words) and rebuild the third row per
+// rhs in the same expression as the thread-per-site kernel.  The arithmetic is
+// that kernel's, bit for bit.
 template <typename P>
-constexpr int shl_words() { return std::is_same<P, PrecBF16>::value ? 18 : 12; }
+constexpr int shl_words() {
+  return std::is_same<P, PrecBF16>::value ? 18 : (std::is_same<P, PrecF32>::value ? 12 : 24);
+}
 __device__ __forceinline__ void shl_put(uint32_t* S, int d, const Bf16Link& U, int lane) {
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
@@ -291,6 +291,22 @@ __device__ __forceinline__ void shl_get(const uint32_t* S, int d, SU3<float>* U,
   for (int k = 0; k < 6; ++k)
     U->m[k] = {__builtin_bit_cast(float, S[(d * 12 + 2 * k) * 64 + lane]),
                __builtin_bit_cast(float, S[(d * 12 + 2 * k + 1) * 64 + lane])};
+  third_row(*U);
+}
+__device__ __forceinline__ void shl_put(uint32_t* S, int d, const SU3<double>& U, int lane) {
+  uint2* S2 = reinterpret_cast<uint2*>(S);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    S2[(d * 12 + 2 * k) * 64 + lane] = __builtin_bit_cast(uint2, U.m[k].r);
+    S2[(d * 12 + 2 * k + 1) * 64 + lane] = __builtin_bit_cast(uint2, U.m[k].i);
+  }
+}
+__device__ __forceinline__ void shl_get(const uint32_t* S, int d, SU3<double>* U, int lane) {
+  const uint2* S2 = reinterpret_cast<const uint2*>(S);
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    U->m[k] = {__builtin_bit_cast(double, S2[(d * 12 + 2 * k) * 64 + lane]),
+               __builtin_bit_cast(double, S2[(d * 12 + 2 * k + 1) * 64 + lane])};
   third_row(*U);
 }
 // the two links of direction MU into LDS (directions 2 MU forward, 2 MU + 1 backward)
@@ -447,12 +463,11 @@ __device__ __forceinline__ uint32_t* shl_lds() {
   return S;
 }
 
-// SHL: the shared-link variant (one 64-site tile for four rhs per workgroup,
-// NR = 1, FP32 or BF16)
+// SHL: the shared-link variant (one 64-site tile for four rhs per workgroup, NR = 1)
 template <typename P, int DAG, int NR, bool ST, bool CHEB = false, bool SHL = false>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a) {
   using R = typename P::real;
-  static_assert(!SHL || (NR == 1 && !CHEB && sizeof(R) == 4 && kBlock == 4 * 64), "shared links: 4 x 1 rhs");
+  static_assert(!SHL || (NR == 1 && !CHEB && kBlock == 4 * 64), "shared links: 4 x 1 rhs");
   int tile, row;
   if constexpr (SHL) {
     if (!hop_block_coords<kSiteTile>(a, &tile, &row)) return;
@@ -789,14 +804,12 @@ static void dispatch_nr(HopArgs a, int nrhs, hipStream_t st, const HopConfig& c)
   // rhs per LDS pass (direction-parallel) or per thread (site): two for FP32
   // and BF16 with an even rhs count when the configuration allows, else one
   constexpr bool narrow = sizeof(typename P::real) == 4;
-  if constexpr (narrow) {
-    // shared links from four rhs on; below that the plain thread-per-site kernel
-    if (c.variant == kHopSiteShared && nrhs >= 4) {
-      a.rows = (nrhs + 3) / 4;
-      hipLaunchKernelGGL((hop_kernel<P, DAG, 1, ST, false, true>), dim3(hop_grid<kSiteTile>(a)), dim3(kBlock), 0, st,
-                         a);
-      return;
-    }
+  // shared links from four rhs on; below that the plain thread-per-site kernel
+  if (c.variant == kHopSiteShared && nrhs >= 4) {
+    a.rows = (nrhs + 3) / 4;
+    hipLaunchKernelGGL((hop_kernel<P, DAG, 1, ST, false, true>), dim3(hop_grid<kSiteTile>(a)), dim3(kBlock), 0, st,
+                       a);
+    return;
   }
   const bool two = narrow && nrhs % 2 == 0 && (c.variant == kHopDirParallel || c.npass >= 2);
   if (c.variant == kHopDirParallel) {
