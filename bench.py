@@ -74,140 +74,146 @@ def hop_gflops(nrhs: int, sites: int, us: float) -> float:
 # sources); otherwise `traffic` is reported as null.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_COUNTERS = {
-    "source_sha256": "9d8cd59c7750761353bd238eaaba6e4b1405de5f8c88e4e804750b0de0999c49",
+    "source_sha256": "020ab83e22a2f4fb050eec0298e575ec73fedfae51b1aa1a89404ab967f64936",
     "per_launch_kib": {
-        "f64:1:0:1:1:0": {"fetch": 913496.9, "write": 196608.0},
-        "f64:1:0:1:1:1": {"fetch": 743393.4, "write": 196608.0},
-        "f64:1:0:1:0:0": {"fetch": 1014398.6, "write": 196608.0},
-        "f64:1:0:1:0:1": {"fetch": 884247.0, "write": 196608.0},
-        "f64:1:0:1:2:0": {"fetch": 865780.2, "write": 196608.0},
-        "f64:1:0:1:2:1": {"fetch": 670386.8, "write": 196608.0},
-        "f64:1:1:1:1:0": {"fetch": 689175.4, "write": 196608.0},
-        "f64:1:1:1:1:1": {"fetch": 689032.5, "write": 196608.0},
-        "f64:1:1:1:0:0": {"fetch": 556634.2, "write": 196608.0},
-        "f64:1:1:1:0:1": {"fetch": 543893.7, "write": 196608.0},
-        "f64:1:1:1:2:0": {"fetch": 568275.3, "write": 196608.0},
-        "f64:1:1:1:2:1": {"fetch": 568168.1, "write": 196608.0},
-        "f32:1:0:1:1:0": {"fetch": 370495.7, "write": 98304.0},
-        "f32:1:0:1:1:1": {"fetch": 302546.1, "write": 98304.0},
-        "f32:1:0:1:0:0": {"fetch": 487680.3, "write": 98304.0},
-        "f32:1:0:1:0:1": {"fetch": 420724.8, "write": 98304.0},
-        "f32:1:0:1:2:0": {"fetch": 396506.2, "write": 98304.0},
-        "f32:1:0:1:2:1": {"fetch": 308374.1, "write": 98304.0},
-        "f32:1:1:1:1:0": {"fetch": 344623.6, "write": 98304.0},
-        "f32:1:1:1:1:1": {"fetch": 343206.9, "write": 98304.0},
-        "f32:1:1:1:0:0": {"fetch": 272701.0, "write": 98304.0},
+        "f64:1:0:1:1:0": {"fetch": 913372.1, "write": 196608.0},
+        "f64:1:0:1:1:1": {"fetch": 743656.6, "write": 196608.0},
+        "f64:1:0:1:0:0": {"fetch": 1013915.1, "write": 196608.0},
+        "f64:1:0:1:0:1": {"fetch": 884293.2, "write": 196608.0},
+        "f64:1:0:1:2:0": {"fetch": 865683.6, "write": 196608.0},
+        "f64:1:0:1:2:1": {"fetch": 666852.8, "write": 196608.1},
+        "f64:1:1:1:1:0": {"fetch": 689258.0, "write": 196608.0},
+        "f64:1:1:1:1:1": {"fetch": 689024.5, "write": 196608.0},
+        "f64:1:1:1:0:0": {"fetch": 558112.7, "write": 196608.0},
+        "f64:1:1:1:0:1": {"fetch": 543882.1, "write": 196608.0},
+        "f64:1:1:1:2:0": {"fetch": 568340.9, "write": 196608.0},
+        "f64:1:1:1:2:1": {"fetch": 568160.1, "write": 196608.0},
+        "f32:1:0:1:1:0": {"fetch": 370523.9, "write": 98304.0},
+        "f32:1:0:1:1:1": {"fetch": 302568.7, "write": 98304.0},
+        "f32:1:0:1:0:0": {"fetch": 488438.3, "write": 98304.0},
+        "f32:1:0:1:0:1": {"fetch": 420652.5, "write": 98304.0},
+        "f32:1:0:1:2:0": {"fetch": 397076.6, "write": 98304.0},
+        "f32:1:0:1:2:1": {"fetch": 308405.8, "write": 98304.0},
+        "f32:1:1:1:1:0": {"fetch": 344628.9, "write": 98304.0},
+        "f32:1:1:1:1:1": {"fetch": 343270.7, "write": 98304.0},
+        "f32:1:1:1:0:0": {"fetch": 272795.6, "write": 98304.0},
         "f32:1:1:1:0:1": {"fetch": 271975.6, "write": 98304.0},
-        "f32:1:1:1:2:0": {"fetch": 284163.3, "write": 98304.0},
-        "f32:1:1:1:2:1": {"fetch": 283829.4, "write": 98304.0},
-        "bf16:1:0:1:1:0": {"fetch": 155509.3, "write": 49152.0},
-        "bf16:1:0:1:1:1": {"fetch": 131144.8, "write": 49152.0},
-        "bf16:1:0:1:0:0": {"fetch": 213253.1, "write": 49152.0},
-        "bf16:1:0:1:0:1": {"fetch": 185417.7, "write": 49152.0},
-        "bf16:1:0:1:2:0": {"fetch": 159557.2, "write": 49152.0},
-        "bf16:1:0:1:2:1": {"fetch": 139436.8, "write": 49152.0},
-        "bf16:1:1:1:1:0": {"fetch": 172064.8, "write": 49152.0},
-        "bf16:1:1:1:1:1": {"fetch": 129137.6, "write": 49152.0},
-        "bf16:1:1:1:0:0": {"fetch": 136051.7, "write": 49152.0},
-        "bf16:1:1:1:0:1": {"fetch": 136049.1, "write": 49152.0},
-        "bf16:1:1:1:2:0": {"fetch": 142125.3, "write": 49152.0},
-        "bf16:1:1:1:2:1": {"fetch": 137884.6, "write": 49152.0},
-        "f64:4:0:1:1:0": {"fetch": 2264326.8, "write": 786432.0},
-        "f64:4:0:1:1:1": {"fetch": 2592094.2, "write": 786432.1},
-        "f64:4:0:1:0:0": {"fetch": 2391678.1, "write": 786432.0},
-        "f64:4:0:1:0:1": {"fetch": 2794149.2, "write": 786433.2},
-        "f64:4:0:1:2:0": {"fetch": 1977590.2, "write": 786432.0},
-        "f64:4:0:1:2:1": {"fetch": 2115297.0, "write": 786432.1},
-        "f64:4:1:1:1:0": {"fetch": 1614727.5, "write": 786432.0},
-        "f64:4:1:1:1:1": {"fetch": 1674605.8, "write": 786432.0},
-        "f64:4:1:1:0:0": {"fetch": 1769885.2, "write": 786432.0},
-        "f64:4:1:1:0:1": {"fetch": 1796038.8, "write": 786432.0},
-        "f64:4:1:1:2:0": {"fetch": 1097212.1, "write": 786432.0},
-        "f64:4:1:1:2:1": {"fetch": 1127403.1, "write": 786432.0},
-        "f64:4:1:2:1:0": {"fetch": 1658395.8, "write": 786432.0},
-        "f64:4:1:2:1:1": {"fetch": 1713753.6, "write": 786432.0},
-        "f64:4:1:2:0:0": {"fetch": 1770475.2, "write": 786432.0},
-        "f64:4:1:2:0:1": {"fetch": 1824037.6, "write": 786432.0},
-        "f64:4:1:2:2:0": {"fetch": 1107475.6, "write": 786432.0},
-        "f64:4:1:2:2:1": {"fetch": 1201687.3, "write": 786432.0},
-        "f64:4:1:4:1:0": {"fetch": 1726279.4, "write": 786432.0},
-        "f64:4:1:4:1:1": {"fetch": 1642047.4, "write": 786432.0},
-        "f64:4:1:4:0:0": {"fetch": 1749222.6, "write": 786432.0},
-        "f64:4:1:4:0:1": {"fetch": 1640163.7, "write": 786432.0},
-        "f64:4:1:4:2:0": {"fetch": 1122227.5, "write": 786432.0},
-        "f64:4:1:4:2:1": {"fetch": 1096886.0, "write": 786432.0},
-        "f32:4:0:1:1:0": {"fetch": 1052272.4, "write": 393216.0},
-        "f32:4:0:1:1:1": {"fetch": 1200200.9, "write": 393216.1},
-        "f32:4:0:1:0:0": {"fetch": 1191458.8, "write": 393216.0},
-        "f32:4:0:1:0:1": {"fetch": 1384565.8, "write": 393216.8},
-        "f32:4:0:1:2:0": {"fetch": 860496.8, "write": 393216.0},
-        "f32:4:0:1:2:1": {"fetch": 928192.6, "write": 393216.2},
-        "f32:4:0:2:1:0": {"fetch": 822773.2, "write": 393216.0},
-        "f32:4:0:2:1:1": {"fetch": 818040.4, "write": 393220.2},
-        "f32:4:0:2:0:0": {"fetch": 1019663.6, "write": 393216.0},
-        "f32:4:0:2:0:1": {"fetch": 1021525.4, "write": 393221.1},
-        "f32:4:0:2:2:0": {"fetch": 575283.3, "write": 393216.0},
-        "f32:4:0:2:2:1": {"fetch": 559357.0, "write": 393218.9},
-        "f32:4:2:1:1:0": {"fetch": 892088.2, "write": 393216.0},
-        "f32:4:2:1:1:1": {"fetch": 824568.2, "write": 393226.4},
-        "f32:4:2:1:0:0": {"fetch": 721293.1, "write": 393216.0},
-        "f32:4:2:1:0:1": {"fetch": 618994.3, "write": 393232.8},
-        "f32:4:2:1:2:0": {"fetch": 672780.1, "write": 393216.0},
-        "f32:4:2:1:2:1": {"fetch": 578189.1, "write": 393219.1},
-        "f32:4:1:1:1:0": {"fetch": 788358.6, "write": 393216.0},
-        "f32:4:1:1:1:1": {"fetch": 796189.1, "write": 393216.0},
-        "f32:4:1:1:0:0": {"fetch": 701364.0, "write": 393216.0},
-        "f32:4:1:1:0:1": {"fetch": 529556.8, "write": 393216.0},
-        "f32:4:1:1:2:0": {"fetch": 546443.1, "write": 393216.0},
-        "f32:4:1:1:2:1": {"fetch": 552052.4, "write": 393216.0},
-        "f32:4:1:2:1:0": {"fetch": 794966.3, "write": 393216.0},
-        "f32:4:1:2:1:1": {"fetch": 790269.2, "write": 393216.0},
-        "f32:4:1:2:0:0": {"fetch": 662014.4, "write": 393216.0},
-        "f32:4:1:2:0:1": {"fetch": 519934.1, "write": 393216.0},
-        "f32:4:1:2:2:0": {"fetch": 548581.2, "write": 393216.0},
-        "f32:4:1:2:2:1": {"fetch": 546702.1, "write": 393216.0},
-        "f32:4:1:4:1:0": {"fetch": 794875.2, "write": 393216.0},
-        "f32:4:1:4:1:1": {"fetch": 790255.2, "write": 393216.0},
-        "f32:4:1:4:0:0": {"fetch": 661927.4, "write": 393216.0},
-        "f32:4:1:4:0:1": {"fetch": 519827.0, "write": 393216.0},
-        "f32:4:1:4:2:0": {"fetch": 548584.8, "write": 393216.0},
-        "f32:4:1:4:2:1": {"fetch": 546705.5, "write": 393216.0},
-        "bf16:4:0:1:1:0": {"fetch": 418194.2, "write": 196608.0},
-        "bf16:4:0:1:1:1": {"fetch": 477033.3, "write": 196608.0},
-        "bf16:4:0:1:0:0": {"fetch": 522985.8, "write": 196608.0},
-        "bf16:4:0:1:0:1": {"fetch": 564065.8, "write": 196608.0},
-        "bf16:4:0:1:2:0": {"fetch": 294265.6, "write": 196608.0},
-        "bf16:4:0:1:2:1": {"fetch": 346296.0, "write": 196608.0},
-        "bf16:4:0:2:1:0": {"fetch": 395524.1, "write": 196608.0},
-        "bf16:4:0:2:1:1": {"fetch": 395290.2, "write": 196608.0},
-        "bf16:4:0:2:0:0": {"fetch": 448955.8, "write": 196608.0},
-        "bf16:4:0:2:0:1": {"fetch": 419162.8, "write": 196608.0},
-        "bf16:4:0:2:2:0": {"fetch": 273563.6, "write": 196608.0},
-        "bf16:4:0:2:2:1": {"fetch": 273851.1, "write": 196608.0},
-        "bf16:4:2:1:1:0": {"fetch": 395515.6, "write": 196608.0},
-        "bf16:4:2:1:1:1": {"fetch": 394244.3, "write": 196608.0},
-        "bf16:4:2:1:0:0": {"fetch": 257979.8, "write": 196608.0},
-        "bf16:4:2:1:0:1": {"fetch": 249157.0, "write": 196608.0},
-        "bf16:4:2:1:2:0": {"fetch": 274074.0, "write": 196608.0},
-        "bf16:4:2:1:2:1": {"fetch": 273260.1, "write": 196608.0},
-        "bf16:4:1:1:1:0": {"fetch": 394149.1, "write": 196608.0},
-        "bf16:4:1:1:1:1": {"fetch": 401083.7, "write": 196608.0},
-        "bf16:4:1:1:0:0": {"fetch": 249367.7, "write": 196608.0},
-        "bf16:4:1:1:0:1": {"fetch": 253801.4, "write": 196608.0},
-        "bf16:4:1:1:2:0": {"fetch": 273285.2, "write": 196608.0},
-        "bf16:4:1:1:2:1": {"fetch": 280872.8, "write": 196608.0},
-        "bf16:4:1:2:1:0": {"fetch": 394307.6, "write": 196608.0},
-        "bf16:4:1:2:1:1": {"fetch": 394270.8, "write": 196608.0},
-        "bf16:4:1:2:0:0": {"fetch": 251114.1, "write": 196608.0},
-        "bf16:4:1:2:0:1": {"fetch": 249124.9, "write": 196608.0},
-        "bf16:4:1:2:2:0": {"fetch": 273429.6, "write": 196608.0},
-        "bf16:4:1:2:2:1": {"fetch": 273405.7, "write": 196608.0},
-        "bf16:4:1:4:1:0": {"fetch": 394310.6, "write": 196608.0},
-        "bf16:4:1:4:1:1": {"fetch": 394270.8, "write": 196608.0},
-        "bf16:4:1:4:0:0": {"fetch": 251092.2, "write": 196608.0},
-        "bf16:4:1:4:0:1": {"fetch": 249125.2, "write": 196608.0},
-        "bf16:4:1:4:2:0": {"fetch": 273430.5, "write": 196608.0},
-        "bf16:4:1:4:2:1": {"fetch": 273405.8, "write": 196608.0},
+        "f32:1:1:1:2:0": {"fetch": 284168.9, "write": 98304.0},
+        "f32:1:1:1:2:1": {"fetch": 283838.4, "write": 98304.0},
+        "bf16:1:0:1:1:0": {"fetch": 155777.4, "write": 49152.0},
+        "bf16:1:0:1:1:1": {"fetch": 130997.4, "write": 49152.0},
+        "bf16:1:0:1:0:0": {"fetch": 213380.7, "write": 49152.0},
+        "bf16:1:0:1:0:1": {"fetch": 185177.5, "write": 49152.0},
+        "bf16:1:0:1:2:0": {"fetch": 159906.9, "write": 49152.0},
+        "bf16:1:0:1:2:1": {"fetch": 139479.9, "write": 49152.0},
+        "bf16:1:1:1:1:0": {"fetch": 172097.1, "write": 49152.0},
+        "bf16:1:1:1:1:1": {"fetch": 129134.5, "write": 49152.0},
+        "bf16:1:1:1:0:0": {"fetch": 136049.6, "write": 49152.0},
+        "bf16:1:1:1:0:1": {"fetch": 136045.9, "write": 49152.0},
+        "bf16:1:1:1:2:0": {"fetch": 142120.9, "write": 49152.0},
+        "bf16:1:1:1:2:1": {"fetch": 137871.6, "write": 49152.0},
+        "f64:4:0:1:1:0": {"fetch": 2273252.6, "write": 786432.0},
+        "f64:4:0:1:1:1": {"fetch": 2593923.6, "write": 786432.4},
+        "f64:4:0:1:0:0": {"fetch": 2365943.1, "write": 786432.0},
+        "f64:4:0:1:0:1": {"fetch": 2774799.3, "write": 786432.6},
+        "f64:4:0:1:2:0": {"fetch": 1981426.0, "write": 786432.0},
+        "f64:4:0:1:2:1": {"fetch": 2126924.5, "write": 786432.1},
+        "f64:4:2:1:1:0": {"fetch": 2163663.7, "write": 786432.0},
+        "f64:4:2:1:1:1": {"fetch": 1907578.9, "write": 786432.0},
+        "f64:4:2:1:0:0": {"fetch": 1795463.8, "write": 786432.0},
+        "f64:4:2:1:0:1": {"fetch": 1554311.6, "write": 786448.9},
+        "f64:4:2:1:2:0": {"fetch": 1762488.3, "write": 786432.0},
+        "f64:4:2:1:2:1": {"fetch": 1479636.9, "write": 786433.6},
+        "f64:4:1:1:1:0": {"fetch": 1646268.8, "write": 786432.0},
+        "f64:4:1:1:1:1": {"fetch": 1680382.2, "write": 786432.0},
+        "f64:4:1:1:0:0": {"fetch": 1769915.8, "write": 786432.0},
+        "f64:4:1:1:0:1": {"fetch": 1797591.3, "write": 786432.0},
+        "f64:4:1:1:2:0": {"fetch": 1097274.4, "write": 786432.0},
+        "f64:4:1:1:2:1": {"fetch": 1129301.6, "write": 786432.0},
+        "f64:4:1:2:1:0": {"fetch": 1707053.6, "write": 786432.0},
+        "f64:4:1:2:1:1": {"fetch": 1746764.3, "write": 786432.0},
+        "f64:4:1:2:0:0": {"fetch": 1770432.6, "write": 786432.0},
+        "f64:4:1:2:0:1": {"fetch": 1825445.8, "write": 786432.0},
+        "f64:4:1:2:2:0": {"fetch": 1107971.9, "write": 786432.0},
+        "f64:4:1:2:2:1": {"fetch": 1201825.8, "write": 786432.0},
+        "f64:4:1:4:1:0": {"fetch": 1677550.3, "write": 786432.0},
+        "f64:4:1:4:1:1": {"fetch": 1602567.6, "write": 786432.0},
+        "f64:4:1:4:0:0": {"fetch": 1747988.6, "write": 786432.0},
+        "f64:4:1:4:0:1": {"fetch": 1640666.4, "write": 786432.0},
+        "f64:4:1:4:2:0": {"fetch": 1121640.4, "write": 786432.0},
+        "f64:4:1:4:2:1": {"fetch": 1096994.2, "write": 786432.0},
+        "f32:4:0:1:1:0": {"fetch": 1053029.8, "write": 393216.0},
+        "f32:4:0:1:1:1": {"fetch": 1199016.6, "write": 393216.4},
+        "f32:4:0:1:0:0": {"fetch": 1191468.8, "write": 393216.0},
+        "f32:4:0:1:0:1": {"fetch": 1384588.9, "write": 393216.1},
+        "f32:4:0:1:2:0": {"fetch": 860712.1, "write": 393216.0},
+        "f32:4:0:1:2:1": {"fetch": 928742.1, "write": 393216.0},
+        "f32:4:0:2:1:0": {"fetch": 822678.2, "write": 393216.0},
+        "f32:4:0:2:1:1": {"fetch": 819559.1, "write": 393217.0},
+        "f32:4:0:2:0:0": {"fetch": 1020684.9, "write": 393216.0},
+        "f32:4:0:2:0:1": {"fetch": 1020875.5, "write": 393216.1},
+        "f32:4:0:2:2:0": {"fetch": 575490.4, "write": 393216.0},
+        "f32:4:0:2:2:1": {"fetch": 560010.5, "write": 393216.4},
+        "f32:4:2:1:1:0": {"fetch": 892158.9, "write": 393216.0},
+        "f32:4:2:1:1:1": {"fetch": 824101.5, "write": 393223.4},
+        "f32:4:2:1:0:0": {"fetch": 723430.1, "write": 393216.0},
+        "f32:4:2:1:0:1": {"fetch": 618456.1, "write": 393241.6},
+        "f32:4:2:1:2:0": {"fetch": 668025.6, "write": 393216.0},
+        "f32:4:2:1:2:1": {"fetch": 577034.2, "write": 393220.6},
+        "f32:4:1:1:1:0": {"fetch": 788359.6, "write": 393216.0},
+        "f32:4:1:1:1:1": {"fetch": 796232.0, "write": 393216.0},
+        "f32:4:1:1:0:0": {"fetch": 700233.4, "write": 393216.0},
+        "f32:4:1:1:0:1": {"fetch": 529257.7, "write": 393216.0},
+        "f32:4:1:1:2:0": {"fetch": 546438.1, "write": 393216.0},
+        "f32:4:1:1:2:1": {"fetch": 551994.8, "write": 393216.0},
+        "f32:4:1:2:1:0": {"fetch": 795120.6, "write": 393216.0},
+        "f32:4:1:2:1:1": {"fetch": 790151.1, "write": 393216.0},
+        "f32:4:1:2:0:0": {"fetch": 658662.1, "write": 393216.0},
+        "f32:4:1:2:0:1": {"fetch": 519677.8, "write": 393216.0},
+        "f32:4:1:2:2:0": {"fetch": 548576.9, "write": 393216.0},
+        "f32:4:1:2:2:1": {"fetch": 546720.6, "write": 393216.0},
+        "f32:4:1:4:1:0": {"fetch": 795108.7, "write": 393216.0},
+        "f32:4:1:4:1:1": {"fetch": 790079.9, "write": 393216.0},
+        "f32:4:1:4:0:0": {"fetch": 658625.8, "write": 393216.0},
+        "f32:4:1:4:0:1": {"fetch": 519741.9, "write": 393216.0},
+        "f32:4:1:4:2:0": {"fetch": 548563.2, "write": 393216.0},
+        "f32:4:1:4:2:1": {"fetch": 546724.4, "write": 393216.0},
+        "bf16:4:0:1:1:0": {"fetch": 418079.3, "write": 196608.0},
+        "bf16:4:0:1:1:1": {"fetch": 478029.1, "write": 196608.0},
+        "bf16:4:0:1:0:0": {"fetch": 522810.1, "write": 196608.0},
+        "bf16:4:0:1:0:1": {"fetch": 564785.6, "write": 196608.0},
+        "bf16:4:0:1:2:0": {"fetch": 294407.1, "write": 196608.0},
+        "bf16:4:0:1:2:1": {"fetch": 346476.2, "write": 196608.0},
+        "bf16:4:0:2:1:0": {"fetch": 395524.5, "write": 196608.0},
+        "bf16:4:0:2:1:1": {"fetch": 395304.5, "write": 196608.0},
+        "bf16:4:0:2:0:0": {"fetch": 448611.1, "write": 196608.0},
+        "bf16:4:0:2:0:1": {"fetch": 419289.6, "write": 196608.0},
+        "bf16:4:0:2:2:0": {"fetch": 273557.5, "write": 196608.0},
+        "bf16:4:0:2:2:1": {"fetch": 274062.6, "write": 196608.0},
+        "bf16:4:2:1:1:0": {"fetch": 395320.6, "write": 196608.0},
+        "bf16:4:2:1:1:1": {"fetch": 394343.1, "write": 196608.0},
+        "bf16:4:2:1:0:0": {"fetch": 258162.4, "write": 196608.0},
+        "bf16:4:2:1:0:1": {"fetch": 249166.9, "write": 196608.0},
+        "bf16:4:2:1:2:0": {"fetch": 274036.5, "write": 196608.0},
+        "bf16:4:2:1:2:1": {"fetch": 273263.6, "write": 196608.0},
+        "bf16:4:1:1:1:0": {"fetch": 394155.1, "write": 196608.0},
+        "bf16:4:1:1:1:1": {"fetch": 401006.0, "write": 196608.0},
+        "bf16:4:1:1:0:0": {"fetch": 249390.4, "write": 196608.0},
+        "bf16:4:1:1:0:1": {"fetch": 253790.6, "write": 196608.0},
+        "bf16:4:1:1:2:0": {"fetch": 273292.6, "write": 196608.0},
+        "bf16:4:1:1:2:1": {"fetch": 280748.6, "write": 196608.0},
+        "bf16:4:1:2:1:0": {"fetch": 394301.4, "write": 196608.0},
+        "bf16:4:1:2:1:1": {"fetch": 394267.2, "write": 196608.0},
+        "bf16:4:1:2:0:0": {"fetch": 251209.2, "write": 196608.0},
+        "bf16:4:1:2:0:1": {"fetch": 249122.8, "write": 196608.0},
+        "bf16:4:1:2:2:0": {"fetch": 273427.8, "write": 196608.0},
+        "bf16:4:1:2:2:1": {"fetch": 273402.5, "write": 196608.0},
+        "bf16:4:1:4:1:0": {"fetch": 394302.7, "write": 196608.0},
+        "bf16:4:1:4:1:1": {"fetch": 394267.2, "write": 196608.0},
+        "bf16:4:1:4:0:0": {"fetch": 251181.1, "write": 196608.0},
+        "bf16:4:1:4:0:1": {"fetch": 249123.0, "write": 196608.0},
+        "bf16:4:1:4:2:0": {"fetch": 273427.5, "write": 196608.0},
+        "bf16:4:1:4:2:1": {"fetch": 273402.5, "write": 196608.0},
     },
 }
 
