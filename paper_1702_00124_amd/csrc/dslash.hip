@@ -459,7 +459,7 @@ __device__ __forceinline__ void cheb_unit(const HopArgs& a, size_t off, int u, i
 
 template <int WORDS>
 __device__ __forceinline__ uint32_t* shl_lds() {
-  __shared__ uint32_t S[8 * WORDS * 64];
+  __shared__ __align__(16) uint32_t S[8 * WORDS * 64];  // FP64 reads it as 8-byte words
   return S;
 }
 
