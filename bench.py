@@ -74,145 +74,145 @@ def hop_gflops(nrhs: int, sites: int, us: float) -> float:
 # sources); otherwise `traffic` is reported as null.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_COUNTERS = {
-    "source_sha256": "020ab83e22a2f4fb050eec0298e575ec73fedfae51b1aa1a89404ab967f64936",
+    "source_sha256": "5063c072b14150bb65eb8535bea70a7f8634373753568b4357ff7000fe3ffd51",
     "per_launch_kib": {
-        "f64:1:0:1:1:0": {"fetch": 913372.1, "write": 196608.0},
-        "f64:1:0:1:1:1": {"fetch": 743656.6, "write": 196608.0},
-        "f64:1:0:1:0:0": {"fetch": 1013915.1, "write": 196608.0},
-        "f64:1:0:1:0:1": {"fetch": 884293.2, "write": 196608.0},
-        "f64:1:0:1:2:0": {"fetch": 865683.6, "write": 196608.0},
-        "f64:1:0:1:2:1": {"fetch": 666852.8, "write": 196608.1},
-        "f64:1:1:1:1:0": {"fetch": 689258.0, "write": 196608.0},
+        "f64:1:0:1:1:0": {"fetch": 912761.6, "write": 196608.0},
+        "f64:1:0:1:1:1": {"fetch": 743422.4, "write": 196608.0},
+        "f64:1:0:1:0:0": {"fetch": 1015627.2, "write": 196608.0},
+        "f64:1:0:1:0:1": {"fetch": 884423.9, "write": 196608.0},
+        "f64:1:0:1:2:0": {"fetch": 867505.6, "write": 196608.0},
+        "f64:1:0:1:2:1": {"fetch": 675855.1, "write": 196608.0},
+        "f64:1:1:1:1:0": {"fetch": 689258.7, "write": 196608.0},
         "f64:1:1:1:1:1": {"fetch": 689024.5, "write": 196608.0},
-        "f64:1:1:1:0:0": {"fetch": 558112.7, "write": 196608.0},
-        "f64:1:1:1:0:1": {"fetch": 543882.1, "write": 196608.0},
-        "f64:1:1:1:2:0": {"fetch": 568340.9, "write": 196608.0},
-        "f64:1:1:1:2:1": {"fetch": 568160.1, "write": 196608.0},
-        "f32:1:0:1:1:0": {"fetch": 370523.9, "write": 98304.0},
-        "f32:1:0:1:1:1": {"fetch": 302568.7, "write": 98304.0},
-        "f32:1:0:1:0:0": {"fetch": 488438.3, "write": 98304.0},
-        "f32:1:0:1:0:1": {"fetch": 420652.5, "write": 98304.0},
-        "f32:1:0:1:2:0": {"fetch": 397076.6, "write": 98304.0},
-        "f32:1:0:1:2:1": {"fetch": 308405.8, "write": 98304.0},
-        "f32:1:1:1:1:0": {"fetch": 344628.9, "write": 98304.0},
-        "f32:1:1:1:1:1": {"fetch": 343270.7, "write": 98304.0},
-        "f32:1:1:1:0:0": {"fetch": 272795.6, "write": 98304.0},
+        "f64:1:1:1:0:0": {"fetch": 558467.4, "write": 196608.0},
+        "f64:1:1:1:0:1": {"fetch": 543881.8, "write": 196608.0},
+        "f64:1:1:1:2:0": {"fetch": 568300.5, "write": 196608.0},
+        "f64:1:1:1:2:1": {"fetch": 568156.5, "write": 196608.0},
+        "f32:1:0:1:1:0": {"fetch": 370858.2, "write": 98304.0},
+        "f32:1:0:1:1:1": {"fetch": 302604.6, "write": 98304.2},
+        "f32:1:0:1:0:0": {"fetch": 488200.2, "write": 98304.0},
+        "f32:1:0:1:0:1": {"fetch": 420665.9, "write": 98304.0},
+        "f32:1:0:1:2:0": {"fetch": 396858.7, "write": 98304.0},
+        "f32:1:0:1:2:1": {"fetch": 308342.5, "write": 98304.0},
+        "f32:1:1:1:1:0": {"fetch": 344631.5, "write": 98304.0},
+        "f32:1:1:1:1:1": {"fetch": 343257.4, "write": 98304.0},
+        "f32:1:1:1:0:0": {"fetch": 272795.9, "write": 98304.0},
         "f32:1:1:1:0:1": {"fetch": 271975.6, "write": 98304.0},
-        "f32:1:1:1:2:0": {"fetch": 284168.9, "write": 98304.0},
-        "f32:1:1:1:2:1": {"fetch": 283838.4, "write": 98304.0},
-        "bf16:1:0:1:1:0": {"fetch": 155777.4, "write": 49152.0},
-        "bf16:1:0:1:1:1": {"fetch": 130997.4, "write": 49152.0},
-        "bf16:1:0:1:0:0": {"fetch": 213380.7, "write": 49152.0},
-        "bf16:1:0:1:0:1": {"fetch": 185177.5, "write": 49152.0},
-        "bf16:1:0:1:2:0": {"fetch": 159906.9, "write": 49152.0},
-        "bf16:1:0:1:2:1": {"fetch": 139479.9, "write": 49152.0},
-        "bf16:1:1:1:1:0": {"fetch": 172097.1, "write": 49152.0},
+        "f32:1:1:1:2:0": {"fetch": 284160.5, "write": 98304.0},
+        "f32:1:1:1:2:1": {"fetch": 283824.0, "write": 98304.0},
+        "bf16:1:0:1:1:0": {"fetch": 155811.5, "write": 49152.0},
+        "bf16:1:0:1:1:1": {"fetch": 130996.9, "write": 49152.0},
+        "bf16:1:0:1:0:0": {"fetch": 213565.9, "write": 49152.0},
+        "bf16:1:0:1:0:1": {"fetch": 185421.6, "write": 49152.0},
+        "bf16:1:0:1:2:0": {"fetch": 159725.4, "write": 49152.0},
+        "bf16:1:0:1:2:1": {"fetch": 139411.4, "write": 49152.0},
+        "bf16:1:1:1:1:0": {"fetch": 172094.5, "write": 49152.0},
         "bf16:1:1:1:1:1": {"fetch": 129134.5, "write": 49152.0},
-        "bf16:1:1:1:0:0": {"fetch": 136049.6, "write": 49152.0},
-        "bf16:1:1:1:0:1": {"fetch": 136045.9, "write": 49152.0},
-        "bf16:1:1:1:2:0": {"fetch": 142120.9, "write": 49152.0},
-        "bf16:1:1:1:2:1": {"fetch": 137871.6, "write": 49152.0},
-        "f64:4:0:1:1:0": {"fetch": 2273252.6, "write": 786432.0},
-        "f64:4:0:1:1:1": {"fetch": 2593923.6, "write": 786432.4},
-        "f64:4:0:1:0:0": {"fetch": 2365943.1, "write": 786432.0},
-        "f64:4:0:1:0:1": {"fetch": 2774799.3, "write": 786432.6},
-        "f64:4:0:1:2:0": {"fetch": 1981426.0, "write": 786432.0},
-        "f64:4:0:1:2:1": {"fetch": 2126924.5, "write": 786432.1},
-        "f64:4:2:1:1:0": {"fetch": 2163663.7, "write": 786432.0},
-        "f64:4:2:1:1:1": {"fetch": 1907578.9, "write": 786432.0},
-        "f64:4:2:1:0:0": {"fetch": 1795463.8, "write": 786432.0},
-        "f64:4:2:1:0:1": {"fetch": 1554311.6, "write": 786448.9},
-        "f64:4:2:1:2:0": {"fetch": 1762488.3, "write": 786432.0},
-        "f64:4:2:1:2:1": {"fetch": 1479636.9, "write": 786433.6},
-        "f64:4:1:1:1:0": {"fetch": 1646268.8, "write": 786432.0},
-        "f64:4:1:1:1:1": {"fetch": 1680382.2, "write": 786432.0},
-        "f64:4:1:1:0:0": {"fetch": 1769915.8, "write": 786432.0},
-        "f64:4:1:1:0:1": {"fetch": 1797591.3, "write": 786432.0},
-        "f64:4:1:1:2:0": {"fetch": 1097274.4, "write": 786432.0},
-        "f64:4:1:1:2:1": {"fetch": 1129301.6, "write": 786432.0},
-        "f64:4:1:2:1:0": {"fetch": 1707053.6, "write": 786432.0},
-        "f64:4:1:2:1:1": {"fetch": 1746764.3, "write": 786432.0},
-        "f64:4:1:2:0:0": {"fetch": 1770432.6, "write": 786432.0},
-        "f64:4:1:2:0:1": {"fetch": 1825445.8, "write": 786432.0},
-        "f64:4:1:2:2:0": {"fetch": 1107971.9, "write": 786432.0},
-        "f64:4:1:2:2:1": {"fetch": 1201825.8, "write": 786432.0},
-        "f64:4:1:4:1:0": {"fetch": 1677550.3, "write": 786432.0},
-        "f64:4:1:4:1:1": {"fetch": 1602567.6, "write": 786432.0},
-        "f64:4:1:4:0:0": {"fetch": 1747988.6, "write": 786432.0},
-        "f64:4:1:4:0:1": {"fetch": 1640666.4, "write": 786432.0},
-        "f64:4:1:4:2:0": {"fetch": 1121640.4, "write": 786432.0},
-        "f64:4:1:4:2:1": {"fetch": 1096994.2, "write": 786432.0},
-        "f32:4:0:1:1:0": {"fetch": 1053029.8, "write": 393216.0},
-        "f32:4:0:1:1:1": {"fetch": 1199016.6, "write": 393216.4},
-        "f32:4:0:1:0:0": {"fetch": 1191468.8, "write": 393216.0},
-        "f32:4:0:1:0:1": {"fetch": 1384588.9, "write": 393216.1},
-        "f32:4:0:1:2:0": {"fetch": 860712.1, "write": 393216.0},
-        "f32:4:0:1:2:1": {"fetch": 928742.1, "write": 393216.0},
-        "f32:4:0:2:1:0": {"fetch": 822678.2, "write": 393216.0},
-        "f32:4:0:2:1:1": {"fetch": 819559.1, "write": 393217.0},
-        "f32:4:0:2:0:0": {"fetch": 1020684.9, "write": 393216.0},
-        "f32:4:0:2:0:1": {"fetch": 1020875.5, "write": 393216.1},
-        "f32:4:0:2:2:0": {"fetch": 575490.4, "write": 393216.0},
-        "f32:4:0:2:2:1": {"fetch": 560010.5, "write": 393216.4},
-        "f32:4:2:1:1:0": {"fetch": 892158.9, "write": 393216.0},
-        "f32:4:2:1:1:1": {"fetch": 824101.5, "write": 393223.4},
-        "f32:4:2:1:0:0": {"fetch": 723430.1, "write": 393216.0},
-        "f32:4:2:1:0:1": {"fetch": 618456.1, "write": 393241.6},
-        "f32:4:2:1:2:0": {"fetch": 668025.6, "write": 393216.0},
-        "f32:4:2:1:2:1": {"fetch": 577034.2, "write": 393220.6},
-        "f32:4:1:1:1:0": {"fetch": 788359.6, "write": 393216.0},
-        "f32:4:1:1:1:1": {"fetch": 796232.0, "write": 393216.0},
-        "f32:4:1:1:0:0": {"fetch": 700233.4, "write": 393216.0},
-        "f32:4:1:1:0:1": {"fetch": 529257.7, "write": 393216.0},
-        "f32:4:1:1:2:0": {"fetch": 546438.1, "write": 393216.0},
-        "f32:4:1:1:2:1": {"fetch": 551994.8, "write": 393216.0},
-        "f32:4:1:2:1:0": {"fetch": 795120.6, "write": 393216.0},
-        "f32:4:1:2:1:1": {"fetch": 790151.1, "write": 393216.0},
-        "f32:4:1:2:0:0": {"fetch": 658662.1, "write": 393216.0},
-        "f32:4:1:2:0:1": {"fetch": 519677.8, "write": 393216.0},
-        "f32:4:1:2:2:0": {"fetch": 548576.9, "write": 393216.0},
-        "f32:4:1:2:2:1": {"fetch": 546720.6, "write": 393216.0},
-        "f32:4:1:4:1:0": {"fetch": 795108.7, "write": 393216.0},
-        "f32:4:1:4:1:1": {"fetch": 790079.9, "write": 393216.0},
-        "f32:4:1:4:0:0": {"fetch": 658625.8, "write": 393216.0},
-        "f32:4:1:4:0:1": {"fetch": 519741.9, "write": 393216.0},
-        "f32:4:1:4:2:0": {"fetch": 548563.2, "write": 393216.0},
-        "f32:4:1:4:2:1": {"fetch": 546724.4, "write": 393216.0},
-        "bf16:4:0:1:1:0": {"fetch": 418079.3, "write": 196608.0},
-        "bf16:4:0:1:1:1": {"fetch": 478029.1, "write": 196608.0},
-        "bf16:4:0:1:0:0": {"fetch": 522810.1, "write": 196608.0},
-        "bf16:4:0:1:0:1": {"fetch": 564785.6, "write": 196608.0},
-        "bf16:4:0:1:2:0": {"fetch": 294407.1, "write": 196608.0},
-        "bf16:4:0:1:2:1": {"fetch": 346476.2, "write": 196608.0},
-        "bf16:4:0:2:1:0": {"fetch": 395524.5, "write": 196608.0},
-        "bf16:4:0:2:1:1": {"fetch": 395304.5, "write": 196608.0},
-        "bf16:4:0:2:0:0": {"fetch": 448611.1, "write": 196608.0},
-        "bf16:4:0:2:0:1": {"fetch": 419289.6, "write": 196608.0},
-        "bf16:4:0:2:2:0": {"fetch": 273557.5, "write": 196608.0},
-        "bf16:4:0:2:2:1": {"fetch": 274062.6, "write": 196608.0},
-        "bf16:4:2:1:1:0": {"fetch": 395320.6, "write": 196608.0},
-        "bf16:4:2:1:1:1": {"fetch": 394343.1, "write": 196608.0},
-        "bf16:4:2:1:0:0": {"fetch": 258162.4, "write": 196608.0},
-        "bf16:4:2:1:0:1": {"fetch": 249166.9, "write": 196608.0},
-        "bf16:4:2:1:2:0": {"fetch": 274036.5, "write": 196608.0},
+        "bf16:1:1:1:0:0": {"fetch": 136048.7, "write": 49152.0},
+        "bf16:1:1:1:0:1": {"fetch": 136045.8, "write": 49152.0},
+        "bf16:1:1:1:2:0": {"fetch": 142121.1, "write": 49152.0},
+        "bf16:1:1:1:2:1": {"fetch": 137862.2, "write": 49152.0},
+        "f64:4:0:1:1:0": {"fetch": 2264036.4, "write": 786432.0},
+        "f64:4:0:1:1:1": {"fetch": 2574642.4, "write": 786432.0},
+        "f64:4:0:1:0:0": {"fetch": 2396478.8, "write": 786432.0},
+        "f64:4:0:1:0:1": {"fetch": 2797765.6, "write": 786433.0},
+        "f64:4:0:1:2:0": {"fetch": 1966202.1, "write": 786432.0},
+        "f64:4:0:1:2:1": {"fetch": 2112441.2, "write": 786432.0},
+        "f64:4:2:1:1:0": {"fetch": 2158536.9, "write": 786432.0},
+        "f64:4:2:1:1:1": {"fetch": 1904074.4, "write": 786432.0},
+        "f64:4:2:1:0:0": {"fetch": 1797211.6, "write": 786432.0},
+        "f64:4:2:1:0:1": {"fetch": 1550027.0, "write": 786449.0},
+        "f64:4:2:1:2:0": {"fetch": 1737927.8, "write": 786432.0},
+        "f64:4:2:1:2:1": {"fetch": 1491612.8, "write": 786434.4},
+        "f64:4:1:1:1:0": {"fetch": 1618731.6, "write": 786432.0},
+        "f64:4:1:1:1:1": {"fetch": 1671151.6, "write": 786432.0},
+        "f64:4:1:1:0:0": {"fetch": 1769876.9, "write": 786432.0},
+        "f64:4:1:1:0:1": {"fetch": 1797876.7, "write": 786432.0},
+        "f64:4:1:1:2:0": {"fetch": 1096789.6, "write": 786432.0},
+        "f64:4:1:1:2:1": {"fetch": 1126431.4, "write": 786432.0},
+        "f64:4:1:2:1:0": {"fetch": 1670566.1, "write": 786432.0},
+        "f64:4:1:2:1:1": {"fetch": 1712691.2, "write": 786432.0},
+        "f64:4:1:2:0:0": {"fetch": 1770383.0, "write": 786432.0},
+        "f64:4:1:2:0:1": {"fetch": 1820200.6, "write": 786432.0},
+        "f64:4:1:2:2:0": {"fetch": 1107671.4, "write": 786432.0},
+        "f64:4:1:2:2:1": {"fetch": 1201626.8, "write": 786432.0},
+        "f64:4:1:4:1:0": {"fetch": 1758755.5, "write": 786432.0},
+        "f64:4:1:4:1:1": {"fetch": 1654775.1, "write": 786432.0},
+        "f64:4:1:4:0:0": {"fetch": 1748037.0, "write": 786432.0},
+        "f64:4:1:4:0:1": {"fetch": 1639506.3, "write": 786432.0},
+        "f64:4:1:4:2:0": {"fetch": 1122551.8, "write": 786432.0},
+        "f64:4:1:4:2:1": {"fetch": 1096926.2, "write": 786432.0},
+        "f32:4:0:1:1:0": {"fetch": 1051158.1, "write": 393216.0},
+        "f32:4:0:1:1:1": {"fetch": 1197997.7, "write": 393216.2},
+        "f32:4:0:1:0:0": {"fetch": 1192784.7, "write": 393216.0},
+        "f32:4:0:1:0:1": {"fetch": 1384213.9, "write": 393216.2},
+        "f32:4:0:1:2:0": {"fetch": 861312.9, "write": 393216.0},
+        "f32:4:0:1:2:1": {"fetch": 928345.4, "write": 393216.2},
+        "f32:4:0:2:1:0": {"fetch": 824000.7, "write": 393216.0},
+        "f32:4:0:2:1:1": {"fetch": 820299.1, "write": 393217.5},
+        "f32:4:0:2:0:0": {"fetch": 1020628.6, "write": 393216.0},
+        "f32:4:0:2:0:1": {"fetch": 1021245.2, "write": 393216.4},
+        "f32:4:0:2:2:0": {"fetch": 575228.8, "write": 393216.0},
+        "f32:4:0:2:2:1": {"fetch": 559885.4, "write": 393216.2},
+        "f32:4:2:1:1:0": {"fetch": 891856.6, "write": 393216.0},
+        "f32:4:2:1:1:1": {"fetch": 824560.2, "write": 393224.2},
+        "f32:4:2:1:0:0": {"fetch": 722026.6, "write": 393216.0},
+        "f32:4:2:1:0:1": {"fetch": 618821.4, "write": 393238.9},
+        "f32:4:2:1:2:0": {"fetch": 670180.8, "write": 393216.0},
+        "f32:4:2:1:2:1": {"fetch": 576731.2, "write": 393220.9},
+        "f32:4:1:1:1:0": {"fetch": 788425.9, "write": 393216.0},
+        "f32:4:1:1:1:1": {"fetch": 796077.4, "write": 393216.0},
+        "f32:4:1:1:0:0": {"fetch": 698201.7, "write": 393216.0},
+        "f32:4:1:1:0:1": {"fetch": 528833.2, "write": 393216.0},
+        "f32:4:1:1:2:0": {"fetch": 546436.9, "write": 393216.0},
+        "f32:4:1:1:2:1": {"fetch": 552026.3, "write": 393216.0},
+        "f32:4:1:2:1:0": {"fetch": 795093.5, "write": 393216.0},
+        "f32:4:1:2:1:1": {"fetch": 790177.7, "write": 393216.0},
+        "f32:4:1:2:0:0": {"fetch": 658807.9, "write": 393216.0},
+        "f32:4:1:2:0:1": {"fetch": 519848.8, "write": 393216.0},
+        "f32:4:1:2:2:0": {"fetch": 548756.8, "write": 393216.0},
+        "f32:4:1:2:2:1": {"fetch": 546735.8, "write": 393216.0},
+        "f32:4:1:4:1:0": {"fetch": 795022.7, "write": 393216.0},
+        "f32:4:1:4:1:1": {"fetch": 790152.8, "write": 393216.0},
+        "f32:4:1:4:0:0": {"fetch": 658870.3, "write": 393216.0},
+        "f32:4:1:4:0:1": {"fetch": 519884.2, "write": 393216.0},
+        "f32:4:1:4:2:0": {"fetch": 548726.4, "write": 393216.0},
+        "f32:4:1:4:2:1": {"fetch": 546736.8, "write": 393216.0},
+        "bf16:4:0:1:1:0": {"fetch": 417760.2, "write": 196608.0},
+        "bf16:4:0:1:1:1": {"fetch": 477404.0, "write": 196608.0},
+        "bf16:4:0:1:0:0": {"fetch": 523169.4, "write": 196608.0},
+        "bf16:4:0:1:0:1": {"fetch": 565987.1, "write": 196608.0},
+        "bf16:4:0:1:2:0": {"fetch": 294195.1, "write": 196608.0},
+        "bf16:4:0:1:2:1": {"fetch": 346531.1, "write": 196608.0},
+        "bf16:4:0:2:1:0": {"fetch": 395547.1, "write": 196608.0},
+        "bf16:4:0:2:1:1": {"fetch": 395407.8, "write": 196608.0},
+        "bf16:4:0:2:0:0": {"fetch": 448498.9, "write": 196608.0},
+        "bf16:4:0:2:0:1": {"fetch": 419367.3, "write": 196608.0},
+        "bf16:4:0:2:2:0": {"fetch": 273536.3, "write": 196608.0},
+        "bf16:4:0:2:2:1": {"fetch": 273946.0, "write": 196608.0},
+        "bf16:4:2:1:1:0": {"fetch": 395309.1, "write": 196608.0},
+        "bf16:4:2:1:1:1": {"fetch": 394389.8, "write": 196608.0},
+        "bf16:4:2:1:0:0": {"fetch": 257784.8, "write": 196608.0},
+        "bf16:4:2:1:0:1": {"fetch": 249163.4, "write": 196608.0},
+        "bf16:4:2:1:2:0": {"fetch": 274031.8, "write": 196608.0},
         "bf16:4:2:1:2:1": {"fetch": 273263.6, "write": 196608.0},
-        "bf16:4:1:1:1:0": {"fetch": 394155.1, "write": 196608.0},
-        "bf16:4:1:1:1:1": {"fetch": 401006.0, "write": 196608.0},
-        "bf16:4:1:1:0:0": {"fetch": 249390.4, "write": 196608.0},
-        "bf16:4:1:1:0:1": {"fetch": 253790.6, "write": 196608.0},
-        "bf16:4:1:1:2:0": {"fetch": 273292.6, "write": 196608.0},
-        "bf16:4:1:1:2:1": {"fetch": 280748.6, "write": 196608.0},
-        "bf16:4:1:2:1:0": {"fetch": 394301.4, "write": 196608.0},
-        "bf16:4:1:2:1:1": {"fetch": 394267.2, "write": 196608.0},
-        "bf16:4:1:2:0:0": {"fetch": 251209.2, "write": 196608.0},
-        "bf16:4:1:2:0:1": {"fetch": 249122.8, "write": 196608.0},
-        "bf16:4:1:2:2:0": {"fetch": 273427.8, "write": 196608.0},
+        "bf16:4:1:1:1:0": {"fetch": 394154.9, "write": 196608.0},
+        "bf16:4:1:1:1:1": {"fetch": 401118.4, "write": 196608.0},
+        "bf16:4:1:1:0:0": {"fetch": 249383.1, "write": 196608.0},
+        "bf16:4:1:1:0:1": {"fetch": 253829.8, "write": 196608.0},
+        "bf16:4:1:1:2:0": {"fetch": 273292.9, "write": 196608.0},
+        "bf16:4:1:1:2:1": {"fetch": 280851.9, "write": 196608.0},
+        "bf16:4:1:2:1:0": {"fetch": 394309.2, "write": 196608.0},
+        "bf16:4:1:2:1:1": {"fetch": 394267.1, "write": 196608.0},
+        "bf16:4:1:2:0:0": {"fetch": 251040.4, "write": 196608.0},
+        "bf16:4:1:2:0:1": {"fetch": 249121.5, "write": 196608.0},
+        "bf16:4:1:2:2:0": {"fetch": 273424.2, "write": 196608.0},
         "bf16:4:1:2:2:1": {"fetch": 273402.5, "write": 196608.0},
-        "bf16:4:1:4:1:0": {"fetch": 394302.7, "write": 196608.0},
-        "bf16:4:1:4:1:1": {"fetch": 394267.2, "write": 196608.0},
-        "bf16:4:1:4:0:0": {"fetch": 251181.1, "write": 196608.0},
-        "bf16:4:1:4:0:1": {"fetch": 249123.0, "write": 196608.0},
-        "bf16:4:1:4:2:0": {"fetch": 273427.5, "write": 196608.0},
+        "bf16:4:1:4:1:0": {"fetch": 394310.0, "write": 196608.0},
+        "bf16:4:1:4:1:1": {"fetch": 394267.1, "write": 196608.0},
+        "bf16:4:1:4:0:0": {"fetch": 251062.6, "write": 196608.0},
+        "bf16:4:1:4:0:1": {"fetch": 249120.9, "write": 196608.0},
+        "bf16:4:1:4:2:0": {"fetch": 273424.9, "write": 196608.0},
         "bf16:4:1:4:2:1": {"fetch": 273402.5, "write": 196608.0},
     },
 }
