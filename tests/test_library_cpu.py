@@ -158,3 +158,25 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(os.path.dirname(HEADER), "..", "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr
+
+
+def test_bench_counter_table_covers_the_kernels_only_launches():
+    """bench.py's 32^3 x 64 HBM traffic table (FETCH_SIZE / WRITE_SIZE per launch) has an
+    entry for every configuration its --kernels-only leg launches with 1 and 4 rhs, in
+    every precision: every configuration the autotuner can keep for the roofline launches
+    (the thread-per-site kernel with one or two rhs per thread, its shared-link variant
+    and the direction-parallel passes, in the three workgroup orders, cached and
+    streaming), so the bench line's traffic is never missing for a tuned choice."""
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(HEADER), ".."))
+    import bench
+    kib = bench.PMC_COUNTERS["per_launch_kib"]
+    for nrhs in (1, 4):
+        for prec in ("f64", "f32", "bf16"):
+            cfgs = bench.kernels_only_configs(prec, nrhs)
+            variants = {c[0] for c in cfgs}
+            assert variants == ({0, 1} if nrhs == 1 else {0, 1, 2}), (prec, nrhs)
+            for cfg in cfgs:
+                key = f"{prec}:{nrhs}:" + ":".join(map(str, cfg))
+                assert key in kib, key
+                assert kib[key]["fetch"] > 0 and kib[key]["write"] > 0
