@@ -377,7 +377,9 @@ class WilsonLattice:
             W.check(self.lib.wl_set_hop_config(self.h, _prec(prec), k, *new))
 
     def set_hop_variant(self, prec, variant: int):
-        """0: thread per site; 1: direction-parallel; for every rhs class."""
+        """0: thread per site; 1: direction-parallel; 2: thread per site with the links
+        shared in LDS across four rhs (from 4 rhs; below that variant 0 runs); for every
+        rhs class."""
         self.set_hop_config(prec, -1, variant=variant)
 
     def autotune(self, cache: Optional[str] = None):
