@@ -282,17 +282,17 @@ def test_dslash_launch_config_invariance(variant, L):
 def test_shared_link_variant_matches_site_kernel(L):
     """The shared-link variant (a workgroup takes one 64-site tile for four rhs
     and reads the tile's links into LDS once) gives the thread-per-site
-    kernel's output bit for bit: every precision, 4, 5 and 8 rhs (a partly idle
-    last group of four), both output parities and the dagger, every workgroup
+    kernel's output bit for bit: every precision, 4, 5, 8 and 16 rhs (5: a partly
+    idle last group of four), both output parities and the dagger, every workgroup
     order, and with the fused epilogue (J with per-rhs shifts); a batched CG
     whose J hops take it (with the fused <p, Jp> partials) converges to the
     oracle's J."""
     say("shared-link variant", L)
     lat, U = make_lattice(L)
-    psi = half_noise(L, 91, nrhs=8)
-    shifts = [0.0, 0.005, 0.05, 0.5, 0.0, 0.005, 0.05, 0.5]
+    psi = half_noise(L, 91, nrhs=16)
+    shifts = [0.0, 0.005, 0.05, 0.5] * 4
     for prec in ("f64", "f32", "bf16"):
-        for nrhs in (4, 5, 8):
+        for nrhs in (4, 5, 8, 16):
             x = lat.import_spinor(torch.from_numpy(psi[:nrhs]), prec)
             outs = {}
             for variant, xcd in ((0, 1), (2, 1), (2, 0)):
